@@ -1,0 +1,63 @@
+"""The synthetic workloads, by name, with their sizes.
+
+  chain12      12-atom chain at 2.5 bohr, 8 AO / 20 RI per atom (96 / 240),
+               48 occupied, decays H 0.5 / T 0.3 / V 0.2, no filter,
+               10 tau / 10 omega, HOMO and LUMO.
+  strip300     300-atom ribbon 7 atoms wide, 13 AO / 40 RI per atom
+               (3900 / 12000), half filled, decays 0.8 / 0.8 / 0.2,
+               filter 1e-9, 12 tau / 12 omega, HOMO-4 .. LUMO+4.
+  strip1000    the same generator at 1000 atoms (13000 / 40000).
+  strip1734    the same generator at 1734 atoms, filter 1e-8.
+  strip<N>     any other atom count with the strip generator (tests).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import system as gsys
+from . import grids as ggrids
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    system: gsys.System
+    n_tau: int
+    n_w: int
+    n_below: int        # states: HOMO-(n_below-1) .. LUMO+(n_above-1)
+    n_above: int
+
+    def states(self):
+        return self.system.states_around_gap(self.n_below, self.n_above)
+
+
+def chain12(seed=0) -> Workload:
+    s = gsys.System(gsys.chain(12), 8, 20, 0.5, 0.3, 0.2, 0.0, seed=seed, n_occ=48)
+    return Workload("chain12", s, 10, 10, 1, 1)
+
+
+def strip(n_atoms: int, seed=0, filter_eps=1e-9, n_ao=13, n_ri=40, n_tau=12,
+          n_below=5, n_above=5) -> Workload:
+    s = gsys.System(gsys.strip(n_atoms), n_ao, n_ri, 0.8, 0.8, 0.2, filter_eps, seed=seed)
+    return Workload(f"strip{n_atoms}", s, n_tau, n_tau, n_below, n_above)
+
+
+def by_name(name: str, seed=0) -> Workload:
+    if name == "chain12":
+        return chain12(seed)
+    if name == "strip1734":
+        return strip(1734, seed, filter_eps=1e-8)
+    if name.startswith("strip"):
+        return strip(int(name[5:]), seed)
+    raise KeyError(name)
+
+
+def grids_for(w: Workload, eps) -> ggrids.Grids:
+    return ggrids.make_grids(eps, w.system.n_occ, w.n_tau, w.n_w)
+
+
+def mu_fermi(eps, n_occ) -> float:
+    eps = np.asarray(eps)
+    return 0.5 * float(eps[n_occ - 1] + eps[n_occ])

@@ -1,0 +1,214 @@
+"""Synthetic GW inputs: geometry, basis layout, H, V, the three-center tensor.
+
+The inputs stand in for the mean-field run and the Gaussian integrals that
+feed the paper's method (Eqs. 1, 4 and 8): atoms on a chain, a ribbon-shaped
+strip or a random 3D packing; every atom carries ``n_ao`` primary and
+``n_ri`` auxiliary functions.  With d the distance between the atoms that
+carry two functions:
+
+  H_{mu nu}   = z * exp(-k_H d_{mu nu})  (mu < nu, mirrored);
+  H_{mu mu}   = z + (2u - 1)             (u uniform in [0,1))
+  (mu nu|P)   = z * exp(-k_T (d_{mu nu} + d_{mu P} + d_{nu P})), symmetric in mu nu
+  V_PQ        = exp(-k_V d_PQ) + delta_PQ
+with z a Philox/Box-Muller normal keyed by the global element index.  The
+mean-field orbitals C and energies eps come from LAPACK ``eigh`` of H
+(orthonormal AO basis, S = 1).
+
+This module holds no arithmetic of the GW method itself; it only produces
+inputs.  The tensor is stored as dense atom-triple "bricks" (a, b, c), each
+``[n_ao(a)][n_ao(b)][n_ri(c)]`` row-major; only the triples whose exact norm
+bound ``Z_MAX * sqrt(n_a n_b n_c) * exp(-k_T s_abc)`` reaches the filter are
+enumerated (the others are below the filter whatever the draws are).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+from . import philox
+
+STREAM_H = 1
+STREAM_H_DIAG = 2
+STREAM_T = 3
+SPACING = 2.5          # bohr
+STRIP_WIDTH = 7
+
+
+def stream_id(tensor: int, sys_id: int = 0) -> int:
+    return tensor + 16 * sys_id
+
+
+# ----------------------------------------------------------------- geometry
+def chain(n_atoms: int, spacing: float = SPACING) -> np.ndarray:
+    xyz = np.zeros((n_atoms, 3))
+    xyz[:, 0] = spacing * np.arange(n_atoms)
+    return xyz
+
+
+def strip(n_atoms: int, width: int = STRIP_WIDTH, spacing: float = SPACING) -> np.ndarray:
+    """Rectangular ribbon: atom k at (s*floor(k/w), s*(k mod w), 0)."""
+    k = np.arange(n_atoms)
+    xyz = np.zeros((n_atoms, 3))
+    xyz[:, 0] = spacing * (k // width)
+    xyz[:, 1] = spacing * (k % width)
+    return xyz
+
+
+def packing(n_atoms: int, seed: int, stream: int, density: float = 0.0148,
+            d_min: float = SPACING, max_tries: int = 200000) -> np.ndarray:
+    """Random sequential addition in a cube of the given number density."""
+    side = (n_atoms / density) ** (1.0 / 3.0)
+    pts = []
+    i = 0
+    while len(pts) < n_atoms:
+        if i >= max_tries:
+            raise RuntimeError("packing did not converge")
+        u = philox.uniform(seed, stream, np.arange(3 * i, 3 * i + 3))
+        p = side * u
+        if all(np.linalg.norm(p - q) >= d_min for q in pts):
+            pts.append(p)
+        i += 1
+    return np.array(pts)
+
+
+def atom_distances(xyz: np.ndarray) -> np.ndarray:
+    diff = xyz[:, None, :] - xyz[None, :, :]
+    return np.sqrt((diff * diff).sum(-1))
+
+
+# ----------------------------------------------------------------- system
+@dataclasses.dataclass
+class System:
+    """One synthetic molecule/strip with its inputs (all float64)."""
+    xyz: np.ndarray            # [n_atoms, 3] bohr
+    n_ao_atom: int
+    n_ri_atom: int
+    k_h: float
+    k_t: float
+    k_v: float
+    filter_eps: float
+    seed: int = 0
+    sys_id: int = 0
+    n_occ: Optional[int] = None
+
+    def __post_init__(self):
+        self.n_atoms = self.xyz.shape[0]
+        self.n_ao = self.n_atoms * self.n_ao_atom
+        self.n_ri = self.n_atoms * self.n_ri_atom
+        if self.n_occ is None:
+            self.n_occ = self.n_ao // 2
+        self.ao_off = np.arange(self.n_atoms + 1, dtype=np.int32) * self.n_ao_atom
+        self.ri_off = np.arange(self.n_atoms + 1, dtype=np.int32) * self.n_ri_atom
+        self.dist = atom_distances(self.xyz)
+        self.ao_atom = np.repeat(np.arange(self.n_atoms), self.n_ao_atom)
+        self.ri_atom = np.repeat(np.arange(self.n_atoms), self.n_ri_atom)
+
+    # ---- H, eigenpairs
+    def hamiltonian(self) -> np.ndarray:
+        n = self.n_ao
+        iu, ju = np.triu_indices(n)
+        tri = (ju.astype(np.uint64) * (ju.astype(np.uint64) + np.uint64(1)) // np.uint64(2)
+               + iu.astype(np.uint64))
+        z = philox.normal(self.seed, stream_id(STREAM_H, self.sys_id), tri)
+        d = self.dist[self.ao_atom[iu], self.ao_atom[ju]]
+        h = np.zeros((n, n))
+        h[iu, ju] = z * np.exp(-self.k_h * d)
+        h = h + np.triu(h, 1).T
+        u = philox.uniform(self.seed, stream_id(STREAM_H_DIAG, self.sys_id), np.arange(n))
+        h[np.arange(n), np.arange(n)] += 2.0 * u - 1.0
+        return h
+
+    def mean_field(self):
+        """(C [n_mo][n_ao] row per MO, eps ascending) from eigh(H)."""
+        w, v = np.linalg.eigh(self.hamiltonian())
+        return np.ascontiguousarray(v.T), w
+
+    # ---- V
+    def coulomb(self) -> np.ndarray:
+        d = self.dist[self.ri_atom[:, None], self.ri_atom[None, :]]
+        return np.exp(-self.k_v * d) + np.eye(self.n_ri)
+
+    # ---- three-center tensor
+    def perimeter(self) -> np.ndarray:
+        """s[a, b, c] = d_ab + (d_ac + d_bc), summed in this order so that
+        s[a, b, c] == s[b, a, c] exactly."""
+        d = self.dist
+        return d[:, :, None] + (d[:, None, :] + d[None, :, :])
+
+    def triples(self) -> np.ndarray:
+        """Kept ordered atom triples (a, b, c), sorted by (c, b, a), int32 [n, 3].
+
+        A triple is enumerated when the norm bound of its brick reaches the
+        filter threshold (all triples when the filter is 0).
+        """
+        na = self.n_atoms
+        size = np.sqrt(float(self.n_ao_atom * self.n_ao_atom * self.n_ri_atom))
+        out = []
+        for c in range(na):
+            s = self.dist + (self.dist[:, c][:, None] + self.dist[:, c][None, :])
+            bound = philox.Z_MAX * size * np.exp(-self.k_t * s)
+            b_idx, a_idx = np.nonzero((bound >= self.filter_eps).T)
+            trip = np.stack([a_idx, b_idx, np.full_like(a_idx, c)], axis=1)
+            out.append(trip)
+        return np.ascontiguousarray(np.concatenate(out).astype(np.int32))
+
+    def brick_size(self) -> int:
+        return self.n_ao_atom * self.n_ao_atom * self.n_ri_atom
+
+    def brick(self, a: int, b: int, c: int) -> np.ndarray:
+        """Brick (a, b, c) as [n_ao(a)][n_ao(b)][n_ri(c)] float64."""
+        mu = np.arange(self.ao_off[a], self.ao_off[a + 1]).astype(np.uint64)
+        nu = np.arange(self.ao_off[b], self.ao_off[b + 1]).astype(np.uint64)
+        p = np.arange(self.ri_off[c], self.ri_off[c + 1]).astype(np.uint64)
+        lo = np.minimum(mu[:, None], nu[None, :])
+        hi = np.maximum(mu[:, None], nu[None, :])
+        tri = hi * (hi + np.uint64(1)) // np.uint64(2) + lo
+        idx = tri[:, :, None] * np.uint64(self.n_ri) + p[None, None, :]
+        z = philox.normal(self.seed, stream_id(STREAM_T, self.sys_id), idx)
+        s = self.dist[a, b] + (self.dist[a, c] + self.dist[b, c])
+        return z * np.exp(-self.k_t * s)
+
+    def bricks(self, trip: np.ndarray, chunk: int = 256) -> np.ndarray:
+        """All bricks of a triple list, shape [n_trip, bs] (vectorised)."""
+        trip = np.asarray(trip)
+        na, nr = self.n_ao_atom, self.n_ri_atom
+        out = np.empty((len(trip), self.brick_size()))
+        li = np.arange(na, dtype=np.uint64)
+        lp = np.arange(nr, dtype=np.uint64)
+        for s0 in range(0, len(trip), chunk):
+            t = trip[s0:s0 + chunk]
+            a, b, c = t[:, 0], t[:, 1], t[:, 2]
+            mu = self.ao_off[a].astype(np.uint64)[:, None] + li[None, :]
+            nu = self.ao_off[b].astype(np.uint64)[:, None] + li[None, :]
+            p = self.ri_off[c].astype(np.uint64)[:, None] + lp[None, :]
+            lo = np.minimum(mu[:, :, None], nu[:, None, :])
+            hi = np.maximum(mu[:, :, None], nu[:, None, :])
+            tri = hi * (hi + np.uint64(1)) // np.uint64(2) + lo
+            idx = tri[:, :, :, None] * np.uint64(self.n_ri) + p[:, None, None, :]
+            z = philox.normal(self.seed, stream_id(STREAM_T, self.sys_id), idx)
+            s = self.dist[a, b] + (self.dist[a, c] + self.dist[b, c])
+            out[s0:s0 + len(t)] = (z * np.exp(-self.k_t * s)[:, None, None, None]).reshape(len(t), -1)
+        return out
+
+    def dense_t3c(self) -> np.ndarray:
+        """The full tensor (mu nu|P) as a dense [n_ao][n_ao][n_ri] array
+        (small systems only; every triple, no enumeration cut)."""
+        n, m = self.n_ao, self.n_ri
+        mu = np.arange(n, dtype=np.uint64)
+        lo = np.minimum(mu[:, None], mu[None, :])
+        hi = np.maximum(mu[:, None], mu[None, :])
+        tri = hi * (hi + np.uint64(1)) // np.uint64(2) + lo
+        idx = tri[:, :, None] * np.uint64(m) + np.arange(m, dtype=np.uint64)[None, None, :]
+        z = philox.normal(self.seed, stream_id(STREAM_T, self.sys_id), idx)
+        aa = self.ao_atom
+        cc = self.ri_atom
+        s = (self.dist[aa[:, None], aa[None, :]][:, :, None]
+             + (self.dist[aa[:, None], cc[None, :]][:, None, :]
+                + self.dist[aa[:, None], cc[None, :]][None, :, :]))
+        return z * np.exp(-self.k_t * s)
+
+    def states_around_gap(self, n_below: int, n_above: int) -> np.ndarray:
+        h = self.n_occ - 1
+        return np.arange(h - n_below + 1, self.n_occ + n_above, dtype=np.int32)
