@@ -1,0 +1,187 @@
+"""Benchmark: one step = the whole G0W0 hot path on one synthetic system.
+
+A step runs the five libgw calls (density matrices, block-sparse chi for all
+tau, screening, diagonal self-energy, QP solution) from device-resident
+inputs.  Reported `value` is the chi + Sigma contraction throughput
+(algorithmic FLOPs of the executed block products / their kernel time);
+`time_to_qp_s` is the wall time of the whole step.
+
+Default workload strip300: 300-atom ribbon 7 atoms wide, 13 AO / 40 RI per
+atom (3900 AO, 12000 RI), half filled, filter 1e-9, 12 tau / 12 omega points,
+Sigma for HOMO-4 .. LUMO+4.  Inputs are seeded and synthetic (gwinputs).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload strip300]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "chi+Sigma contraction TFLOP/s & time-to-QP; mixed/learned vs FP64 at 1 meV"
+PEAK_FP64_MFMA_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup(name, seed=0):
+    import torch
+    from gwinputs import configs, device as gdev
+    from paper_2104_09857_amd import gw
+    t0 = time.perf_counter()
+    w = configs.by_name(name, seed)
+    s = w.system
+    C, eps = s.mean_field()
+    g = configs.grids_for(w, eps)
+    mu = configs.mu_fermi(eps, s.n_occ)
+    trip = s.triples()
+    log(f"[setup] {name}: {s.n_atoms} atoms, {s.n_ao} AO, {s.n_ri} RI, {len(trip)} triples, "
+        f"host prep {time.perf_counter() - t0:.1f} s")
+    t3c = gdev.bricks_on_device(s, trip)
+    V = torch.as_tensor(s.coulomb(), device="cuda")
+    Cd = torch.as_tensor(C, device="cuda")
+    torch.cuda.synchronize()
+    sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c)
+    log(f"[setup] device inputs ready ({t3c.numel() * 8 / 1e9:.1f} GB bricks), "
+        f"{time.perf_counter() - t0:.1f} s")
+    return dict(w=w, s=s, C=C, eps=eps, g=g, mu=mu, trip=trip, sys=sysd, Cd=Cd, V=V, t3c=t3c)
+
+
+def step(ctx):
+    from paper_2104_09857_amd import pipeline
+    g = ctx["g"]
+    return pipeline.g0w0(ctx["sys"], ctx["Cd"], ctx["eps"], ctx["mu"], ctx["V"], g.tau, g.omega,
+                         g.cos_w, g.sin_w, g.icos_w, ctx["w"].states(), ctx["s"].filter_eps,
+                         events=True, chi_timing=True)
+
+
+def cpu_baseline(ctx, out, budget_s=20.0):
+    """The oracle on a bounded sample: chi blocks (c, c') at tau_0, contracted
+    from the same bricks (the input generator's device copy) and D(tau_0)."""
+    from oracle import chi as ochi
+    s = ctx["s"]
+    d_occ = out["d_occ"][0].cpu().numpy()
+    d_vir = out["d_vir"][0].cpu().numpy()
+    trip = ctx["trip"]
+    rng = np.random.default_rng(0)
+    mid = s.n_atoms // 2
+    pairs = [(mid, mid), (mid, mid + 9)] + [tuple(sorted(rng.integers(0, s.n_atoms, 2))) for _ in range(30)]
+    cache = {}
+    loaded = set()
+
+    def load(c):
+        rows = np.nonzero(trip[:, 2] == c)[0]
+        vals = ctx["t3c"][rows].cpu().numpy()
+        for r, v in zip(rows, vals):
+            cache[tuple(trip[r])] = v.reshape(s.n_ao_atom, s.n_ao_atom, s.n_ri_atom)
+
+    flops = 0.0
+    elapsed = 0.0
+    done = []
+    nr = s.n_ri_atom
+    for (c, c2) in pairs:
+        for cc in (c, c2):
+            if cc not in loaded:
+                load(cc)
+                loaded.add(cc)
+        n_lam = len({t[0] for t in trip[trip[:, 2] == c]}) * s.n_ao_atom
+        n_mu = len({t[0] for t in trip[trip[:, 2] == c2]}) * s.n_ao_atom
+        t0 = time.perf_counter()
+        ochi.chi_block(c, c2, trip, lambda a, b, cc: cache[(a, b, cc)], d_occ, d_vir, s.ao_off,
+                       s.ri_off, s.filter_eps)
+        elapsed += time.perf_counter() - t0
+        # M: mu x lambda x (sigma P); N: mu x nu x (Q sigma); chi: P x Q x (mu sigma)
+        flops += (2.0 * n_mu * n_lam * n_lam * nr + 2.0 * n_mu * n_mu * nr * n_lam
+                  + 2.0 * nr * nr * n_mu * n_lam)
+        done.append((int(c), int(c2)))
+        if elapsed > budget_s:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": flops / elapsed / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(done)} chi blocks (c, c') at tau_0 of the same workload, FP64 "
+                      f"NumPy/OpenBLAS dense within the brick supports, {elapsed:.1f} s: {done}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="strip300")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding by tau is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = setup(args.workload)
+    for i in range(args.warmup):
+        t0 = time.perf_counter()
+        step(ctx)
+        torch.cuda.synchronize()
+        log(f"[warmup {i}] {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = []
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        outs.append(step(ctx))
+        log(f"[step {i}] {time.perf_counter() - ts:.2f} s stages(ms) "
+            + json.dumps({k: round(v, 1) for k, v in outs[-1]['ms'].items()}))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = outs[-1]
+    cs, ss = out["chi_stats"], out["sig_stats"]
+    chi_ms = float(np.mean([o["ms"]["chi"] for o in outs]))
+    sig_ms = float(np.mean([o["ms"]["sigma"] for o in outs]))
+    flops = cs["flops_ab"] + cs["flops_c"] + ss["flops"]
+    value = flops / ((chi_ms + sig_ms) / 1e3) / 1e12
+    # dominant kernel: the outer contraction (stage C), timed per launch on the library's stream
+    c_ms = float(np.mean([o["chi_stats"]["ms_stage"][2] for o in outs]))
+    c_n = out["chi_stats"]["n_launch"][2]
+    c_flops = out["chi_stats"]["flops_stage"][2]
+    per_launch_ms = c_ms / max(c_n, 1)
+    achieved = (c_flops / max(c_n, 1)) / (per_launch_ms / 1e3) / 1e12
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            traffic = json.load(open(args.traffic_json)).get(args.workload)
+        except Exception:
+            traffic = None
+    s = ctx["s"]
+    res = {
+        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "n_atoms": s.n_atoms, "n_ao": s.n_ao, "n_ri": s.n_ri,
+                   "n_occ": s.n_occ, "n_tau": ctx["w"].n_tau, "filter_eps": s.filter_eps,
+                   "n_gw": len(ctx["w"].states()), "n_trip": int(len(ctx["trip"])),
+                   "n_trip_kept": int(cs["n_trip_kept"])},
+        "time_to_qp_s": wall / args.steps,
+        "stage_ms": {k: round(v, 2) for k, v in out["ms"].items()},
+        "flops": {"chi_ab": cs["flops_ab"], "chi_c": cs["flops_c"], "sigma": ss["flops"]},
+        "e_qp": [float(x) for x in out["e_qp"]], "qp_status": [int(x) for x in out["status"]],
+        "roofline": {"kernel": "tile_gemm_kernel<4,10,StageC> (chi outer contraction)",
+                     "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
+                     "traffic": traffic, "launches": int(c_n), "avg_launch_ms": per_launch_ms},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(ctx, out)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/* Low-scaling GW hot path on MI355X (gfx950): C ABI of libgw.so.
+ *
+ * Method: Wilhelm, Golze, Talirz, Hutter, Pignedoli, "Towards GW calculations
+ * on thousands of atoms", J. Phys. Chem. Lett. (2018), arXiv:2104.09857.
+ * Five calls take the mean-field input to quasiparticle energies:
+ *
+ *   gw_build_gt       imaginary-time density matrices            (Eq. 2)
+ *   gw_contract_chi   block-sparse polarizability chi_PQ(i tau)  (Eq. 3)
+ *   gw_screen_w       chi(i w), epsilon, W^c(i w), W^c(i tau)    (Eqs. 5-9)
+ *   gw_contract_sigma diagonal Sigma^c_n(i tau) and Sigma^x_n    (Eqs. 10-11)
+ *   gw_continue_qp    transforms, Pade, Newton on the QP eq.     (Eq. 12)
+ *
+ * Real convention used throughout (the printed i-factors of Eqs. 2, 3, 10
+ * dropped; same physics): energies are shifted by mu_F,
+ *   D^occ(tau) = sum_{i occ} exp(+(eps_i - mu_F) tau) c_i c_i^T
+ *   D^vir(tau) = sum_{a vir} exp(-(eps_a - mu_F) tau) c_a c_a^T,  tau >= 0
+ *   chi_PQ(tau) = - sum_{mu sigma} [sum_l (l sigma P) D^occ_{mu l}]
+ *                                  [sum_nu (mu nu Q) D^vir_{nu sigma}]
+ * (per spin channel; negative semidefinite).
+ *
+ * Conventions of every call:
+ *  - Pointers marked "dev" are device pointers, "host" are host pointers.
+ *  - The caller owns and allocates inputs and outputs; the library never
+ *    frees caller memory.  Calls allocate and free their own scratch
+ *    (stream-ordered) and return GW_ERR_NOMEM when that fails.
+ *  - Calls are asynchronous on `stream` except where a result is written to
+ *    host memory (then they synchronize the stream before returning).
+ *  - Arguments are validated on the host before any launch; on error nothing
+ *    is launched and gw_last_error() describes the problem.
+ *  - Matrices are row-major FP64.  All atoms of a system carry the same
+ *    number of AO functions (ao_per_atom) and RI functions (ri_per_atom).
+ */
+#ifndef GW_H_
+#define GW_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gw_status;
+enum {
+  GW_OK = 0,
+  GW_ERR_ARG = 1,          /* invalid argument (nothing launched)            */
+  GW_ERR_HIP = 2,          /* a HIP runtime call failed                      */
+  GW_ERR_NOMEM = 3,        /* scratch allocation failed                      */
+  GW_ERR_NOT_SPD = 4,      /* Cholesky of V or of epsilon(i w) failed        */
+  GW_ERR_NO_CONVERGE = 5,  /* Newton did not converge for at least one state */
+  GW_ERR_BLAS = 6          /* rocBLAS / rocSOLVER returned an error          */
+};
+
+typedef enum { GW_FP64 = 0 } gw_prec;
+
+/* One molecule / strip.  Atom-triple bricks (a, b, c) of the three-center
+ * tensor (mu nu|P) (Eq. 4): mu on AO atom a, nu on AO atom b, P on RI atom c.
+ * Brick i of `trip` is stored at t3c + i * ao_per_atom^2 * ri_per_atom as
+ * [mu][nu][P] row-major.  The list must contain (b, a, c) whenever it contains
+ * (a, b, c) (the tensor is symmetric in mu nu); triples left out are zero. */
+typedef struct {
+  int32_t n_atoms;
+  int32_t ao_per_atom;     /* n_ao = n_atoms * ao_per_atom                   */
+  int32_t ri_per_atom;     /* n_ri = n_atoms * ri_per_atom                   */
+  int32_t n_occ;           /* occupied MOs, 1 <= n_occ < n_ao                */
+  int64_t n_trip;
+  const int32_t *trip;     /* host [n_trip][3] = (a, b, c)                   */
+  const double *t3c;       /* dev  [n_trip][ao][ao][ri]                      */
+} gw_system;
+
+/* Imaginary-time density matrices (Eq. 2).
+ * C: dev [n_ao][n_ao], row n = MO n (orthonormal AO basis); eps: host [n_ao]
+ * ascending; tau: host [n_tau] >= 0.  Writes d_occ, d_vir: dev
+ * [n_tau][n_ao][n_ao].  Either output may be NULL to skip it.
+ * Errors: GW_ERR_ARG for bad sizes, unsorted eps, negative/non-finite tau. */
+gw_status gw_build_gt(const gw_system *s, const double *C, const double *eps, double mu_f,
+                      int32_t n_tau, const double *tau, double *d_occ, double *d_vir,
+                      hipStream_t stream);
+
+typedef struct {
+  int32_t prec;            /* gw_prec; only GW_FP64                           */
+  double filter_eps;       /* atom-block filter (Frobenius norm), >= 0        */
+  int32_t timing;          /* 1: time every stage launch with HIP events on
+                              `stream` (fills ms_stage)                        */
+} gw_chi_opts;
+
+typedef struct {
+  int64_t n_trip_kept;     /* bricks at or above the filter                   */
+  int64_t n_dblk_dropped;  /* D(tau) atom blocks below the filter (all tau)   */
+  int64_t n_chiblk_dropped;/* chi output atom blocks zeroed (all tau)         */
+  double flops_ab;         /* algorithmic flops of the two half contractions  */
+  double flops_c;          /* algorithmic flops of the outer contraction      */
+  double ms_total;         /* wall time of the call (host clock, synchronized)*/
+  double ms_stage[3];      /* summed kernel time of the half contractions A,
+                              B and of the outer contraction C (timing = 1)   */
+  int64_t n_launch[3];     /* launches of each stage                          */
+  double flops_stage[3];   /* algorithmic flops of each stage                 */
+} gw_chi_stats;
+
+/* Polarizability chi_PQ(tau_j) for all tau at once (Eq. 3), with the atom-block
+ * filter of the paper's computational details: bricks of norm < filter_eps and
+ * D(tau) atom blocks of norm < filter_eps are dropped, then chi atom blocks of
+ * norm < filter_eps are zeroed.
+ * d_occ, d_vir: dev [n_tau][n_ao][n_ao] (symmetric); chi: dev
+ * [n_tau][n_ri][n_ri], overwritten, symmetric (upper blocks computed,
+ * mirrored).  stats (host, may be NULL) is filled; the call synchronizes the
+ * stream once to read the kept-brick mask and again at the end when stats is
+ * non-NULL. */
+gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double *d_vir,
+                          int32_t n_tau, const gw_chi_opts *opts, double *chi,
+                          gw_chi_stats *stats, hipStream_t stream);
+
+/* Screening (Eqs. 5-9) with RI overlap metric S = 1:
+ *   chi(i w_k) = 2 spin sum_j cos_w[k][j] chi(tau_j)
+ *   V = L L^T, eps(i w_k) = 1 - L^T chi(i w_k) L
+ *   W^c(i w_k) = L [eps^-1 - 1] L^T
+ *   wc(tau_j)  = 1/2 sum_k icos_w[j][k] W^c(i w_k)
+ * chi: dev [n_tau][n_ri][n_ri]; V: dev [n_ri][n_ri] SPD; cos_w: host
+ * [n_w][n_tau]; icos_w: host [n_tau][n_w]; wc: dev [n_tau][n_ri][n_ri].
+ * Errors: GW_ERR_NOT_SPD when V or some eps(i w_k) is not positive definite
+ * (the stream is synchronized to read the factorization status). */
+gw_status gw_screen_w(const gw_system *s, const double *chi, const double *V, int32_t n_tau,
+                      int32_t n_w, const double *cos_w, const double *icos_w, double spin,
+                      double *wc, hipStream_t stream);
+
+typedef struct {
+  double flops;            /* algorithmic flops of the self-energy products   */
+  double ms_total;
+} gw_sigma_stats;
+
+/* Diagonal self-energy pieces (Eqs. 10-11) for the listed MOs:
+ *   B^n_{mu P}      = sum_nu C_{n nu} (nu mu P)
+ *   sig_occ[n][j]   = <D^occ(tau_j), B^n W^c(tau_j) B^nT>_F
+ *   sig_vir[n][j]   = <D^vir(tau_j), B^n W^c(tau_j) B^nT>_F
+ *   sig_x[n]        = -<D^occ(0), B^n V B^nT>_F
+ * The same filter as gw_contract_chi is applied to the bricks and to the D
+ * atom blocks.  states: host [n_gw] MO indices; C: dev [n_ao][n_ao];
+ * d_occ, d_vir, wc: dev stacks of n_tau; d_occ0: dev [n_ao][n_ao] = D^occ(0);
+ * V: dev [n_ri][n_ri]; outputs are host arrays (the call synchronizes). */
+gw_status gw_contract_sigma(const gw_system *s, int32_t n_gw, const int32_t *states,
+                            const double *C, const double *d_occ, const double *d_vir,
+                            const double *d_occ0, const double *wc, const double *V,
+                            int32_t n_tau, double filter_eps, double *sig_occ, double *sig_vir,
+                            double *sig_x, gw_sigma_stats *stats, hipStream_t stream);
+
+typedef struct {
+  double pade_window;      /* use only nodes with w_k <= window; <= 0: all    */
+  double newton_tol;       /* stop when |dE| < tol (Ha); <= 0: 1e-10           */
+  int32_t max_iter;        /* <= 0: 100                                        */
+} gw_qp_opts;
+
+/* Quasiparticle energies (Eq. 12), host only:
+ *   Sigma^c_n(i w_k) = sum_j cos_w[k][j] (vir - occ)[n][j]
+ *                      + i sum_j sin_w[k][j] (vir + occ)[n][j]
+ * Thiele continued-fraction Pade on nodes +i w_k (virtual states) or -i w_k
+ * with conjugated values (occupied), then Newton from E = eps_n on
+ *   E - eps_n + vxc_n - sig_x_n - Re Sigma^c_n(E - mu_F) = 0.
+ * state_status[n] = GW_OK or GW_ERR_NO_CONVERGE (e_qp[n] = NaN then); the
+ * call returns GW_ERR_NO_CONVERGE if any state failed. */
+gw_status gw_continue_qp(int32_t n_gw, const double *sig_occ, const double *sig_vir,
+                         const double *sig_x, const double *eps_n, const double *vxc_n,
+                         const int32_t *is_occ, double mu_f, int32_t n_tau, int32_t n_w,
+                         const double *omega, const double *cos_w, const double *sin_w,
+                         const gw_qp_opts *opts, double *e_qp, int32_t *state_status);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *gw_last_error(void);
+/* Library version string. */
+const char *gw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GW_H_ */

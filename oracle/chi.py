@@ -29,9 +29,9 @@ def chi_eq3(t3c, d_occ, d_vir):
     out = np.empty((d_occ.shape[0], n_ri, n_ri))
     for j in range(d_occ.shape[0]):
         # M_{mu sigma P} = sum_lambda (lambda sigma P) G_{mu lambda}
-        m = np.einsum("ml,lsp->msp", d_occ[j], t3c, optimize=True)
+        m = np.ascontiguousarray(np.einsum("ml,lsp->msp", d_occ[j], t3c, optimize=True))
         # N_{mu sigma Q} = sum_nu (mu nu Q) G_{nu sigma}
-        n = np.einsum("mnq,ns->msq", t3c, d_vir[j], optimize=True)
+        n = np.ascontiguousarray(np.einsum("mnq,ns->msq", t3c, d_vir[j], optimize=True))
         # chi_PQ = - sum_{mu sigma} M N
         out[j] = -np.einsum("msp,msq->pq", m, n, optimize=True)
     return out

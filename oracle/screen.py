@@ -25,7 +25,7 @@ class NotSPD(ValueError):
 
 def chi_omega(chi_tau, cos_w, spin):
     """[n_w][n_ri][n_ri] from [n_tau][n_ri][n_ri]."""
-    return 2.0 * spin * np.einsum("kj,jpq->kpq", cos_w, chi_tau, optimize=True)
+    return np.ascontiguousarray(2.0 * spin * np.einsum("kj,jpq->kpq", cos_w, chi_tau, optimize=True))
 
 
 def cholesky_lower(a):
@@ -52,7 +52,7 @@ def screen_w(chi_tau, V, cos_w, icos_w, spin):
     L = cholesky_lower(V)
     chi_w = chi_omega(chi_tau, cos_w, spin)
     wcw = np.stack([wc_omega(chi_w[k], L) for k in range(chi_w.shape[0])])
-    return 0.5 * np.einsum("jk,kpq->jpq", icos_w, wcw, optimize=True)
+    return np.ascontiguousarray(0.5 * np.einsum("jk,kpq->jpq", icos_w, wcw, optimize=True))
 
 
 def wc_omega_sqrt(chi_w, V):

@@ -18,13 +18,15 @@ import numpy as np
 
 def half_transform(C, t3c, states):
     """B[n][mu][P] for the listed states."""
-    return np.einsum("kn,nmp->kmp", C[states], t3c, optimize=True)
+    return np.ascontiguousarray(np.einsum("kn,nmp->kmp", C[states], t3c, optimize=True))
 
 
 def sigma_pieces(b, d, w):
     """<D, B W B^T>_F for each state: b [n_gw][n_ao][n_ri], d [n_ao][n_ao],
     w [n_ri][n_ri] -> [n_gw], in the order of Eq. 10."""
     out = np.empty(b.shape[0])
+    d = np.ascontiguousarray(d)
+    w = np.ascontiguousarray(w)
     for k in range(b.shape[0]):
         z = w @ b[k].T                      # Z_{P nu} = sum_Q W_PQ B_{nu Q}
         y = b[k] @ z                        # Y_{mu nu} = sum_P B_{mu P} Z_{P nu}

@@ -1,0 +1,409 @@
+// Block-sparse polarizability chi_PQ(tau) (Eq. 3) on FP64 MFMA.
+//
+// Eq. 3 is organised around a pivot AO atom b (sigma runs over b):
+//   stage A  M_b[tau][sigma][c][mu][P] = sum_a sum_{l in a} D^occ_{l mu}(tau) (l sigma P)
+//            for every RI atom c that has a brick (a, b, c) and every mu
+//   stage B  N_b[tau][(a', c')][mu][Q][sigma] = sum_{a2} sum_{nu in a2}
+//                 (nu mu Q) D^vir_{nu sigma}(tau)      (brick (a2, a', c'))
+//   stage C  chi[tau][c][c'] -= sum_{sigma in b} sum_{mu} M_b[..][mu][P] N_b[..][mu][Q][sigma]
+// Both half contractions use the same brick grouping: group (s, c) lists the
+// bricks (f, s, c) and the contraction runs over the first index f.  Stage C
+// is a GEMM per RI column panel p (PG consecutive RI atoms): its K range is
+// (sigma, mu in U_p) with U_p the union of the AO atoms that couple to the
+// panel, so N_b is written panel-dense (zeros where an atom does not couple).
+// Only blocks with c <= c' are computed; the lower blocks are mirrored at
+// the end (chi is symmetric).  The half-contracted tensors never exceed one
+// pivot (O(n_tau * N_AO * |S|/N_atoms) doubles).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+#include "gw_internal.hpp"
+#include "tile_gemm.hpp"
+
+namespace gw {
+namespace {
+
+constexpr int A_WM = 4, A_NB = 11;   // stage A tile 128 x 176
+constexpr int B_NB = 11;             // stage B tile (32 WM) x 176
+constexpr int C_WM = 4, C_NB = 10;   // stage C tile 128 x 160
+
+struct StageA {
+  struct Tile : TileBase {
+    int g, slot, tau, row0, col0, seg0;
+  };
+  static constexpr bool kAScale = false, kDot = false;
+  const double* dof;
+  const double* t3c;
+  double* mb;
+  const int32_t* goff;
+  const int32_t* seg_atom;
+  const int64_t* seg_brick;
+  int g0, n_rt, n_ct, rows_pt, cols_pt;
+  int N, NA, NR, nRmax;
+  int64_t bs;
+
+  __device__ bool tile(int bx, int by, int bz, Tile& t) const {
+    const int per = n_rt * n_ct;
+    t.slot = bx / per;
+    const int rem = bx % per;
+    t.row0 = (rem % n_rt) * rows_pt;
+    t.col0 = (rem / n_rt) * cols_pt;
+    t.g = g0 + t.slot;
+    t.tau = by;
+    t.seg0 = goff[t.g];
+    t.K = NA * (goff[t.g + 1] - t.seg0);
+    t.rows = min(rows_pt, N - t.row0);
+    t.cols = min(cols_pt, NA * NR - t.col0);
+    return t.rows > 0 && t.cols > 0;
+  }
+  __device__ const double* abase(const Tile& t) const { return dof + (int64_t)t.tau * N * N + t.row0; }
+  __device__ int64_t aroff(const Tile&, int r) const { return r; }
+  __device__ int64_t akoff(const Tile& t, int k) const {
+    return (int64_t)(seg_atom[t.seg0 + k / NA] * NA + k % NA) * N;
+  }
+  __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
+  __device__ int64_t bkoff(const Tile& t, int k) const {
+    return seg_brick[t.seg0 + k / NA] * bs + (int64_t)(k % NA) * NA * NR;
+  }
+  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ void store(const Tile& t, int r, int c, double v) const {
+    const int mu = t.row0 + r, col = t.col0 + c;
+    const int sg = col / NR, P = col % NR;
+    mb[(((int64_t)t.tau * NA + sg) * nRmax + t.slot) * N * NR + (int64_t)mu * NR + P] = v;
+  }
+  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ void dot_out(const Tile&, double, double) const {}
+};
+
+struct StageB {
+  struct Tile : TileBase {
+    int g, row0, col0, seg0, p, cl, slot, KU;
+  };
+  static constexpr bool kAScale = false, kDot = false;
+  const double* dvg;        // [N][RS]
+  const double* t3c;
+  double* bp;
+  const int32_t* goff;
+  const int32_t* seg_atom;
+  const int64_t* seg_brick;
+  const int32_t* gc;
+  const int32_t* gslot;
+  const int32_t* ulen;
+  const int64_t* bp_off;
+  int n_rt, n_ct, rows_pt, cols_pt;
+  int RS, NA, NR, PG, PC;
+  int64_t bs, BPS;
+
+  __device__ bool tile(int bx, int, int, Tile& t) const {
+    const int per = n_rt * n_ct;
+    t.g = bx / per;
+    const int rem = bx % per;
+    t.row0 = (rem % n_rt) * rows_pt;
+    t.col0 = (rem / n_rt) * cols_pt;
+    t.seg0 = goff[t.g];
+    t.K = NA * (goff[t.g + 1] - t.seg0);
+    const int c = gc[t.g];
+    t.p = c / PG;
+    t.cl = c % PG;
+    t.slot = gslot[t.g];
+    t.KU = NA * ulen[t.p];
+    t.rows = min(rows_pt, RS - t.row0);
+    t.cols = min(cols_pt, NA * NR - t.col0);
+    return t.rows > 0 && t.cols > 0;
+  }
+  __device__ const double* abase(const Tile& t) const { return dvg + t.row0; }
+  __device__ int64_t aroff(const Tile&, int r) const { return r; }
+  __device__ int64_t akoff(const Tile& t, int k) const {
+    return (int64_t)(seg_atom[t.seg0 + k / NA] * NA + k % NA) * RS;
+  }
+  __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
+  __device__ int64_t bkoff(const Tile& t, int k) const {
+    return seg_brick[t.seg0 + k / NA] * bs + (int64_t)(k % NA) * NA * NR;
+  }
+  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ void store(const Tile& t, int r, int c, double v) const {
+    const int row = t.row0 + r, col = t.col0 + c;
+    const int tau = row / NA, sg = row % NA;
+    const int mul = col / NR, Q = col % NR;
+    bp[(int64_t)tau * BPS + bp_off[t.p] + ((int64_t)sg * t.KU + t.slot * NA + mul) * PC + t.cl * NR + Q] = v;
+  }
+  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ void dot_out(const Tile&, double, double) const {}
+};
+
+struct StageC {
+  struct Tile : TileBase {
+    int p, tau, row0, KU, km0;
+  };
+  static constexpr bool kAScale = false, kDot = false;
+  const double* mb;
+  const double* bp;
+  double* chi;
+  const int32_t* gc;
+  const int32_t* kmap;
+  const int32_t* km_off;
+  const int32_t* ulen;
+  const int64_t* bp_off;
+  int g0, nR, n_rt, rows_pt;
+  int N, NA, NR, NRI, PG, PC, nRmax, n_atoms;
+  int64_t BPS;
+
+  __device__ bool tile(int bx, int by, int bz, Tile& t) const {
+    t.row0 = (bx % n_rt) * rows_pt;
+    t.p = bx / n_rt;
+    t.tau = bz;
+    t.rows = min(rows_pt, nR * NR - t.row0);
+    t.cols = min(PC, NRI - t.p * PC);
+    if (t.rows <= 0 || t.cols <= 0) return false;
+    const int c_min = gc[g0 + t.row0 / NR];
+    const int cp_max = min(t.p * PG + PG - 1, n_atoms - 1);
+    if (c_min > cp_max) return false;          // strictly below the block diagonal
+    t.KU = NA * ulen[t.p];
+    t.km0 = km_off[t.p];
+    t.K = NA * t.KU;
+    return t.K > 0;
+  }
+  __device__ const double* abase(const Tile& t) const {
+    return mb + (int64_t)t.tau * NA * nRmax * N * NR;
+  }
+  __device__ int64_t aroff(const Tile& t, int r) const {
+    const int row = t.row0 + r;
+    return (int64_t)(row / NR) * N * NR + row % NR;
+  }
+  __device__ int64_t akoff(const Tile& t, int k) const {
+    const int sg = k / t.KU, u = k - sg * t.KU;
+    return (int64_t)sg * nRmax * N * NR + (int64_t)kmap[t.km0 + u] * NR;
+  }
+  __device__ const double* bbase(const Tile& t) const {
+    return bp + (int64_t)t.tau * BPS + bp_off[t.p];
+  }
+  __device__ int64_t bkoff(const Tile&, int k) const { return (int64_t)k * PC; }
+  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ void store(const Tile& t, int r, int c, double v) const {
+    const int row = t.row0 + r;
+    const int64_t P = (int64_t)gc[g0 + row / NR] * NR + row % NR;
+    const int64_t Q = (int64_t)t.p * PC + c;
+    double* dst = chi + (int64_t)t.tau * NRI * NRI + P * NRI + Q;
+    *dst -= v;
+  }
+  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ void dot_out(const Tile&, double, double) const {}
+};
+
+__global__ void gather_dvir_kernel(const double* __restrict__ dv, double* __restrict__ dvg, int N,
+                                   int NA, int n_tau, int b) {
+  const int RS = n_tau * NA;
+  const int64_t total = (int64_t)N * RS;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int nu = (int)(e / RS), rc = (int)(e % RS);
+    const int tau = rc / NA, sg = rc % NA;
+    dvg[e] = dv[(int64_t)tau * N * N + (int64_t)nu * N + (int64_t)b * NA + sg];
+  }
+}
+
+template <int WM>
+hipError_t launch_stage_b(StageB sb, int n_groups, hipStream_t st) {
+  sb.rows_pt = 32 * WM;
+  sb.cols_pt = 16 * B_NB;
+  sb.n_rt = (sb.RS + sb.rows_pt - 1) / sb.rows_pt;
+  sb.n_ct = (sb.NA * sb.NR + sb.cols_pt - 1) / sb.cols_pt;
+  return launch_tile_gemm<WM, B_NB>(sb, dim3((unsigned)(n_groups * sb.n_rt * sb.n_ct)), st);
+}
+
+}  // namespace
+}  // namespace gw
+
+using namespace gw;
+
+extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, const double* d_vir,
+                                     int32_t n_tau, const gw_chi_opts* opts, double* chi,
+                                     gw_chi_stats* stats, hipStream_t st) {
+  clear_error();
+  const auto t_start = std::chrono::steady_clock::now();
+  gw_status rc = check_system(s);
+  if (rc != GW_OK) return rc;
+  GW_CHECK_ARG(d_occ && d_vir && chi, "d_occ, d_vir and chi must be non-null");
+  GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
+  const double eps_f = opts ? opts->filter_eps : 0.0;
+  GW_CHECK_ARG(std::isfinite(eps_f) && eps_f >= 0.0, "filter_eps must be finite and >= 0");
+  GW_CHECK_ARG(!opts || opts->prec == GW_FP64, "only GW_FP64 is supported");
+  const int na = s->n_atoms, NA = s->ao_per_atom, NR = s->ri_per_atom;
+  GW_CHECK_ARG(NR <= 16 * C_NB, "ri_per_atom must be <= 160");
+  const int N = na * NA, NRI = na * NR;
+  const int64_t bs = (int64_t)NA * NA * NR;
+  GW_CHECK_ARG((int64_t)n_tau * NA <= (1 << 20), "n_tau * ao_per_atom too large");
+
+  Scratch sc(st);
+  if (stats) *stats = gw_chi_stats{};
+  GW_HIP(hipMemsetAsync(chi, 0, sizeof(double) * (size_t)n_tau * NRI * NRI, st));
+  if (s->n_trip == 0) return GW_OK;
+  // ---- tensor filter and grouping (host)
+  BrickGroups G;
+  if ((rc = build_groups(s, eps_f, st, sc, G)) != GW_OK) return rc;
+  const int n_groups = G.n_groups();
+  const auto& gs = G.gs;
+  const auto& gcv = G.gc;
+  const auto& goff = G.goff;
+  const auto& gb_start = G.gb_start;
+  int nRmax = 0;
+  for (int b = 0; b < na; ++b) nRmax = std::max(nRmax, gb_start[b + 1] - gb_start[b]);
+
+  // ---- column panels of PG RI atoms; U_p = AO atoms coupling to the panel
+  const int PG = std::max(1, (16 * C_NB) / NR), PC = PG * NR;
+  const Panels pan = build_panels(na, PG, PC, gcv, gs, NA, NA);
+  const int n_pan = pan.n_pan;
+  const int64_t BPS = pan.off[n_pan];
+
+  // ---- scratch
+  double *dof = nullptr, *dvf = nullptr, *dvg = nullptr, *mb = nullptr, *bp = nullptr;
+  uint8_t* dropped = nullptr;
+  const int RS = n_tau * NA;
+  const size_t dsz = (size_t)n_tau * N * N;
+  if ((rc = sc.alloc(&dof, dsz)) != GW_OK) return rc;
+  if ((rc = sc.alloc(&dvf, dsz)) != GW_OK) return rc;
+  if ((rc = sc.alloc(&dvg, (size_t)N * RS)) != GW_OK) return rc;
+  if ((rc = sc.alloc(&mb, (size_t)n_tau * NA * std::max(nRmax, 1) * N * NR)) != GW_OK) return rc;
+  if ((rc = sc.alloc(&bp, (size_t)n_tau * BPS)) != GW_OK) return rc;
+  const size_t nflag = (size_t)n_tau * na * na;
+  if ((rc = sc.alloc(&dropped, 3 * nflag)) != GW_OK) return rc;
+  int32_t *d_goff, *d_seg_atom, *d_gc, *d_gslot, *d_ulen, *d_kmap, *d_km_off;
+  int64_t *d_seg_brick, *d_bp_off;
+  if ((rc = sc.upload(&d_goff, goff)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_seg_atom, G.seg_atom)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_seg_brick, G.seg_brick)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_gc, gcv)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_gslot, pan.gslot)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_ulen, pan.ulen)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_kmap, pan.kmap)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_km_off, pan.km_off)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_bp_off, pan.off)) != GW_OK) return rc;
+  GW_HIP(hipMemsetAsync(bp, 0, sizeof(double) * (size_t)n_tau * BPS, st));
+
+  // ---- D filter (copies)
+  GW_HIP(filter_square_blocks(d_occ, dof, n_tau, na, NA, eps_f, dropped, st));
+  GW_HIP(filter_square_blocks(d_vir, dvf, n_tau, na, NA, eps_f, dropped + nflag, st));
+
+  // ---- pivot loop
+  StageA sa{};
+  sa.dof = dof; sa.t3c = s->t3c; sa.mb = mb; sa.goff = d_goff; sa.seg_atom = d_seg_atom;
+  sa.seg_brick = d_seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = 16 * A_NB;
+  sa.n_rt = (N + sa.rows_pt - 1) / sa.rows_pt;
+  sa.n_ct = (NA * NR + sa.cols_pt - 1) / sa.cols_pt;
+  sa.N = N; sa.NA = NA; sa.NR = NR; sa.nRmax = std::max(nRmax, 1); sa.bs = bs;
+
+  StageB sb{};
+  sb.dvg = dvg; sb.t3c = s->t3c; sb.bp = bp; sb.goff = d_goff; sb.seg_atom = d_seg_atom;
+  sb.seg_brick = d_seg_brick; sb.gc = d_gc; sb.gslot = d_gslot; sb.ulen = d_ulen;
+  sb.bp_off = d_bp_off; sb.RS = RS; sb.NA = NA; sb.NR = NR; sb.PG = PG; sb.PC = PC; sb.bs = bs;
+  sb.BPS = BPS;
+
+  StageC scx{};
+  scx.mb = mb; scx.bp = bp; scx.chi = chi; scx.gc = d_gc; scx.kmap = d_kmap; scx.km_off = d_km_off;
+  scx.ulen = d_ulen; scx.bp_off = d_bp_off; scx.rows_pt = 32 * C_WM; scx.N = N; scx.NA = NA;
+  scx.NR = NR; scx.NRI = NRI; scx.PG = PG; scx.PC = PC; scx.nRmax = std::max(nRmax, 1);
+  scx.n_atoms = na; scx.BPS = BPS;
+
+  double flops_ab = 0.0, flops_c = 0.0, flops_a = 0.0, flops_b = 0.0;
+  const bool timing = opts && opts->timing;
+  std::vector<hipEvent_t> evs;
+  auto mark = [&](void) -> hipError_t {
+    if (!timing) return hipSuccess;
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    evs.push_back(e);
+    return hipEventRecord(e, st);
+  };
+  int64_t n_launch[3] = {0, 0, 0};
+  struct EvGuard {
+    std::vector<hipEvent_t>& v;
+    ~EvGuard() {
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    }
+  } ev_guard{evs};
+  int64_t nnz_elems = G.n_kept * bs;
+  // |A(c')| per RI atom: number of groups with that c
+  std::vector<int32_t> acount(na, 0);
+  for (int g = 0; g < n_groups; ++g) acount[gcv[g]]++;
+  std::vector<double> asuffix(na + 1, 0.0);   // sum_{c' >= c} |A(c')|
+  for (int c = na - 1; c >= 0; --c) asuffix[c] = asuffix[c + 1] + acount[c];
+
+  for (int b = 0; b < na; ++b) {
+    const int g0 = gb_start[b], nR = gb_start[b + 1] - g0;
+    if (nR == 0) continue;
+    {
+      const int64_t total = (int64_t)N * RS;
+      const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+      hipLaunchKernelGGL(gather_dvir_kernel, dim3(blocks), dim3(256), 0, st, dvf, dvg, N, NA,
+                         n_tau, b);
+      GW_HIP(hipGetLastError());
+    }
+    sa.g0 = g0;
+    GW_HIP(mark());
+    GW_HIP((launch_tile_gemm<A_WM, A_NB>(sa, dim3((unsigned)(nR * sa.n_rt * sa.n_ct), n_tau), st)));
+    GW_HIP(mark());
+    hipError_t e;
+    if (RS <= 64) e = launch_stage_b<2>(sb, n_groups, st);
+    else if (RS <= 96) e = launch_stage_b<3>(sb, n_groups, st);
+    else if (RS <= 128) e = launch_stage_b<4>(sb, n_groups, st);
+    else if (RS <= 160) e = launch_stage_b<5>(sb, n_groups, st);
+    else e = launch_stage_b<4>(sb, n_groups, st);
+    GW_HIP(e);
+    GW_HIP(mark());
+    scx.g0 = g0;
+    scx.nR = nR;
+    scx.n_rt = (nR * NR + scx.rows_pt - 1) / scx.rows_pt;
+    GW_HIP((launch_tile_gemm<C_WM, C_NB>(scx, dim3((unsigned)(scx.n_rt * n_pan), 1, n_tau), st)));
+    GW_HIP(mark());
+    n_launch[0]++; n_launch[1]++; n_launch[2]++;
+
+    int64_t nnz_b = 0;
+    for (int g = g0; g < g0 + nR; ++g) nnz_b += (int64_t)(goff[g + 1] - goff[g]) * bs;
+    flops_a += 2.0 * N * (double)nnz_b;
+    flops_b += 2.0 * NA * (double)nnz_elems;
+    flops_ab += 2.0 * N * (double)nnz_b + 2.0 * NA * (double)nnz_elems;
+    for (int g = g0; g < g0 + nR; ++g)
+      flops_c += 2.0 * NR * NR * NA * NA * asuffix[gcv[g]];
+  }
+
+  // ---- symmetric completion and output filter
+  GW_HIP(mirror_lower_blocks(chi, n_tau, NRI, NR, st));
+  if (eps_f > 0.0)
+    GW_HIP(filter_square_blocks(chi, chi, n_tau, na, NR, eps_f, dropped + 2 * nflag, st));
+
+  if (stats) {
+    std::vector<uint8_t> fl(3 * nflag);
+    GW_HIP(hipMemcpyAsync(fl.data(), dropped, fl.size(), hipMemcpyDeviceToHost, st));
+    GW_HIP(hipStreamSynchronize(st));
+    int64_t dd = 0, dc = 0;
+    for (size_t i = 0; i < 2 * nflag; ++i) dd += fl[i];
+    if (eps_f > 0.0)
+      for (size_t i = 2 * nflag; i < 3 * nflag; ++i) dc += fl[i];
+    stats->n_trip_kept = G.n_kept;
+    stats->n_dblk_dropped = dd;
+    stats->n_chiblk_dropped = dc;
+    stats->flops_ab = flops_ab * n_tau;
+    stats->flops_c = flops_c * n_tau;
+    for (int k = 0; k < 3; ++k) {
+      stats->ms_stage[k] = 0.0;
+      stats->n_launch[k] = n_launch[k];
+    }
+    stats->flops_stage[0] = flops_a * n_tau;
+    stats->flops_stage[1] = flops_b * n_tau;
+    stats->flops_stage[2] = flops_c * n_tau;
+    for (size_t i = 0; timing && i + 3 < evs.size(); i += 4) {
+      float ms;
+      GW_HIP(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
+      stats->ms_stage[0] += ms;
+      GW_HIP(hipEventElapsedTime(&ms, evs[i + 1], evs[i + 2]));
+      stats->ms_stage[1] += ms;
+      GW_HIP(hipEventElapsedTime(&ms, evs[i + 2], evs[i + 3]));
+      stats->ms_stage[2] += ms;
+    }
+    stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return GW_OK;
+}

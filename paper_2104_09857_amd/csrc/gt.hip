@@ -1,0 +1,103 @@
+// Imaginary-time density matrices (Eq. 2) on FP64 MFMA:
+//   D^occ(tau_j)_{mu nu} = sum_{i < n_occ} C_{i mu} exp(+(eps_i - mu_F) tau_j) C_{i nu}
+//   D^vir(tau_j)_{mu nu} = sum_{a >= n_occ} C_{a mu} exp(-(eps_a - mu_F) tau_j) C_{a nu}
+// One launch for all tau and both branches; the weight multiplies the A
+// operand as it is staged.
+#include <cmath>
+
+#include "gw_internal.hpp"
+#include "tile_gemm.hpp"
+
+namespace gw {
+namespace {
+
+constexpr int G_WM = 4, G_NB = 8;   // 128 x 128 tiles
+
+struct GtProblem {
+  struct Tile : TileBase {
+    int row0, col0, tau, branch;
+  };
+  static constexpr bool kAScale = true, kDot = false;
+  const double* C;
+  const double* w;          // [2][n_tau][n_ao] weights (zeros beyond the branch's K)
+  double* out[2];
+  int N, n_occ, n_tau, n_rt;
+
+  __device__ bool tile(int bx, int by, int bz, Tile& t) const {
+    t.row0 = (bx % n_rt) * 32 * G_WM;
+    t.col0 = (bx / n_rt) * 16 * G_NB;
+    t.tau = by;
+    t.branch = bz;
+    if (out[bz] == nullptr) return false;
+    t.K = bz == 0 ? n_occ : N - n_occ;
+    t.rows = min(32 * G_WM, N - t.row0);
+    t.cols = min(16 * G_NB, N - t.col0);
+    return t.rows > 0 && t.cols > 0;
+  }
+  __device__ const double* kbase(const Tile& t) const {
+    return C + (t.branch == 0 ? 0 : (int64_t)n_occ * N);
+  }
+  __device__ const double* abase(const Tile& t) const { return kbase(t) + t.row0; }
+  __device__ int64_t aroff(const Tile&, int r) const { return r; }
+  __device__ int64_t akoff(const Tile&, int k) const { return (int64_t)k * N; }
+  __device__ double ascale(const Tile& t, int k) const {
+    return w[((int64_t)t.branch * n_tau + t.tau) * N + k];
+  }
+  __device__ const double* bbase(const Tile& t) const { return kbase(t) + t.col0; }
+  __device__ int64_t bkoff(const Tile&, int k) const { return (int64_t)k * N; }
+  __device__ void store(const Tile& t, int r, int c, double v) const {
+    out[t.branch][(int64_t)t.tau * N * N + (int64_t)(t.row0 + r) * N + t.col0 + c] = v;
+  }
+  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ void dot_out(const Tile&, double, double) const {}
+};
+
+}  // namespace
+}  // namespace gw
+
+using namespace gw;
+
+extern "C" gw_status gw_build_gt(const gw_system* s, const double* C, const double* eps,
+                                 double mu_f, int32_t n_tau, const double* tau, double* d_occ,
+                                 double* d_vir, hipStream_t st) {
+  clear_error();
+  GW_CHECK_ARG(s != nullptr, "system is null");
+  GW_CHECK_ARG(s->n_atoms > 0 && s->ao_per_atom > 0, "bad system sizes");
+  const int64_t N64 = (int64_t)s->n_atoms * s->ao_per_atom;
+  GW_CHECK_ARG(N64 < (1 << 30), "system too large");
+  const int N = (int)N64;
+  GW_CHECK_ARG(s->n_occ >= 1 && s->n_occ < N, "n_occ must be in [1, n_ao)");
+  GW_CHECK_ARG(C && eps && tau, "C, eps and tau must be non-null");
+  GW_CHECK_ARG(d_occ || d_vir, "at least one output is required");
+  GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
+  GW_CHECK_ARG(std::isfinite(mu_f), "mu_f must be finite");
+  for (int i = 0; i < N; ++i) {
+    GW_CHECK_ARG(std::isfinite(eps[i]), "eps must be finite");
+    GW_CHECK_ARG(i == 0 || eps[i] >= eps[i - 1], "eps must be ascending");
+  }
+  for (int j = 0; j < n_tau; ++j) GW_CHECK_ARG(std::isfinite(tau[j]) && tau[j] >= 0.0, "tau must be finite and >= 0");
+
+  std::vector<double> w((size_t)2 * n_tau * N, 0.0);
+  for (int j = 0; j < n_tau; ++j) {
+    for (int i = 0; i < s->n_occ; ++i) w[(size_t)j * N + i] = std::exp((eps[i] - mu_f) * tau[j]);
+    for (int a = s->n_occ; a < N; ++a)
+      w[((size_t)n_tau + j) * N + (a - s->n_occ)] = std::exp(-(eps[a] - mu_f) * tau[j]);
+  }
+  Scratch sc(st);
+  double* d_w = nullptr;
+  gw_status rc = sc.upload(&d_w, w);
+  if (rc != GW_OK) return rc;
+
+  GtProblem p{};
+  p.C = C;
+  p.w = d_w;
+  p.out[0] = d_occ;
+  p.out[1] = d_vir;
+  p.N = N;
+  p.n_occ = s->n_occ;
+  p.n_tau = n_tau;
+  p.n_rt = (N + 32 * G_WM - 1) / (32 * G_WM);
+  const int n_ct = (N + 16 * G_NB - 1) / (16 * G_NB);
+  GW_HIP((launch_tile_gemm<G_WM, G_NB>(p, dim3((unsigned)(p.n_rt * n_ct), n_tau, 2), st)));
+  return GW_OK;
+}

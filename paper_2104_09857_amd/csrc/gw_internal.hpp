@@ -1,0 +1,120 @@
+// Internal helpers of libgw: status handling, scratch memory, shared kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "gw.h"
+
+namespace gw {
+
+void set_error(const std::string& msg);
+void clear_error();
+
+#define GW_CHECK_ARG(cond, msg)      \
+  do {                               \
+    if (!(cond)) {                   \
+      ::gw::set_error(msg);          \
+      return GW_ERR_ARG;             \
+    }                                \
+  } while (0)
+
+#define GW_HIP(call)                                                           \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ::gw::set_error(std::string("HIP error in ") + #call + ": " +            \
+                      hipGetErrorString(e_));                                  \
+      return GW_ERR_HIP;                                                       \
+    }                                                                          \
+  } while (0)
+
+// Stream-ordered scratch allocations released when the owner goes out of scope.
+class Scratch {
+ public:
+  explicit Scratch(hipStream_t st) : st_(st) {}
+  ~Scratch() {
+    for (void* p : ptrs_) (void)hipFreeAsync(p, st_);
+  }
+  template <class T>
+  gw_status alloc(T** out, size_t count) {
+    void* p = nullptr;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMallocAsync(&p, bytes, st_);
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      set_error("scratch allocation of " + std::to_string(bytes) + " bytes failed");
+      return GW_ERR_NOMEM;
+    }
+    ptrs_.push_back(p);
+    *out = static_cast<T*>(p);
+    return GW_OK;
+  }
+  template <class T>
+  gw_status upload(T** out, const std::vector<T>& host) {
+    gw_status s = alloc(out, host.size());
+    if (s != GW_OK) return s;
+    if (!host.empty()) {
+      hipError_t e = hipMemcpyAsync(*out, host.data(), host.size() * sizeof(T),
+                                    hipMemcpyHostToDevice, st_);
+      if (e != hipSuccess) {
+        set_error(std::string("upload failed: ") + hipGetErrorString(e));
+        return GW_ERR_HIP;
+      }
+    }
+    return GW_OK;
+  }
+
+ private:
+  hipStream_t st_;
+  std::vector<void*> ptrs_;
+};
+
+// Validates the system description (host side, before any launch).
+gw_status check_system(const gw_system* s);
+
+// Kept bricks grouped by (second atom s, RI atom c); each group lists the
+// bricks (f, s, c) in ascending first atom f.  Groups are ordered by (s, c).
+struct BrickGroups {
+  int64_t n_kept = 0;
+  std::vector<int32_t> gs, gc, goff, seg_atom;   // goff: [n_groups + 1] into seg_*
+  std::vector<int64_t> seg_brick;
+  std::vector<int32_t> gb_start;                 // [n_atoms + 1] first group of each s
+  int n_groups() const { return (int)gs.size(); }
+};
+
+// Brick norms on the device, filter (norm < eps dropped), grouping on the host.
+// Synchronizes the stream once.
+gw_status build_groups(const gw_system* s, double eps, hipStream_t st, Scratch& sc,
+                       BrickGroups& out);
+
+// Column panels of PG consecutive atoms for a block-sparse GEMM whose K range
+// is the union U_p of the atoms coupled to the panel's columns.  Each group g
+// couples column atom col_atom[g] to K atom k_atom[g]; K atom a contributes
+// `per` consecutive functions (a * per + i) to kmap.  Panel p holds
+// rows_factor * per * |U_p| rows of PC columns starting at off[p].
+struct Panels {
+  int PG = 1, PC = 0, n_pan = 0;
+  std::vector<int32_t> ulen, km_off, kmap, gslot;
+  std::vector<int64_t> off;
+};
+Panels build_panels(int n_atoms, int PG, int PC, const std::vector<int32_t>& col_atom,
+                    const std::vector<int32_t>& k_atom, int per, int rows_factor);
+
+// Frobenius norms of `n` consecutive bricks of `bs` doubles (one wave each).
+hipError_t brick_norms(const double* t3c, int64_t n, int64_t bs, double* out, hipStream_t st);
+
+// Copy of a stack of n_mat square matrices (n_atoms*na) with every na x na atom
+// block of Frobenius norm < eps set to zero; dropped[m*n_atoms^2 + a*n_atoms + b]
+// = 1 for dropped blocks (may be null).
+hipError_t filter_square_blocks(const double* in, double* out, int n_mat, int n_atoms, int na,
+                                double eps, uint8_t* dropped, hipStream_t st);
+
+// x[m] lower atom blocks (row atom > col atom) <- transpose of the upper ones.
+hipError_t mirror_lower_blocks(double* x, int n_mat, int n, int nb, hipStream_t st);
+
+}  // namespace gw

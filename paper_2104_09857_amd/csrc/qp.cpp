@@ -1,0 +1,123 @@
+// Quasiparticle energies (Eq. 12), host FP64.
+//   Sigma^c_n(i w_k) = sum_j c_kj (vir - occ)(tau_j) + i sum_j s_kj (vir + occ)(tau_j)
+// Pade interpolant as a Thiele continued fraction (Vidberg & Serene, J. Low
+// Temp. Phys. 29, 179 (1977)):
+//   C(z) = a_1 / (1 + a_2 (z - z_1) / (1 + a_3 (z - z_2) / (1 + ...)))
+// with a_p = g_p(z_p), g_1(z_i) = f_i and
+//   g_p(z_i) = (g_{p-1}(z_{p-1}) - g_{p-1}(z_i)) / ((z_i - z_{p-1}) g_{p-1}(z_i)),
+// evaluated with the three-term recurrence for numerator and denominator
+// (and their z derivatives).  Virtual states use nodes +i w_k, occupied
+// states -i w_k with conjugated values.  Newton-Raphson from E = eps_n on
+//   f(E) = E - eps_n + vxc_n - sig_x_n - Re Sigma^c_n(E - mu_F).
+#include <cmath>
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "gw.h"
+
+namespace gw {
+void set_error(const std::string& msg);
+void clear_error();
+}
+
+namespace {
+
+using cplx = std::complex<double>;
+
+std::vector<cplx> thiele_coeffs(const std::vector<cplx>& z, std::vector<cplx> g) {
+  const size_t n = z.size();
+  std::vector<cplx> a(n);
+  if (n == 0) return a;
+  a[0] = g[0];
+  for (size_t p = 1; p < n; ++p) {
+    for (size_t i = p; i < n; ++i) g[i] = (g[p - 1] - g[i]) / ((z[i] - z[p - 1]) * g[i]);
+    a[p] = g[p];
+  }
+  return a;
+}
+
+void thiele_eval(const std::vector<cplx>& zn, const std::vector<cplx>& a, cplx z, cplx* val,
+                 cplx* der) {
+  cplx ap = 0.0, ac = a[0], bp = 1.0, bc = 1.0;
+  cplx dap = 0.0, dac = 0.0, dbp = 0.0, dbc = 0.0;
+  for (size_t n = 1; n < a.size(); ++n) {
+    const cplx fac = (z - zn[n - 1]) * a[n];
+    const cplx an = ac + fac * ap, bn = bc + fac * bp;
+    const cplx dan = dac + a[n] * ap + fac * dap, dbn = dbc + a[n] * bp + fac * dbp;
+    ap = ac; ac = an; bp = bc; bc = bn;
+    dap = dac; dac = dan; dbp = dbc; dbc = dbn;
+  }
+  *val = ac / bc;
+  *der = (dac * bc - ac * dbc) / (bc * bc);
+}
+
+}  // namespace
+
+extern "C" gw_status gw_continue_qp(int32_t n_gw, const double* sig_occ, const double* sig_vir,
+                                    const double* sig_x, const double* eps_n, const double* vxc_n,
+                                    const int32_t* is_occ, double mu_f, int32_t n_tau, int32_t n_w,
+                                    const double* omega, const double* cos_w, const double* sin_w,
+                                    const gw_qp_opts* opts, double* e_qp, int32_t* state_status) {
+  gw::clear_error();
+  if (n_gw < 1 || n_tau < 1 || n_w < 1 || !sig_occ || !sig_vir || !sig_x || !eps_n || !is_occ ||
+      !omega || !cos_w || !sin_w || !e_qp || !state_status || !std::isfinite(mu_f)) {
+    gw::set_error("gw_continue_qp: invalid argument");
+    return GW_ERR_ARG;
+  }
+  const double window = opts ? opts->pade_window : 0.0;
+  const double tol = (opts && opts->newton_tol > 0) ? opts->newton_tol : 1e-10;
+  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 100;
+  for (int k = 0; k < n_w; ++k)
+    if (!(omega[k] > 0) || !std::isfinite(omega[k])) {
+      gw::set_error("gw_continue_qp: omega must be positive and finite");
+      return GW_ERR_ARG;
+    }
+  gw_status ret = GW_OK;
+  for (int n = 0; n < n_gw; ++n) {
+    // transforms to the imaginary axis
+    std::vector<cplx> zn, fv;
+    for (int k = 0; k < n_w; ++k) {
+      if (window > 0 && omega[k] > window) continue;
+      double re = 0.0, im = 0.0;
+      for (int j = 0; j < n_tau; ++j) {
+        const double so = sig_occ[(size_t)n * n_tau + j], sv = sig_vir[(size_t)n * n_tau + j];
+        re += cos_w[(size_t)k * n_tau + j] * (sv - so);
+        im += sin_w[(size_t)k * n_tau + j] * (sv + so);
+      }
+      if (is_occ[n]) {
+        zn.push_back(cplx(0.0, -omega[k]));
+        fv.push_back(cplx(re, -im));
+      } else {
+        zn.push_back(cplx(0.0, omega[k]));
+        fv.push_back(cplx(re, im));
+      }
+    }
+    state_status[n] = GW_ERR_NO_CONVERGE;
+    e_qp[n] = std::nan("");
+    if (zn.empty()) {
+      ret = GW_ERR_NO_CONVERGE;
+      continue;
+    }
+    const std::vector<cplx> a = thiele_coeffs(zn, fv);
+    const double vxc = vxc_n ? vxc_n[n] : 0.0;
+    double e = eps_n[n];
+    for (int it = 0; it < max_iter; ++it) {
+      cplx val, der;
+      thiele_eval(zn, a, cplx(e - mu_f, 0.0), &val, &der);
+      const double f = e - eps_n[n] + vxc - sig_x[n] - val.real();
+      const double fp = 1.0 - der.real();
+      const double de = -f / fp;
+      e += de;
+      if (!std::isfinite(e)) break;
+      if (std::fabs(de) < tol) {
+        state_status[n] = GW_OK;
+        e_qp[n] = e;
+        break;
+      }
+    }
+    if (state_status[n] != GW_OK) ret = GW_ERR_NO_CONVERGE;
+  }
+  if (ret != GW_OK) gw::set_error("Newton did not converge for at least one state");
+  return ret;
+}

@@ -1,0 +1,326 @@
+// Diagonal self-energy pieces (Eqs. 10-11) on FP64 MFMA.
+//   B^n_{mu P} = sum_nu C_{n nu} (nu mu P)                (half transform, once)
+//   Z^n_{P nu} = sum_Q W_PQ B^n_{nu Q}                     inner sum of Eq. 10
+//   sig_occ_n  = sum_{mu nu} D^occ_{mu nu} sum_P B^n_{mu P} Z^n_{P nu}
+//   sig_vir_n  = the same with D^vir (both dots in one pass)
+//   sig_x_n    = - the same with W := V, D := D^occ(0)     (Eq. 11)
+// B^n is block sparse: block (mu atom s, RI atom c) exists when a brick
+// (f, s, c) is kept.  It is stored panel-dense over AO column panels (PGa
+// atoms): panel q holds rows k = (RI atom in U_q, P) and columns (s, mu),
+// U_q = RI atoms coupled to the panel.  The same panels feed both the W
+// product (K = Q) and the final contraction (K = P).
+#include <chrono>
+#include <cmath>
+
+#include "gw_internal.hpp"
+#include "tile_gemm.hpp"
+
+namespace gw {
+namespace {
+
+constexpr int H_NB = 11;            // half transform: rows n_gw (32*WM), cols 176
+constexpr int Z_WM = 4, Z_NB = 10;  // W product / dot: 128 x 160 tiles
+
+struct HalfProblem {
+  struct Tile : TileBase {
+    int g, row0, col0, seg0, q, al, slot;
+  };
+  static constexpr bool kAScale = false, kDot = false;
+  const double* cg;         // [N][RS], RS = n_gw
+  const double* t3c;
+  double* fp;
+  const int32_t* goff;
+  const int32_t* seg_atom;
+  const int64_t* seg_brick;
+  const int32_t* gs;
+  const int32_t* gslot;
+  const int64_t* poff;
+  int n_rt, n_ct, rows_pt, cols_pt;
+  int RS, NA, NR, PGa, PCa;
+  int64_t bs, FPS;
+
+  __device__ bool tile(int bx, int, int, Tile& t) const {
+    const int per = n_rt * n_ct;
+    t.g = bx / per;
+    const int rem = bx % per;
+    t.row0 = (rem % n_rt) * rows_pt;
+    t.col0 = (rem / n_rt) * cols_pt;
+    t.seg0 = goff[t.g];
+    t.K = NA * (goff[t.g + 1] - t.seg0);
+    const int sa = gs[t.g];
+    t.q = sa / PGa;
+    t.al = sa % PGa;
+    t.slot = gslot[t.g];
+    t.rows = min(rows_pt, RS - t.row0);
+    t.cols = min(cols_pt, NA * NR - t.col0);
+    return t.rows > 0 && t.cols > 0;
+  }
+  __device__ const double* abase(const Tile& t) const { return cg + t.row0; }
+  __device__ int64_t aroff(const Tile&, int r) const { return r; }
+  __device__ int64_t akoff(const Tile& t, int k) const {
+    return (int64_t)(seg_atom[t.seg0 + k / NA] * NA + k % NA) * RS;
+  }
+  __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
+  __device__ int64_t bkoff(const Tile& t, int k) const {
+    return seg_brick[t.seg0 + k / NA] * bs + (int64_t)(k % NA) * NA * NR;
+  }
+  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ void store(const Tile& t, int r, int c, double v) const {
+    const int n = t.row0 + r, col = t.col0 + c;
+    const int mul = col / NR, P = col % NR;
+    fp[(int64_t)n * FPS + poff[t.q] + (int64_t)(t.slot * NR + P) * PCa + t.al * NA + mul] = v;
+  }
+  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ void dot_out(const Tile&, double, double) const {}
+};
+
+// Z[n][P][nu] = sum_{k in panel q} W[Q(k)][P] * Fp[n][q][k][nu - q*PCa]
+struct ZProblem {
+  struct Tile : TileBase {
+    int row0, q, n, km0;
+  };
+  static constexpr bool kAScale = false, kDot = false;
+  const double* w;          // [NRI][NRI] symmetric
+  const double* fp;
+  double* z;                // [n_gw][NRI][N]
+  const int32_t* kmap;
+  const int32_t* km_off;
+  const int32_t* ulen;
+  const int64_t* poff;
+  int n_rt, rows_pt, NRI, N, NR, PCa;
+  int64_t FPS;
+
+  __device__ bool tile(int bx, int, int bz, Tile& t) const {
+    t.row0 = (bx % n_rt) * rows_pt;
+    t.q = bx / n_rt;
+    t.n = bz;
+    t.rows = min(rows_pt, NRI - t.row0);
+    t.cols = min(PCa, N - t.q * PCa);
+    t.K = NR * ulen[t.q];
+    t.km0 = km_off[t.q];
+    return t.rows > 0 && t.cols > 0 && t.K > 0;
+  }
+  __device__ const double* abase(const Tile& t) const { return w + t.row0; }
+  __device__ int64_t aroff(const Tile&, int r) const { return r; }
+  __device__ int64_t akoff(const Tile& t, int k) const { return (int64_t)kmap[t.km0 + k] * NRI; }
+  __device__ const double* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
+  __device__ int64_t bkoff(const Tile&, int k) const { return (int64_t)k * PCa; }
+  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ void store(const Tile& t, int r, int c, double v) const {
+    z[((int64_t)t.n * NRI + t.row0 + r) * N + (int64_t)t.q * PCa + c] = v;
+  }
+  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ void dot_out(const Tile&, double, double) const {}
+};
+
+// sum_{nu mu} D[nu][mu] * sum_{k in panel q} Z[n][P(k)][nu] Fp[n][q][k][mu - q*PCa]
+struct DotProblem {
+  struct Tile : TileBase {
+    int row0, q, n, km0, tile_id;
+  };
+  static constexpr bool kAScale = false, kDot = true;
+  const double* z;
+  const double* fp;
+  const double* d0;         // [N][N]
+  const double* d1;         // [N][N]
+  double* partial;          // [n_gw][n_tiles][2]
+  const int32_t* kmap;
+  const int32_t* km_off;
+  const int32_t* ulen;
+  const int64_t* poff;
+  int n_rt, n_tiles, rows_pt, NRI, N, NR, PCa;
+  int64_t FPS;
+
+  __device__ bool tile(int bx, int, int bz, Tile& t) const {
+    t.row0 = (bx % n_rt) * rows_pt;
+    t.q = bx / n_rt;
+    t.n = bz;
+    t.tile_id = bx;
+    t.rows = min(rows_pt, N - t.row0);
+    t.cols = min(PCa, N - t.q * PCa);
+    t.K = NR * ulen[t.q];
+    t.km0 = km_off[t.q];
+    if (t.rows <= 0 || t.cols <= 0 || t.K <= 0) {
+      // an empty tile still reports zero so that every partial is written
+      if (threadIdx.x == 0) {
+        partial[((int64_t)t.n * n_tiles + t.tile_id) * 2] = 0.0;
+        partial[((int64_t)t.n * n_tiles + t.tile_id) * 2 + 1] = 0.0;
+      }
+      return false;
+    }
+    return true;
+  }
+  __device__ const double* abase(const Tile& t) const {
+    return z + (int64_t)t.n * NRI * N + t.row0;
+  }
+  __device__ int64_t aroff(const Tile&, int r) const { return r; }
+  __device__ int64_t akoff(const Tile& t, int k) const { return (int64_t)kmap[t.km0 + k] * N; }
+  __device__ const double* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
+  __device__ int64_t bkoff(const Tile&, int k) const { return (int64_t)k * PCa; }
+  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ void store(const Tile&, int, int, double) const {}
+  __device__ void dot(const Tile& t, int r, int c, double v, double& s0, double& s1) const {
+    const int64_t e = (int64_t)(t.row0 + r) * N + (int64_t)t.q * PCa + c;
+    s0 += v * d0[e];
+    s1 += v * d1[e];
+  }
+  __device__ void dot_out(const Tile& t, double s0, double s1) const {
+    partial[((int64_t)t.n * n_tiles + t.tile_id) * 2] = s0;
+    partial[((int64_t)t.n * n_tiles + t.tile_id) * 2 + 1] = s1;
+  }
+};
+
+__global__ void gather_rows_kernel(const double* __restrict__ C, const int32_t* __restrict__ rows,
+                                   double* __restrict__ cg, int N, int n_rows) {
+  const int64_t total = (int64_t)N * n_rows;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int nu = (int)(e / n_rows), k = (int)(e % n_rows);
+    cg[e] = C[(int64_t)rows[k] * N + nu];
+  }
+}
+
+template <int WM>
+hipError_t launch_half(HalfProblem hp, int n_groups, hipStream_t st) {
+  hp.rows_pt = 32 * WM;
+  hp.cols_pt = 16 * H_NB;
+  hp.n_rt = (hp.RS + hp.rows_pt - 1) / hp.rows_pt;
+  hp.n_ct = (hp.NA * hp.NR + hp.cols_pt - 1) / hp.cols_pt;
+  return launch_tile_gemm<WM, H_NB>(hp, dim3((unsigned)(n_groups * hp.n_rt * hp.n_ct)), st);
+}
+
+}  // namespace
+}  // namespace gw
+
+using namespace gw;
+
+extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const int32_t* states,
+                                       const double* C, const double* d_occ, const double* d_vir,
+                                       const double* d_occ0, const double* wc, const double* V,
+                                       int32_t n_tau, double filter_eps, double* sig_occ,
+                                       double* sig_vir, double* sig_x, gw_sigma_stats* stats,
+                                       hipStream_t st) {
+  clear_error();
+  const auto t_start = std::chrono::steady_clock::now();
+  gw_status rc = check_system(s);
+  if (rc != GW_OK) return rc;
+  const int na = s->n_atoms, NA = s->ao_per_atom, NR = s->ri_per_atom;
+  const int N = na * NA, NRI = na * NR;
+  GW_CHECK_ARG(n_gw >= 1 && n_gw <= 128, "n_gw must be in [1, 128]");
+  GW_CHECK_ARG(states != nullptr, "states is null");
+  for (int i = 0; i < n_gw; ++i) GW_CHECK_ARG(states[i] >= 0 && states[i] < N, "state index out of range");
+  GW_CHECK_ARG(C && d_occ && d_vir && d_occ0 && wc && V, "null device pointer");
+  GW_CHECK_ARG(sig_occ && sig_vir && sig_x, "null output pointer");
+  GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
+  GW_CHECK_ARG(std::isfinite(filter_eps) && filter_eps >= 0.0, "filter_eps must be finite and >= 0");
+  GW_CHECK_ARG(NA <= 16 * Z_NB, "ao_per_atom must be <= 160");
+  if (stats) *stats = gw_sigma_stats{};
+
+  Scratch sc(st);
+  BrickGroups G;
+  if ((rc = build_groups(s, filter_eps, st, sc, G)) != GW_OK) return rc;
+  const int n_groups = G.n_groups();
+  const int64_t bs = (int64_t)NA * NA * NR;
+
+  // AO column panels (mu atoms); K atoms = RI atoms coupled through a kept brick
+  const int PGa = std::max(1, (16 * Z_NB) / NA), PCa = PGa * NA;
+  const Panels pan = build_panels(na, PGa, PCa, G.gs, G.gc, NR, 1);
+  const int n_pan = pan.n_pan;
+  const int64_t FPS = pan.off[n_pan];
+
+  double *dof, *dvf, *d0f, *cg, *fp, *z, *partial;
+  int32_t* d_states;
+  const size_t dsz = (size_t)n_tau * N * N;
+  if ((rc = sc.alloc(&dof, dsz)) != GW_OK) return rc;
+  if ((rc = sc.alloc(&dvf, dsz)) != GW_OK) return rc;
+  if ((rc = sc.alloc(&d0f, (size_t)N * N)) != GW_OK) return rc;
+  if ((rc = sc.alloc(&cg, (size_t)N * n_gw)) != GW_OK) return rc;
+  if ((rc = sc.alloc(&fp, (size_t)n_gw * std::max<int64_t>(FPS, 1))) != GW_OK) return rc;
+  if ((rc = sc.alloc(&z, (size_t)n_gw * NRI * N)) != GW_OK) return rc;
+  const int z_rt = (NRI + 32 * Z_WM - 1) / (32 * Z_WM);
+  const int y_rt = (N + 32 * Z_WM - 1) / (32 * Z_WM);
+  const int n_tiles = y_rt * n_pan;
+  const int n_slots = n_tau + 1;
+  if ((rc = sc.alloc(&partial, (size_t)n_slots * n_gw * n_tiles * 2)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_states, std::vector<int32_t>(states, states + n_gw))) != GW_OK) return rc;
+  int32_t *d_goff, *d_seg_atom, *d_gs, *d_gslot, *d_ulen, *d_kmap, *d_km_off;
+  int64_t *d_seg_brick, *d_poff;
+  if ((rc = sc.upload(&d_goff, G.goff)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_seg_atom, G.seg_atom)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_seg_brick, G.seg_brick)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_gs, G.gs)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_gslot, pan.gslot)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_ulen, pan.ulen)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_kmap, pan.kmap)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_km_off, pan.km_off)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_poff, pan.off)) != GW_OK) return rc;
+
+  GW_HIP(filter_square_blocks(d_occ, dof, n_tau, na, NA, filter_eps, nullptr, st));
+  GW_HIP(filter_square_blocks(d_vir, dvf, n_tau, na, NA, filter_eps, nullptr, st));
+  GW_HIP(filter_square_blocks(d_occ0, d0f, 1, na, NA, filter_eps, nullptr, st));
+  GW_HIP(hipMemsetAsync(fp, 0, sizeof(double) * (size_t)n_gw * std::max<int64_t>(FPS, 1), st));
+  // panels without coupled RI atoms never write their Z columns; those stay 0
+  GW_HIP(hipMemsetAsync(z, 0, sizeof(double) * (size_t)n_gw * NRI * N, st));
+  {
+    const int64_t total = (int64_t)N * n_gw;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks), dim3(256), 0, st, C, d_states, cg, N, n_gw);
+    GW_HIP(hipGetLastError());
+  }
+
+  // half transform B^n (all states at once)
+  if (n_groups > 0) {
+    HalfProblem hp{};
+    hp.cg = cg; hp.t3c = s->t3c; hp.fp = fp; hp.goff = d_goff; hp.seg_atom = d_seg_atom;
+    hp.seg_brick = d_seg_brick; hp.gs = d_gs; hp.gslot = d_gslot; hp.poff = d_poff;
+    hp.RS = n_gw; hp.NA = NA; hp.NR = NR; hp.PGa = PGa; hp.PCa = PCa; hp.bs = bs; hp.FPS = FPS;
+    hipError_t e = n_gw <= 64 ? launch_half<2>(hp, n_groups, st) : launch_half<4>(hp, n_groups, st);
+    GW_HIP(e);
+  }
+
+  ZProblem zp{};
+  zp.fp = fp; zp.z = z; zp.kmap = d_kmap; zp.km_off = d_km_off; zp.ulen = d_ulen; zp.poff = d_poff;
+  zp.n_rt = z_rt; zp.rows_pt = 32 * Z_WM; zp.NRI = NRI; zp.N = N; zp.NR = NR; zp.PCa = PCa;
+  zp.FPS = FPS;
+  DotProblem dp{};
+  dp.z = z; dp.fp = fp; dp.kmap = d_kmap; dp.km_off = d_km_off; dp.ulen = d_ulen; dp.poff = d_poff;
+  dp.n_rt = y_rt; dp.n_tiles = n_tiles; dp.rows_pt = 32 * Z_WM; dp.NRI = NRI; dp.N = N; dp.NR = NR;
+  dp.PCa = PCa; dp.FPS = FPS;
+
+  for (int j = 0; j < n_slots; ++j) {
+    const bool xslot = (j == n_tau);
+    zp.w = xslot ? V : wc + (int64_t)j * NRI * NRI;
+    GW_HIP((launch_tile_gemm<Z_WM, Z_NB>(zp, dim3((unsigned)(z_rt * n_pan), 1, n_gw), st)));
+    dp.d0 = xslot ? d0f : dof + (int64_t)j * N * N;
+    dp.d1 = xslot ? d0f : dvf + (int64_t)j * N * N;
+    dp.partial = partial + (size_t)j * n_gw * n_tiles * 2;
+    GW_HIP((launch_tile_gemm<Z_WM, Z_NB>(dp, dim3((unsigned)n_tiles, 1, n_gw), st)));
+  }
+
+  std::vector<double> hp((size_t)n_slots * n_gw * n_tiles * 2);
+  GW_HIP(hipMemcpyAsync(hp.data(), partial, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
+  GW_HIP(hipStreamSynchronize(st));
+  for (int j = 0; j < n_slots; ++j)
+    for (int n = 0; n < n_gw; ++n) {
+      double s0 = 0.0, s1 = 0.0;
+      const double* p = hp.data() + ((size_t)j * n_gw + n) * n_tiles * 2;
+      for (int t = 0; t < n_tiles; ++t) {
+        s0 += p[2 * t];
+        s1 += p[2 * t + 1];
+      }
+      if (j == n_tau) {
+        sig_x[n] = -s0;
+      } else {
+        sig_occ[(size_t)n * n_tau + j] = s0;
+        sig_vir[(size_t)n * n_tau + j] = s1;
+      }
+    }
+  if (stats) {
+    const double nnzb = (double)n_groups * NA * NR;
+    const double half = 2.0 * n_gw * NA * (double)G.n_kept * bs;
+    const double per_slot = n_gw * (2.0 * NRI * nnzb + 2.0 * N * nnzb + 4.0 * (double)N * N);
+    stats->flops = half + per_slot * n_slots;
+    stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return GW_OK;
+}

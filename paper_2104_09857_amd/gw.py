@@ -1,0 +1,206 @@
+"""ctypes binding of libgw.so (include/gw.h): argument marshalling only.
+
+Device arrays are torch CUDA (ROCm) float64 tensors, host arrays are NumPy.
+Every computation happens in libgw.so; when the library is missing this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgw.so")
+
+GW_OK, GW_ERR_ARG, GW_ERR_HIP, GW_ERR_NOMEM, GW_ERR_NOT_SPD, GW_ERR_NO_CONVERGE, GW_ERR_BLAS = range(7)
+GW_FP64 = 0
+
+
+class GWError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libgw error {code}: {msg}")
+        self.code = code
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("ao_per_atom", ctypes.c_int32),
+                ("ri_per_atom", ctypes.c_int32), ("n_occ", ctypes.c_int32),
+                ("n_trip", ctypes.c_int64), ("trip", ctypes.c_void_p), ("t3c", ctypes.c_void_p)]
+
+
+class _ChiOpts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("filter_eps", ctypes.c_double), ("timing", ctypes.c_int32)]
+
+
+class _ChiStats(ctypes.Structure):
+    _fields_ = [("n_trip_kept", ctypes.c_int64), ("n_dblk_dropped", ctypes.c_int64),
+                ("n_chiblk_dropped", ctypes.c_int64), ("flops_ab", ctypes.c_double),
+                ("flops_c", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_stage", ctypes.c_double * 3), ("n_launch", ctypes.c_int64 * 3),
+                ("flops_stage", ctypes.c_double * 3)]
+
+
+class _SigmaStats(ctypes.Structure):
+    _fields_ = [("flops", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+class _QpOpts(ctypes.Structure):
+    _fields_ = [("pade_window", ctypes.c_double), ("newton_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32)]
+
+
+_LIB = None
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_D = ctypes.c_double
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.gw_build_gt.argtypes = [_P, _P, _P, _D, _I32, _P, _P, _P, _P]
+        L.gw_contract_chi.argtypes = [_P, _P, _P, _I32, _P, _P, _P, _P]
+        L.gw_screen_w.argtypes = [_P, _P, _P, _I32, _I32, _P, _P, _D, _P, _P]
+        L.gw_contract_sigma.argtypes = [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _I32, _D, _P, _P, _P,
+                                        _P, _P]
+        L.gw_continue_qp.argtypes = [_I32, _P, _P, _P, _P, _P, _P, _D, _I32, _I32, _P, _P, _P, _P,
+                                     _P, _P]
+        for f in ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma",
+                  "gw_continue_qp"):
+            getattr(L, f).restype = ctypes.c_int32
+        L.gw_last_error.restype = ctypes.c_char_p
+        L.gw_last_error.argtypes = []
+        L.gw_version.restype = ctypes.c_char_p
+        L.gw_version.argtypes = []
+        _LIB = L
+    return _LIB
+
+
+EXPORTED = ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma",
+            "gw_continue_qp", "gw_last_error", "gw_version")
+
+
+def _check(code):
+    if code != GW_OK:
+        raise GWError(code, lib().gw_last_error().decode())
+
+
+def _host(a, dtype=np.float64):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev(t):
+    import torch
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device arguments must be contiguous CUDA tensors"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class System:
+    """A system description (gw_system) with its host triple list and device bricks."""
+
+    def __init__(self, n_atoms, ao_per_atom, ri_per_atom, n_occ, trip, t3c):
+        self.trip = np.ascontiguousarray(trip, dtype=np.int32).reshape(-1, 3)
+        self.t3c = t3c
+        self.c = _System(int(n_atoms), int(ao_per_atom), int(ri_per_atom), int(n_occ),
+                         len(self.trip), self.trip.ctypes.data_as(ctypes.c_void_p).value,
+                         t3c.data_ptr() if t3c is not None and len(self.trip) else None)
+        self.n_ao = n_atoms * ao_per_atom
+        self.n_ri = n_atoms * ri_per_atom
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def build_gt(sys, C, eps, mu_f, tau, d_occ=None, d_vir=None, stream=None):
+    import torch
+    tau_h, tau_p = _host(tau)
+    eps_h, eps_p = _host(eps)
+    n = sys.n_ao
+    # None: allocate the output; False: skip that branch (NULL pointer)
+    if d_occ is None:
+        d_occ = torch.empty((len(tau_h), n, n), dtype=torch.float64, device=C.device)
+    if d_vir is None:
+        d_vir = torch.empty((len(tau_h), n, n), dtype=torch.float64, device=C.device)
+    d_occ = None if d_occ is False else d_occ
+    d_vir = None if d_vir is False else d_vir
+    _check(lib().gw_build_gt(sys.ref, _dev(C), eps_p, float(mu_f), len(tau_h), tau_p,
+                             _dev(d_occ), _dev(d_vir), _stream(stream)))
+    return d_occ, d_vir
+
+
+def contract_chi(sys, d_occ, d_vir, filter_eps=0.0, chi=None, stream=None, timing=False):
+    import torch
+    n_tau = d_occ.shape[0]
+    if chi is None:
+        chi = torch.empty((n_tau, sys.n_ri, sys.n_ri), dtype=torch.float64, device=d_occ.device)
+    opts = _ChiOpts(GW_FP64, float(filter_eps), int(bool(timing)))
+    st = _ChiStats()
+    _check(lib().gw_contract_chi(sys.ref, _dev(d_occ), _dev(d_vir), n_tau, ctypes.byref(opts),
+                                 _dev(chi), ctypes.byref(st), _stream(stream)))
+    stats = {k: (list(getattr(st, k)) if k in ("ms_stage", "n_launch", "flops_stage")
+                 else getattr(st, k)) for k, _ in _ChiStats._fields_}
+    return chi, stats
+
+
+def screen_w(sys, chi, V, cos_w, icos_w, spin=2.0, wc=None, stream=None):
+    import torch
+    cw, cw_p = _host(cos_w)
+    iw, iw_p = _host(icos_w)
+    n_w, n_tau = cw.shape
+    if wc is None:
+        wc = torch.empty_like(chi)
+    _check(lib().gw_screen_w(sys.ref, _dev(chi), _dev(V), n_tau, n_w, cw_p, iw_p, float(spin),
+                             _dev(wc), _stream(stream)))
+    return wc
+
+
+def contract_sigma(sys, states, C, d_occ, d_vir, d_occ0, wc, V, filter_eps=0.0, stream=None):
+    st_h, st_p = _host(states, np.int32)
+    n_gw, n_tau = len(st_h), d_occ.shape[0]
+    so = np.zeros((n_gw, n_tau))
+    sv = np.zeros((n_gw, n_tau))
+    sx = np.zeros(n_gw)
+    stats = _SigmaStats()
+    _check(lib().gw_contract_sigma(sys.ref, n_gw, st_p, _dev(C), _dev(d_occ), _dev(d_vir),
+                                   _dev(d_occ0), _dev(wc), _dev(V), n_tau, float(filter_eps),
+                                   so.ctypes.data_as(_P), sv.ctypes.data_as(_P),
+                                   sx.ctypes.data_as(_P), ctypes.byref(stats), _stream(stream)))
+    return so, sv, sx, {"flops": stats.flops, "ms_total": stats.ms_total}
+
+
+def continue_qp(sig_occ, sig_vir, sig_x, eps_n, vxc_n, is_occ, mu_f, omega, cos_w, sin_w,
+                window=0.0, tol=1e-10, max_iter=100, raise_on_fail=False):
+    so, so_p = _host(sig_occ)
+    sv, sv_p = _host(sig_vir)
+    sx, sx_p = _host(sig_x)
+    en, en_p = _host(eps_n)
+    vx, vx_p = _host(vxc_n)
+    io, io_p = _host(is_occ, np.int32)
+    om, om_p = _host(omega)
+    cw, cw_p = _host(cos_w)
+    sw, sw_p = _host(sin_w)
+    n_gw, n_tau = so.shape
+    e = np.zeros(n_gw)
+    status = np.zeros(n_gw, dtype=np.int32)
+    opts = _QpOpts(float(window), float(tol), int(max_iter))
+    code = lib().gw_continue_qp(n_gw, so_p, sv_p, sx_p, en_p, vx_p, io_p, float(mu_f), n_tau,
+                                len(om), om_p, cw_p, sw_p, ctypes.byref(opts),
+                                e.ctypes.data_as(_P), status.ctypes.data_as(_P))
+    if code not in (GW_OK, GW_ERR_NO_CONVERGE) or (raise_on_fail and code != GW_OK):
+        _check(code)
+    return e, status

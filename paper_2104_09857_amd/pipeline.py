@@ -1,0 +1,49 @@
+"""The five ABI calls chained from device-resident inputs to QP energies.
+
+Only orchestration: each step is one call into libgw.so.  Per-stage wall
+times come from HIP events recorded on the stream the library runs on.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import gw
+
+
+def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_eps,
+         spin=2.0, vxc=None, window=0.0, stream=None, events=False, chi_timing=False):
+    import torch
+    st = torch.cuda.current_stream() if stream is None else stream
+    ev = {}
+
+    def mark(name):
+        if events:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(st)
+            ev[name] = e
+
+    states = np.asarray(states, dtype=np.int32)
+    eps = np.asarray(eps, dtype=np.float64)
+    mark("start")
+    d_occ, d_vir = gw.build_gt(sys, C, eps, mu_f, tau, stream=st)
+    d0, _ = gw.build_gt(sys, C, eps, mu_f, [0.0], d_vir=False, stream=st)
+    mark("gt")
+    chi, chi_stats = gw.contract_chi(sys, d_occ, d_vir, filter_eps, stream=st, timing=chi_timing)
+    mark("chi")
+    wc = gw.screen_w(sys, chi, V, cos_w, icos_w, spin, stream=st)
+    mark("screen")
+    so, sv, sx, sig_stats = gw.contract_sigma(sys, states, C, d_occ, d_vir, d0, wc, V, filter_eps,
+                                              stream=st)
+    mark("sigma")
+    vxc = np.zeros(len(states)) if vxc is None else np.asarray(vxc, dtype=np.float64)
+    is_occ = (states < sys.c.n_occ).astype(np.int32)
+    e_qp, status = gw.continue_qp(so, sv, sx, eps[states], vxc, is_occ, mu_f, omega, cos_w, sin_w,
+                                  window)
+    mark("qp")
+    out = dict(d_occ=d_occ, d_vir=d_vir, chi=chi, wc=wc, sig_occ=so, sig_vir=sv, sig_x=sx,
+               e_qp=e_qp, status=status, chi_stats=chi_stats, sig_stats=sig_stats)
+    if events:
+        st.synchronize()
+        names = list(ev)
+        out["ms"] = {names[i]: ev[names[i - 1]].elapsed_time(ev[names[i]]) for i in range(1, len(names))}
+    return out
