@@ -173,7 +173,7 @@ def main():
         "stage_ms": {k: round(v, 2) for k, v in out["ms"].items()},
         "flops": {"chi_ab": cs["flops_ab"], "chi_c": cs["flops_c"], "sigma": ss["flops"]},
         "e_qp": [float(x) for x in out["e_qp"]], "qp_status": [int(x) for x in out["status"]],
-        "roofline": {"kernel": "tile_gemm_kernel<4,10,StageC> (chi outer contraction)",
+        "roofline": {"kernel": "tile_gemm_kernel<4,2,5,16,StageC> (chi outer contraction)",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
                      "traffic": traffic, "launches": int(c_n), "avg_launch_ms": per_launch_ms},

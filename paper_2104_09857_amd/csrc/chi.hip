@@ -25,15 +25,20 @@
 namespace gw {
 namespace {
 
-constexpr int A_WM = 4, A_NB = 11;   // stage A tile 128 x 176
-constexpr int B_NB = 11;             // stage B tile (32 WM) x 176
-constexpr int C_WM = 4, C_NB = 10;   // stage C tile 128 x 160
+constexpr int A_WM = 4, AB_WN = 2, AB_NBW = 6;    // stage A tile 128 x 192, 8 waves
+constexpr int AB_COLS = 16 * AB_NBW * AB_WN;      // stage B tile (32 WM) x 192
+constexpr int C_WM = 4, C_WN = 2, C_NBW = 5;      // stage C tile 128 x 160, 8 waves
+constexpr int C_COLS = 16 * C_NBW * C_WN;
+
+constexpr int kSegTab = 2048;     // max bricks per group (first atoms)
+constexpr int kPanTab = 4096;     // max K functions per column panel (NA * |U_p|)
 
 struct StageA {
   struct Tile : TileBase {
-    int g, slot, tau, row0, col0, seg0;
+    int g, slot, tau, row0, col0, seg0, nseg;
   };
   static constexpr bool kAScale = false, kDot = false;
+  static constexpr int kTabA = kSegTab, kTabB = kSegTab;
   const double* dof;
   const double* t3c;
   double* mb;
@@ -43,6 +48,7 @@ struct StageA {
   int g0, n_rt, n_ct, rows_pt, cols_pt;
   int N, NA, NR, nRmax;
   int64_t bs;
+  FastDiv fdNA, fdNR;
 
   __device__ bool tile(int bx, int by, int bz, Tile& t) const {
     const int per = n_rt * n_ct;
@@ -53,35 +59,52 @@ struct StageA {
     t.g = g0 + t.slot;
     t.tau = by;
     t.seg0 = goff[t.g];
-    t.K = NA * (goff[t.g + 1] - t.seg0);
+    t.nseg = goff[t.g + 1] - t.seg0;
+    t.K = NA * t.nseg;
     t.rows = min(rows_pt, N - t.row0);
     t.cols = min(cols_pt, NA * NR - t.col0);
     return t.rows > 0 && t.cols > 0;
   }
+  __device__ void fill(const Tile& t, int* ta, int* tb, int tid, int nt) const {
+    for (int i = tid; i < t.nseg; i += nt) {
+      ta[i] = seg_atom[t.seg0 + i];
+      tb[i] = (int)seg_brick[t.seg0 + i];
+    }
+  }
   __device__ const double* abase(const Tile& t) const { return dof + (int64_t)t.tau * N * N + t.row0; }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile& t, int k) const {
-    return (int64_t)(seg_atom[t.seg0 + k / NA] * NA + k % NA) * N;
+  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
+    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
+    return (int64_t)(ta[sg] * NA + i) * N;
   }
   __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
-  __device__ int64_t bkoff(const Tile& t, int k) const {
-    return seg_brick[t.seg0 + k / NA] * bs + (int64_t)(k % NA) * NA * NR;
+  __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
+    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
+    return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
   }
   __device__ double ascale(const Tile&, int) const { return 1.0; }
-  __device__ void store(const Tile& t, int r, int c, double v) const {
-    const int mu = t.row0 + r, col = t.col0 + c;
-    const int sg = col / NR, P = col % NR;
-    mb[(((int64_t)t.tau * NA + sg) * nRmax + t.slot) * N * NR + (int64_t)mu * NR + P] = v;
+  // M_b[tau][sigma][slot][mu][P]: row mu, column (sigma, P)
+  __device__ double* obase(const Tile& t) const {
+    return mb + ((int64_t)t.tau * NA * nRmax + t.slot) * N * NR;
   }
-  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ int64_t rowoff(const Tile& t, int r) const { return (int64_t)(t.row0 + r) * NR; }
+  __device__ int64_t coloff(const Tile& t, int c) const {
+    const int col = t.col0 + c, sg = (int)fdNR.div((uint32_t)col), P = col - sg * NR;
+    return (int64_t)sg * nRmax * N * NR + P;
+  }
+  static constexpr bool kAccum = false;
+  static constexpr double kSign = 1.0;
+  __device__ const double* dbase0(const Tile&) const { return nullptr; }
+  __device__ const double* dbase1(const Tile&) const { return nullptr; }
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
 struct StageB {
   struct Tile : TileBase {
-    int g, row0, col0, seg0, p, cl, slot, KU;
+    int g, row0, col0, seg0, nseg, p, cl, slot, KU;
   };
   static constexpr bool kAScale = false, kDot = false;
+  static constexpr int kTabA = kSegTab, kTabB = kSegTab;
   const double* dvg;        // [N][RS]
   const double* t3c;
   double* bp;
@@ -95,6 +118,7 @@ struct StageB {
   int n_rt, n_ct, rows_pt, cols_pt;
   int RS, NA, NR, PG, PC;
   int64_t bs, BPS;
+  FastDiv fdNA, fdNR;
 
   __device__ bool tile(int bx, int, int, Tile& t) const {
     const int per = n_rt * n_ct;
@@ -103,7 +127,8 @@ struct StageB {
     t.row0 = (rem % n_rt) * rows_pt;
     t.col0 = (rem / n_rt) * cols_pt;
     t.seg0 = goff[t.g];
-    t.K = NA * (goff[t.g + 1] - t.seg0);
+    t.nseg = goff[t.g + 1] - t.seg0;
+    t.K = NA * t.nseg;
     const int c = gc[t.g];
     t.p = c / PG;
     t.cl = c % PG;
@@ -113,31 +138,48 @@ struct StageB {
     t.cols = min(cols_pt, NA * NR - t.col0);
     return t.rows > 0 && t.cols > 0;
   }
+  __device__ void fill(const Tile& t, int* ta, int* tb, int tid, int nt) const {
+    for (int i = tid; i < t.nseg; i += nt) {
+      ta[i] = seg_atom[t.seg0 + i];
+      tb[i] = (int)seg_brick[t.seg0 + i];
+    }
+  }
   __device__ const double* abase(const Tile& t) const { return dvg + t.row0; }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile& t, int k) const {
-    return (int64_t)(seg_atom[t.seg0 + k / NA] * NA + k % NA) * RS;
+  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
+    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
+    return (int64_t)(ta[sg] * NA + i) * RS;
   }
   __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
-  __device__ int64_t bkoff(const Tile& t, int k) const {
-    return seg_brick[t.seg0 + k / NA] * bs + (int64_t)(k % NA) * NA * NR;
+  __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
+    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
+    return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
   }
   __device__ double ascale(const Tile&, int) const { return 1.0; }
-  __device__ void store(const Tile& t, int r, int c, double v) const {
-    const int row = t.row0 + r, col = t.col0 + c;
-    const int tau = row / NA, sg = row % NA;
-    const int mul = col / NR, Q = col % NR;
-    bp[(int64_t)tau * BPS + bp_off[t.p] + ((int64_t)sg * t.KU + t.slot * NA + mul) * PC + t.cl * NR + Q] = v;
+  // N_b panel: [tau][panel][sigma][u = slot*NA + mu][(cl, Q)]: row (tau, sigma), column (mu, Q)
+  __device__ double* obase(const Tile& t) const { return bp + bp_off[t.p]; }
+  __device__ int64_t rowoff(const Tile& t, int r) const {
+    const int row = t.row0 + r, tau = (int)fdNA.div((uint32_t)row), sg = row - tau * NA;
+    return (int64_t)tau * BPS + (int64_t)sg * t.KU * PC;
   }
-  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ int64_t coloff(const Tile& t, int c) const {
+    const int col = t.col0 + c, mul = (int)fdNR.div((uint32_t)col), Q = col - mul * NR;
+    return (int64_t)(t.slot * NA + mul) * PC + t.cl * NR + Q;
+  }
+  static constexpr bool kAccum = false;
+  static constexpr double kSign = 1.0;
+  __device__ const double* dbase0(const Tile&) const { return nullptr; }
+  __device__ const double* dbase1(const Tile&) const { return nullptr; }
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
 struct StageC {
   struct Tile : TileBase {
     int p, tau, row0, KU, km0;
+    FastDiv fdKU;
   };
   static constexpr bool kAScale = false, kDot = false;
+  static constexpr int kTabA = kPanTab, kTabB = 0;
   const double* mb;
   const double* bp;
   double* chi;
@@ -149,6 +191,7 @@ struct StageC {
   int g0, nR, n_rt, rows_pt;
   int N, NA, NR, NRI, PG, PC, nRmax, n_atoms;
   int64_t BPS;
+  FastDiv fdNR;
 
   __device__ bool tile(int bx, int by, int bz, Tile& t) const {
     t.row0 = (bx % n_rt) * rows_pt;
@@ -163,32 +206,39 @@ struct StageC {
     t.KU = NA * ulen[t.p];
     t.km0 = km_off[t.p];
     t.K = NA * t.KU;
+    t.fdKU.set((uint32_t)t.KU);
     return t.K > 0;
+  }
+  __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
+    for (int i = tid; i < t.KU; i += nt) ta[i] = kmap[t.km0 + i] * NR;
   }
   __device__ const double* abase(const Tile& t) const {
     return mb + (int64_t)t.tau * NA * nRmax * N * NR;
   }
   __device__ int64_t aroff(const Tile& t, int r) const {
-    const int row = t.row0 + r;
-    return (int64_t)(row / NR) * N * NR + row % NR;
+    const int row = t.row0 + r, sl = (int)fdNR.div((uint32_t)row);
+    return (int64_t)sl * N * NR + (row - sl * NR);
   }
-  __device__ int64_t akoff(const Tile& t, int k) const {
-    const int sg = k / t.KU, u = k - sg * t.KU;
-    return (int64_t)sg * nRmax * N * NR + (int64_t)kmap[t.km0 + u] * NR;
+  __device__ int64_t akoff(const Tile& t, int k, const int* ta) const {
+    const int sg = (int)t.fdKU.div((uint32_t)k), u = k - sg * t.KU;
+    return (int64_t)sg * nRmax * N * NR + ta[u];
   }
   __device__ const double* bbase(const Tile& t) const {
     return bp + (int64_t)t.tau * BPS + bp_off[t.p];
   }
-  __device__ int64_t bkoff(const Tile&, int k) const { return (int64_t)k * PC; }
+  __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PC; }
   __device__ double ascale(const Tile&, int) const { return 1.0; }
-  __device__ void store(const Tile& t, int r, int c, double v) const {
-    const int row = t.row0 + r;
-    const int64_t P = (int64_t)gc[g0 + row / NR] * NR + row % NR;
-    const int64_t Q = (int64_t)t.p * PC + c;
-    double* dst = chi + (int64_t)t.tau * NRI * NRI + P * NRI + Q;
-    *dst -= v;
+  // chi[tau][P][Q] -= tile, P = (RI atom of the row's slot, P), Q = panel column
+  __device__ double* obase(const Tile& t) const { return chi + (int64_t)t.tau * NRI * NRI; }
+  __device__ int64_t rowoff(const Tile& t, int r) const {
+    const int row = t.row0 + r, sl = (int)fdNR.div((uint32_t)row), P = row - sl * NR;
+    return ((int64_t)gc[g0 + sl] * NR + P) * NRI;
   }
-  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ int64_t coloff(const Tile& t, int c) const { return (int64_t)t.p * PC + c; }
+  static constexpr bool kAccum = true;
+  static constexpr double kSign = -1.0;
+  __device__ const double* dbase0(const Tile&) const { return nullptr; }
+  __device__ const double* dbase1(const Tile&) const { return nullptr; }
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
@@ -207,10 +257,10 @@ __global__ void gather_dvir_kernel(const double* __restrict__ dv, double* __rest
 template <int WM>
 hipError_t launch_stage_b(StageB sb, int n_groups, hipStream_t st) {
   sb.rows_pt = 32 * WM;
-  sb.cols_pt = 16 * B_NB;
+  sb.cols_pt = AB_COLS;
   sb.n_rt = (sb.RS + sb.rows_pt - 1) / sb.rows_pt;
   sb.n_ct = (sb.NA * sb.NR + sb.cols_pt - 1) / sb.cols_pt;
-  return launch_tile_gemm<WM, B_NB>(sb, dim3((unsigned)(n_groups * sb.n_rt * sb.n_ct)), st);
+  return launch_tile_gemm<WM, AB_WN, AB_NBW, 16>(sb, dim3((unsigned)(n_groups * sb.n_rt * sb.n_ct)), st);
 }
 
 }  // namespace
@@ -231,7 +281,7 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   GW_CHECK_ARG(std::isfinite(eps_f) && eps_f >= 0.0, "filter_eps must be finite and >= 0");
   GW_CHECK_ARG(!opts || opts->prec == GW_FP64, "only GW_FP64 is supported");
   const int na = s->n_atoms, NA = s->ao_per_atom, NR = s->ri_per_atom;
-  GW_CHECK_ARG(NR <= 16 * C_NB, "ri_per_atom must be <= 160");
+  GW_CHECK_ARG(NR <= C_COLS, "ri_per_atom must be <= 160");
   const int N = na * NA, NRI = na * NR;
   const int64_t bs = (int64_t)NA * NA * NR;
   GW_CHECK_ARG((int64_t)n_tau * NA <= (1 << 20), "n_tau * ao_per_atom too large");
@@ -252,10 +302,14 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   for (int b = 0; b < na; ++b) nRmax = std::max(nRmax, gb_start[b + 1] - gb_start[b]);
 
   // ---- column panels of PG RI atoms; U_p = AO atoms coupling to the panel
-  const int PG = std::max(1, (16 * C_NB) / NR), PC = PG * NR;
+  const int PG = std::max(1, C_COLS / NR), PC = PG * NR;
   const Panels pan = build_panels(na, PG, PC, gcv, gs, NA, NA);
   const int n_pan = pan.n_pan;
   const int64_t BPS = pan.off[n_pan];
+  for (int g = 0; g < n_groups; ++g)
+    GW_CHECK_ARG(goff[g + 1] - goff[g] <= kSegTab, "too many bricks in one (atom, RI atom) group");
+  for (int p = 0; p < n_pan; ++p)
+    GW_CHECK_ARG(NA * pan.ulen[p] <= kPanTab, "too many AO atoms coupled to one RI column panel");
 
   // ---- scratch
   double *dof = nullptr, *dvf = nullptr, *dvg = nullptr, *mb = nullptr, *bp = nullptr;
@@ -289,22 +343,27 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   // ---- pivot loop
   StageA sa{};
   sa.dof = dof; sa.t3c = s->t3c; sa.mb = mb; sa.goff = d_goff; sa.seg_atom = d_seg_atom;
-  sa.seg_brick = d_seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = 16 * A_NB;
+  sa.seg_brick = d_seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = AB_COLS;
   sa.n_rt = (N + sa.rows_pt - 1) / sa.rows_pt;
   sa.n_ct = (NA * NR + sa.cols_pt - 1) / sa.cols_pt;
   sa.N = N; sa.NA = NA; sa.NR = NR; sa.nRmax = std::max(nRmax, 1); sa.bs = bs;
+  sa.fdNA.set((uint32_t)NA);
+  sa.fdNR.set((uint32_t)NR);
 
   StageB sb{};
   sb.dvg = dvg; sb.t3c = s->t3c; sb.bp = bp; sb.goff = d_goff; sb.seg_atom = d_seg_atom;
   sb.seg_brick = d_seg_brick; sb.gc = d_gc; sb.gslot = d_gslot; sb.ulen = d_ulen;
   sb.bp_off = d_bp_off; sb.RS = RS; sb.NA = NA; sb.NR = NR; sb.PG = PG; sb.PC = PC; sb.bs = bs;
   sb.BPS = BPS;
+  sb.fdNA.set((uint32_t)NA);
+  sb.fdNR.set((uint32_t)NR);
 
   StageC scx{};
   scx.mb = mb; scx.bp = bp; scx.chi = chi; scx.gc = d_gc; scx.kmap = d_kmap; scx.km_off = d_km_off;
   scx.ulen = d_ulen; scx.bp_off = d_bp_off; scx.rows_pt = 32 * C_WM; scx.N = N; scx.NA = NA;
   scx.NR = NR; scx.NRI = NRI; scx.PG = PG; scx.PC = PC; scx.nRmax = std::max(nRmax, 1);
   scx.n_atoms = na; scx.BPS = BPS;
+  scx.fdNR.set((uint32_t)NR);
 
   double flops_ab = 0.0, flops_c = 0.0, flops_a = 0.0, flops_b = 0.0;
   const bool timing = opts && opts->timing;
@@ -343,7 +402,7 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
     }
     sa.g0 = g0;
     GW_HIP(mark());
-    GW_HIP((launch_tile_gemm<A_WM, A_NB>(sa, dim3((unsigned)(nR * sa.n_rt * sa.n_ct), n_tau), st)));
+    GW_HIP((launch_tile_gemm<A_WM, AB_WN, AB_NBW, 16>(sa, dim3((unsigned)(nR * sa.n_rt * sa.n_ct), n_tau), st)));
     GW_HIP(mark());
     hipError_t e;
     if (RS <= 64) e = launch_stage_b<2>(sb, n_groups, st);
@@ -356,7 +415,7 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
     scx.g0 = g0;
     scx.nR = nR;
     scx.n_rt = (nR * NR + scx.rows_pt - 1) / scx.rows_pt;
-    GW_HIP((launch_tile_gemm<C_WM, C_NB>(scx, dim3((unsigned)(scx.n_rt * n_pan), 1, n_tau), st)));
+    GW_HIP((launch_tile_gemm<C_WM, C_WN, C_NBW, 16>(scx, dim3((unsigned)(scx.n_rt * n_pan), 1, n_tau), st)));
     GW_HIP(mark());
     n_launch[0]++; n_launch[1]++; n_launch[2]++;
 

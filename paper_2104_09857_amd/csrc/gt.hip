@@ -11,13 +11,15 @@
 namespace gw {
 namespace {
 
-constexpr int G_WM = 4, G_NB = 8;   // 128 x 128 tiles
+constexpr int G_WM = 4, G_WN = 2, G_NBW = 4;   // 128 x 128 tiles, 8 waves
+constexpr int G_COLS = 16 * G_NBW * G_WN;
 
 struct GtProblem {
   struct Tile : TileBase {
     int row0, col0, tau, branch;
   };
   static constexpr bool kAScale = true, kDot = false;
+  static constexpr int kTabA = 0, kTabB = 0;
   const double* C;
   const double* w;          // [2][n_tau][n_ao] weights (zeros beyond the branch's K)
   double* out[2];
@@ -25,13 +27,13 @@ struct GtProblem {
 
   __device__ bool tile(int bx, int by, int bz, Tile& t) const {
     t.row0 = (bx % n_rt) * 32 * G_WM;
-    t.col0 = (bx / n_rt) * 16 * G_NB;
+    t.col0 = (bx / n_rt) * G_COLS;
     t.tau = by;
     t.branch = bz;
     if (out[bz] == nullptr) return false;
     t.K = bz == 0 ? n_occ : N - n_occ;
     t.rows = min(32 * G_WM, N - t.row0);
-    t.cols = min(16 * G_NB, N - t.col0);
+    t.cols = min(G_COLS, N - t.col0);
     return t.rows > 0 && t.cols > 0;
   }
   __device__ const double* kbase(const Tile& t) const {
@@ -39,16 +41,22 @@ struct GtProblem {
   }
   __device__ const double* abase(const Tile& t) const { return kbase(t) + t.row0; }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile&, int k) const { return (int64_t)k * N; }
+  __device__ void fill(const Tile&, int*, int*, int, int) const {}
+  __device__ int64_t akoff(const Tile&, int k, const int*) const { return (int64_t)k * N; }
   __device__ double ascale(const Tile& t, int k) const {
     return w[((int64_t)t.branch * n_tau + t.tau) * N + k];
   }
   __device__ const double* bbase(const Tile& t) const { return kbase(t) + t.col0; }
-  __device__ int64_t bkoff(const Tile&, int k) const { return (int64_t)k * N; }
-  __device__ void store(const Tile& t, int r, int c, double v) const {
-    out[t.branch][(int64_t)t.tau * N * N + (int64_t)(t.row0 + r) * N + t.col0 + c] = v;
+  __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * N; }
+  __device__ double* obase(const Tile& t) const {
+    return out[t.branch] + (int64_t)t.tau * N * N + (int64_t)t.row0 * N + t.col0;
   }
-  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ int64_t rowoff(const Tile&, int r) const { return (int64_t)r * N; }
+  __device__ int64_t coloff(const Tile&, int c) const { return c; }
+  static constexpr bool kAccum = false;
+  static constexpr double kSign = 1.0;
+  __device__ const double* dbase0(const Tile&) const { return nullptr; }
+  __device__ const double* dbase1(const Tile&) const { return nullptr; }
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
@@ -97,7 +105,7 @@ extern "C" gw_status gw_build_gt(const gw_system* s, const double* C, const doub
   p.n_occ = s->n_occ;
   p.n_tau = n_tau;
   p.n_rt = (N + 32 * G_WM - 1) / (32 * G_WM);
-  const int n_ct = (N + 16 * G_NB - 1) / (16 * G_NB);
-  GW_HIP((launch_tile_gemm<G_WM, G_NB>(p, dim3((unsigned)(p.n_rt * n_ct), n_tau, 2), st)));
+  const int n_ct = (N + G_COLS - 1) / (G_COLS);
+  GW_HIP((launch_tile_gemm<G_WM, G_WN, G_NBW, 16>(p, dim3((unsigned)(p.n_rt * n_ct), n_tau, 2), st)));
   return GW_OK;
 }

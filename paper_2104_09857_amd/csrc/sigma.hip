@@ -18,14 +18,19 @@
 namespace gw {
 namespace {
 
-constexpr int H_NB = 11;            // half transform: rows n_gw (32*WM), cols 176
-constexpr int Z_WM = 4, Z_NB = 10;  // W product / dot: 128 x 160 tiles
+constexpr int H_WN = 2, H_NBW = 6;  // half transform: rows n_gw (32*WM), cols 192
+constexpr int Z_WM = 4, Z_WN = 2, Z_NBW = 5;   // W product / dot: 128 x 160 tiles, 8 waves
+constexpr int Z_COLS = 16 * Z_NBW * Z_WN;
+
+constexpr int kSegTab = 2048;     // max bricks per group
+constexpr int kPanTab = 8192;     // max K functions per AO column panel (NR * |U_q|)
 
 struct HalfProblem {
   struct Tile : TileBase {
-    int g, row0, col0, seg0, q, al, slot;
+    int g, row0, col0, seg0, nseg, q, al, slot;
   };
   static constexpr bool kAScale = false, kDot = false;
+  static constexpr int kTabA = kSegTab, kTabB = kSegTab;
   const double* cg;         // [N][RS], RS = n_gw
   const double* t3c;
   double* fp;
@@ -38,6 +43,7 @@ struct HalfProblem {
   int n_rt, n_ct, rows_pt, cols_pt;
   int RS, NA, NR, PGa, PCa;
   int64_t bs, FPS;
+  FastDiv fdNA, fdNR;
 
   __device__ bool tile(int bx, int, int, Tile& t) const {
     const int per = n_rt * n_ct;
@@ -46,7 +52,8 @@ struct HalfProblem {
     t.row0 = (rem % n_rt) * rows_pt;
     t.col0 = (rem / n_rt) * cols_pt;
     t.seg0 = goff[t.g];
-    t.K = NA * (goff[t.g + 1] - t.seg0);
+    t.nseg = goff[t.g + 1] - t.seg0;
+    t.K = NA * t.nseg;
     const int sa = gs[t.g];
     t.q = sa / PGa;
     t.al = sa % PGa;
@@ -55,22 +62,35 @@ struct HalfProblem {
     t.cols = min(cols_pt, NA * NR - t.col0);
     return t.rows > 0 && t.cols > 0;
   }
+  __device__ void fill(const Tile& t, int* ta, int* tb, int tid, int nt) const {
+    for (int i = tid; i < t.nseg; i += nt) {
+      ta[i] = seg_atom[t.seg0 + i];
+      tb[i] = (int)seg_brick[t.seg0 + i];
+    }
+  }
   __device__ const double* abase(const Tile& t) const { return cg + t.row0; }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile& t, int k) const {
-    return (int64_t)(seg_atom[t.seg0 + k / NA] * NA + k % NA) * RS;
+  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
+    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
+    return (int64_t)(ta[sg] * NA + i) * RS;
   }
   __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
-  __device__ int64_t bkoff(const Tile& t, int k) const {
-    return seg_brick[t.seg0 + k / NA] * bs + (int64_t)(k % NA) * NA * NR;
+  __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
+    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
+    return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
   }
   __device__ double ascale(const Tile&, int) const { return 1.0; }
-  __device__ void store(const Tile& t, int r, int c, double v) const {
-    const int n = t.row0 + r, col = t.col0 + c;
-    const int mul = col / NR, P = col % NR;
-    fp[(int64_t)n * FPS + poff[t.q] + (int64_t)(t.slot * NR + P) * PCa + t.al * NA + mul] = v;
+  // Fp[n][panel q][(slot, P)][(al, mu)]: row n, column (mu, P)
+  __device__ double* obase(const Tile& t) const { return fp + poff[t.q] + t.al * NA; }
+  __device__ int64_t rowoff(const Tile& t, int r) const { return (int64_t)(t.row0 + r) * FPS; }
+  __device__ int64_t coloff(const Tile& t, int c) const {
+    const int col = t.col0 + c, mul = (int)fdNR.div((uint32_t)col), P = col - mul * NR;
+    return (int64_t)(t.slot * NR + P) * PCa + mul;
   }
-  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  static constexpr bool kAccum = false;
+  static constexpr double kSign = 1.0;
+  __device__ const double* dbase0(const Tile&) const { return nullptr; }
+  __device__ const double* dbase1(const Tile&) const { return nullptr; }
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
@@ -80,6 +100,7 @@ struct ZProblem {
     int row0, q, n, km0;
   };
   static constexpr bool kAScale = false, kDot = false;
+  static constexpr int kTabA = kPanTab, kTabB = 0;
   const double* w;          // [NRI][NRI] symmetric
   const double* fp;
   double* z;                // [n_gw][NRI][N]
@@ -100,16 +121,24 @@ struct ZProblem {
     t.km0 = km_off[t.q];
     return t.rows > 0 && t.cols > 0 && t.K > 0;
   }
+  __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
+    for (int i = tid; i < t.K; i += nt) ta[i] = kmap[t.km0 + i];
+  }
   __device__ const double* abase(const Tile& t) const { return w + t.row0; }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile& t, int k) const { return (int64_t)kmap[t.km0 + k] * NRI; }
+  __device__ int64_t akoff(const Tile&, int k, const int* ta) const { return (int64_t)ta[k] * NRI; }
   __device__ const double* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
-  __device__ int64_t bkoff(const Tile&, int k) const { return (int64_t)k * PCa; }
+  __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PCa; }
   __device__ double ascale(const Tile&, int) const { return 1.0; }
-  __device__ void store(const Tile& t, int r, int c, double v) const {
-    z[((int64_t)t.n * NRI + t.row0 + r) * N + (int64_t)t.q * PCa + c] = v;
+  __device__ double* obase(const Tile& t) const {
+    return z + ((int64_t)t.n * NRI + t.row0) * N + (int64_t)t.q * PCa;
   }
-  __device__ void dot(const Tile&, int, int, double, double&, double&) const {}
+  __device__ int64_t rowoff(const Tile&, int r) const { return (int64_t)r * N; }
+  __device__ int64_t coloff(const Tile&, int c) const { return c; }
+  static constexpr bool kAccum = false;
+  static constexpr double kSign = 1.0;
+  __device__ const double* dbase0(const Tile&) const { return nullptr; }
+  __device__ const double* dbase1(const Tile&) const { return nullptr; }
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
@@ -119,6 +148,7 @@ struct DotProblem {
     int row0, q, n, km0, tile_id;
   };
   static constexpr bool kAScale = false, kDot = true;
+  static constexpr int kTabA = kPanTab, kTabB = 0;
   const double* z;
   const double* fp;
   const double* d0;         // [N][N]
@@ -153,17 +183,21 @@ struct DotProblem {
   __device__ const double* abase(const Tile& t) const {
     return z + (int64_t)t.n * NRI * N + t.row0;
   }
-  __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile& t, int k) const { return (int64_t)kmap[t.km0 + k] * N; }
-  __device__ const double* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
-  __device__ int64_t bkoff(const Tile&, int k) const { return (int64_t)k * PCa; }
-  __device__ double ascale(const Tile&, int) const { return 1.0; }
-  __device__ void store(const Tile&, int, int, double) const {}
-  __device__ void dot(const Tile& t, int r, int c, double v, double& s0, double& s1) const {
-    const int64_t e = (int64_t)(t.row0 + r) * N + (int64_t)t.q * PCa + c;
-    s0 += v * d0[e];
-    s1 += v * d1[e];
+  __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
+    for (int i = tid; i < t.K; i += nt) ta[i] = kmap[t.km0 + i];
   }
+  __device__ int64_t aroff(const Tile&, int r) const { return r; }
+  __device__ int64_t akoff(const Tile&, int k, const int* ta) const { return (int64_t)ta[k] * N; }
+  __device__ const double* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
+  __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PCa; }
+  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ double* obase(const Tile&) const { return nullptr; }
+  __device__ const double* dbase0(const Tile& t) const { return d0 + (int64_t)t.row0 * N + (int64_t)t.q * PCa; }
+  __device__ const double* dbase1(const Tile& t) const { return d1 + (int64_t)t.row0 * N + (int64_t)t.q * PCa; }
+  __device__ int64_t rowoff(const Tile&, int r) const { return (int64_t)r * N; }
+  __device__ int64_t coloff(const Tile&, int c) const { return c; }
+  static constexpr bool kAccum = false;
+  static constexpr double kSign = 1.0;
   __device__ void dot_out(const Tile& t, double s0, double s1) const {
     partial[((int64_t)t.n * n_tiles + t.tile_id) * 2] = s0;
     partial[((int64_t)t.n * n_tiles + t.tile_id) * 2 + 1] = s1;
@@ -183,10 +217,10 @@ __global__ void gather_rows_kernel(const double* __restrict__ C, const int32_t* 
 template <int WM>
 hipError_t launch_half(HalfProblem hp, int n_groups, hipStream_t st) {
   hp.rows_pt = 32 * WM;
-  hp.cols_pt = 16 * H_NB;
+  hp.cols_pt = 16 * H_NBW * H_WN;
   hp.n_rt = (hp.RS + hp.rows_pt - 1) / hp.rows_pt;
   hp.n_ct = (hp.NA * hp.NR + hp.cols_pt - 1) / hp.cols_pt;
-  return launch_tile_gemm<WM, H_NB>(hp, dim3((unsigned)(n_groups * hp.n_rt * hp.n_ct)), st);
+  return launch_tile_gemm<WM, H_WN, H_NBW, 16>(hp, dim3((unsigned)(n_groups * hp.n_rt * hp.n_ct)), st);
 }
 
 }  // namespace
@@ -213,7 +247,7 @@ extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const i
   GW_CHECK_ARG(sig_occ && sig_vir && sig_x, "null output pointer");
   GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
   GW_CHECK_ARG(std::isfinite(filter_eps) && filter_eps >= 0.0, "filter_eps must be finite and >= 0");
-  GW_CHECK_ARG(NA <= 16 * Z_NB, "ao_per_atom must be <= 160");
+  GW_CHECK_ARG(NA <= Z_COLS, "ao_per_atom must be <= 160");
   if (stats) *stats = gw_sigma_stats{};
 
   Scratch sc(st);
@@ -223,10 +257,14 @@ extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const i
   const int64_t bs = (int64_t)NA * NA * NR;
 
   // AO column panels (mu atoms); K atoms = RI atoms coupled through a kept brick
-  const int PGa = std::max(1, (16 * Z_NB) / NA), PCa = PGa * NA;
+  const int PGa = std::max(1, (Z_COLS) / NA), PCa = PGa * NA;
   const Panels pan = build_panels(na, PGa, PCa, G.gs, G.gc, NR, 1);
   const int n_pan = pan.n_pan;
   const int64_t FPS = pan.off[n_pan];
+  for (int g = 0; g < n_groups; ++g)
+    GW_CHECK_ARG(G.goff[g + 1] - G.goff[g] <= kSegTab, "too many bricks in one (atom, RI atom) group");
+  for (int q = 0; q < n_pan; ++q)
+    GW_CHECK_ARG(NR * pan.ulen[q] <= kPanTab, "too many RI atoms coupled to one AO column panel");
 
   double *dof, *dvf, *d0f, *cg, *fp, *z, *partial;
   int32_t* d_states;
@@ -274,6 +312,8 @@ extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const i
     hp.cg = cg; hp.t3c = s->t3c; hp.fp = fp; hp.goff = d_goff; hp.seg_atom = d_seg_atom;
     hp.seg_brick = d_seg_brick; hp.gs = d_gs; hp.gslot = d_gslot; hp.poff = d_poff;
     hp.RS = n_gw; hp.NA = NA; hp.NR = NR; hp.PGa = PGa; hp.PCa = PCa; hp.bs = bs; hp.FPS = FPS;
+    hp.fdNA.set((uint32_t)NA);
+    hp.fdNR.set((uint32_t)NR);
     hipError_t e = n_gw <= 64 ? launch_half<2>(hp, n_groups, st) : launch_half<4>(hp, n_groups, st);
     GW_HIP(e);
   }
@@ -290,11 +330,11 @@ extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const i
   for (int j = 0; j < n_slots; ++j) {
     const bool xslot = (j == n_tau);
     zp.w = xslot ? V : wc + (int64_t)j * NRI * NRI;
-    GW_HIP((launch_tile_gemm<Z_WM, Z_NB>(zp, dim3((unsigned)(z_rt * n_pan), 1, n_gw), st)));
+    GW_HIP((launch_tile_gemm<Z_WM, Z_WN, Z_NBW, 16>(zp, dim3((unsigned)(z_rt * n_pan), 1, n_gw), st)));
     dp.d0 = xslot ? d0f : dof + (int64_t)j * N * N;
     dp.d1 = xslot ? d0f : dvf + (int64_t)j * N * N;
     dp.partial = partial + (size_t)j * n_gw * n_tiles * 2;
-    GW_HIP((launch_tile_gemm<Z_WM, Z_NB>(dp, dim3((unsigned)n_tiles, 1, n_gw), st)));
+    GW_HIP((launch_tile_gemm<Z_WM, Z_WN, Z_NBW, 16>(dp, dim3((unsigned)n_tiles, 1, n_gw), st)));
   }
 
   std::vector<double> hp((size_t)n_slots * n_gw * n_tiles * 2);

@@ -9,16 +9,24 @@
 // opposite LDS bank halves).  The next chunk is prefetched into registers
 // while the current one feeds the matrix cores.
 //
-// A problem type P supplies the index maps (all offsets in doubles):
-//   bool   tile(bx, by, bz, Tile&)   fills rows/cols/K; false = skip tile
-//   const double* abase(t), int64_t aroff(t, r), int64_t akoff(t, k)
-//   const double* bbase(t), int64_t bkoff(t, k)
-//   double ascale(t, k)             (only if P::kAScale)
-//   void   store(t, r, c, v)        (kDot == false) or
-//   void dot(t, r, c, v, s0&, s1&), void dot_out(t, s0, s1)   (kDot == true):
-//   two weighted sums of the tile instead of a store
+// Index maps come from the problem type P (offsets in doubles):
+//   bool tile(bx, by, bz, Tile&)        rows/cols/K of the tile; false = skip
+//   void fill(const Tile&, int* ta, int* tb, tid, nthreads)
+//                                       per-tile int tables in LDS (P::kTabA /
+//                                       P::kTabB entries) read by the maps below
+//   const double* abase(t), int64 aroff(t, r), int64 akoff(t, k, ta)
+//   const double* bbase(t), int64 bkoff(t, k, tb)
+//   double ascale(t, k)                 (only if P::kAScale)
 // so A(r, k) = abase[aroff(r) + akoff(k)] (* ascale(k)) and
-// B(k, c) = bbase[bkoff(k) + c]; entries outside rows/cols/K read as zero.
+// B(k, c) = bbase[bkoff(k) + c]; entries outside rows/cols/K read as zero
+// (branch-free: out-of-range lanes load element 0 and discard it).
+// Output offsets are separable, out(r, c) at rowoff(t, r) + coloff(t, c):
+//   kDot == false: double* obase(t); the tile is stored (kAccum == false) or
+//                  added with factor kSign to what is there (kAccum == true)
+//   kDot == true:  const double* dbase0(t), dbase1(t); the tile is reduced to
+//                  s0 = sum C * D0, s1 = sum C * D1, passed to dot_out(t, s0, s1)
+// The LDS tables replace dependent global loads of the index arrays, and
+// divisions by per-tile extents use FastDiv (multiply-high).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,67 +35,102 @@ namespace gw {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int KC = 16;
-
 __host__ __device__ constexpr int lds_stride(int n) { return n + (16 - n % 32 + 32) % 32; }
+
+// q = k / d for k * d < 2^32 (the hosts that size K check this)
+struct FastDiv {
+  uint64_t m;   // ceil(2^32 / d), 2^32 for d = 1
+  __host__ __device__ void set(uint32_t d) { m = (0x100000000ull + d - 1) / d; }
+  __device__ __forceinline__ uint32_t div(uint32_t k) const { return (uint32_t)(((uint64_t)k * m) >> 32); }
+};
 
 struct TileBase {
   int rows, cols, K;
 };
 
-template <int WM, int NB, class P>
-__global__ __launch_bounds__(64 * WM) void tile_gemm_kernel(P p) {
-  constexpr int ROWS = 32 * WM, COLS = 16 * NB, NT = 64 * WM;
+template <int WM, int WN, int NB, int KC, class P>
+__global__ __launch_bounds__(64 * WM * WN) void tile_gemm_kernel(P p) {
+  constexpr int ROWS = 32 * WM, COLS = 16 * NB * WN, NT = 64 * WM * WN;
   constexpr int AST = lds_stride(ROWS), BST = lds_stride(COLS);
-  constexpr int APT = KC * ROWS / NT;                 // = 8
+  constexpr int KSTEP = NT / ROWS;                    // k rows of A per pass of the threads
+  constexpr int APT = KC / KSTEP;
   constexpr int BPT = (KC * COLS + NT - 1) / NT;
+  static_assert(NT % ROWS == 0 && KC % KSTEP == 0, "A staging layout");
   __shared__ double As[KC * AST];
   __shared__ double Bs[KC * BST];
+  __shared__ int tabA[P::kTabA > 0 ? P::kTabA : 1];
+  __shared__ int tabB[P::kTabB > 0 ? P::kTabB : 1];
 
   typename P::Tile t;
   if (!p.tile(blockIdx.x, blockIdx.y, blockIdx.z, t)) return;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  p.fill(t, tabA, tabB, tid, NT);
+  __syncthreads();
   const double* __restrict__ abase = p.abase(t);
   const double* __restrict__ bbase = p.bbase(t);
 
-  // this thread's A row is fixed: r = tid % ROWS, k = tid / ROWS + 2 i
+  // this thread's A row is fixed: r = tid % ROWS, k = tid / ROWS + KSTEP i
   const int ar = tid % ROWS;
   const bool arow_ok = ar < t.rows;
   const int64_t aro = arow_ok ? p.aroff(t, ar) : 0;
   const int ak0 = tid / ROWS;
 
   double ra[APT], rbv[BPT];
+  double ascl[P::kAScale ? APT : 1];
+  uint32_t amask = 0u, bmask = 0u;
+  const int kmax = t.K - 1;
   auto load = [&](int k0) {
+    // offsets for a clamped k first (no branches, table reads batched), then the loads
+    int64_t aoff[APT], boff[BPT];
 #pragma unroll
     for (int i = 0; i < APT; ++i) {
-      const int k = k0 + ak0 + 2 * i;
-      double v = 0.0;
-      if (arow_ok && k < t.K) {
-        v = abase[aro + p.akoff(t, k)];
-        if constexpr (P::kAScale) v *= p.ascale(t, k);
-      }
-      ra[i] = v;
+      const int k = k0 + ak0 + KSTEP * i;
+      aoff[i] = p.akoff(t, k < kmax ? k : kmax, tabA);
+    }
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+      const int e = tid + i * NT;
+      const int kl = e / COLS;
+      const int k = k0 + (kl < KC ? kl : KC - 1);
+      boff[i] = p.bkoff(t, k < kmax ? k : kmax, tabB);
+    }
+    // raw values now; out-of-range entries are zeroed at stash time so that
+    // nothing waits on these loads before the matrix-core work of this chunk
+    amask = 0u;
+    bmask = 0u;
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+      const int k = k0 + ak0 + KSTEP * i;
+      const bool ok = arow_ok && k < t.K;
+      amask |= ok ? (1u << i) : 0u;
+      ra[i] = abase[ok ? aro + aoff[i] : 0];
+      if constexpr (P::kAScale) ascl[i] = p.ascale(t, k < kmax ? k : kmax);
     }
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
       const int e = tid + i * NT;
       const int c = e % COLS, kl = e / COLS;
       const int k = k0 + kl;
-      double v = 0.0;
-      if (kl < KC && c < t.cols && k < t.K) v = bbase[p.bkoff(t, k) + c];
-      rbv[i] = v;
+      const bool ok = kl < KC && c < t.cols && k < t.K;
+      bmask |= ok ? (1u << i) : 0u;
+      rbv[i] = bbase[ok ? boff[i] + c : 0];
     }
   };
   auto stash = [&]() {
 #pragma unroll
-    for (int i = 0; i < APT; ++i) As[(ak0 + 2 * i) * AST + ar] = ra[i];
+    for (int i = 0; i < APT; ++i) {
+      double v = ra[i];
+      if constexpr (P::kAScale) v *= ascl[i];
+      As[(ak0 + KSTEP * i) * AST + ar] = ((amask >> i) & 1u) ? v : 0.0;
+    }
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
       const int e = tid + i * NT;
       const int c = e % COLS, kl = e / COLS;
-      if (kl < KC) Bs[kl * BST + c] = rbv[i];
+      if (kl < KC) Bs[kl * BST + c] = ((bmask >> i) & 1u) ? rbv[i] : 0.0;
     }
   };
 
@@ -107,11 +150,11 @@ __global__ __launch_bounds__(64 * WM) void tile_gemm_kernel(P p) {
 #pragma unroll
     for (int kk = 0; kk < KC / 4; ++kk) {
       const int krow = 4 * kk + lk;
-      const double a0 = As[krow * AST + wave * 32 + lr];
-      const double a1 = As[krow * AST + wave * 32 + 16 + lr];
+      const double a0 = As[krow * AST + wm * 32 + lr];
+      const double a1 = As[krow * AST + wm * 32 + 16 + lr];
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
-        const double b = Bs[krow * BST + cb * 16 + lr];
+        const double b = Bs[krow * BST + (wn * NB + cb) * 16 + lr];
         acc[0][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][cb], 0, 0, 0);
         acc[1][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][cb], 0, 0, 0);
       }
@@ -125,56 +168,90 @@ __global__ __launch_bounds__(64 * WM) void tile_gemm_kernel(P p) {
 
   // D layout of the 16x16x4 f64 MFMA on gfx950 (measured): lane l, element i
   // -> row 4*i + l/16, col l%16
+  int64_t ro[2][4];
+  bool rv[2][4];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm * 32 + rb * 16 + 4 * i + lk;
+      rv[rb][i] = r < t.rows;
+      ro[rb][i] = rv[rb][i] ? p.rowoff(t, r) : 0;
+    }
   if constexpr (!P::kDot) {
+    double* __restrict__ ob = p.obase(t);
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int cb = 0; cb < NB; ++cb) {
+      const int c = (wn * NB + cb) * 16 + lr;
+      const bool cv = c < t.cols;
+      const int64_t co = cv ? p.coloff(t, c) : 0;
+      if constexpr (P::kAccum) {
+        double old[2][4];
 #pragma unroll
-      for (int cb = 0; cb < NB; ++cb)
+        for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = wave * 32 + rb * 16 + 4 * i + lk;
-          const int c = cb * 16 + lr;
-          if (r < t.rows && c < t.cols) p.store(t, r, c, acc[rb][cb][i]);
-        }
+          for (int i = 0; i < 4; ++i) old[rb][i] = ob[(rv[rb][i] && cv) ? ro[rb][i] + co : 0];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (rv[rb][i] && cv) ob[ro[rb][i] + co] = old[rb][i] + P::kSign * acc[rb][cb][i];
+      } else {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (rv[rb][i] && cv) ob[ro[rb][i] + co] = acc[rb][cb][i];
+      }
+    }
   } else {
+    const double* __restrict__ d0 = p.dbase0(t);
+    const double* __restrict__ d1 = p.dbase1(t);
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int cb = 0; cb < NB; ++cb) {
+      const int c = (wn * NB + cb) * 16 + lr;
+      const bool cv = c < t.cols;
+      const int64_t co = cv ? p.coloff(t, c) : 0;
 #pragma unroll
-      for (int cb = 0; cb < NB; ++cb)
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int r = wave * 32 + rb * 16 + 4 * i + lk;
-          const int c = cb * 16 + lr;
-          if (r < t.rows && c < t.cols) p.dot(t, r, c, acc[rb][cb][i], s0, s1);
+          const bool ok = rv[rb][i] && cv;
+          const int64_t e = ok ? ro[rb][i] + co : 0;
+          const double x0 = d0[e], x1 = d1[e];
+          s0 += ok ? acc[rb][cb][i] * x0 : 0.0;
+          s1 += ok ? acc[rb][cb][i] * x1 : 0.0;
         }
+    }
     // fixed-order block reduction (deterministic)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       s0 += __shfl_xor(s0, off, 64);
       s1 += __shfl_xor(s1, off, 64);
     }
-    __shared__ double red[2 * WM];
+    constexpr int NW = WM * WN;
+    __shared__ double red[2 * NW];
     if (lane == 0) {
       red[wave] = s0;
-      red[WM + wave] = s1;
+      red[NW + wave] = s1;
     }
     __syncthreads();
     if (tid == 0) {
       double t0 = 0.0, t1 = 0.0;
-      for (int w = 0; w < WM; ++w) {
+      for (int w = 0; w < NW; ++w) {
         t0 += red[w];
-        t1 += red[WM + w];
+        t1 += red[NW + w];
       }
       p.dot_out(t, t0, t1);
     }
   }
 }
 
-template <int WM, int NB, class P>
+template <int WM, int WN, int NB, int KC, class P>
 inline hipError_t launch_tile_gemm(const P& p, dim3 grid, hipStream_t st) {
   if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
-  hipLaunchKernelGGL((tile_gemm_kernel<WM, NB, P>), grid, dim3(64 * WM), 0, st, p);
+  hipLaunchKernelGGL((tile_gemm_kernel<WM, WN, NB, KC, P>), grid, dim3(64 * WM * WN), 0, st, p);
   return hipGetLastError();
 }
 
