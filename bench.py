@@ -56,12 +56,12 @@ def setup(name, seed=0):
     return dict(w=w, s=s, C=C, eps=eps, g=g, mu=mu, trip=trip, sys=sysd, Cd=Cd, V=V, t3c=t3c)
 
 
-def step(ctx):
+def step(ctx, prec="fp64"):
     from paper_2104_09857_amd import pipeline
     g = ctx["g"]
     return pipeline.g0w0(ctx["sys"], ctx["Cd"], ctx["eps"], ctx["mu"], ctx["V"], g.tau, g.omega,
                          g.cos_w, g.sin_w, g.icos_w, ctx["w"].states(), ctx["s"].filter_eps,
-                         events=True, chi_timing=True)
+                         events=True, chi_timing=True, prec=prec)
 
 
 def cpu_baseline(ctx, out, budget_s=20.0):
@@ -118,6 +118,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="strip300")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "bf16x3"],
+                    help="arithmetic of the timed chi contraction")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the extra untimed run of the other precision form")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -129,7 +133,7 @@ def main():
     ctx = setup(args.workload)
     for i in range(args.warmup):
         t0 = time.perf_counter()
-        step(ctx)
+        step(ctx, args.prec)
         torch.cuda.synchronize()
         log(f"[warmup {i}] {time.perf_counter() - t0:.2f} s")
     torch.cuda.synchronize()
@@ -137,7 +141,7 @@ def main():
     outs = []
     for i in range(args.steps):
         ts = time.perf_counter()
-        outs.append(step(ctx))
+        outs.append(step(ctx, args.prec))
         log(f"[step {i}] {time.perf_counter() - ts:.2f} s stages(ms) "
             + json.dumps({k: round(v, 1) for k, v in outs[-1]['ms'].items()}))
     torch.cuda.synchronize()
@@ -164,7 +168,9 @@ def main():
     res = {
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "bf16x3 (fp32 accumulate, fp64 across tiles)",
+        "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": s.n_atoms, "n_ao": s.n_ao, "n_ri": s.n_ri,
                    "n_occ": s.n_occ, "n_tau": ctx["w"].n_tau, "filter_eps": s.filter_eps,
                    "n_gw": len(ctx["w"].states()), "n_trip": int(len(ctx["trip"])),
@@ -172,12 +178,36 @@ def main():
         "time_to_qp_s": wall / args.steps,
         "stage_ms": {k: round(v, 2) for k, v in out["ms"].items()},
         "flops": {"chi_ab": cs["flops_ab"], "chi_c": cs["flops_c"], "sigma": ss["flops"]},
+        "chi_stage": {"names": ["A (D^occ half)", "B (D^vir half)", "C (outer)"],
+                      "ms": [round(x, 1) for x in cs["ms_stage"]],
+                      "tflops": [f / (m / 1e3) / 1e12 if m > 0 else None
+                                 for f, m in zip(cs["flops_stage"], cs["ms_stage"])],
+                      "launches": list(cs["n_launch"])},
         "e_qp": [float(x) for x in out["e_qp"]], "qp_status": [int(x) for x in out["status"]],
-        "roofline": {"kernel": "tile_gemm_kernel<4,2,5,16,StageC> (chi outer contraction)",
+        "roofline": {"kernel": "tile_gemm_kernel<4,2,5,32,StageC> (chi outer contraction)",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
                      "traffic": traffic, "launches": int(c_n), "avg_launch_ms": per_launch_ms},
     }
+    if not args.no_compare:
+        other = "bf16x3" if args.prec == "fp64" else "fp64"
+        t1 = time.perf_counter()
+        o2 = step(ctx, other)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter() - t1
+        e64, e2 = (out, o2) if args.prec == "fp64" else (o2, out)
+        ok = (e64["status"] == 0) & (e2["status"] == 0)
+        de = np.abs(e2["e_qp"] - e64["e_qp"])[ok] * 27211.386245988 if args.prec == "fp64" else \
+            np.abs(out["e_qp"] - o2["e_qp"])[ok] * 27211.386245988
+        chi64 = (out if args.prec == "fp64" else o2)["ms"]["chi"]
+        chibf = (o2 if args.prec == "fp64" else out)["ms"]["chi"]
+        res["precision_form"] = {
+            "prec": "bf16x3", "chi_ms_fp64": chi64, "chi_ms_bf16x3": chibf,
+            "chi_speedup": chi64 / chibf,
+            "time_to_qp_s_other": t2, "other": other,
+            "max_abs_dE_meV_vs_fp64": float(de.max()) if de.size else None,
+            "dE_meV": [float(x) for x in de],
+            "status_bf16x3": [int(x) for x in (o2 if args.prec == "fp64" else out)["status"]]}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(ctx, out)
     print(json.dumps(res), flush=True)

@@ -52,7 +52,10 @@ enum {
   GW_ERR_BLAS = 6          /* rocBLAS / rocSOLVER returned an error          */
 };
 
-typedef enum { GW_FP64 = 0 } gw_prec;
+/* Arithmetic of the chi contraction: GW_FP64 (FP64 MFMA throughout) or
+ * GW_BF16X3 (operands split into bf16 hi + lo, three bf16 MFMA products with
+ * FP32 accumulation inside a tile, FP64 accumulation across tiles). */
+typedef enum { GW_FP64 = 0, GW_BF16X3 = 2 } gw_prec;
 
 /* One molecule / strip.  Atom-triple bricks (a, b, c) of the three-center
  * tensor (mu nu|P) (Eq. 4): mu on AO atom a, nu on AO atom b, P on RI atom c.
@@ -79,7 +82,7 @@ gw_status gw_build_gt(const gw_system *s, const double *C, const double *eps, do
                       hipStream_t stream);
 
 typedef struct {
-  int32_t prec;            /* gw_prec; only GW_FP64                           */
+  int32_t prec;            /* gw_prec                                         */
   double filter_eps;       /* atom-block filter (Frobenius norm), >= 0        */
   int32_t timing;          /* 1: time every stage launch with HIP events on
                               `stream` (fills ms_stage)                        */

@@ -20,6 +20,7 @@
 #include <numeric>
 
 #include "gw_internal.hpp"
+#include "tile_bf16x3.hpp"
 #include "tile_gemm.hpp"
 
 namespace gw {
@@ -29,6 +30,7 @@ constexpr int A_WM = 4, AB_WN = 2, AB_NBW = 6;    // stage A tile 128 x 192, 8 w
 constexpr int AB_COLS = 16 * AB_NBW * AB_WN;      // stage B tile (32 WM) x 192
 constexpr int C_WM = 4, C_WN = 2, C_NBW = 5;      // stage C tile 128 x 160, 8 waves
 constexpr int C_COLS = 16 * C_NBW * C_WN;
+constexpr int C_KC = 32;                          // K chunk staged per barrier pair
 
 constexpr int kSegTab = 2048;     // max bricks per group (first atoms)
 constexpr int kPanTab = 4096;     // max K functions per column panel (NA * |U_p|)
@@ -263,6 +265,8 @@ hipError_t launch_stage_b(StageB sb, int n_groups, hipStream_t st) {
   return launch_tile_gemm<WM, AB_WN, AB_NBW, 16>(sb, dim3((unsigned)(n_groups * sb.n_rt * sb.n_ct)), st);
 }
 
+#include "chi_bf16x3.inc"
+
 }  // namespace
 }  // namespace gw
 
@@ -279,7 +283,8 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
   const double eps_f = opts ? opts->filter_eps : 0.0;
   GW_CHECK_ARG(std::isfinite(eps_f) && eps_f >= 0.0, "filter_eps must be finite and >= 0");
-  GW_CHECK_ARG(!opts || opts->prec == GW_FP64, "only GW_FP64 is supported");
+  const int prec = opts ? opts->prec : GW_FP64;
+  GW_CHECK_ARG(prec == GW_FP64 || prec == GW_BF16X3, "prec must be GW_FP64 or GW_BF16X3");
   const int na = s->n_atoms, NA = s->ao_per_atom, NR = s->ri_per_atom;
   GW_CHECK_ARG(NR <= C_COLS, "ri_per_atom must be <= 160");
   const int N = na * NA, NRI = na * NR;
@@ -318,9 +323,12 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   const size_t dsz = (size_t)n_tau * N * N;
   if ((rc = sc.alloc(&dof, dsz)) != GW_OK) return rc;
   if ((rc = sc.alloc(&dvf, dsz)) != GW_OK) return rc;
-  if ((rc = sc.alloc(&dvg, (size_t)N * RS)) != GW_OK) return rc;
-  if ((rc = sc.alloc(&mb, (size_t)n_tau * NA * std::max(nRmax, 1) * N * NR)) != GW_OK) return rc;
-  if ((rc = sc.alloc(&bp, (size_t)n_tau * BPS)) != GW_OK) return rc;
+  const bool fp64 = prec == GW_FP64;
+  if (fp64) {
+    if ((rc = sc.alloc(&dvg, (size_t)N * RS)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&mb, (size_t)n_tau * NA * std::max(nRmax, 1) * N * NR)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&bp, (size_t)n_tau * BPS)) != GW_OK) return rc;
+  }
   const size_t nflag = (size_t)n_tau * na * na;
   if ((rc = sc.alloc(&dropped, 3 * nflag)) != GW_OK) return rc;
   int32_t *d_goff, *d_seg_atom, *d_gc, *d_gslot, *d_ulen, *d_kmap, *d_km_off;
@@ -334,7 +342,7 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   if ((rc = sc.upload(&d_kmap, pan.kmap)) != GW_OK) return rc;
   if ((rc = sc.upload(&d_km_off, pan.km_off)) != GW_OK) return rc;
   if ((rc = sc.upload(&d_bp_off, pan.off)) != GW_OK) return rc;
-  GW_HIP(hipMemsetAsync(bp, 0, sizeof(double) * (size_t)n_tau * BPS, st));
+  if (fp64) GW_HIP(hipMemsetAsync(bp, 0, sizeof(double) * (size_t)n_tau * BPS, st));
 
   // ---- D filter (copies)
   GW_HIP(filter_square_blocks(d_occ, dof, n_tau, na, NA, eps_f, dropped, st));
@@ -390,33 +398,107 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   std::vector<double> asuffix(na + 1, 0.0);   // sum_{c' >= c} |A(c')|
   for (int c = na - 1; c >= 0; --c) asuffix[c] = asuffix[c + 1] + acount[c];
 
+  // ---- split-precision form: operands as bf16 hi/lo pairs, FP32 accumulation
+  // within a tile, FP64 accumulation across pivots
+  uint16_t *th = nullptr, *tl = nullptr, *doh = nullptr, *dol = nullptr, *dvh = nullptr, *dvl = nullptr;
+  uint16_t *mh = nullptr, *ml = nullptr, *nh = nullptr, *nl = nullptr;
+  std::vector<int64_t> poffb(n_pan + 1, 0);
+  for (int p = 0; p < n_pan; ++p) poffb[p + 1] = poffb[p] + (int64_t)NA * pan.ulen[p] * PC * 16;
+  const int64_t BPS16 = poffb[n_pan];
+  int64_t* d_poffb = nullptr;
+  if (!fp64) {
+    const size_t tsz = (size_t)s->n_trip * NR * NA * 16, dsz16 = (size_t)n_tau * N * na * 16;
+    const size_t msz = (size_t)n_tau * std::max(nRmax, 1) * N * NR * 16, nsz = (size_t)n_tau * BPS16;
+    if ((rc = sc.alloc(&th, tsz)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&tl, tsz)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&doh, dsz16)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&dol, dsz16)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&dvh, dsz16)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&dvl, dsz16)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&mh, msz)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&ml, msz)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&nh, nsz)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&nl, nsz)) != GW_OK) return rc;
+    if ((rc = sc.upload(&d_poffb, poffb)) != GW_OK) return rc;
+    GW_HIP(hipMemsetAsync(mh, 0, 2 * msz, st));
+    GW_HIP(hipMemsetAsync(ml, 0, 2 * msz, st));
+    GW_HIP(hipMemsetAsync(nh, 0, 2 * nsz, st));
+    GW_HIP(hipMemsetAsync(nl, 0, 2 * nsz, st));
+    auto blocks = [](int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 1 << 20); };
+    hipLaunchKernelGGL(split_t_kernel, dim3(blocks((int64_t)tsz)), dim3(256), 0, st, s->t3c, th, tl,
+                       s->n_trip, NA, NR);
+    GW_HIP(hipGetLastError());
+    hipLaunchKernelGGL(split_d_kernel, dim3(blocks((int64_t)dsz16)), dim3(256), 0, st, dof, doh, dol,
+                       n_tau, N, na, NA);
+    GW_HIP(hipGetLastError());
+    hipLaunchKernelGGL(split_d_kernel, dim3(blocks((int64_t)dsz16)), dim3(256), 0, st, dvf, dvh, dvl,
+                       n_tau, N, na, NA);
+    GW_HIP(hipGetLastError());
+  }
+  StageABf ba{};
+  ba.dh = doh; ba.dl = dol; ba.th = th; ba.tl = tl; ba.mh = mh; ba.ml = ml; ba.goff = d_goff;
+  ba.seg_atom = d_seg_atom; ba.seg_brick = d_seg_brick; ba.rows_pt = 16 * 4 * 4;
+  ba.cols_pt = 16 * BF_NB_AB * BF_WN; ba.n_rt = (N + ba.rows_pt - 1) / ba.rows_pt;
+  ba.n_ct = (NA * NR + ba.cols_pt - 1) / ba.cols_pt; ba.N = N; ba.NA = NA; ba.NR = NR; ba.na = na;
+  ba.nRmax = std::max(nRmax, 1); ba.fdNA.set((uint32_t)NA);
+  StageBBf bb{};
+  bb.dh = dvh; bb.dl = dvl; bb.th = th; bb.tl = tl; bb.nh = nh; bb.nl = nl; bb.goff = d_goff;
+  bb.seg_atom = d_seg_atom; bb.seg_brick = d_seg_brick; bb.gc = d_gc; bb.gslot = d_gslot;
+  bb.poffb = d_poffb; bb.N = N; bb.NA = NA; bb.NR = NR; bb.na = na; bb.RS = RS; bb.PG = PG;
+  bb.PC = PC; bb.BPS16 = BPS16; bb.fdNA.set((uint32_t)NA);
+  StageCBf bc{};
+  bc.mh = mh; bc.ml = ml; bc.nh = nh; bc.nl = nl; bc.chi = chi; bc.gc = d_gc; bc.kmap = d_kmap;
+  bc.km_off = d_km_off; bc.ulen = d_ulen; bc.poffb = d_poffb; bc.rows_pt = 16 * 4 * 4; bc.N = N;
+  bc.NA = NA; bc.NR = NR; bc.NRI = NRI; bc.PG = PG; bc.PC = PC; bc.nRmax = std::max(nRmax, 1);
+  bc.n_atoms = na; bc.BPS16 = BPS16; bc.fdNR.set((uint32_t)NR);
+
   for (int b = 0; b < na; ++b) {
     const int g0 = gb_start[b], nR = gb_start[b + 1] - g0;
     if (nR == 0) continue;
-    {
-      const int64_t total = (int64_t)N * RS;
-      const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-      hipLaunchKernelGGL(gather_dvir_kernel, dim3(blocks), dim3(256), 0, st, dvf, dvg, N, NA,
-                         n_tau, b);
-      GW_HIP(hipGetLastError());
+    if (fp64) {
+      {
+        const int64_t total = (int64_t)N * RS;
+        const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+        hipLaunchKernelGGL(gather_dvir_kernel, dim3(blocks), dim3(256), 0, st, dvf, dvg, N, NA,
+                           n_tau, b);
+        GW_HIP(hipGetLastError());
+      }
+      sa.g0 = g0;
+      GW_HIP(mark());
+      GW_HIP((launch_tile_gemm<A_WM, AB_WN, AB_NBW, 16>(sa, dim3((unsigned)(nR * sa.n_rt * sa.n_ct), n_tau), st)));
+      GW_HIP(mark());
+      hipError_t e;
+      if (RS <= 64) e = launch_stage_b<2>(sb, n_groups, st);
+      else if (RS <= 96) e = launch_stage_b<3>(sb, n_groups, st);
+      else if (RS <= 128) e = launch_stage_b<4>(sb, n_groups, st);
+      else if (RS <= 160) e = launch_stage_b<5>(sb, n_groups, st);
+      else e = launch_stage_b<4>(sb, n_groups, st);
+      GW_HIP(e);
+      GW_HIP(mark());
+      scx.g0 = g0;
+      scx.nR = nR;
+      scx.n_rt = (nR * NR + scx.rows_pt - 1) / scx.rows_pt;
+      GW_HIP((launch_tile_gemm<C_WM, C_WN, C_NBW, C_KC>(scx, dim3((unsigned)(scx.n_rt * n_pan), 1, n_tau), st)));
+      GW_HIP(mark());
+    } else {
+      ba.g0 = g0;
+      GW_HIP(mark());
+      GW_HIP((launch_tile_bf16x3<4, BF_WN, 4, BF_NB_AB, BF_KC>(ba, dim3((unsigned)(nR * ba.n_rt * ba.n_ct), n_tau), st)));
+      GW_HIP(mark());
+      bb.b = b;
+      hipError_t e;
+      if (RS <= 64) e = launch_stage_b_bf<2>(bb, n_groups, st);
+      else if (RS <= 96) e = launch_stage_b_bf<3>(bb, n_groups, st);
+      else if (RS <= 128) e = launch_stage_b_bf<4>(bb, n_groups, st);
+      else e = launch_stage_b_bf<5>(bb, n_groups, st);
+      GW_HIP(e);
+      GW_HIP(mark());
+      bc.g0 = g0;
+      bc.nR = nR;
+      bc.n_rt = (nR * NR + bc.rows_pt - 1) / bc.rows_pt;
+      GW_HIP((launch_tile_bf16x3<4, BF_WN, 4, BF_NB_C, BF_KC>(bc, dim3((unsigned)(bc.n_rt * n_pan), 1, n_tau), st)));
+      GW_HIP(mark());
     }
-    sa.g0 = g0;
-    GW_HIP(mark());
-    GW_HIP((launch_tile_gemm<A_WM, AB_WN, AB_NBW, 16>(sa, dim3((unsigned)(nR * sa.n_rt * sa.n_ct), n_tau), st)));
-    GW_HIP(mark());
-    hipError_t e;
-    if (RS <= 64) e = launch_stage_b<2>(sb, n_groups, st);
-    else if (RS <= 96) e = launch_stage_b<3>(sb, n_groups, st);
-    else if (RS <= 128) e = launch_stage_b<4>(sb, n_groups, st);
-    else if (RS <= 160) e = launch_stage_b<5>(sb, n_groups, st);
-    else e = launch_stage_b<4>(sb, n_groups, st);
-    GW_HIP(e);
-    GW_HIP(mark());
-    scx.g0 = g0;
-    scx.nR = nR;
-    scx.n_rt = (nR * NR + scx.rows_pt - 1) / scx.rows_pt;
-    GW_HIP((launch_tile_gemm<C_WM, C_WN, C_NBW, 16>(scx, dim3((unsigned)(scx.n_rt * n_pan), 1, n_tau), st)));
-    GW_HIP(mark());
     n_launch[0]++; n_launch[1]++; n_launch[2]++;
 
     int64_t nnz_b = 0;

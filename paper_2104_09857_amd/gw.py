@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libgw.so")
 
 GW_OK, GW_ERR_ARG, GW_ERR_HIP, GW_ERR_NOMEM, GW_ERR_NOT_SPD, GW_ERR_NO_CONVERGE, GW_ERR_BLAS = range(7)
 GW_FP64 = 0
+GW_BF16X3 = 2
+PRECISIONS = {"fp64": GW_FP64, "bf16x3": GW_BF16X3}
 
 
 class GWError(RuntimeError):
@@ -143,12 +145,13 @@ def build_gt(sys, C, eps, mu_f, tau, d_occ=None, d_vir=None, stream=None):
     return d_occ, d_vir
 
 
-def contract_chi(sys, d_occ, d_vir, filter_eps=0.0, chi=None, stream=None, timing=False):
+def contract_chi(sys, d_occ, d_vir, filter_eps=0.0, chi=None, stream=None, timing=False,
+                 prec="fp64"):
     import torch
     n_tau = d_occ.shape[0]
     if chi is None:
         chi = torch.empty((n_tau, sys.n_ri, sys.n_ri), dtype=torch.float64, device=d_occ.device)
-    opts = _ChiOpts(GW_FP64, float(filter_eps), int(bool(timing)))
+    opts = _ChiOpts(PRECISIONS[prec], float(filter_eps), int(bool(timing)))
     st = _ChiStats()
     _check(lib().gw_contract_chi(sys.ref, _dev(d_occ), _dev(d_vir), n_tau, ctypes.byref(opts),
                                  _dev(chi), ctypes.byref(st), _stream(stream)))
