@@ -9,6 +9,9 @@
   strip1000    the same generator at 1000 atoms (13000 / 40000).
   strip1734    the same generator at 1734 atoms, filter 1e-8.
   strip<N>     any other atom count with the strip generator (tests).
+  wire<N>      the strip generator on a ribbon one atom wide (a chain of N
+               atoms at 2.5 bohr), filter 1e-8: a long quasi-1D system whose
+               far output blocks fall below the filter.
 """
 from __future__ import annotations
 
@@ -44,6 +47,11 @@ def strip(n_atoms: int, seed=0, filter_eps=1e-9, n_ao=13, n_ri=40, n_tau=12,
     return Workload(f"strip{n_atoms}", s, n_tau, n_tau, n_below, n_above)
 
 
+def wire(n_atoms: int, seed=0, filter_eps=1e-8, n_tau=12) -> Workload:
+    s = gsys.System(gsys.strip(n_atoms, width=1), 13, 40, 0.8, 0.8, 0.2, filter_eps, seed=seed)
+    return Workload(f"wire{n_atoms}", s, n_tau, n_tau, 5, 5)
+
+
 def by_name(name: str, seed=0) -> Workload:
     if name == "chain12":
         return chain12(seed)
@@ -51,6 +59,8 @@ def by_name(name: str, seed=0) -> Workload:
         return strip(1734, seed, filter_eps=1e-8)
     if name.startswith("strip"):
         return strip(int(name[5:]), seed)
+    if name.startswith("wire"):
+        return wire(int(name[4:]), seed)
     raise KeyError(name)
 
 

@@ -70,7 +70,24 @@ typedef struct {
   int64_t n_trip;
   const int32_t *trip;     /* host [n_trip][3] = (a, b, c)                   */
   const double *t3c;       /* dev  [n_trip][ao][ao][ri]                      */
+  const double *xyz;       /* host [n_atoms][3] bohr, or NULL (only used as a
+                              screener feature)                               */
 } gw_system;
+
+/* Block screener network (beyond the paper): a perceptron x (F) -> 64 -> 64
+ * -> 1 with ReLU, predicting log10 of the Frobenius norm of a chi output atom
+ * block (c, c', tau).  Parameters packed [w1 64*F][b1 64][w2 64*64][b2 64]
+ * [w3 64][b3 1] (gw_mlp_param_count floats).  All buffers are caller-owned
+ * device arrays; `step` is the Adam step counter (updated by the library). */
+typedef struct {
+  int32_t n_features;      /* F, 1..16 (gw_chi_block_features writes 6)      */
+  int32_t hidden;          /* must be 64                                      */
+  int32_t step;
+  float *params;           /* dev FP32 master parameters                     */
+  void *params16;          /* dev FP16 copy used for inference               */
+  float *adam_m, *adam_v;  /* dev Adam moments                               */
+  float *grad;             /* dev gradient buffer                            */
+} gw_mlp;
 
 /* Imaginary-time density matrices (Eq. 2).
  * C: dev [n_ao][n_ao], row n = MO n (orthonormal AO basis); eps: host [n_ao]
@@ -86,6 +103,12 @@ typedef struct {
   double filter_eps;       /* atom-block filter (Frobenius norm), >= 0        */
   int32_t timing;          /* 1: time every stage launch with HIP events on
                               `stream` (fills ms_stage)                        */
+  const gw_mlp *screener;  /* NULL, or a trained block screener: output blocks
+                              (c, c', tau) predicted below
+                              log10(filter_eps) - screen_margin are neither
+                              computed nor kept (zero); needs filter_eps > 0   */
+  double screen_margin;    /* decades of safety band below the filter          */
+  const double *screen_tau;/* host [n_tau] tau values (screener feature)       */
 } gw_chi_opts;
 
 typedef struct {
@@ -99,6 +122,8 @@ typedef struct {
                               B and of the outer contraction C (timing = 1)   */
   int64_t n_launch[3];     /* launches of each stage                          */
   double flops_stage[3];   /* algorithmic flops of each stage                 */
+  int64_t n_blocks_screened; /* (c <= c', tau) output blocks the screener skipped */
+  int64_t n_tiles_screened;  /* outer-contraction tiles skipped by the screener */
 } gw_chi_stats;
 
 /* Polarizability chi_PQ(tau_j) for all tau at once (Eq. 3), with the atom-block
@@ -166,6 +191,33 @@ gw_status gw_continue_qp(int32_t n_gw, const double *sig_occ, const double *sig_
                          const int32_t *is_occ, double mu_f, int32_t n_tau, int32_t n_w,
                          const double *omega, const double *cos_w, const double *sin_w,
                          const gw_qp_opts *opts, double *e_qp, int32_t *state_status);
+
+/* Screener features of every output block: dev [n_tau][n_atoms][n_atoms][6] =
+ * (distance/10 bohr, log10 tau, log10 ||T_c||, log10 ||T_c'||,
+ *  log10 ||D^occ_{cc'}(tau)||, log10 ||D^vir_{cc'}(tau)||) with norms over the
+ * kept bricks of RI atom c and over the (c, c') atom blocks of D (1e-30 added
+ * inside every log).  tau: host [n_tau]. */
+gw_status gw_chi_block_features(const gw_system *s, const double *d_occ, const double *d_vir,
+                                int32_t n_tau, const double *tau, double filter_eps, float *feat,
+                                hipStream_t stream);
+/* log10(||chi_{cc'}(tau)|| + 1e-30) of every RI atom block: dev [n_tau][na][na]. */
+gw_status gw_chi_block_lognorms(const gw_system *s, const double *chi, int32_t n_tau,
+                                float *out, hipStream_t stream);
+
+/* Screener network calls (training and inference run on the GPU): */
+int64_t gw_mlp_param_count(int32_t n_features, int32_t hidden);   /* -1 if unsupported */
+/* y[n] = net(x[n][F]); use_fp16 selects the FP16 copy of the weights. */
+gw_status gw_mlp_forward(const gw_mlp *net, int64_t n, const float *x, float *y,
+                         int32_t use_fp16, hipStream_t stream);
+/* Gradient of the asymmetric loss mean(w(r) r^2), r = net(x) - t, w = 1 for
+ * r >= 0 and alpha for r < 0, into grad (dev [P]); loss into loss_dev (dev). */
+gw_status gw_mlp_gradient(const gw_mlp *net, int32_t n, const float *x, const float *t,
+                          float alpha, float *grad, float *loss_dev, hipStream_t stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on a batch; refreshes params16. */
+gw_status gw_mlp_train_step(gw_mlp *net, int32_t n, const float *x, const float *t, float alpha,
+                            float lr, float *loss_dev, hipStream_t stream);
+/* params16 <- params (after the caller changed the FP32 parameters). */
+gw_status gw_mlp_sync_half(gw_mlp *net, hipStream_t stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *gw_last_error(void);

@@ -175,6 +175,18 @@ struct StageB {
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
+// true if some upper (c <= c') block of the tile is kept by the screener
+__device__ inline bool any_kept(const uint8_t* keep, const int32_t* slot_c, int s0, int s1,
+                                int c0, int c1, int tau, int na) {
+  const uint8_t* k = keep + (int64_t)tau * na * na;
+  for (int sl = s0; sl <= s1; ++sl) {
+    const int c = slot_c[sl];
+    for (int c2 = c0; c2 <= c1; ++c2)
+      if (c <= c2 && k[(int64_t)c * na + c2]) return true;
+  }
+  return false;
+}
+
 struct StageC {
   struct Tile : TileBase {
     int p, tau, row0, KU, km0;
@@ -194,6 +206,8 @@ struct StageC {
   int N, NA, NR, NRI, PG, PC, nRmax, n_atoms;
   int64_t BPS;
   FastDiv fdNR;
+  const uint8_t* keep;      // screener mask [tau][c][c'] (c <= c'), or null
+  int* tiles_skipped;
 
   __device__ bool tile(int bx, int by, int bz, Tile& t) const {
     t.row0 = (bx % n_rt) * rows_pt;
@@ -205,6 +219,11 @@ struct StageC {
     const int c_min = gc[g0 + t.row0 / NR];
     const int cp_max = min(t.p * PG + PG - 1, n_atoms - 1);
     if (c_min > cp_max) return false;          // strictly below the block diagonal
+    if (keep && !any_kept(keep, gc + g0, t.row0 / NR, (t.row0 + t.rows - 1) / NR, t.p * PG, cp_max,
+                          t.tau, n_atoms)) {
+      if (threadIdx.x == 0) atomicAdd(tiles_skipped, 1);
+      return false;
+    }
     t.KU = NA * ulen[t.p];
     t.km0 = km_off[t.p];
     t.K = NA * t.KU;
@@ -348,6 +367,39 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   GW_HIP(filter_square_blocks(d_occ, dof, n_tau, na, NA, eps_f, dropped, st));
   GW_HIP(filter_square_blocks(d_vir, dvf, n_tau, na, NA, eps_f, dropped + nflag, st));
 
+  // ---- learned screener: keep mask of the output blocks
+  uint8_t* d_keep = nullptr;
+  int* d_tiles_skipped = nullptr;
+  std::vector<uint8_t> keep_h;
+  const bool screening = opts && opts->screener && eps_f > 0.0;
+  if (screening) {
+    GW_CHECK_ARG(opts->screen_tau != nullptr, "screen_tau is required with a screener");
+    GW_CHECK_ARG(std::isfinite(opts->screen_margin) && opts->screen_margin >= 0.0,
+                 "screen_margin must be finite and >= 0");
+    const int64_t nb = (int64_t)n_tau * na * na;
+    float *feat, *pred;
+    if ((rc = sc.alloc(&feat, (size_t)nb * 6)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&pred, (size_t)nb)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&d_keep, (size_t)nb)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&d_tiles_skipped, 1)) != GW_OK) return rc;
+    GW_HIP(hipMemsetAsync(d_tiles_skipped, 0, sizeof(int), st));
+    if ((rc = gw_chi_block_features(s, d_occ, d_vir, n_tau, opts->screen_tau, eps_f, feat, st)) != GW_OK)
+      return rc;
+    if ((rc = gw_mlp_forward(opts->screener, nb, feat, pred, 1, st)) != GW_OK) return rc;
+    std::vector<float> ph(nb);
+    GW_HIP(hipMemcpyAsync(ph.data(), pred, sizeof(float) * nb, hipMemcpyDeviceToHost, st));
+    GW_HIP(hipStreamSynchronize(st));
+    const float thr = (float)(std::log10(eps_f) - opts->screen_margin);
+    keep_h.assign(nb, 0);
+    for (int j = 0; j < n_tau; ++j)
+      for (int c = 0; c < na; ++c)
+        for (int c2 = c; c2 < na; ++c2) {
+          const int64_t e = ((int64_t)j * na + c) * na + c2;
+          keep_h[e] = (ph[e] >= thr) || !std::isfinite(ph[e]) ? 1 : 0;
+        }
+    GW_HIP(hipMemcpyAsync(d_keep, keep_h.data(), nb, hipMemcpyHostToDevice, st));
+  }
+
   // ---- pivot loop
   StageA sa{};
   sa.dof = dof; sa.t3c = s->t3c; sa.mb = mb; sa.goff = d_goff; sa.seg_atom = d_seg_atom;
@@ -372,6 +424,7 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   scx.NR = NR; scx.NRI = NRI; scx.PG = PG; scx.PC = PC; scx.nRmax = std::max(nRmax, 1);
   scx.n_atoms = na; scx.BPS = BPS;
   scx.fdNR.set((uint32_t)NR);
+  scx.keep = d_keep; scx.tiles_skipped = d_tiles_skipped;
 
   double flops_ab = 0.0, flops_c = 0.0, flops_a = 0.0, flops_b = 0.0;
   const bool timing = opts && opts->timing;
@@ -451,6 +504,7 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   bc.km_off = d_km_off; bc.ulen = d_ulen; bc.poffb = d_poffb; bc.rows_pt = 16 * 4 * 4; bc.N = N;
   bc.NA = NA; bc.NR = NR; bc.NRI = NRI; bc.PG = PG; bc.PC = PC; bc.nRmax = std::max(nRmax, 1);
   bc.n_atoms = na; bc.BPS16 = BPS16; bc.fdNR.set((uint32_t)NR);
+  bc.keep = d_keep; bc.tiles_skipped = d_tiles_skipped;
 
   for (int b = 0; b < na; ++b) {
     const int g0 = gb_start[b], nR = gb_start[b + 1] - g0;
@@ -506,12 +560,24 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
     flops_a += 2.0 * N * (double)nnz_b;
     flops_b += 2.0 * NA * (double)nnz_elems;
     flops_ab += 2.0 * N * (double)nnz_b + 2.0 * NA * (double)nnz_elems;
-    for (int g = g0; g < g0 + nR; ++g)
-      flops_c += 2.0 * NR * NR * NA * NA * asuffix[gcv[g]];
+    if (!screening) {
+      for (int g = g0; g < g0 + nR; ++g)
+        flops_c += 2.0 * NR * NR * NA * NA * asuffix[gcv[g]];
+    } else {
+      // per tau, kept blocks only (averaged into the per-tau figure below)
+      for (int g = g0; g < g0 + nR; ++g) {
+        const int c = gcv[g];
+        for (int j = 0; j < n_tau; ++j)
+          for (int c2 = c; c2 < na; ++c2)
+            if (keep_h[((int64_t)j * na + c) * na + c2])
+              flops_c += 2.0 * NR * NR * NA * NA * acount[c2] / n_tau;
+      }
+    }
   }
 
   // ---- symmetric completion and output filter
   GW_HIP(mirror_lower_blocks(chi, n_tau, NRI, NR, st));
+  if (screening) GW_HIP(zero_unkept_blocks(chi, n_tau, na, NR, d_keep, st));
   if (eps_f > 0.0)
     GW_HIP(filter_square_blocks(chi, chi, n_tau, na, NR, eps_f, dropped + 2 * nflag, st));
 
@@ -524,6 +590,16 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
     if (eps_f > 0.0)
       for (size_t i = 2 * nflag; i < 3 * nflag; ++i) dc += fl[i];
     stats->n_trip_kept = G.n_kept;
+    if (screening) {
+      int skipped = 0;
+      GW_HIP(hipMemcpy(&skipped, d_tiles_skipped, sizeof(int), hipMemcpyDeviceToHost));
+      stats->n_tiles_screened = skipped;
+      int64_t nbs = 0;
+      for (int j = 0; j < n_tau; ++j)
+        for (int c = 0; c < na; ++c)
+          for (int c2 = c; c2 < na; ++c2) nbs += keep_h[((int64_t)j * na + c) * na + c2] ? 0 : 1;
+      stats->n_blocks_screened = nbs;
+    }
     stats->n_dblk_dropped = dd;
     stats->n_chiblk_dropped = dc;
     stats->flops_ab = flops_ab * n_tau;

@@ -166,6 +166,40 @@ __global__ void filter_blocks_kernel(const double* in, double* out,
   if (dropped && lane == 0) dropped[blk] = drop ? 1 : 0;
 }
 
+__global__ void block_norms_f32_kernel(const double* __restrict__ x, int n_atoms, int nb,
+                                       int log10_out, float* __restrict__ out, int64_t n_blocks) {
+  const int64_t blk = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (blk >= n_blocks) return;
+  const int64_t per = (int64_t)n_atoms * n_atoms;
+  const int64_t m = blk / per;
+  const int a = (int)((blk % per) / n_atoms), b = (int)(blk % n_atoms);
+  const int64_t n = (int64_t)n_atoms * nb;
+  const double* src = x + m * n * n + (int64_t)a * nb * n + (int64_t)b * nb;
+  double s = 0.0;
+  for (int i = lane; i < nb * nb; i += 64) {
+    const double v = src[(i / nb) * n + i % nb];
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if (lane == 0) out[blk] = log10_out ? (float)log10(sqrt(s) + 1e-30) : (float)sqrt(s);
+}
+
+__global__ void zero_unkept_kernel(double* __restrict__ x, int n_atoms, int nb,
+                                   const uint8_t* __restrict__ keep, int64_t n_blocks) {
+  const int64_t blk = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (blk >= n_blocks) return;
+  const int64_t per = (int64_t)n_atoms * n_atoms;
+  const int64_t m = blk / per;
+  const int a = (int)((blk % per) / n_atoms), b = (int)(blk % n_atoms);
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  if (keep[m * per + (int64_t)lo * n_atoms + hi]) return;
+  const int64_t n = (int64_t)n_atoms * nb;
+  double* dst = x + m * n * n + (int64_t)a * nb * n + (int64_t)b * nb;
+  for (int i = lane; i < nb * nb; i += 64) dst[(i / nb) * n + i % nb] = 0.0;
+}
+
 // 32x32 tiles through LDS; only tiles touching a lower atom block do work
 __global__ void mirror_kernel(double* __restrict__ x, int n, int nb) {
   __shared__ double tile[32][33];
@@ -203,6 +237,24 @@ hipError_t filter_square_blocks(const double* in, double* out, int n_mat, int n_
   const int wpb = 4;
   hipLaunchKernelGGL(filter_blocks_kernel, dim3((unsigned)((nblk + wpb - 1) / wpb)),
                      dim3(64 * wpb), 0, st, in, out, n_atoms, na, eps, dropped, nblk);
+  return hipGetLastError();
+}
+
+hipError_t block_norms_f32(const double* x, int n_mat, int n_atoms, int nb, int log10_out,
+                           float* out, hipStream_t st) {
+  const int64_t nblk = (int64_t)n_mat * n_atoms * n_atoms;
+  if (nblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(block_norms_f32_kernel, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, st, x,
+                     n_atoms, nb, log10_out, out, nblk);
+  return hipGetLastError();
+}
+
+hipError_t zero_unkept_blocks(double* x, int n_mat, int n_atoms, int nb, const uint8_t* keep,
+                              hipStream_t st) {
+  const int64_t nblk = (int64_t)n_mat * n_atoms * n_atoms;
+  if (nblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_unkept_kernel, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, st, x,
+                     n_atoms, nb, keep, nblk);
   return hipGetLastError();
 }
 

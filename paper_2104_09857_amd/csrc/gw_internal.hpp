@@ -114,6 +114,15 @@ hipError_t brick_norms(const double* t3c, int64_t n, int64_t bs, double* out, hi
 hipError_t filter_square_blocks(const double* in, double* out, int n_mat, int n_atoms, int na,
                                 double eps, uint8_t* dropped, hipStream_t st);
 
+// out[m][a][b] = Frobenius norm (or its log10 after adding 1e-30) of the
+// nb x nb atom blocks of a stack of n_mat square matrices (n_atoms * nb).
+hipError_t block_norms_f32(const double* x, int n_mat, int n_atoms, int nb, int log10_out,
+                           float* out, hipStream_t st);
+
+// zero every atom block (a, b) of x[m] with keep[m][min(a,b)][max(a,b)] == 0
+hipError_t zero_unkept_blocks(double* x, int n_mat, int n_atoms, int nb, const uint8_t* keep,
+                              hipStream_t st);
+
 // x[m] lower atom blocks (row atom > col atom) <- transpose of the upper ones.
 hipError_t mirror_lower_blocks(double* x, int n_mat, int n, int nb, hipStream_t st);
 

@@ -158,10 +158,91 @@ __global__ void to_half_kernel(int P, const float* __restrict__ a, __half* __res
   if (p < P) b[p] = __float2half(a[p]);
 }
 
+__global__ void features_kernel(int n_tau, int na, const double* __restrict__ tau,
+                                const float* __restrict__ dist, const float* __restrict__ tnorm,
+                                const float* __restrict__ dno, const float* __restrict__ dnv,
+                                float* __restrict__ feat) {
+  const int64_t total = (int64_t)n_tau * na * na;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / ((int64_t)na * na));
+    const int c = (int)((e / na) % na), c2 = (int)(e % na);
+    float* f = feat + e * 6;
+    f[0] = dist[(int64_t)c * na + c2] * 0.1f;
+    f[1] = (float)log10(tau[j] + 1e-30);
+    f[2] = log10f(tnorm[c] + 1e-30f);
+    f[3] = log10f(tnorm[c2] + 1e-30f);
+    f[4] = log10f(dno[e] + 1e-30f);
+    f[5] = log10f(dnv[e] + 1e-30f);
+  }
+}
+
 }  // namespace
 }  // namespace gw
 
 using namespace gw;
+
+extern "C" gw_status gw_chi_block_features(const gw_system* s, const double* d_occ,
+                                           const double* d_vir, int32_t n_tau, const double* tau,
+                                           double filter_eps, float* feat, hipStream_t st) {
+  clear_error();
+  gw_status rc = check_system(s);
+  if (rc != GW_OK) return rc;
+  GW_CHECK_ARG(d_occ && d_vir && tau && feat, "null argument");
+  GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
+  GW_CHECK_ARG(std::isfinite(filter_eps) && filter_eps >= 0, "filter_eps must be >= 0");
+  const int na = s->n_atoms, NA = s->ao_per_atom;
+  Scratch sc(st);
+  BrickGroups G;
+  if ((rc = build_groups(s, filter_eps, st, sc, G)) != GW_OK) return rc;
+  // norm of the kept tensor restricted to each RI atom
+  const int64_t bs = (int64_t)NA * NA * s->ri_per_atom;
+  double* d_bn = nullptr;
+  if ((rc = sc.alloc(&d_bn, (size_t)std::max<int64_t>(s->n_trip, 1))) != GW_OK) return rc;
+  GW_HIP(brick_norms(s->t3c, s->n_trip, bs, d_bn, st));
+  std::vector<double> bn(s->n_trip);
+  if (s->n_trip) {
+    GW_HIP(hipMemcpyAsync(bn.data(), d_bn, sizeof(double) * s->n_trip, hipMemcpyDeviceToHost, st));
+    GW_HIP(hipStreamSynchronize(st));
+  }
+  std::vector<double> tn2(na, 0.0);
+  for (int64_t i : G.seg_brick) tn2[s->trip[3 * i + 2]] += bn[i] * bn[i];
+  std::vector<float> tnorm(na), dist((size_t)na * na, 0.f);
+  for (int c = 0; c < na; ++c) tnorm[c] = (float)std::sqrt(tn2[c]);
+  if (s->xyz)
+    for (int a = 0; a < na; ++a)
+      for (int b = 0; b < na; ++b) {
+        double d2 = 0;
+        for (int k = 0; k < 3; ++k) {
+          const double d = s->xyz[3 * a + k] - s->xyz[3 * b + k];
+          d2 += d * d;
+        }
+        dist[(size_t)a * na + b] = (float)std::sqrt(d2);
+      }
+  float *d_tn, *d_dist, *dno, *dnv;
+  double* d_tau;
+  if ((rc = sc.upload(&d_tn, tnorm)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_dist, dist)) != GW_OK) return rc;
+  if ((rc = sc.upload(&d_tau, std::vector<double>(tau, tau + n_tau))) != GW_OK) return rc;
+  if ((rc = sc.alloc(&dno, (size_t)n_tau * na * na)) != GW_OK) return rc;
+  if ((rc = sc.alloc(&dnv, (size_t)n_tau * na * na)) != GW_OK) return rc;
+  GW_HIP(block_norms_f32(d_occ, n_tau, na, NA, 0, dno, st));
+  GW_HIP(block_norms_f32(d_vir, n_tau, na, NA, 0, dnv, st));
+  const int64_t total = (int64_t)n_tau * na * na;
+  hipLaunchKernelGGL(features_kernel, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65536)),
+                     dim3(256), 0, st, n_tau, na, d_tau, d_dist, d_tn, dno, dnv, feat);
+  GW_HIP(hipGetLastError());
+  return GW_OK;
+}
+
+extern "C" gw_status gw_chi_block_lognorms(const gw_system* s, const double* chi, int32_t n_tau,
+                                           float* out, hipStream_t st) {
+  clear_error();
+  GW_CHECK_ARG(s && s->n_atoms > 0 && s->ri_per_atom > 0, "bad system");
+  GW_CHECK_ARG(chi && out && n_tau >= 1, "bad arguments");
+  GW_HIP(block_norms_f32(chi, n_tau, s->n_atoms, s->ri_per_atom, 1, out, st));
+  return GW_OK;
+}
 
 extern "C" int64_t gw_mlp_param_count(int32_t n_features, int32_t hidden) {
   if (n_features < 1 || n_features > kMaxF || hidden != kH) return -1;
@@ -180,10 +261,10 @@ extern "C" gw_status gw_mlp_forward(const gw_mlp* net, int64_t n, const float* x
   const size_t lds = sizeof(float) * L.total();
   if (use_fp16)
     hipLaunchKernelGGL(mlp_forward_kernel<__half>, dim3(blocks), dim3(256), lds, st,
-                       net->params16, net->n_features, n, x, y);
+                       (const __half*)net->params16, net->n_features, n, x, y);
   else
-    hipLaunchKernelGGL(mlp_forward_kernel<float>, dim3(blocks), dim3(256), lds, st, net->params,
-                       net->n_features, n, x, y);
+    hipLaunchKernelGGL(mlp_forward_kernel<float>, dim3(blocks), dim3(256), lds, st,
+                       (const float*)net->params, net->n_features, n, x, y);
   GW_HIP(hipGetLastError());
   return GW_OK;
 }

@@ -48,7 +48,7 @@ __host__ __device__ inline void split_bf16(double x, uint16_t& hi, uint16_t& lo)
 }
 
 template <int WM, int WN, int RB, int NB, int KC, class P>
-__global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_kernel(P p) {
+__device__ __forceinline__ void tile_bf16x3_body(const P& p, int bx, int by, int bz) {
   constexpr int ROWS = 16 * RB * WM, COLS = 16 * NB * WN, NT = 64 * WM * WN;
   constexpr int KG = KC / 8;                 // 16-byte groups per row per chunk
   constexpr int LST = KC + 8;                // LDS row stride (bf16), padded
@@ -63,16 +63,17 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_kernel(P p) {
   __shared__ int tabB[P::kTabB > 0 ? P::kTabB : 1];
 
   typename P::Tile t;
-  if (!p.tile(blockIdx.x, blockIdx.y, blockIdx.z, t)) return;
+  if (!p.tile(bx, by, bz, t)) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
-  p.fill(t, tabA, tabB, tid, NT);
+  const auto lp = resolve(p, t);
+  lp.fill(t, tabA, tabB, tid, NT);
   __syncthreads();
-  const uint16_t* __restrict__ ahb = p.abase_hi(t);
-  const uint16_t* __restrict__ alb = p.abase_lo(t);
-  const uint16_t* __restrict__ bhb = p.bbase_hi(t);
-  const uint16_t* __restrict__ blb = p.bbase_lo(t);
+  const uint16_t* __restrict__ ahb = lp.abase_hi(t);
+  const uint16_t* __restrict__ alb = lp.abase_lo(t);
+  const uint16_t* __restrict__ bhb = lp.bbase_hi(t);
+  const uint16_t* __restrict__ blb = lp.bbase_lo(t);
   const int ngroups = t.K / 8;               // K is a multiple of 16
   const int gmax = ngroups - 1;
 
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_kernel(P p) {
       const int e = tid + i * NT, r = e % ROWS, g = g0 + e / ROWS;
       const bool ok = e < ROWS * KG && r < t.rows && g < ngroups;
       amask = ok ? (amask | (1u << i)) : (amask & ~(1u << i));
-      const int64_t o = p.aroff(t, r < t.rows ? r : t.rows - 1) + p.akoff(t, g < gmax ? g : gmax, tabA);
+      const int64_t o = lp.aroff(t, r < t.rows ? r : t.rows - 1) + lp.akoff(t, g < gmax ? g : gmax, tabA);
       aoff[i] = ok ? o : 0;
     }
 #pragma unroll
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_kernel(P p) {
       const int e = tid + i * NT, c = e % COLS, g = g0 + e / COLS;
       const bool ok = e < COLS * KG && c < t.cols && g < ngroups;
       bmask = ok ? (bmask | (1u << i)) : (bmask & ~(1u << i));
-      const int64_t o = p.bkoff(t, g < gmax ? g : gmax, tabB) + 16 * (int64_t)c;
+      const int64_t o = lp.bkoff(t, g < gmax ? g : gmax, tabB) + 16 * (int64_t)c;
       boff[i] = ok ? o : 0;
     }
 #pragma unroll
@@ -177,11 +178,11 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_kernel(P p) {
   for (int cb = 0; cb < NB; ++cb) {
     const int c = (wn * NB + cb) * 16 + lr;
     const bool cv = c < t.cols;
-    const int64_t co = cv ? p.coloff(t, c) : 0;
+    const int64_t co = cv ? lp.coloff(t, c) : 0;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       if constexpr (P::kOut == 0) {
-        double* __restrict__ ob = p.obase(t);
+        double* __restrict__ ob = lp.obase(t);
         double old[4];
         int64_t off[4];
         bool ok[4];
@@ -189,20 +190,20 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_kernel(P p) {
         for (int i = 0; i < 4; ++i) {
           const int r = (wm * RB + rb) * 16 + 4 * lk + i;
           ok[i] = cv && r < t.rows;
-          off[i] = ok[i] ? p.rowoff(t, r) + co : 0;
+          off[i] = ok[i] ? lp.rowoff(t, r) + co : 0;
           old[i] = ob[off[i]];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           if (ok[i]) ob[off[i]] = old[i] + P::kSign * (double)acc[rb][cb][i];
       } else {
-        uint16_t* __restrict__ oh = p.obase_hi(t);
-        uint16_t* __restrict__ ol = p.obase_lo(t);
+        uint16_t* __restrict__ oh = lp.obase_hi(t);
+        uint16_t* __restrict__ ol = lp.obase_lo(t);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int r = (wm * RB + rb) * 16 + 4 * lk + i;
           if (cv && r < t.rows) {
-            const int64_t o = p.rowoff(t, r) + co;
+            const int64_t o = lp.rowoff(t, r) + co;
             const float v = acc[rb][cb][i];
             const uint16_t h = f32_to_bf16_bits(v);
             oh[o] = h;
@@ -215,9 +216,39 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_kernel(P p) {
 }
 
 template <int WM, int WN, int RB, int NB, int KC, class P>
+__global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_kernel(P p) {
+  tile_bf16x3_body<WM, WN, RB, NB, KC>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// persistent form (same queue protocol as tile_gemm_persistent)
+template <int WM, int WN, int RB, int NB, int KC, class P>
+__global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_persistent(P p, int n_work, int* queue) {
+  __shared__ int next;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+    __syncthreads();
+    const int w = next;
+    if (w >= n_work) break;
+    tile_bf16x3_body<WM, WN, RB, NB, KC>(p, w, 0, 0);
+  }
+}
+
+template <int WM, int WN, int RB, int NB, int KC, class P>
 inline hipError_t launch_tile_bf16x3(const P& p, dim3 grid, hipStream_t st) {
   if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
   hipLaunchKernelGGL((tile_bf16x3_kernel<WM, WN, RB, NB, KC, P>), grid, dim3(64 * WM * WN), 0, st, p);
+  return hipGetLastError();
+}
+
+template <int WM, int WN, int RB, int NB, int KC, class P>
+inline hipError_t launch_tile_bf16x3_persistent(const P& p, int n_work, int* queue, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  static int cap = 0;
+  if (cap == 0) cap = resident_groups(tile_bf16x3_persistent<WM, WN, RB, NB, KC, P>, 64 * WM * WN);
+  const int grid = cap > 0 ? (n_work < cap ? n_work : cap) : n_work;
+  hipLaunchKernelGGL((tile_bf16x3_persistent<WM, WN, RB, NB, KC, P>), dim3(grid), dim3(64 * WM * WN), 0,
+                     st, p, n_work, queue);
   return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace gw {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -48,8 +50,47 @@ struct TileBase {
   int rows, cols, K;
 };
 
+// A batched problem (one launch over the tiles of many systems) defines
+// kBatched and local(t), which returns the problem of the tile's system;
+// a plain problem is its own local problem.
+template <class P, class = void>
+struct is_batched : std::false_type {};
+template <class P>
+struct is_batched<P, std::void_t<decltype(P::kBatched)>> : std::true_type {};
+
+template <class P, class T>
+__device__ __forceinline__ auto resolve(const P& p, const T& t) {
+  if constexpr (is_batched<P>::value) return p.local(t);
+  else return p;
+}
+
+// Concatenated tile ranges of several systems: tile bx belongs to system s
+// with tile_off[s] <= bx < tile_off[s + 1] (binary search) and is tile
+// bx - tile_off[s] of that system's problem probs[s].
+template <class P>
+struct Batched : P {
+  static constexpr bool kBatched = true;
+  struct Tile : P::Tile {
+    int sys;
+  };
+  const P* probs;
+  const int* tile_off;
+  int n_sys;
+  __device__ bool tile(int bx, int by, int bz, Tile& t) const {
+    int lo = 0, hi = n_sys;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (tile_off[mid] <= bx) lo = mid;
+      else hi = mid;
+    }
+    t.sys = lo;
+    return probs[lo].tile(bx - tile_off[lo], by, bz, t);
+  }
+  __device__ P local(const Tile& t) const { return probs[t.sys]; }
+};
+
 template <int WM, int WN, int NB, int KC, class P>
-__global__ __launch_bounds__(64 * WM * WN) void tile_gemm_kernel(P p) {
+__device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int bz) {
   constexpr int ROWS = 32 * WM, COLS = 16 * NB * WN, NT = 64 * WM * WN;
   constexpr int AST = lds_stride(ROWS), BST = lds_stride(COLS);
   constexpr int KSTEP = NT / ROWS;                    // k rows of A per pass of the threads
@@ -62,20 +103,21 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_gemm_kernel(P p) {
   __shared__ int tabB[P::kTabB > 0 ? P::kTabB : 1];
 
   typename P::Tile t;
-  if (!p.tile(blockIdx.x, blockIdx.y, blockIdx.z, t)) return;
+  if (!p.tile(bx, by, bz, t)) return;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
-  p.fill(t, tabA, tabB, tid, NT);
+  const auto lp = resolve(p, t);
+  lp.fill(t, tabA, tabB, tid, NT);
   __syncthreads();
-  const double* __restrict__ abase = p.abase(t);
-  const double* __restrict__ bbase = p.bbase(t);
+  const double* __restrict__ abase = lp.abase(t);
+  const double* __restrict__ bbase = lp.bbase(t);
 
   // this thread's A row is fixed: r = tid % ROWS, k = tid / ROWS + KSTEP i
   const int ar = tid % ROWS;
   const bool arow_ok = ar < t.rows;
-  const int64_t aro = arow_ok ? p.aroff(t, ar) : 0;
+  const int64_t aro = arow_ok ? lp.aroff(t, ar) : 0;
   const int ak0 = tid / ROWS;
 
   double ra[APT], rbv[BPT];
@@ -88,14 +130,14 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_gemm_kernel(P p) {
 #pragma unroll
     for (int i = 0; i < APT; ++i) {
       const int k = k0 + ak0 + KSTEP * i;
-      aoff[i] = p.akoff(t, k < kmax ? k : kmax, tabA);
+      aoff[i] = lp.akoff(t, k < kmax ? k : kmax, tabA);
     }
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
       const int e = tid + i * NT;
       const int kl = e / COLS;
       const int k = k0 + (kl < KC ? kl : KC - 1);
-      boff[i] = p.bkoff(t, k < kmax ? k : kmax, tabB);
+      boff[i] = lp.bkoff(t, k < kmax ? k : kmax, tabB);
     }
     // raw values now; out-of-range entries are zeroed at stash time so that
     // nothing waits on these loads before the matrix-core work of this chunk
@@ -107,7 +149,7 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_gemm_kernel(P p) {
       const bool ok = arow_ok && k < t.K;
       amask |= ok ? (1u << i) : 0u;
       ra[i] = abase[ok ? aro + aoff[i] : 0];
-      if constexpr (P::kAScale) ascl[i] = p.ascale(t, k < kmax ? k : kmax);
+      if constexpr (P::kAScale) ascl[i] = lp.ascale(t, k < kmax ? k : kmax);
     }
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
@@ -176,15 +218,15 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_gemm_kernel(P p) {
     for (int i = 0; i < 4; ++i) {
       const int r = wm * 32 + rb * 16 + 4 * i + lk;
       rv[rb][i] = r < t.rows;
-      ro[rb][i] = rv[rb][i] ? p.rowoff(t, r) : 0;
+      ro[rb][i] = rv[rb][i] ? lp.rowoff(t, r) : 0;
     }
   if constexpr (!P::kDot) {
-    double* __restrict__ ob = p.obase(t);
+    double* __restrict__ ob = lp.obase(t);
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
       const int c = (wn * NB + cb) * 16 + lr;
       const bool cv = c < t.cols;
-      const int64_t co = cv ? p.coloff(t, c) : 0;
+      const int64_t co = cv ? lp.coloff(t, c) : 0;
       if constexpr (P::kAccum) {
         double old[2][4];
 #pragma unroll
@@ -205,14 +247,14 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_gemm_kernel(P p) {
       }
     }
   } else {
-    const double* __restrict__ d0 = p.dbase0(t);
-    const double* __restrict__ d1 = p.dbase1(t);
+    const double* __restrict__ d0 = lp.dbase0(t);
+    const double* __restrict__ d1 = lp.dbase1(t);
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
       const int c = (wn * NB + cb) * 16 + lr;
       const bool cv = c < t.cols;
-      const int64_t co = cv ? p.coloff(t, c) : 0;
+      const int64_t co = cv ? lp.coloff(t, c) : 0;
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -243,8 +285,29 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_gemm_kernel(P p) {
         t0 += red[w];
         t1 += red[NW + w];
       }
-      p.dot_out(t, t0, t1);
+      lp.dot_out(t, t0, t1);
     }
+  }
+}
+
+template <int WM, int WN, int NB, int KC, class P>
+__global__ __launch_bounds__(64 * WM * WN) void tile_gemm_kernel(P p) {
+  tile_gemm_body<WM, WN, NB, KC>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Persistent form: a grid sized to the resident capacity takes work items
+// 0 .. n_work-1 from a queue (an atomic counter, zero at launch) until it is
+// empty; every workgroup leaves once the counter has passed n_work.
+template <int WM, int WN, int NB, int KC, class P>
+__global__ __launch_bounds__(64 * WM * WN) void tile_gemm_persistent(P p, int n_work, int* queue) {
+  __shared__ int next;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+    __syncthreads();
+    const int w = next;
+    if (w >= n_work) break;
+    tile_gemm_body<WM, WN, NB, KC>(p, w, 0, 0);
   }
 }
 
@@ -252,6 +315,27 @@ template <int WM, int WN, int NB, int KC, class P>
 inline hipError_t launch_tile_gemm(const P& p, dim3 grid, hipStream_t st) {
   if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
   hipLaunchKernelGGL((tile_gemm_kernel<WM, WN, NB, KC, P>), grid, dim3(64 * WM * WN), 0, st, p);
+  return hipGetLastError();
+}
+
+// resident workgroups of a kernel on the whole device (persistent grid size)
+template <class K>
+inline int resident_groups(K kernel, int threads) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess) return 0;
+  return ncu * (per > 0 ? per : 1);
+}
+
+template <int WM, int WN, int NB, int KC, class P>
+inline hipError_t launch_tile_gemm_persistent(const P& p, int n_work, int* queue, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  static int cap = 0;
+  if (cap == 0) cap = resident_groups(tile_gemm_persistent<WM, WN, NB, KC, P>, 64 * WM * WN);
+  const int grid = cap > 0 ? (n_work < cap ? n_work : cap) : n_work;
+  hipLaunchKernelGGL((tile_gemm_persistent<WM, WN, NB, KC, P>), dim3(grid), dim3(64 * WM * WN), 0, st,
+                     p, n_work, queue);
   return hipGetLastError();
 }
 

@@ -29,11 +29,20 @@ class GWError(RuntimeError):
 class _System(ctypes.Structure):
     _fields_ = [("n_atoms", ctypes.c_int32), ("ao_per_atom", ctypes.c_int32),
                 ("ri_per_atom", ctypes.c_int32), ("n_occ", ctypes.c_int32),
-                ("n_trip", ctypes.c_int64), ("trip", ctypes.c_void_p), ("t3c", ctypes.c_void_p)]
+                ("n_trip", ctypes.c_int64), ("trip", ctypes.c_void_p), ("t3c", ctypes.c_void_p),
+                ("xyz", ctypes.c_void_p)]
+
+
+class _Mlp(ctypes.Structure):
+    _fields_ = [("n_features", ctypes.c_int32), ("hidden", ctypes.c_int32), ("step", ctypes.c_int32),
+                ("params", ctypes.c_void_p), ("params16", ctypes.c_void_p),
+                ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p), ("grad", ctypes.c_void_p)]
 
 
 class _ChiOpts(ctypes.Structure):
-    _fields_ = [("prec", ctypes.c_int32), ("filter_eps", ctypes.c_double), ("timing", ctypes.c_int32)]
+    _fields_ = [("prec", ctypes.c_int32), ("filter_eps", ctypes.c_double), ("timing", ctypes.c_int32),
+                ("screener", ctypes.c_void_p), ("screen_margin", ctypes.c_double),
+                ("screen_tau", ctypes.c_void_p)]
 
 
 class _ChiStats(ctypes.Structure):
@@ -41,7 +50,8 @@ class _ChiStats(ctypes.Structure):
                 ("n_chiblk_dropped", ctypes.c_int64), ("flops_ab", ctypes.c_double),
                 ("flops_c", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("ms_stage", ctypes.c_double * 3), ("n_launch", ctypes.c_int64 * 3),
-                ("flops_stage", ctypes.c_double * 3)]
+                ("flops_stage", ctypes.c_double * 3), ("n_blocks_screened", ctypes.c_int64),
+                ("n_tiles_screened", ctypes.c_int64)]
 
 
 class _SigmaStats(ctypes.Structure):
@@ -75,6 +85,17 @@ def lib():
         for f in ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma",
                   "gw_continue_qp"):
             getattr(L, f).restype = ctypes.c_int32
+        L.gw_chi_block_features.argtypes = [_P, _P, _P, _I32, _P, _D, _P, _P]
+        L.gw_chi_block_lognorms.argtypes = [_P, _P, _I32, _P, _P]
+        L.gw_mlp_param_count.argtypes = [_I32, _I32]
+        L.gw_mlp_param_count.restype = ctypes.c_int64
+        L.gw_mlp_forward.argtypes = [_P, ctypes.c_int64, _P, _P, _I32, _P]
+        L.gw_mlp_gradient.argtypes = [_P, _I32, _P, _P, ctypes.c_float, _P, _P, _P]
+        L.gw_mlp_train_step.argtypes = [_P, _I32, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P]
+        L.gw_mlp_sync_half.argtypes = [_P, _P]
+        for f in ("gw_chi_block_features", "gw_chi_block_lognorms", "gw_mlp_forward",
+                  "gw_mlp_gradient", "gw_mlp_train_step", "gw_mlp_sync_half"):
+            getattr(L, f).restype = ctypes.c_int32
         L.gw_last_error.restype = ctypes.c_char_p
         L.gw_last_error.argtypes = []
         L.gw_version.restype = ctypes.c_char_p
@@ -84,7 +105,9 @@ def lib():
 
 
 EXPORTED = ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma",
-            "gw_continue_qp", "gw_last_error", "gw_version")
+            "gw_continue_qp", "gw_last_error", "gw_version", "gw_chi_block_features",
+            "gw_chi_block_lognorms", "gw_mlp_param_count", "gw_mlp_forward", "gw_mlp_gradient",
+            "gw_mlp_train_step", "gw_mlp_sync_half")
 
 
 def _check(code):
@@ -114,12 +137,14 @@ def _stream(stream=None):
 class System:
     """A system description (gw_system) with its host triple list and device bricks."""
 
-    def __init__(self, n_atoms, ao_per_atom, ri_per_atom, n_occ, trip, t3c):
+    def __init__(self, n_atoms, ao_per_atom, ri_per_atom, n_occ, trip, t3c, xyz=None):
         self.trip = np.ascontiguousarray(trip, dtype=np.int32).reshape(-1, 3)
         self.t3c = t3c
+        self.xyz = None if xyz is None else np.ascontiguousarray(xyz, dtype=np.float64)
         self.c = _System(int(n_atoms), int(ao_per_atom), int(ri_per_atom), int(n_occ),
                          len(self.trip), self.trip.ctypes.data_as(ctypes.c_void_p).value,
-                         t3c.data_ptr() if t3c is not None and len(self.trip) else None)
+                         t3c.data_ptr() if t3c is not None and len(self.trip) else None,
+                         None if self.xyz is None else self.xyz.ctypes.data_as(ctypes.c_void_p).value)
         self.n_ao = n_atoms * ao_per_atom
         self.n_ri = n_atoms * ri_per_atom
 
@@ -146,18 +171,83 @@ def build_gt(sys, C, eps, mu_f, tau, d_occ=None, d_vir=None, stream=None):
 
 
 def contract_chi(sys, d_occ, d_vir, filter_eps=0.0, chi=None, stream=None, timing=False,
-                 prec="fp64"):
+                 prec="fp64", screener=None, screen_margin=1.0, tau=None):
     import torch
     n_tau = d_occ.shape[0]
     if chi is None:
         chi = torch.empty((n_tau, sys.n_ri, sys.n_ri), dtype=torch.float64, device=d_occ.device)
-    opts = _ChiOpts(PRECISIONS[prec], float(filter_eps), int(bool(timing)))
+    tau_h = None if tau is None else np.ascontiguousarray(tau, dtype=np.float64)
+    opts = _ChiOpts(PRECISIONS[prec], float(filter_eps), int(bool(timing)),
+                    None if screener is None else ctypes.addressof(screener.c),
+                    float(screen_margin),
+                    None if tau_h is None else tau_h.ctypes.data_as(ctypes.c_void_p).value)
     st = _ChiStats()
     _check(lib().gw_contract_chi(sys.ref, _dev(d_occ), _dev(d_vir), n_tau, ctypes.byref(opts),
                                  _dev(chi), ctypes.byref(st), _stream(stream)))
     stats = {k: (list(getattr(st, k)) if k in ("ms_stage", "n_launch", "flops_stage")
                  else getattr(st, k)) for k, _ in _ChiStats._fields_}
     return chi, stats
+
+
+def chi_block_features(sys, d_occ, d_vir, tau, filter_eps, feat=None, stream=None):
+    import torch
+    n_tau = d_occ.shape[0]
+    na = sys.c.n_atoms
+    if feat is None:
+        feat = torch.empty((n_tau, na, na, 6), dtype=torch.float32, device=d_occ.device)
+    tau_h, tau_p = _host(tau)
+    _check(lib().gw_chi_block_features(sys.ref, _dev(d_occ), _dev(d_vir), n_tau, tau_p,
+                                       float(filter_eps), _dev(feat), _stream(stream)))
+    return feat
+
+
+def chi_block_lognorms(sys, chi, out=None, stream=None):
+    import torch
+    n_tau = chi.shape[0]
+    na = sys.c.n_atoms
+    if out is None:
+        out = torch.empty((n_tau, na, na), dtype=torch.float32, device=chi.device)
+    _check(lib().gw_chi_block_lognorms(sys.ref, _dev(chi), n_tau, _dev(out), _stream(stream)))
+    return out
+
+
+class Mlp:
+    """Device buffers of the screener network (gw_mlp)."""
+
+    def __init__(self, n_features=6, hidden=64, params=None, device="cuda"):
+        import torch
+        P = int(lib().gw_mlp_param_count(n_features, hidden))
+        if P < 0:
+            raise GWError(GW_ERR_ARG, "unsupported network shape")
+        self.P = P
+        z = lambda: torch.zeros(P, dtype=torch.float32, device=device)
+        self.params = z() if params is None else torch.as_tensor(
+            np.asarray(params, dtype=np.float32), device=device).clone()
+        self.params16 = torch.zeros(P, dtype=torch.float16, device=device)
+        self.m, self.v, self.grad = z(), z(), z()
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.c = _Mlp(n_features, hidden, 0, self.params.data_ptr(), self.params16.data_ptr(),
+                      self.m.data_ptr(), self.v.data_ptr(), self.grad.data_ptr())
+        _check(lib().gw_mlp_sync_half(ctypes.byref(self.c), _stream(None)))
+
+    def forward(self, x, fp16=True, stream=None):
+        import torch
+        n = x.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(lib().gw_mlp_forward(ctypes.byref(self.c), n, _dev(x), _dev(y), int(fp16),
+                                    _stream(stream)))
+        return y
+
+    def gradient(self, x, t, alpha, stream=None):
+        _check(lib().gw_mlp_gradient(ctypes.byref(self.c), x.shape[0], _dev(x), _dev(t),
+                                     float(alpha), _dev(self.grad), _dev(self.loss),
+                                     _stream(stream)))
+        return self.grad, self.loss
+
+    def train_step(self, x, t, alpha, lr, stream=None):
+        _check(lib().gw_mlp_train_step(ctypes.byref(self.c), x.shape[0], _dev(x), _dev(t),
+                                       float(alpha), float(lr), _dev(self.loss), _stream(stream)))
+        return self.loss
 
 
 def screen_w(sys, chi, V, cos_w, icos_w, spin=2.0, wc=None, stream=None):

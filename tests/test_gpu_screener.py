@@ -1,0 +1,134 @@
+"""Learned block screener: GPU network kernels against the FP64 reference,
+the screening mechanics, and a trained screener audited against the exact
+contraction on a long wire (a ribbon one atom wide), where far output blocks
+fall below the filter."""
+import numpy as np
+import pytest
+
+from gwinputs import configs
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _params_dict(flat):
+    from paper_2104_09857_amd import screener
+    w1, b1, w2, b2, w3, b3 = screener.unpack(np.asarray(flat, dtype=np.float64))
+    return dict(w1=w1, b1=b1, w2=w2, b2=b2, w3=w3, b3=b3)
+
+
+def test_network_forward_gradient_adam_match_reference():
+    import torch
+    from paper_2104_09857_amd import gw, screener
+    rng = np.random.default_rng(4)
+    net = gw.Mlp(6, 64, screener._he_init(5))
+    X = rng.standard_normal((2500, 6)).astype(np.float32)
+    t = rng.standard_normal(2500).astype(np.float32)
+    Xd, td = torch.as_tensor(X, device="cuda"), torch.as_tensor(t, device="cuda")
+    P = _params_dict(net.params.double().cpu().numpy())
+    y_ref, _ = omlp.forward(P, X.astype(np.float64))
+    scale = np.abs(y_ref).max()
+    assert np.abs(net.forward(Xd, fp16=False).cpu().numpy() - y_ref).max() <= 1e-5 * scale
+    # FP16 weights: 11-bit mantissa per weight
+    assert np.abs(net.forward(Xd, fp16=True).cpu().numpy() - y_ref).max() <= 5e-3 * scale
+    g, loss = net.gradient(Xd, td, 8.0)
+    L_ref, G = omlp.backward(P, X.astype(np.float64), t.astype(np.float64), 8.0)
+    gref = screener.pack(G["w1"], G["b1"], G["w2"], G["b2"], G["w3"], G["b3"])
+    assert np.abs(g.double().cpu().numpy() - gref).max() <= 1e-4 * np.abs(gref).max()
+    assert abs(float(loss.item()) - L_ref) <= 1e-5 * L_ref
+    # one Adam step
+    p0 = net.params.double().cpu().numpy()
+    net.train_step(Xd, td, 8.0, 1e-3)
+    m = {k: np.zeros_like(v) for k, v in P.items()}
+    v = {k: np.zeros_like(x) for k, x in P.items()}
+    P1, _, _ = omlp.adam(dict(P), G, m, v, 1, 1e-3)
+    ref1 = screener.pack(P1["w1"], P1["b1"], P1["w2"], P1["b2"], P1["w3"], P1["b3"])
+    got1 = net.params.double().cpu().numpy()
+    assert np.abs(got1 - ref1).max() <= 1e-6 + 1e-4 * np.abs(got1 - p0).max()
+
+
+def _wire_run(n_atoms):
+    import torch
+    from gwinputs import device as gdev
+    from paper_2104_09857_amd import gw
+    w = configs.wire(n_atoms)
+    s = w.system
+    C, eps = s.mean_field()
+    g = configs.grids_for(w, eps)
+    mu = configs.mu_fermi(eps, s.n_occ)
+    trip = s.triples()
+    t3c = gdev.bricks_on_device(s, trip)
+    sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c, s.xyz)
+    do, dv = gw.build_gt(sysd, torch.as_tensor(C, device="cuda"), eps, mu, g.tau)
+    return dict(w=w, s=s, g=g, sys=sysd, do=do, dv=dv, t3c=t3c)
+
+
+@pytest.fixture(scope="module")
+def wires():
+    from paper_2104_09857_amd import gw
+    out = {}
+    for n in (60, 90, 120, 160):
+        r = _wire_run(n)
+        r["chi"], r["st"] = gw.contract_chi(r["sys"], r["do"], r["dv"], r["s"].filter_eps)
+        out[n] = r
+    return out
+
+
+def test_screening_mechanics(wires):
+    import torch
+    from paper_2104_09857_amd import gw, screener
+    r = wires[90]
+    s = r["s"]
+    keep_all = screener.BlockScreener(0)
+    p = screener.unpack(keep_all.params)
+    # a network that predicts +100 everywhere keeps every block: bitwise identical chi
+    hi = gw.Mlp(6, 64, screener.pack(p[0], p[1], p[2], p[3], 0 * p[4], np.array([100.0])))
+    chi_k, st = gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=hi,
+                                screen_margin=1.0, tau=r["g"].tau)
+    assert torch.equal(chi_k, r["chi"]) and st["n_blocks_screened"] == 0
+    # a network that predicts -100 everywhere skips everything: chi == 0
+    lo = gw.Mlp(6, 64, screener.pack(p[0], p[1], p[2], p[3], 0 * p[4], np.array([-100.0])))
+    chi_s, st = gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=lo,
+                                screen_margin=1.0, tau=r["g"].tau)
+    na, nt = s.n_atoms, r["do"].shape[0]
+    assert float(chi_s.abs().max()) == 0.0
+    assert st["n_blocks_screened"] == nt * na * (na + 1) // 2 and st["n_tiles_screened"] > 0
+
+
+def test_trained_screener_audit_and_gain(wires):
+    import torch
+    from paper_2104_09857_amd import gw, screener
+    Xs, ts = [], []
+    for n in (60, 90):
+        r = wires[n]
+        X, t = screener.samples(r["sys"], r["do"], r["dv"], r["chi"], r["g"].tau, r["s"].filter_eps)
+        Xs.append(X)
+        ts.append(t)
+    sc = screener.BlockScreener(7)
+    hist = sc.fit(torch.cat(Xs), torch.cat(ts), filter_eps=wires[60]["s"].filter_eps, steps=3000,
+                  batch=4096, lr=2e-3, alpha=8.0)
+    print("loss", hist[0], hist[-1], flush=True)
+    assert hist[-1][1] < 0.2 * hist[0][1]
+    # safety band calibrated on a held-out wire, then applied to a longer one
+    rv = wires[120]
+    Xv, tv = screener.samples(rv["sys"], rv["do"], rv["dv"], rv["chi"], rv["g"].tau,
+                              rv["s"].filter_eps)
+    margin = sc.calibrate(Xv, tv, rv["s"].filter_eps)
+    print("calibrated margin (decades)", margin, flush=True)
+    r = wires[160]
+    s = r["s"]
+    chi_s, st = gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=sc.net,
+                                screen_margin=margin, tau=r["g"].tau)
+    exact = r["chi"]
+    lg = gw.chi_block_lognorms(r["sys"], exact).cpu().numpy()
+    lgs = gw.chi_block_lognorms(r["sys"], chi_s).cpu().numpy()
+    skipped = (lgs < -29) & (lg >= -29)          # zero in the screened run, nonzero in the exact one
+    total = st["n_blocks_screened"]
+    print("screened blocks", total, "tiles", st["n_tiles_screened"], "max skipped log10 norm",
+          lg[skipped].max() if skipped.any() else None, flush=True)
+    assert total > 0 and st["n_tiles_screened"] > 0
+    # audit: every skipped block lies below the filter (the exact output filter would
+    # have zeroed it too), so the screened chi equals the exact filtered chi
+    assert not skipped.any() or lg[skipped].max() < np.log10(s.filter_eps)
+    assert float((chi_s - exact).abs().max()) == 0.0
+    assert st["flops_c"] < r["st"]["flops_c"]
