@@ -11,6 +11,11 @@ atom (3900 AO, 12000 RI), half filled, filter 1e-9, 12 tau / 12 omega points,
 Sigma for HOMO-4 .. LUMO+4.  Inputs are seeded and synthetic (gwinputs).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload strip300]
+
+Workload mol<M> (e.g. mol64) times the batched form instead: one step = one
+execution of a gw_chi_batch plan (chi for all tau of M molecules of 10-40
+atoms, captured in a hipGraph, tile variant and launch mode autotuned),
+next to M one-system gw_contract_chi calls and the eager plan.
 """
 from __future__ import annotations
 
@@ -111,6 +116,135 @@ def cpu_baseline(ctx, out, budget_s=20.0):
                       f"NumPy/OpenBLAS dense within the brick supports, {elapsed:.1f} s: {done}"}
 
 
+def setup_molecules(n_mol, seed=0):
+    import torch
+    from gwinputs import configs, device as gdev
+    from paper_2104_09857_amd import gw
+    t0 = time.perf_counter()
+    ws = configs.molecules(n_mol, seed)
+    ms = []
+    for w in ws:
+        s = w.system
+        C, eps = s.mean_field()
+        g = configs.grids_for(w, eps)
+        mu = configs.mu_fermi(eps, s.n_occ)
+        trip = s.triples()
+        t3c = gdev.bricks_on_device(s, trip)
+        sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c)
+        do, dv = gw.build_gt(sysd, torch.as_tensor(C, device="cuda"), eps, mu, g.tau)
+        ms.append(dict(w=w, s=s, sys=sysd, t3c=t3c, trip=trip, do=do, dv=dv))
+    torch.cuda.synchronize()
+    n = [m["s"].n_atoms for m in ms]
+    log(f"[setup] mol{n_mol}: atoms {min(n)}..{max(n)} (sum {sum(n)}), "
+        f"{sum(m['t3c'].numel() for m in ms) * 8 / 1e9:.1f} GB bricks, {time.perf_counter() - t0:.1f} s")
+    return ms
+
+
+def bench_batched(args):
+    """The batched form on M molecules (see the module docstring)."""
+    import tempfile
+    import torch
+    from paper_2104_09857_amd import gw
+    n_mol = int(args.workload[3:])
+    ms = setup_molecules(n_mol)
+    eps_f = ms[0]["s"].filter_eps
+    n_tau = ms[0]["do"].shape[0]
+    systems = [m["sys"] for m in ms]
+    do, dv = [m["do"] for m in ms], [m["dv"] for m in ms]
+    stream = torch.cuda.Stream()
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    # reference: one gw_contract_chi call per molecule
+    ref = [gw.contract_chi(m["sys"], m["do"], m["dv"], eps_f, prec=args.prec)[0] for m in ms]
+    seq_ms = timed(lambda: [gw.contract_chi(m["sys"], m["do"], m["dv"], eps_f, chi=r, prec=args.prec)
+                            for m, r in zip(ms, ref)], 1)
+    log(f"[batched] sequential one-system calls: {seq_ms:.1f} ms")
+    # one-system plans (made beforehand), executed one after another
+    singles = [gw.ChiBatch([m["sys"]], n_tau, eps_f, prec=args.prec, stream=stream) for m in ms]
+
+    def run_singles():
+        with torch.cuda.stream(stream):
+            for p1, m, r in zip(singles, ms, ref):
+                p1.execute([m["do"]], [m["dv"]], [r], stats=False, stream=stream)
+
+    run_singles()
+    seq_plan_ms = timed(run_singles, 1)
+    for p1 in singles:
+        p1.close()
+    del singles
+    log(f"[batched] sequential one-system plans: {seq_plan_ms:.1f} ms")
+    plan = gw.ChiBatch(systems, n_tau, eps_f, prec=args.prec, timing=True, stream=stream)
+    out = plan.outputs()
+    # eager, default configuration, per-stage events
+    with torch.cuda.stream(stream):
+        st = plan.execute(do, dv, out, stream=stream)
+    stream.synchronize()
+    eager_ms = st["ms_total"]
+    same = all(torch.equal(a, b) for a, b in zip(out, ref))
+    cache = args.tune_cache or os.path.join(tempfile.mkdtemp(), "gw_autotune.txt")
+    with torch.cuda.stream(stream):
+        tune_ms = plan.tune(do, dv, out, reps=1, cache_path=cache, stream=stream)
+    variant, persistent, _ = plan.config()
+    log(f"[batched] eager default {eager_ms:.1f} ms, tuned variant {variant} persistent {persistent} "
+        f"{tune_ms:.1f} ms")
+    # per-stage times of the tuned configuration (eager)
+    with torch.cuda.stream(stream):
+        st = plan.execute(do, dv, out, stream=stream)
+    stream.synchronize()
+
+    def run_graph():
+        with torch.cuda.stream(stream):
+            plan.execute(do, dv, out, graph=True, stats=False, stream=stream)
+
+    for i in range(args.warmup):
+        run_graph()
+        stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        run_graph()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    graph_ms = wall / args.steps * 1e3
+    same_graph = all(torch.equal(a, b) for a, b in zip(out, ref))
+    flops = st["flops_ab"] + st["flops_c"]
+    c_ms, c_n, c_fl = st["ms_stage"][2], st["n_launch"][2], st["flops_stage"][2]
+    achieved = (c_fl / max(c_n, 1)) / ((c_ms / max(c_n, 1)) / 1e3) / 1e12
+    peak = PEAK_FP64_MFMA_TFLOPS if args.prec == "fp64" else 2500.0
+    n = [m["s"].n_atoms for m in ms]
+    res = {
+        "metric": METRIC, "value": flops / (graph_ms / 1e3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": graph_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "bf16x3 (fp32 accumulate, fp64 across tiles)",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "form": "batched chi (gw_chi_batch, hipGraph)",
+                   "n_mol": n_mol, "atoms_min": min(n), "atoms_max": max(n), "atoms_sum": sum(n),
+                   "n_tau": n_tau, "filter_eps": eps_f, "ao_per_atom": 13, "ri_per_atom": 40},
+        "batched": {"sequential_calls_ms": seq_ms, "sequential_plans_ms": seq_plan_ms,
+                    "eager_default_ms": eager_ms, "tuned_ms": tune_ms,
+                    "graph_ms": graph_ms, "speedup_vs_sequential_calls": seq_ms / graph_ms,
+                    "speedup_vs_sequential_plans": seq_plan_ms / graph_ms,
+                    "tuned_variant": variant, "tuned_persistent": persistent,
+                    "equal_to_single_calls": bool(same and same_graph),
+                    "flops": flops, "stage_ms": [round(x, 2) for x in st["ms_stage"]],
+                    "stage_launches": list(st["n_launch"])},
+        "roofline": {"kernel": "stage C (outer contraction), batched launches", "bound": "mfma",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None, "launches": int(c_n), "avg_launch_ms": c_ms / max(c_n, 1)},
+    }
+    plan.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +257,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the extra untimed run of the other precision form")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--tune-cache", default=None, help="autotune cache file of the batched form")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -130,6 +265,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload.startswith("mol"):
+        bench_batched(args)
+        return
     ctx = setup(args.workload)
     for i in range(args.warmup):
         t0 = time.perf_counter()

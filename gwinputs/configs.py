@@ -12,6 +12,12 @@
   wire<N>      the strip generator on a ribbon one atom wide (a chain of N
                atoms at 2.5 bohr), filter 1e-8: a long quasi-1D system whose
                far output blocks fall below the filter.
+  mol<M>       M independent molecules for the batched form: atom counts
+               drawn uniformly from [10, 40] (Philox uniform, stream 7),
+               3D random sequential packings of number density 0.0148 / bohr^3
+               with minimum distance 2.5 bohr, 13 AO / 40 RI per atom,
+               decays 0.8 / 0.8 / 0.2, filter 1e-9, 12 tau, HOMO / LUMO.
+               Molecule m uses sys_id m (its own random streams).
 """
 from __future__ import annotations
 
@@ -50,6 +56,24 @@ def strip(n_atoms: int, seed=0, filter_eps=1e-9, n_ao=13, n_ri=40, n_tau=12,
 def wire(n_atoms: int, seed=0, filter_eps=1e-8, n_tau=12) -> Workload:
     s = gsys.System(gsys.strip(n_atoms, width=1), 13, 40, 0.8, 0.8, 0.2, filter_eps, seed=seed)
     return Workload(f"wire{n_atoms}", s, n_tau, n_tau, 5, 5)
+
+
+STREAM_SIZES = 7
+STREAM_PACKING = 8
+
+
+def molecules(n_mol: int, seed=0, lo=10, hi=40, filter_eps=1e-9, n_tau=12, n_ao=13,
+              n_ri=40) -> list:
+    """The molecule set of the batched form (see the module docstring)."""
+    from . import philox
+    u = philox.uniform(seed, STREAM_SIZES, np.arange(n_mol))
+    sizes = lo + np.minimum((u * (hi - lo + 1)).astype(np.int64), hi - lo)
+    out = []
+    for m, n in enumerate(sizes):
+        xyz = gsys.packing(int(n), seed, STREAM_PACKING + 16 * m)
+        s = gsys.System(xyz, n_ao, n_ri, 0.8, 0.8, 0.2, filter_eps, seed=seed, sys_id=m)
+        out.append(Workload(f"mol{n_mol}[{m}]", s, n_tau, n_tau, 1, 1))
+    return out
 
 
 def by_name(name: str, seed=0) -> Workload:

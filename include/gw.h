@@ -132,12 +132,67 @@ typedef struct {
  * norm < filter_eps are zeroed.
  * d_occ, d_vir: dev [n_tau][n_ao][n_ao] (symmetric); chi: dev
  * [n_tau][n_ri][n_ri], overwritten, symmetric (upper blocks computed,
- * mirrored).  stats (host, may be NULL) is filled; the call synchronizes the
- * stream once to read the kept-brick mask and again at the end when stats is
- * non-NULL. */
+ * mirrored).  stats (host, may be NULL) is filled.  The call is synchronous:
+ * it reads the kept-brick mask on the host first and releases its scratch
+ * (plain device allocations) before returning.  It runs the batched form
+ * below on one system, eagerly, with the default tile variant. */
 gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double *d_vir,
                           int32_t n_tau, const gw_chi_opts *opts, double *chi,
                           gw_chi_stats *stats, hipStream_t stream);
+
+/* Batched persistent form of gw_contract_chi (Eq. 3 for many independent
+ * systems, e.g. the molecules of a benchmark set).
+ *
+ * A plan is made once per set of systems: it filters and groups the bricks
+ * of every system (brick norms are read on the host), lays out the stage-C
+ * column panels, allocates the scratch of one pivot's half-contracted
+ * tensors per system (plain device allocations, held until destroy) and,
+ * for GW_BF16X3, splits the bricks into bf16 hi/lo once.  The plan is valid
+ * for the brick VALUES present at creation: t3c pointers and contents must
+ * not change until gw_chi_batch_destroy.  All systems must share
+ * ao_per_atom and ri_per_atom; opts->screener must be NULL.
+ *
+ * An execution walks the pivot atom index i = 0 .. max n_atoms - 1 and
+ * issues, per stage, one launch over the tiles of every system with a pivot
+ * atom i, for all n_tau points at once.  Results equal n_sys calls of
+ * gw_contract_chi with the same opts (same arithmetic, same order).
+ *
+ * gw_chi_batch_create: systems host [n_sys]; *plan receives the handle.
+ *   Synchronizes `stream`.
+ * gw_chi_batch_execute: d_occ, d_vir, chi are HOST arrays of n_sys device
+ *   pointers with the layouts of gw_contract_chi (chi overwritten).
+ *   use_graph = 0: eager launches (opts->timing fills ms_stage);
+ *   use_graph = 1: the launch sequence is captured into a hipGraph on first
+ *   use and replayed afterwards; it is captured again when any pointer, the
+ *   stream or the tile configuration changes.  Needs a created (non-NULL)
+ *   stream.  Without stats the call is asynchronous; with stats it
+ *   synchronizes to read the filter counts.  Calls on one plan must not
+ *   overlap (they share its scratch).
+ * gw_chi_batch_set_config / get_config: stage-C tile variant
+ *   (0 .. n_variants-1) and launch mode (persistent = 1: a resident grid
+ *   takes tiles from a device queue, largest systems first; 0: one
+ *   workgroup per tile).
+ * gw_chi_batch_tune: autotuner.  If cache_path (may be NULL) holds an entry
+ *   for the plan's shape class (precision, AO/RI per atom, n_tau, log2 of
+ *   the system count and of the mean atom count) that configuration is
+ *   taken; otherwise every (variant, mode) is run reps times eagerly, the
+ *   fastest is kept and appended to cache_path.  *ms_out (host, may be NULL)
+ *   receives its time per execution.  Overwrites chi.
+ * gw_chi_batch_destroy: releases the plan (synchronizes the device). */
+typedef struct gw_chi_batch gw_chi_batch;
+
+gw_status gw_chi_batch_create(int32_t n_sys, const gw_system *systems, int32_t n_tau,
+                              const gw_chi_opts *opts, gw_chi_batch **plan, hipStream_t stream);
+gw_status gw_chi_batch_execute(gw_chi_batch *plan, const double *const *d_occ,
+                               const double *const *d_vir, double *const *chi,
+                               int32_t use_graph, gw_chi_stats *stats, hipStream_t stream);
+gw_status gw_chi_batch_set_config(gw_chi_batch *plan, int32_t variant, int32_t persistent);
+gw_status gw_chi_batch_get_config(const gw_chi_batch *plan, int32_t *variant,
+                                  int32_t *persistent, int32_t *n_variants);
+gw_status gw_chi_batch_tune(gw_chi_batch *plan, const double *const *d_occ,
+                            const double *const *d_vir, double *const *chi, int32_t reps,
+                            const char *cache_path, double *ms_out, hipStream_t stream);
+gw_status gw_chi_batch_destroy(gw_chi_batch *plan);
 
 /* Screening (Eqs. 5-9) with RI overlap metric S = 1:
  *   chi(i w_k) = 2 spin sum_j cos_w[k][j] chi(tau_j)

@@ -1,295 +1,880 @@
-// Block-sparse polarizability chi_PQ(tau) (Eq. 3) on FP64 MFMA.
+// Block-sparse polarizability chi_PQ(tau) (Eq. 3): plans and launches.
 //
-// Eq. 3 is organised around a pivot AO atom b (sigma runs over b):
-//   stage A  M_b[tau][sigma][c][mu][P] = sum_a sum_{l in a} D^occ_{l mu}(tau) (l sigma P)
-//            for every RI atom c that has a brick (a, b, c) and every mu
-//   stage B  N_b[tau][(a', c')][mu][Q][sigma] = sum_{a2} sum_{nu in a2}
-//                 (nu mu Q) D^vir_{nu sigma}(tau)      (brick (a2, a', c'))
-//   stage C  chi[tau][c][c'] -= sum_{sigma in b} sum_{mu} M_b[..][mu][P] N_b[..][mu][Q][sigma]
-// Both half contractions use the same brick grouping: group (s, c) lists the
-// bricks (f, s, c) and the contraction runs over the first index f.  Stage C
-// is a GEMM per RI column panel p (PG consecutive RI atoms): its K range is
-// (sigma, mu in U_p) with U_p the union of the AO atoms that couple to the
-// panel, so N_b is written panel-dense (zeros where an atom does not couple).
-// Only blocks with c <= c' are computed; the lower blocks are mirrored at
-// the end (chi is symmetric).  The half-contracted tensors never exceed one
-// pivot (O(n_tau * N_AO * |S|/N_atoms) doubles).
+// A plan holds, for every system of a batch, the brick grouping (kept
+// bricks after the norm filter), the RI column panels of stage C, scratch for
+// one pivot's half-contracted tensors and the problem descriptions of the
+// three stages (chi_stages.hpp).  Execution walks the pivot index
+// i = 0 .. max(n_atoms) - 1 and issues per stage ONE launch over the tiles
+// of every system that has a pivot atom i, for all tau at once, so a batch of
+// uneven molecules fills the chip with a few launches per pivot index instead
+// of a few per (molecule, pivot).  Launches are plain grids or persistent
+// grids that take tiles from a device queue (largest systems first).  The
+// whole sequence can be captured once into a hipGraph and replayed.  The
+// stage-C tile shape and the launch mode are chosen per shape class by an
+// autotuner that times the candidates on the plan and caches the winner in a
+// text file.  gw_contract_chi is the one-system, eager case of the same code.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <fstream>
+#include <memory>
+#include <new>
 #include <numeric>
+#include <sstream>
 
-#include "gw_internal.hpp"
-#include "tile_bf16x3.hpp"
-#include "tile_gemm.hpp"
+#include "chi_stages.hpp"
 
 namespace gw {
 namespace {
 
-constexpr int A_WM = 4, AB_WN = 2, AB_NBW = 6;    // stage A tile 128 x 192, 8 waves
-constexpr int AB_COLS = 16 * AB_NBW * AB_WN;      // stage B tile (32 WM) x 192
-constexpr int C_WM = 4, C_WN = 2, C_NBW = 5;      // stage C tile 128 x 160, 8 waves
-constexpr int C_COLS = 16 * C_NBW * C_WN;
-constexpr int C_KC = 32;                          // K chunk staged per barrier pair
+// stage-C tile variants: rows of a tile (columns are one 160-wide panel)
+//   FP64    0: <WM 4, KC 32> 128 rows   1: <WM 2, KC 32> 64 rows   2: <WM 4, KC 16> 128 rows
+//   BF16x3  0: <WM 4, RB 4> 256 rows    1: <WM 4, RB 2> 128 rows   2: <WM 2, RB 4> 128 rows
+constexpr int kNVar = 3;
+int c_rows(int prec, int v) {
+  static const int f64[kNVar] = {128, 64, 128}, bf[kNVar] = {256, 128, 128};
+  return prec == GW_FP64 ? f64[v] : bf[v];
+}
+// stage-B waves (FP64) / row blocks (BF16x3) by the row count n_tau * NA
+int b_wm(int RS) { return RS <= 64 ? 2 : RS <= 96 ? 3 : RS <= 128 ? 4 : RS <= 160 ? 5 : 4; }
+int b_rb(int RS) { return RS <= 64 ? 2 : RS <= 96 ? 3 : RS <= 128 ? 4 : 5; }
 
-constexpr int kSegTab = 2048;     // max bricks per group (first atoms)
-constexpr int kPanTab = 4096;     // max K functions per column panel (NA * |U_p|)
+// Work of one stage at every pivot index, for a batched launch.
+template <class P>
+struct Table {
+  std::vector<BatchEntry<P>> ent;
+  std::vector<int32_t> toff;
+  std::vector<int> ent0, toff0, n, work;
+  BatchEntry<P>* d_ent = nullptr;
+  int32_t* d_toff = nullptr;
+  size_t cap_ent = 0, cap_toff = 0;
 
-struct StageA {
-  struct Tile : TileBase {
-    int g, slot, tau, row0, col0, seg0, nseg;
-  };
-  static constexpr bool kAScale = false, kDot = false;
-  static constexpr int kTabA = kSegTab, kTabB = kSegTab;
-  const double* dof;
-  const double* t3c;
-  double* mb;
-  const int32_t* goff;
-  const int32_t* seg_atom;
-  const int64_t* seg_brick;
-  int g0, n_rt, n_ct, rows_pt, cols_pt;
-  int N, NA, NR, nRmax;
-  int64_t bs;
-  FastDiv fdNA, fdNR;
-
-  __device__ bool tile(int bx, int by, int bz, Tile& t) const {
-    const int per = n_rt * n_ct;
-    t.slot = bx / per;
-    const int rem = bx % per;
-    t.row0 = (rem % n_rt) * rows_pt;
-    t.col0 = (rem / n_rt) * cols_pt;
-    t.g = g0 + t.slot;
-    t.tau = by;
-    t.seg0 = goff[t.g];
-    t.nseg = goff[t.g + 1] - t.seg0;
-    t.K = NA * t.nseg;
-    t.rows = min(rows_pt, N - t.row0);
-    t.cols = min(cols_pt, NA * NR - t.col0);
-    return t.rows > 0 && t.cols > 0;
+  void begin(int n_piv) {
+    ent.clear();
+    toff.clear();
+    ent0.assign(n_piv, 0);
+    toff0.assign(n_piv, 0);
+    n.assign(n_piv, 0);
+    work.assign(n_piv, 0);
   }
-  __device__ void fill(const Tile& t, int* ta, int* tb, int tid, int nt) const {
-    for (int i = tid; i < t.nseg; i += nt) {
-      ta[i] = seg_atom[t.seg0 + i];
-      tb[i] = (int)seg_brick[t.seg0 + i];
+  void open(int piv) {
+    ent0[piv] = (int)ent.size();
+    toff0[piv] = (int)toff.size();
+    toff.push_back(0);
+  }
+  void add(int piv, const P& p, int gx, int gy, int gz) {
+    ent.push_back(BatchEntry<P>{p, gx, gy});
+    work[piv] += gx * gy * gz;
+    toff.push_back(work[piv]);
+    n[piv]++;
+  }
+  gw_status upload(Scratch& mem, hipStream_t st) {
+    if (ent.size() > cap_ent) {
+      gw_status rc = mem.alloc(&d_ent, ent.size());
+      if (rc != GW_OK) return rc;
+      cap_ent = ent.size();
     }
+    if (toff.size() > cap_toff) {
+      gw_status rc = mem.alloc(&d_toff, toff.size());
+      if (rc != GW_OK) return rc;
+      cap_toff = toff.size();
+    }
+    if (!ent.empty())
+      GW_HIP(hipMemcpyAsync(d_ent, ent.data(), ent.size() * sizeof(ent[0]), hipMemcpyHostToDevice, st));
+    if (!toff.empty())
+      GW_HIP(hipMemcpyAsync(d_toff, toff.data(), toff.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    return GW_OK;
   }
-  __device__ const double* abase(const Tile& t) const { return dof + (int64_t)t.tau * N * N + t.row0; }
-  __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
-    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
-    return (int64_t)(ta[sg] * NA + i) * N;
+  Batched<P> at(int piv) const {
+    Batched<P> b{};
+    b.ent = d_ent + ent0[piv];
+    b.tile_off = d_toff + toff0[piv];
+    b.n_sys = n[piv];
+    return b;
   }
-  __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
-  __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
-    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
-    return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
-  }
-  __device__ double ascale(const Tile&, int) const { return 1.0; }
-  // M_b[tau][sigma][slot][mu][P]: row mu, column (sigma, P)
-  __device__ double* obase(const Tile& t) const {
-    return mb + ((int64_t)t.tau * NA * nRmax + t.slot) * N * NR;
-  }
-  __device__ int64_t rowoff(const Tile& t, int r) const { return (int64_t)(t.row0 + r) * NR; }
-  __device__ int64_t coloff(const Tile& t, int c) const {
-    const int col = t.col0 + c, sg = (int)fdNR.div((uint32_t)col), P = col - sg * NR;
-    return (int64_t)sg * nRmax * N * NR + P;
-  }
-  static constexpr bool kAccum = false;
-  static constexpr double kSign = 1.0;
-  __device__ const double* dbase0(const Tile&) const { return nullptr; }
-  __device__ const double* dbase1(const Tile&) const { return nullptr; }
-  __device__ void dot_out(const Tile&, double, double) const {}
 };
 
-struct StageB {
-  struct Tile : TileBase {
-    int g, row0, col0, seg0, nseg, p, cl, slot, KU;
-  };
-  static constexpr bool kAScale = false, kDot = false;
-  static constexpr int kTabA = kSegTab, kTabB = kSegTab;
-  const double* dvg;        // [N][RS]
-  const double* t3c;
-  double* bp;
-  const int32_t* goff;
-  const int32_t* seg_atom;
-  const int64_t* seg_brick;
-  const int32_t* gc;
-  const int32_t* gslot;
-  const int32_t* ulen;
-  const int64_t* bp_off;
-  int n_rt, n_ct, rows_pt, cols_pt;
-  int RS, NA, NR, PG, PC;
-  int64_t bs, BPS;
-  FastDiv fdNA, fdNR;
-
-  __device__ bool tile(int bx, int, int, Tile& t) const {
-    const int per = n_rt * n_ct;
-    t.g = bx / per;
-    const int rem = bx % per;
-    t.row0 = (rem % n_rt) * rows_pt;
-    t.col0 = (rem / n_rt) * cols_pt;
-    t.seg0 = goff[t.g];
-    t.nseg = goff[t.g + 1] - t.seg0;
-    t.K = NA * t.nseg;
-    const int c = gc[t.g];
-    t.p = c / PG;
-    t.cl = c % PG;
-    t.slot = gslot[t.g];
-    t.KU = NA * ulen[t.p];
-    t.rows = min(rows_pt, RS - t.row0);
-    t.cols = min(cols_pt, NA * NR - t.col0);
-    return t.rows > 0 && t.cols > 0;
-  }
-  __device__ void fill(const Tile& t, int* ta, int* tb, int tid, int nt) const {
-    for (int i = tid; i < t.nseg; i += nt) {
-      ta[i] = seg_atom[t.seg0 + i];
-      tb[i] = (int)seg_brick[t.seg0 + i];
-    }
-  }
-  __device__ const double* abase(const Tile& t) const { return dvg + t.row0; }
-  __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
-    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
-    return (int64_t)(ta[sg] * NA + i) * RS;
-  }
-  __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
-  __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
-    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
-    return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
-  }
-  __device__ double ascale(const Tile&, int) const { return 1.0; }
-  // N_b panel: [tau][panel][sigma][u = slot*NA + mu][(cl, Q)]: row (tau, sigma), column (mu, Q)
-  __device__ double* obase(const Tile& t) const { return bp + bp_off[t.p]; }
-  __device__ int64_t rowoff(const Tile& t, int r) const {
-    const int row = t.row0 + r, tau = (int)fdNA.div((uint32_t)row), sg = row - tau * NA;
-    return (int64_t)tau * BPS + (int64_t)sg * t.KU * PC;
-  }
-  __device__ int64_t coloff(const Tile& t, int c) const {
-    const int col = t.col0 + c, mul = (int)fdNR.div((uint32_t)col), Q = col - mul * NR;
-    return (int64_t)(t.slot * NA + mul) * PC + t.cl * NR + Q;
-  }
-  static constexpr bool kAccum = false;
-  static constexpr double kSign = 1.0;
-  __device__ const double* dbase0(const Tile&) const { return nullptr; }
-  __device__ const double* dbase1(const Tile&) const { return nullptr; }
-  __device__ void dot_out(const Tile&, double, double) const {}
+// One system of a plan.
+struct SysPlan {
+  gw_system s{};
+  int na = 0, N = 0, NRI = 0, n_groups = 0, nRmax = 1, PG = 1, PC = 0, n_pan = 0;
+  int64_t bs = 0, BPS = 0, BPS16 = 0;
+  BrickGroups G;
+  Panels pan;
+  std::vector<int32_t> acount;
+  std::vector<double> asuffix;
+  double fl_a = 0.0, fl_b = 0.0, fl_c = 0.0;   // FLOPs per tau (all blocks)
+  double *dof = nullptr, *dvf = nullptr, *dvg = nullptr, *mb = nullptr, *bp = nullptr;
+  uint8_t* dropped = nullptr;
+  uint16_t *th = nullptr, *tl = nullptr, *doh = nullptr, *dol = nullptr, *dvh = nullptr, *dvl = nullptr;
+  uint16_t *mh = nullptr, *ml = nullptr, *nh = nullptr, *nl = nullptr;
+  uint8_t* keep = nullptr;          // screener mask (one-system calls only)
+  StageA sa{};
+  StageB sb{};
+  StageC sc{};
+  StageABf ba{};
+  StageBBf bb{};
+  StageCBf bc{};
 };
-
-// true if some upper (c <= c') block of the tile is kept by the screener
-__device__ inline bool any_kept(const uint8_t* keep, const int32_t* slot_c, int s0, int s1,
-                                int c0, int c1, int tau, int na) {
-  const uint8_t* k = keep + (int64_t)tau * na * na;
-  for (int sl = s0; sl <= s1; ++sl) {
-    const int c = slot_c[sl];
-    for (int c2 = c0; c2 <= c1; ++c2)
-      if (c <= c2 && k[(int64_t)c * na + c2]) return true;
-  }
-  return false;
-}
-
-struct StageC {
-  struct Tile : TileBase {
-    int p, tau, row0, KU, km0;
-    FastDiv fdKU;
-  };
-  static constexpr bool kAScale = false, kDot = false;
-  static constexpr int kTabA = kPanTab, kTabB = 0;
-  const double* mb;
-  const double* bp;
-  double* chi;
-  const int32_t* gc;
-  const int32_t* kmap;
-  const int32_t* km_off;
-  const int32_t* ulen;
-  const int64_t* bp_off;
-  int g0, nR, n_rt, rows_pt;
-  int N, NA, NR, NRI, PG, PC, nRmax, n_atoms;
-  int64_t BPS;
-  FastDiv fdNR;
-  const uint8_t* keep;      // screener mask [tau][c][c'] (c <= c'), or null
-  int* tiles_skipped;
-
-  __device__ bool tile(int bx, int by, int bz, Tile& t) const {
-    t.row0 = (bx % n_rt) * rows_pt;
-    t.p = bx / n_rt;
-    t.tau = bz;
-    t.rows = min(rows_pt, nR * NR - t.row0);
-    t.cols = min(PC, NRI - t.p * PC);
-    if (t.rows <= 0 || t.cols <= 0) return false;
-    const int c_min = gc[g0 + t.row0 / NR];
-    const int cp_max = min(t.p * PG + PG - 1, n_atoms - 1);
-    if (c_min > cp_max) return false;          // strictly below the block diagonal
-    if (keep && !any_kept(keep, gc + g0, t.row0 / NR, (t.row0 + t.rows - 1) / NR, t.p * PG, cp_max,
-                          t.tau, n_atoms)) {
-      if (threadIdx.x == 0) atomicAdd(tiles_skipped, 1);
-      return false;
-    }
-    t.KU = NA * ulen[t.p];
-    t.km0 = km_off[t.p];
-    t.K = NA * t.KU;
-    t.fdKU.set((uint32_t)t.KU);
-    return t.K > 0;
-  }
-  __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
-    for (int i = tid; i < t.KU; i += nt) ta[i] = kmap[t.km0 + i] * NR;
-  }
-  __device__ const double* abase(const Tile& t) const {
-    return mb + (int64_t)t.tau * NA * nRmax * N * NR;
-  }
-  __device__ int64_t aroff(const Tile& t, int r) const {
-    const int row = t.row0 + r, sl = (int)fdNR.div((uint32_t)row);
-    return (int64_t)sl * N * NR + (row - sl * NR);
-  }
-  __device__ int64_t akoff(const Tile& t, int k, const int* ta) const {
-    const int sg = (int)t.fdKU.div((uint32_t)k), u = k - sg * t.KU;
-    return (int64_t)sg * nRmax * N * NR + ta[u];
-  }
-  __device__ const double* bbase(const Tile& t) const {
-    return bp + (int64_t)t.tau * BPS + bp_off[t.p];
-  }
-  __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PC; }
-  __device__ double ascale(const Tile&, int) const { return 1.0; }
-  // chi[tau][P][Q] -= tile, P = (RI atom of the row's slot, P), Q = panel column
-  __device__ double* obase(const Tile& t) const { return chi + (int64_t)t.tau * NRI * NRI; }
-  __device__ int64_t rowoff(const Tile& t, int r) const {
-    const int row = t.row0 + r, sl = (int)fdNR.div((uint32_t)row), P = row - sl * NR;
-    return ((int64_t)gc[g0 + sl] * NR + P) * NRI;
-  }
-  __device__ int64_t coloff(const Tile& t, int c) const { return (int64_t)t.p * PC + c; }
-  static constexpr bool kAccum = true;
-  static constexpr double kSign = -1.0;
-  __device__ const double* dbase0(const Tile&) const { return nullptr; }
-  __device__ const double* dbase1(const Tile&) const { return nullptr; }
-  __device__ void dot_out(const Tile&, double, double) const {}
-};
-
-__global__ void gather_dvir_kernel(const double* __restrict__ dv, double* __restrict__ dvg, int N,
-                                   int NA, int n_tau, int b) {
-  const int RS = n_tau * NA;
-  const int64_t total = (int64_t)N * RS;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int nu = (int)(e / RS), rc = (int)(e % RS);
-    const int tau = rc / NA, sg = rc % NA;
-    dvg[e] = dv[(int64_t)tau * N * N + (int64_t)nu * N + (int64_t)b * NA + sg];
-  }
-}
-
-template <int WM>
-hipError_t launch_stage_b(StageB sb, int n_groups, hipStream_t st) {
-  sb.rows_pt = 32 * WM;
-  sb.cols_pt = AB_COLS;
-  sb.n_rt = (sb.RS + sb.rows_pt - 1) / sb.rows_pt;
-  sb.n_ct = (sb.NA * sb.NR + sb.cols_pt - 1) / sb.cols_pt;
-  return launch_tile_gemm<WM, AB_WN, AB_NBW, 16>(sb, dim3((unsigned)(n_groups * sb.n_rt * sb.n_ct)), st);
-}
-
-#include "chi_bf16x3.inc"
 
 }  // namespace
 }  // namespace gw
 
 using namespace gw;
+
+struct gw_chi_batch {
+  int n_sys = 0, n_tau = 0, NA = 0, NR = 0, prec = GW_FP64, max_na = 0;
+  double eps_f = 0.0;
+  bool timing = false;
+  Scratch mem;
+  std::vector<SysPlan> sys;
+  std::vector<int> order;            // systems by decreasing size
+  int variant = 0, persistent = 0;
+  int RS = 0;
+  Table<StageA> tA;
+  Table<StageB> tB;
+  Table<StageC> tC;
+  Table<StageABf> tAb;
+  Table<StageBBf> tBb;
+  Table<StageCBf> tCb;
+  std::vector<GatherEnt> gath;
+  std::vector<int> gath0, gathn;
+  GatherEnt* d_gath = nullptr;
+  int* queues = nullptr;
+  int n_queues = 0;
+  int* tiles_skipped = nullptr;
+  // pointers the stage-C tables and the captured graph were built for
+  std::vector<double*> bound_chi;
+  std::vector<const double*> g_occ, g_vir;
+  int c_built_variant = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_variant = -1, g_persistent = -1;
+  hipStream_t g_stream = nullptr;
+  std::vector<hipEvent_t> ev;        // per-stage timing events (eager runs)
+
+  explicit gw_chi_batch(hipStream_t st) : mem(st, false) {}
+  ~gw_chi_batch() {
+    drop_graph();
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  }
+};
+
+namespace gw {
+namespace {
+
+gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream_t st) {
+  const int n_tau = B.n_tau, NA = B.NA, NR = B.NR;
+  P.s = *s;
+  P.na = s->n_atoms;
+  P.N = P.na * NA;
+  P.NRI = P.na * NR;
+  P.bs = (int64_t)NA * NA * NR;
+  const int na = P.na, N = P.N;
+  gw_status rc;
+  if (s->n_trip > 0) {
+    Scratch tmp(st);
+    if ((rc = build_groups(s, B.eps_f, st, tmp, P.G)) != GW_OK) return rc;
+  } else {
+    P.G.goff.assign(1, 0);
+    P.G.gb_start.assign(na + 1, 0);
+  }
+  const BrickGroups& G = P.G;
+  P.n_groups = G.n_groups();
+  P.nRmax = 1;
+  for (int b = 0; b < na; ++b) P.nRmax = std::max(P.nRmax, G.gb_start[b + 1] - G.gb_start[b]);
+  P.PG = std::max(1, C_COLS / NR);
+  P.PC = P.PG * NR;
+  P.pan = build_panels(na, P.PG, P.PC, G.gc, G.gs, NA, NA);
+  P.n_pan = P.pan.n_pan;
+  P.BPS = P.pan.off[P.n_pan];
+  for (int g = 0; g < P.n_groups; ++g)
+    GW_CHECK_ARG(G.goff[g + 1] - G.goff[g] <= kSegTab, "too many bricks in one (atom, RI atom) group");
+  for (int p = 0; p < P.n_pan; ++p)
+    GW_CHECK_ARG(NA * P.pan.ulen[p] <= kPanTab, "too many AO atoms coupled to one RI column panel");
+
+  // FLOPs of the three stages per tau (every output block computed)
+  P.acount.assign(na, 0);
+  for (int g = 0; g < P.n_groups; ++g) P.acount[G.gc[g]]++;
+  P.asuffix.assign(na + 1, 0.0);
+  for (int c = na - 1; c >= 0; --c) P.asuffix[c] = P.asuffix[c + 1] + P.acount[c];
+  const double nnz = (double)G.n_kept * P.bs;
+  for (int b = 0; b < na; ++b) {
+    const int g0 = G.gb_start[b], nR = G.gb_start[b + 1] - g0;
+    if (nR == 0) continue;
+    int64_t nnz_b = 0;
+    for (int g = g0; g < g0 + nR; ++g) nnz_b += (int64_t)(G.goff[g + 1] - G.goff[g]) * P.bs;
+    P.fl_a += 2.0 * N * (double)nnz_b;
+    P.fl_b += 2.0 * NA * nnz;
+    for (int g = g0; g < g0 + nR; ++g) P.fl_c += 2.0 * NR * NR * NA * NA * P.asuffix[G.gc[g]];
+  }
+
+  // scratch of the plan (one pivot's half-contracted tensors)
+  Scratch& M = B.mem;
+  const int RS = n_tau * NA;
+  const size_t dsz = (size_t)n_tau * N * N, nflag = (size_t)n_tau * na * na;
+  if ((rc = M.alloc(&P.dof, dsz)) != GW_OK) return rc;
+  if ((rc = M.alloc(&P.dvf, dsz)) != GW_OK) return rc;
+  if ((rc = M.alloc(&P.dropped, 3 * nflag)) != GW_OK) return rc;
+  int32_t *d_goff, *d_seg_atom, *d_gc, *d_gslot, *d_ulen, *d_kmap, *d_km_off;
+  int64_t *d_seg_brick, *d_bp_off;
+  if ((rc = M.upload(&d_goff, G.goff)) != GW_OK) return rc;
+  if ((rc = M.upload(&d_seg_atom, G.seg_atom)) != GW_OK) return rc;
+  if ((rc = M.upload(&d_seg_brick, G.seg_brick)) != GW_OK) return rc;
+  if ((rc = M.upload(&d_gc, G.gc)) != GW_OK) return rc;
+  if ((rc = M.upload(&d_gslot, P.pan.gslot)) != GW_OK) return rc;
+  if ((rc = M.upload(&d_ulen, P.pan.ulen)) != GW_OK) return rc;
+  if ((rc = M.upload(&d_kmap, P.pan.kmap)) != GW_OK) return rc;
+  if ((rc = M.upload(&d_km_off, P.pan.km_off)) != GW_OK) return rc;
+  if ((rc = M.upload(&d_bp_off, P.pan.off)) != GW_OK) return rc;
+
+  if (B.prec == GW_FP64) {
+    if ((rc = M.alloc(&P.dvg, (size_t)N * RS)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.mb, (size_t)n_tau * NA * P.nRmax * N * NR)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.bp, (size_t)n_tau * P.BPS)) != GW_OK) return rc;
+    // entries of N_b that no group writes stay zero for the life of the plan
+    GW_HIP(hipMemsetAsync(P.bp, 0, sizeof(double) * (size_t)n_tau * P.BPS, st));
+
+    StageA& sa = P.sa;
+    sa.dof = P.dof; sa.t3c = s->t3c; sa.mb = P.mb; sa.goff = d_goff; sa.seg_atom = d_seg_atom;
+    sa.seg_brick = d_seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = AB_COLS;
+    sa.n_rt = (N + sa.rows_pt - 1) / sa.rows_pt;
+    sa.n_ct = (NA * NR + sa.cols_pt - 1) / sa.cols_pt;
+    sa.N = N; sa.NA = NA; sa.NR = NR; sa.nRmax = P.nRmax; sa.bs = P.bs;
+    sa.fdNA.set((uint32_t)NA);
+    sa.fdNR.set((uint32_t)NR);
+
+    StageB& sb = P.sb;
+    sb.dvg = P.dvg; sb.t3c = s->t3c; sb.bp = P.bp; sb.goff = d_goff; sb.seg_atom = d_seg_atom;
+    sb.seg_brick = d_seg_brick; sb.gc = d_gc; sb.gslot = d_gslot; sb.ulen = d_ulen;
+    sb.bp_off = d_bp_off; sb.RS = RS; sb.NA = NA; sb.NR = NR; sb.PG = P.PG; sb.PC = P.PC;
+    sb.bs = P.bs; sb.BPS = P.BPS;
+    sb.rows_pt = 32 * b_wm(RS);
+    sb.cols_pt = AB_COLS;
+    sb.n_rt = (RS + sb.rows_pt - 1) / sb.rows_pt;
+    sb.n_ct = (NA * NR + sb.cols_pt - 1) / sb.cols_pt;
+    sb.fdNA.set((uint32_t)NA);
+    sb.fdNR.set((uint32_t)NR);
+
+    StageC& sc = P.sc;
+    sc.mb = P.mb; sc.bp = P.bp; sc.gc = d_gc; sc.kmap = d_kmap; sc.km_off = d_km_off;
+    sc.ulen = d_ulen; sc.bp_off = d_bp_off; sc.N = N; sc.NA = NA; sc.NR = NR; sc.NRI = P.NRI;
+    sc.PG = P.PG; sc.PC = P.PC; sc.nRmax = P.nRmax; sc.n_atoms = na; sc.BPS = P.BPS;
+    sc.fdNR.set((uint32_t)NR);
+  } else {
+    // split-precision form: operands as bf16 hi/lo pairs; T is split once per plan
+    std::vector<int64_t> poffb(P.n_pan + 1, 0);
+    for (int p = 0; p < P.n_pan; ++p)
+      poffb[p + 1] = poffb[p] + (int64_t)NA * P.pan.ulen[p] * P.PC * 16;
+    P.BPS16 = poffb[P.n_pan];
+    int64_t* d_poffb;
+    if ((rc = M.upload(&d_poffb, poffb)) != GW_OK) return rc;
+    const size_t tsz = (size_t)s->n_trip * NR * NA * 16, dsz16 = (size_t)n_tau * N * na * 16;
+    const size_t msz = (size_t)n_tau * P.nRmax * N * NR * 16, nsz = (size_t)n_tau * P.BPS16;
+    if ((rc = M.alloc(&P.th, tsz)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.tl, tsz)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.doh, dsz16)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.dol, dsz16)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.dvh, dsz16)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.dvl, dsz16)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.mh, msz)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.ml, msz)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.nh, nsz)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.nl, nsz)) != GW_OK) return rc;
+    // padding lanes (sigma >= NA) and uncoupled panel entries stay zero
+    GW_HIP(hipMemsetAsync(P.mh, 0, 2 * msz, st));
+    GW_HIP(hipMemsetAsync(P.ml, 0, 2 * msz, st));
+    GW_HIP(hipMemsetAsync(P.nh, 0, 2 * nsz, st));
+    GW_HIP(hipMemsetAsync(P.nl, 0, 2 * nsz, st));
+    if (s->n_trip > 0) {
+      const unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)tsz + 255) / 256, 1 << 20);
+      hipLaunchKernelGGL(split_t_kernel, dim3(blocks), dim3(256), 0, st, s->t3c, P.th, P.tl,
+                         s->n_trip, NA, NR);
+      GW_HIP(hipGetLastError());
+    }
+
+    StageABf& ba = P.ba;
+    ba.dh = P.doh; ba.dl = P.dol; ba.th = P.th; ba.tl = P.tl; ba.mh = P.mh; ba.ml = P.ml;
+    ba.goff = d_goff; ba.seg_atom = d_seg_atom; ba.seg_brick = d_seg_brick;
+    ba.rows_pt = 16 * 4 * 4; ba.cols_pt = 16 * BF_NB_AB * BF_WN;
+    ba.n_rt = (N + ba.rows_pt - 1) / ba.rows_pt;
+    ba.n_ct = (NA * NR + ba.cols_pt - 1) / ba.cols_pt;
+    ba.N = N; ba.NA = NA; ba.NR = NR; ba.na = na; ba.nRmax = P.nRmax;
+    ba.fdNA.set((uint32_t)NA);
+
+    StageBBf& bb = P.bb;
+    bb.dh = P.dvh; bb.dl = P.dvl; bb.th = P.th; bb.tl = P.tl; bb.nh = P.nh; bb.nl = P.nl;
+    bb.goff = d_goff; bb.seg_atom = d_seg_atom; bb.seg_brick = d_seg_brick; bb.gc = d_gc;
+    bb.gslot = d_gslot; bb.poffb = d_poffb; bb.N = N; bb.NA = NA; bb.NR = NR; bb.na = na;
+    bb.RS = RS; bb.PG = P.PG; bb.PC = P.PC; bb.BPS16 = P.BPS16;
+    bb.rows_pt = 16 * b_rb(RS) * 2;
+    bb.cols_pt = 16 * BF_NB_AB * BF_WN;
+    bb.n_rt = (RS + bb.rows_pt - 1) / bb.rows_pt;
+    bb.n_ct = (NA * NR + bb.cols_pt - 1) / bb.cols_pt;
+    bb.fdNA.set((uint32_t)NA);
+
+    StageCBf& bc = P.bc;
+    bc.mh = P.mh; bc.ml = P.ml; bc.nh = P.nh; bc.nl = P.nl; bc.gc = d_gc; bc.kmap = d_kmap;
+    bc.km_off = d_km_off; bc.ulen = d_ulen; bc.poffb = d_poffb; bc.N = N; bc.NA = NA;
+    bc.NR = NR; bc.NRI = P.NRI; bc.PG = P.PG; bc.PC = P.PC; bc.nRmax = P.nRmax;
+    bc.n_atoms = na; bc.BPS16 = P.BPS16;
+    bc.fdNR.set((uint32_t)NR);
+  }
+  return GW_OK;
+}
+
+// tables of stages A and B (and the D^vir gathers) for every pivot index
+gw_status build_ab_tables(gw_chi_batch& B, hipStream_t st) {
+  const int n_piv = B.max_na, n_tau = B.n_tau;
+  const bool fp64 = B.prec == GW_FP64;
+  if (fp64) {
+    B.tA.begin(n_piv);
+    B.tB.begin(n_piv);
+    B.gath.clear();
+    B.gath0.assign(n_piv, 0);
+    B.gathn.assign(n_piv, 0);
+  } else {
+    B.tAb.begin(n_piv);
+    B.tBb.begin(n_piv);
+  }
+  for (int piv = 0; piv < n_piv; ++piv) {
+    if (fp64) {
+      B.tA.open(piv);
+      B.tB.open(piv);
+      B.gath0[piv] = (int)B.gath.size();
+    } else {
+      B.tAb.open(piv);
+      B.tBb.open(piv);
+    }
+    for (int m : B.order) {
+      SysPlan& P = B.sys[m];
+      if (piv >= P.na) continue;
+      const int g0 = P.G.gb_start[piv], nR = P.G.gb_start[piv + 1] - g0;
+      if (nR == 0) continue;
+      if (fp64) {
+        StageA a = P.sa;
+        a.g0 = g0;
+        B.tA.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
+        B.tB.add(piv, P.sb, P.n_groups * P.sb.n_rt * P.sb.n_ct, 1, 1);
+        B.gath.push_back(GatherEnt{P.dvf, P.dvg, P.N, piv});
+        B.gathn[piv]++;
+      } else {
+        StageABf a = P.ba;
+        a.g0 = g0;
+        B.tAb.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
+        StageBBf b = P.bb;
+        b.b = piv;
+        B.tBb.add(piv, b, P.n_groups * b.n_rt * b.n_ct, 1, 1);
+      }
+    }
+  }
+  gw_status rc;
+  if (fp64) {
+    if ((rc = B.tA.upload(B.mem, st)) != GW_OK) return rc;
+    if ((rc = B.tB.upload(B.mem, st)) != GW_OK) return rc;
+    if ((rc = B.mem.upload(&B.d_gath, B.gath)) != GW_OK) return rc;
+  } else {
+    if ((rc = B.tAb.upload(B.mem, st)) != GW_OK) return rc;
+    if ((rc = B.tBb.upload(B.mem, st)) != GW_OK) return rc;
+  }
+  return GW_OK;
+}
+
+// stage-C tables for the current variant and output pointers
+gw_status build_c_tables(gw_chi_batch& B, double* const* chi, hipStream_t st) {
+  const int n_piv = B.max_na, n_tau = B.n_tau, rows = c_rows(B.prec, B.variant);
+  const bool fp64 = B.prec == GW_FP64;
+  if (fp64) B.tC.begin(n_piv);
+  else B.tCb.begin(n_piv);
+  for (int piv = 0; piv < n_piv; ++piv) {
+    if (fp64) B.tC.open(piv);
+    else B.tCb.open(piv);
+    for (int m : B.order) {
+      SysPlan& P = B.sys[m];
+      if (piv >= P.na) continue;
+      const int g0 = P.G.gb_start[piv], nR = P.G.gb_start[piv + 1] - g0;
+      if (nR == 0) continue;
+      const int n_rt = (nR * B.NR + rows - 1) / rows;
+      if (fp64) {
+        StageC c = P.sc;
+        c.chi = chi[m];
+        c.g0 = g0;
+        c.nR = nR;
+        c.rows_pt = rows;
+        c.n_rt = n_rt;
+        c.keep = P.keep;
+        c.tiles_skipped = B.tiles_skipped;
+        B.tC.add(piv, c, n_rt * P.n_pan, 1, n_tau);
+      } else {
+        StageCBf c = P.bc;
+        c.chi = chi[m];
+        c.g0 = g0;
+        c.nR = nR;
+        c.rows_pt = rows;
+        c.n_rt = n_rt;
+        c.keep = P.keep;
+        c.tiles_skipped = B.tiles_skipped;
+        B.tCb.add(piv, c, n_rt * P.n_pan, 1, n_tau);
+      }
+    }
+  }
+  B.bound_chi.assign(chi, chi + B.n_sys);
+  B.c_built_variant = B.variant;
+  return fp64 ? B.tC.upload(B.mem, st) : B.tCb.upload(B.mem, st);
+}
+
+// With queue == nullptr the call only computes the persistent grid size of
+// the kernel (done at plan creation, outside any graph capture).
+template <int WM, int WN, int NB, int KC, class P>
+hipError_t run_f64(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t st) {
+  if (!queue) {
+    (void)persistent_cap_gemm<WM, WN, NB, KC, Batched<P>>();
+    return hipSuccess;
+  }
+  const int work = T.work[piv];
+  if (T.n[piv] == 0 || work == 0) return hipSuccess;
+  if (!pers && T.n[piv] == 1) {         // one system: its own 3D grid, problem in kernel arguments
+    const BatchEntry<P>& e = T.ent[T.ent0[piv]];
+    return launch_tile_gemm<WM, WN, NB, KC>(e.p, dim3(e.gx, e.gy, work / (e.gx * e.gy)), st);
+  }
+  const Batched<P> b = T.at(piv);
+  return pers ? launch_tile_gemm_persistent<WM, WN, NB, KC>(b, work, queue, st)
+              : launch_tile_gemm<WM, WN, NB, KC>(b, dim3((unsigned)work), st);
+}
+
+template <int WM, int WN, int RB, int NB, int KC, class P>
+hipError_t run_bf(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t st) {
+  if (!queue) {
+    (void)persistent_cap_bf16x3<WM, WN, RB, NB, KC, Batched<P>>();
+    return hipSuccess;
+  }
+  const int work = T.work[piv];
+  if (T.n[piv] == 0 || work == 0) return hipSuccess;
+  if (!pers && T.n[piv] == 1) {
+    const BatchEntry<P>& e = T.ent[T.ent0[piv]];
+    return launch_tile_bf16x3<WM, WN, RB, NB, KC>(e.p, dim3(e.gx, e.gy, work / (e.gx * e.gy)), st);
+  }
+  const Batched<P> b = T.at(piv);
+  return pers ? launch_tile_bf16x3_persistent<WM, WN, RB, NB, KC>(b, work, queue, st)
+              : launch_tile_bf16x3<WM, WN, RB, NB, KC>(b, dim3((unsigned)work), st);
+}
+
+hipError_t stage_b_f64(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  switch (b_wm(B.RS)) {
+    case 2: return run_f64<2, AB_WN, AB_NBW, 16>(B.tB, piv, pers, q, st);
+    case 3: return run_f64<3, AB_WN, AB_NBW, 16>(B.tB, piv, pers, q, st);
+    case 5: return run_f64<5, AB_WN, AB_NBW, 16>(B.tB, piv, pers, q, st);
+    default: return run_f64<4, AB_WN, AB_NBW, 16>(B.tB, piv, pers, q, st);
+  }
+}
+hipError_t stage_c_f64(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  switch (B.variant) {
+    case 1: return run_f64<2, C_WN, C_NBW, C_KC>(B.tC, piv, pers, q, st);
+    case 2: return run_f64<4, C_WN, C_NBW, 16>(B.tC, piv, pers, q, st);
+    default: return run_f64<4, C_WN, C_NBW, C_KC>(B.tC, piv, pers, q, st);
+  }
+}
+hipError_t stage_b_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  switch (b_rb(B.RS)) {
+    case 2: return run_bf<2, BF_WN, 2, BF_NB_AB, BF_KC>(B.tBb, piv, pers, q, st);
+    case 3: return run_bf<2, BF_WN, 3, BF_NB_AB, BF_KC>(B.tBb, piv, pers, q, st);
+    case 4: return run_bf<2, BF_WN, 4, BF_NB_AB, BF_KC>(B.tBb, piv, pers, q, st);
+    default: return run_bf<2, BF_WN, 5, BF_NB_AB, BF_KC>(B.tBb, piv, pers, q, st);
+  }
+}
+hipError_t stage_c_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  switch (B.variant) {
+    case 1: return run_bf<4, BF_WN, 2, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
+    case 2: return run_bf<2, BF_WN, 4, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
+    default: return run_bf<4, BF_WN, 4, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
+  }
+}
+
+// persistent grid sizes of every kernel a plan may launch
+void prime(gw_chi_batch& B) {
+  const int v0 = B.variant;
+  for (int v = 0; v < kNVar; ++v) {
+    B.variant = v;
+    if (B.prec == GW_FP64) {
+      (void)run_f64<A_WM, AB_WN, AB_NBW, 16>(B.tA, 0, true, nullptr, nullptr);
+      (void)stage_b_f64(B, 0, true, nullptr, nullptr);
+      (void)stage_c_f64(B, 0, true, nullptr, nullptr);
+    } else {
+      (void)run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, 0, true, nullptr, nullptr);
+      (void)stage_b_bf(B, 0, true, nullptr, nullptr);
+      (void)stage_c_bf(B, 0, true, nullptr, nullptr);
+    }
+  }
+  B.variant = v0;
+}
+
+// Every launch of one execution, in stream order (no allocation, copy,
+// memset or synchronization: the sequence may be captured into a graph).
+// With `ev` (eager runs only) events bracket each stage of each pivot.
+gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const* vir,
+                  double* const* chi, std::vector<hipEvent_t>* ev, hipStream_t st) {
+  const int n_tau = B.n_tau, NA = B.NA, NR = B.NR;
+  const bool fp64 = B.prec == GW_FP64, pers = B.persistent != 0;
+  GW_HIP(fill_zero(B.queues, B.n_queues, st));
+  for (int m = 0; m < B.n_sys; ++m) {
+    SysPlan& P = B.sys[m];
+    const size_t nflag = (size_t)n_tau * P.na * P.na;
+    GW_HIP(fill_zero(chi[m], 2 * (int64_t)n_tau * P.NRI * P.NRI, st));
+    if (P.s.n_trip == 0) continue;
+    GW_HIP(filter_square_blocks(occ[m], P.dof, n_tau, P.na, NA, B.eps_f, P.dropped, st));
+    GW_HIP(filter_square_blocks(vir[m], P.dvf, n_tau, P.na, NA, B.eps_f, P.dropped + nflag, st));
+    if (!fp64) {
+      const int64_t dsz16 = (int64_t)n_tau * P.N * P.na * 16;
+      const unsigned blocks = (unsigned)std::min<int64_t>((dsz16 + 255) / 256, 1 << 20);
+      hipLaunchKernelGGL(split_d_kernel, dim3(blocks), dim3(256), 0, st, P.dof, P.doh, P.dol, n_tau,
+                         P.N, P.na, NA);
+      GW_HIP(hipGetLastError());
+      hipLaunchKernelGGL(split_d_kernel, dim3(blocks), dim3(256), 0, st, P.dvf, P.dvh, P.dvl, n_tau,
+                         P.N, P.na, NA);
+      GW_HIP(hipGetLastError());
+    }
+  }
+  auto mark = [&](int piv, int k) -> hipError_t {
+    return ev ? hipEventRecord((*ev)[4 * piv + k], st) : hipSuccess;
+  };
+  for (int piv = 0; piv < B.max_na; ++piv) {
+    int* q = B.queues + 3 * piv;
+    if (fp64) {
+      if (B.gathn[piv] > 0) {
+        int64_t most = 0;
+        for (int e = 0; e < B.gathn[piv]; ++e)
+          most = std::max<int64_t>(most, (int64_t)B.gath[B.gath0[piv] + e].N * n_tau * NA);
+        const unsigned bx = (unsigned)std::min<int64_t>((most + 255) / 256, 4096);
+        hipLaunchKernelGGL(gather_dvir_kernel, dim3(bx, (unsigned)B.gathn[piv]), dim3(256), 0, st,
+                           B.d_gath + B.gath0[piv], NA, n_tau);
+        GW_HIP(hipGetLastError());
+      }
+      GW_HIP(mark(piv, 0));
+      GW_HIP((run_f64<A_WM, AB_WN, AB_NBW, 16>(B.tA, piv, pers, q, st)));
+      GW_HIP(mark(piv, 1));
+      GW_HIP(stage_b_f64(B, piv, pers, q + 1, st));
+      GW_HIP(mark(piv, 2));
+      GW_HIP(stage_c_f64(B, piv, pers, q + 2, st));
+      GW_HIP(mark(piv, 3));
+    } else {
+      GW_HIP(mark(piv, 0));
+      GW_HIP((run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, piv, pers, q, st)));
+      GW_HIP(mark(piv, 1));
+      GW_HIP(stage_b_bf(B, piv, pers, q + 1, st));
+      GW_HIP(mark(piv, 2));
+      GW_HIP(stage_c_bf(B, piv, pers, q + 2, st));
+      GW_HIP(mark(piv, 3));
+    }
+  }
+  // symmetric completion and output filter
+  for (int m = 0; m < B.n_sys; ++m) {
+    SysPlan& P = B.sys[m];
+    if (P.s.n_trip == 0) continue;
+    const size_t nflag = (size_t)n_tau * P.na * P.na;
+    GW_HIP(mirror_lower_blocks(chi[m], n_tau, P.NRI, NR, st));
+    if (P.keep) GW_HIP(zero_unkept_blocks(chi[m], n_tau, P.na, NR, P.keep, st));
+    if (B.eps_f > 0.0)
+      GW_HIP(filter_square_blocks(chi[m], chi[m], n_tau, P.na, NR, B.eps_f, P.dropped + 2 * nflag, st));
+  }
+  return GW_OK;
+}
+
+gw_status check_ptrs(const gw_chi_batch* B, const double* const* occ, const double* const* vir,
+                     double* const* chi) {
+  GW_CHECK_ARG(occ && vir && chi, "d_occ, d_vir and chi arrays must be non-null");
+  for (int m = 0; m < B->n_sys; ++m)
+    GW_CHECK_ARG(occ[m] && vir[m] && chi[m], "every d_occ, d_vir and chi pointer must be non-null");
+  return GW_OK;
+}
+
+// One execution: eager launches, or replay of the captured graph (captured
+// on first use and again whenever the pointers or the configuration change).
+gw_status execute(gw_chi_batch& B, const double* const* occ, const double* const* vir,
+                  double* const* chi, bool use_graph, gw_chi_stats* stats, hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  gw_status rc;
+  const bool rebind = B.c_built_variant != B.variant ||
+                      !std::equal(B.bound_chi.begin(), B.bound_chi.end(), chi) ||
+                      (int)B.bound_chi.size() != B.n_sys;
+  if (rebind) {
+    B.drop_graph();
+    if ((rc = build_c_tables(B, chi, st)) != GW_OK) return rc;
+  }
+  const bool timing = B.timing && !use_graph;
+  if (use_graph) {
+    const bool same = B.gexec && B.g_variant == B.variant && B.g_persistent == B.persistent &&
+                      B.g_stream == st && std::equal(B.g_occ.begin(), B.g_occ.end(), occ) &&
+                      std::equal(B.g_vir.begin(), B.g_vir.end(), vir);
+    if (!same) {
+      B.drop_graph();
+      GW_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      rc = enqueue(B, occ, vir, chi, nullptr, st);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(st, &g);
+      if (rc != GW_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      GW_HIP(e);
+      B.graph = g;
+      GW_HIP(hipGraphInstantiate(&B.gexec, B.graph, nullptr, nullptr, 0));
+      B.g_variant = B.variant;
+      B.g_persistent = B.persistent;
+      B.g_stream = st;
+      B.g_occ.assign(occ, occ + B.n_sys);
+      B.g_vir.assign(vir, vir + B.n_sys);
+    }
+    GW_HIP(hipGraphLaunch(B.gexec, st));
+  } else {
+    if (timing && B.ev.size() < 4 * (size_t)B.max_na) {
+      while (B.ev.size() < 4 * (size_t)B.max_na) {
+        hipEvent_t e;
+        GW_HIP(hipEventCreate(&e));
+        B.ev.push_back(e);
+      }
+    }
+    if ((rc = enqueue(B, occ, vir, chi, timing ? &B.ev : nullptr, st)) != GW_OK) return rc;
+  }
+
+  if (stats) {
+    *stats = gw_chi_stats{};
+    int64_t dd = 0, dc = 0, kept = 0;
+    double fa = 0.0, fb = 0.0, fc = 0.0;
+    for (const SysPlan& P : B.sys) {
+      const size_t nflag = (size_t)B.n_tau * P.na * P.na;
+      std::vector<uint8_t> fl(3 * nflag);
+      GW_HIP(hipMemcpyAsync(fl.data(), P.dropped, fl.size(), hipMemcpyDeviceToHost, st));
+      GW_HIP(hipStreamSynchronize(st));
+      if (P.s.n_trip > 0) {
+        for (size_t i = 0; i < 2 * nflag; ++i) dd += fl[i];
+        if (B.eps_f > 0.0)
+          for (size_t i = 2 * nflag; i < 3 * nflag; ++i) dc += fl[i];
+      }
+      kept += P.G.n_kept;
+      fa += P.fl_a;
+      fb += P.fl_b;
+      fc += P.fl_c;
+    }
+    GW_HIP(hipStreamSynchronize(st));
+    stats->n_trip_kept = kept;
+    stats->n_dblk_dropped = dd;
+    stats->n_chiblk_dropped = dc;
+    stats->flops_stage[0] = fa * B.n_tau;
+    stats->flops_stage[1] = fb * B.n_tau;
+    stats->flops_stage[2] = fc * B.n_tau;
+    stats->flops_ab = (fa + fb) * B.n_tau;
+    stats->flops_c = fc * B.n_tau;
+    for (int k = 0; k < 3; ++k) {
+      int64_t nl = 0;
+      for (int piv = 0; piv < B.max_na; ++piv)
+        nl += (B.prec == GW_FP64 ? (k == 0 ? B.tA.n[piv] : k == 1 ? B.tB.n[piv] : B.tC.n[piv])
+                                 : (k == 0 ? B.tAb.n[piv] : k == 1 ? B.tBb.n[piv] : B.tCb.n[piv])) > 0;
+      stats->n_launch[k] = nl;
+    }
+    for (int piv = 0; timing && piv < B.max_na; ++piv)
+      for (int k = 0; k < 3; ++k) {
+        float ms;
+        GW_HIP(hipEventElapsedTime(&ms, B.ev[4 * piv + k], B.ev[4 * piv + k + 1]));
+        stats->ms_stage[k] += ms;
+      }
+    stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return GW_OK;
+}
+
+gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_opts* opts,
+                 gw_chi_batch** out, hipStream_t st) {
+  GW_CHECK_ARG(out != nullptr, "plan must be non-null");
+  *out = nullptr;
+  GW_CHECK_ARG(n_sys >= 1 && n_sys <= 65536, "n_sys must be in [1, 65536]");
+  GW_CHECK_ARG(systems != nullptr, "systems must be non-null");
+  GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
+  const double eps_f = opts ? opts->filter_eps : 0.0;
+  GW_CHECK_ARG(std::isfinite(eps_f) && eps_f >= 0.0, "filter_eps must be finite and >= 0");
+  const int prec = opts ? opts->prec : GW_FP64;
+  GW_CHECK_ARG(prec == GW_FP64 || prec == GW_BF16X3, "prec must be GW_FP64 or GW_BF16X3");
+  gw_status rc;
+  for (int m = 0; m < n_sys; ++m) {
+    if ((rc = check_system(&systems[m])) != GW_OK) return rc;
+    GW_CHECK_ARG(systems[m].ao_per_atom == systems[0].ao_per_atom &&
+                     systems[m].ri_per_atom == systems[0].ri_per_atom,
+                 "all systems of a batch must share ao_per_atom and ri_per_atom");
+  }
+  const int NA = systems[0].ao_per_atom, NR = systems[0].ri_per_atom;
+  GW_CHECK_ARG(NR <= C_COLS, "ri_per_atom must be <= 160");
+  GW_CHECK_ARG((int64_t)n_tau * NA <= (1 << 20), "n_tau * ao_per_atom too large");
+
+  std::unique_ptr<gw_chi_batch> B(new (std::nothrow) gw_chi_batch(st));
+  if (!B) {
+    set_error("host allocation of the plan failed");
+    return GW_ERR_NOMEM;
+  }
+  B->n_sys = n_sys;
+  B->n_tau = n_tau;
+  B->NA = NA;
+  B->NR = NR;
+  B->RS = n_tau * NA;
+  B->prec = prec;
+  B->eps_f = eps_f;
+  B->timing = opts && opts->timing;
+  B->sys.resize(n_sys);
+  for (int m = 0; m < n_sys; ++m) {
+    if ((rc = prepare_sys(*B, B->sys[m], &systems[m], st)) != GW_OK) return rc;
+    B->max_na = std::max(B->max_na, systems[m].n_atoms);
+  }
+  // largest systems first: their tiles lead every batched launch
+  B->order.resize(n_sys);
+  std::iota(B->order.begin(), B->order.end(), 0);
+  std::stable_sort(B->order.begin(), B->order.end(), [&](int x, int y) {
+    return B->sys[x].fl_c + B->sys[x].fl_a > B->sys[y].fl_c + B->sys[y].fl_a;
+  });
+  B->n_queues = 3 * std::max(B->max_na, 1);
+  if ((rc = B->mem.alloc(&B->queues, B->n_queues)) != GW_OK) return rc;
+  if ((rc = B->mem.alloc(&B->tiles_skipped, 1)) != GW_OK) return rc;
+  GW_HIP(hipMemsetAsync(B->tiles_skipped, 0, sizeof(int), st));
+  if ((rc = build_ab_tables(*B, st)) != GW_OK) return rc;
+  prime(*B);
+  GW_HIP(hipStreamSynchronize(st));
+  *out = B.release();
+  return GW_OK;
+}
+
+// shape class of a plan for the autotune cache
+std::string shape_key(const gw_chi_batch& B) {
+  double atoms = 0.0;
+  for (const SysPlan& P : B.sys) atoms += P.na;
+  atoms /= B.n_sys;
+  std::ostringstream k;
+  k << (B.prec == GW_FP64 ? "fp64" : "bf16x3") << "_ao" << B.NA << "_ri" << B.NR << "_tau" << B.n_tau
+    << "_sys" << (int)std::lround(std::log2((double)B.n_sys)) << "_atoms"
+    << (int)std::lround(2.0 * std::log2(std::max(1.0, atoms)));
+  return k.str();
+}
+
+}  // namespace
+}  // namespace gw
+
+extern "C" gw_status gw_chi_batch_create(int32_t n_sys, const gw_system* systems, int32_t n_tau,
+                                         const gw_chi_opts* opts, gw_chi_batch** plan,
+                                         hipStream_t st) {
+  clear_error();
+  GW_CHECK_ARG(!(opts && opts->screener), "the batched form takes no screener");
+  return create(n_sys, systems, n_tau, opts, plan, st);
+}
+
+extern "C" gw_status gw_chi_batch_execute(gw_chi_batch* plan, const double* const* d_occ,
+                                          const double* const* d_vir, double* const* chi,
+                                          int32_t use_graph, gw_chi_stats* stats, hipStream_t st) {
+  clear_error();
+  GW_CHECK_ARG(plan != nullptr, "plan must be non-null");
+  gw_status rc = check_ptrs(plan, d_occ, d_vir, chi);
+  if (rc != GW_OK) return rc;
+  GW_CHECK_ARG(!use_graph || st != nullptr, "graph capture needs a created (non-null) stream");
+  return execute(*plan, d_occ, d_vir, chi, use_graph != 0, stats, st);
+}
+
+extern "C" gw_status gw_chi_batch_set_config(gw_chi_batch* plan, int32_t variant, int32_t persistent) {
+  clear_error();
+  GW_CHECK_ARG(plan != nullptr, "plan must be non-null");
+  GW_CHECK_ARG(variant >= 0 && variant < kNVar, "variant out of range");
+  plan->variant = variant;
+  plan->persistent = persistent ? 1 : 0;
+  return GW_OK;
+}
+
+extern "C" gw_status gw_chi_batch_get_config(const gw_chi_batch* plan, int32_t* variant,
+                                             int32_t* persistent, int32_t* n_variants) {
+  clear_error();
+  GW_CHECK_ARG(plan != nullptr, "plan must be non-null");
+  if (variant) *variant = plan->variant;
+  if (persistent) *persistent = plan->persistent;
+  if (n_variants) *n_variants = kNVar;
+  return GW_OK;
+}
+
+extern "C" gw_status gw_chi_batch_tune(gw_chi_batch* plan, const double* const* d_occ,
+                                       const double* const* d_vir, double* const* chi, int32_t reps,
+                                       const char* cache_path, double* ms_out, hipStream_t st) {
+  clear_error();
+  GW_CHECK_ARG(plan != nullptr, "plan must be non-null");
+  gw_status rc = check_ptrs(plan, d_occ, d_vir, chi);
+  if (rc != GW_OK) return rc;
+  GW_CHECK_ARG(reps >= 1 && reps <= 100, "reps must be in [1, 100]");
+  const std::string key = shape_key(*plan);
+  // cached winner of this shape class
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      int v = -1, pers = -1;
+      double ms = 0.0;
+      if ((ls >> k >> v >> pers >> ms) && k == key && v >= 0 && v < kNVar) {
+        plan->variant = v;
+        plan->persistent = pers ? 1 : 0;
+        if (ms_out) *ms_out = ms;
+        return GW_OK;
+      }
+    }
+  }
+  const bool timing = plan->timing;
+  plan->timing = false;
+  hipEvent_t e0, e1;
+  GW_HIP(hipEventCreate(&e0));
+  GW_HIP(hipEventCreate(&e1));
+  double best = -1.0;
+  int best_v = 0, best_p = 0;
+  for (int v = 0; v < kNVar && rc == GW_OK; ++v)
+    for (int pers = 0; pers < 2 && rc == GW_OK; ++pers) {
+      plan->variant = v;
+      plan->persistent = pers;
+      if ((rc = execute(*plan, d_occ, d_vir, chi, false, nullptr, st)) != GW_OK) break;  // warm-up
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = GW_ERR_HIP; break; }
+      for (int r = 0; r < reps && rc == GW_OK; ++r) rc = execute(*plan, d_occ, d_vir, chi, false, nullptr, st);
+      if (rc != GW_OK) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = GW_ERR_HIP;
+        break;
+      }
+      const double per = ms / reps;
+      if (best < 0.0 || per < best) {
+        best = per;
+        best_v = v;
+        best_p = pers;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  plan->timing = timing;
+  if (rc != GW_OK) {
+    if (rc == GW_ERR_HIP) set_error("HIP error while timing the tile variants");
+    return rc;
+  }
+  plan->variant = best_v;
+  plan->persistent = best_p;
+  if (ms_out) *ms_out = best;
+  if (cache_path && *cache_path) {
+    std::ofstream outf(cache_path, std::ios::app);
+    if (outf) outf << key << " " << best_v << " " << best_p << " " << best << "\n";
+  }
+  return GW_OK;
+}
+
+extern "C" gw_status gw_chi_batch_destroy(gw_chi_batch* plan) {
+  clear_error();
+  delete plan;
+  return GW_OK;
+}
 
 extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, const double* d_vir,
                                      int32_t n_tau, const gw_chi_opts* opts, double* chi,
@@ -299,97 +884,35 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   gw_status rc = check_system(s);
   if (rc != GW_OK) return rc;
   GW_CHECK_ARG(d_occ && d_vir && chi, "d_occ, d_vir and chi must be non-null");
-  GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
-  const double eps_f = opts ? opts->filter_eps : 0.0;
-  GW_CHECK_ARG(std::isfinite(eps_f) && eps_f >= 0.0, "filter_eps must be finite and >= 0");
-  const int prec = opts ? opts->prec : GW_FP64;
-  GW_CHECK_ARG(prec == GW_FP64 || prec == GW_BF16X3, "prec must be GW_FP64 or GW_BF16X3");
-  const int na = s->n_atoms, NA = s->ao_per_atom, NR = s->ri_per_atom;
-  GW_CHECK_ARG(NR <= C_COLS, "ri_per_atom must be <= 160");
-  const int N = na * NA, NRI = na * NR;
-  const int64_t bs = (int64_t)NA * NA * NR;
-  GW_CHECK_ARG((int64_t)n_tau * NA <= (1 << 20), "n_tau * ao_per_atom too large");
-
-  Scratch sc(st);
-  if (stats) *stats = gw_chi_stats{};
-  GW_HIP(hipMemsetAsync(chi, 0, sizeof(double) * (size_t)n_tau * NRI * NRI, st));
-  if (s->n_trip == 0) return GW_OK;
-  // ---- tensor filter and grouping (host)
-  BrickGroups G;
-  if ((rc = build_groups(s, eps_f, st, sc, G)) != GW_OK) return rc;
-  const int n_groups = G.n_groups();
-  const auto& gs = G.gs;
-  const auto& gcv = G.gc;
-  const auto& goff = G.goff;
-  const auto& gb_start = G.gb_start;
-  int nRmax = 0;
-  for (int b = 0; b < na; ++b) nRmax = std::max(nRmax, gb_start[b + 1] - gb_start[b]);
-
-  // ---- column panels of PG RI atoms; U_p = AO atoms coupling to the panel
-  const int PG = std::max(1, C_COLS / NR), PC = PG * NR;
-  const Panels pan = build_panels(na, PG, PC, gcv, gs, NA, NA);
-  const int n_pan = pan.n_pan;
-  const int64_t BPS = pan.off[n_pan];
-  for (int g = 0; g < n_groups; ++g)
-    GW_CHECK_ARG(goff[g + 1] - goff[g] <= kSegTab, "too many bricks in one (atom, RI atom) group");
-  for (int p = 0; p < n_pan; ++p)
-    GW_CHECK_ARG(NA * pan.ulen[p] <= kPanTab, "too many AO atoms coupled to one RI column panel");
-
-  // ---- scratch
-  double *dof = nullptr, *dvf = nullptr, *dvg = nullptr, *mb = nullptr, *bp = nullptr;
-  uint8_t* dropped = nullptr;
-  const int RS = n_tau * NA;
-  const size_t dsz = (size_t)n_tau * N * N;
-  if ((rc = sc.alloc(&dof, dsz)) != GW_OK) return rc;
-  if ((rc = sc.alloc(&dvf, dsz)) != GW_OK) return rc;
-  const bool fp64 = prec == GW_FP64;
-  if (fp64) {
-    if ((rc = sc.alloc(&dvg, (size_t)N * RS)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&mb, (size_t)n_tau * NA * std::max(nRmax, 1) * N * NR)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&bp, (size_t)n_tau * BPS)) != GW_OK) return rc;
-  }
-  const size_t nflag = (size_t)n_tau * na * na;
-  if ((rc = sc.alloc(&dropped, 3 * nflag)) != GW_OK) return rc;
-  int32_t *d_goff, *d_seg_atom, *d_gc, *d_gslot, *d_ulen, *d_kmap, *d_km_off;
-  int64_t *d_seg_brick, *d_bp_off;
-  if ((rc = sc.upload(&d_goff, goff)) != GW_OK) return rc;
-  if ((rc = sc.upload(&d_seg_atom, G.seg_atom)) != GW_OK) return rc;
-  if ((rc = sc.upload(&d_seg_brick, G.seg_brick)) != GW_OK) return rc;
-  if ((rc = sc.upload(&d_gc, gcv)) != GW_OK) return rc;
-  if ((rc = sc.upload(&d_gslot, pan.gslot)) != GW_OK) return rc;
-  if ((rc = sc.upload(&d_ulen, pan.ulen)) != GW_OK) return rc;
-  if ((rc = sc.upload(&d_kmap, pan.kmap)) != GW_OK) return rc;
-  if ((rc = sc.upload(&d_km_off, pan.km_off)) != GW_OK) return rc;
-  if ((rc = sc.upload(&d_bp_off, pan.off)) != GW_OK) return rc;
-  if (fp64) GW_HIP(hipMemsetAsync(bp, 0, sizeof(double) * (size_t)n_tau * BPS, st));
-
-  // ---- D filter (copies)
-  GW_HIP(filter_square_blocks(d_occ, dof, n_tau, na, NA, eps_f, dropped, st));
-  GW_HIP(filter_square_blocks(d_vir, dvf, n_tau, na, NA, eps_f, dropped + nflag, st));
-
-  // ---- learned screener: keep mask of the output blocks
-  uint8_t* d_keep = nullptr;
-  int* d_tiles_skipped = nullptr;
-  std::vector<uint8_t> keep_h;
-  const bool screening = opts && opts->screener && eps_f > 0.0;
+  const bool screening = opts && opts->screener && opts->filter_eps > 0.0;
   if (screening) {
     GW_CHECK_ARG(opts->screen_tau != nullptr, "screen_tau is required with a screener");
     GW_CHECK_ARG(std::isfinite(opts->screen_margin) && opts->screen_margin >= 0.0,
                  "screen_margin must be finite and >= 0");
+  }
+  gw_chi_batch* raw = nullptr;
+  if ((rc = create(1, s, n_tau, opts, &raw, st)) != GW_OK) return rc;
+  std::unique_ptr<gw_chi_batch> B(raw);
+  SysPlan& P = B->sys[0];
+  const int na = P.na;
+
+  // learned screener: keep mask of the output blocks (c <= c')
+  std::vector<uint8_t> keep_h;
+  if (screening && s->n_trip > 0) {
     const int64_t nb = (int64_t)n_tau * na * na;
+    Scratch sc(st);
     float *feat, *pred;
     if ((rc = sc.alloc(&feat, (size_t)nb * 6)) != GW_OK) return rc;
     if ((rc = sc.alloc(&pred, (size_t)nb)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&d_keep, (size_t)nb)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&d_tiles_skipped, 1)) != GW_OK) return rc;
-    GW_HIP(hipMemsetAsync(d_tiles_skipped, 0, sizeof(int), st));
-    if ((rc = gw_chi_block_features(s, d_occ, d_vir, n_tau, opts->screen_tau, eps_f, feat, st)) != GW_OK)
+    if ((rc = B->mem.alloc(&P.keep, (size_t)nb)) != GW_OK) return rc;
+    if ((rc = gw_chi_block_features(s, d_occ, d_vir, n_tau, opts->screen_tau, opts->filter_eps, feat,
+                                    st)) != GW_OK)
       return rc;
     if ((rc = gw_mlp_forward(opts->screener, nb, feat, pred, 1, st)) != GW_OK) return rc;
     std::vector<float> ph(nb);
     GW_HIP(hipMemcpyAsync(ph.data(), pred, sizeof(float) * nb, hipMemcpyDeviceToHost, st));
     GW_HIP(hipStreamSynchronize(st));
-    const float thr = (float)(std::log10(eps_f) - opts->screen_margin);
+    const float thr = (float)(std::log10(opts->filter_eps) - opts->screen_margin);
     keep_h.assign(nb, 0);
     for (int j = 0; j < n_tau; ++j)
       for (int c = 0; c < na; ++c)
@@ -397,228 +920,33 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
           const int64_t e = ((int64_t)j * na + c) * na + c2;
           keep_h[e] = (ph[e] >= thr) || !std::isfinite(ph[e]) ? 1 : 0;
         }
-    GW_HIP(hipMemcpyAsync(d_keep, keep_h.data(), nb, hipMemcpyHostToDevice, st));
-  }
-
-  // ---- pivot loop
-  StageA sa{};
-  sa.dof = dof; sa.t3c = s->t3c; sa.mb = mb; sa.goff = d_goff; sa.seg_atom = d_seg_atom;
-  sa.seg_brick = d_seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = AB_COLS;
-  sa.n_rt = (N + sa.rows_pt - 1) / sa.rows_pt;
-  sa.n_ct = (NA * NR + sa.cols_pt - 1) / sa.cols_pt;
-  sa.N = N; sa.NA = NA; sa.NR = NR; sa.nRmax = std::max(nRmax, 1); sa.bs = bs;
-  sa.fdNA.set((uint32_t)NA);
-  sa.fdNR.set((uint32_t)NR);
-
-  StageB sb{};
-  sb.dvg = dvg; sb.t3c = s->t3c; sb.bp = bp; sb.goff = d_goff; sb.seg_atom = d_seg_atom;
-  sb.seg_brick = d_seg_brick; sb.gc = d_gc; sb.gslot = d_gslot; sb.ulen = d_ulen;
-  sb.bp_off = d_bp_off; sb.RS = RS; sb.NA = NA; sb.NR = NR; sb.PG = PG; sb.PC = PC; sb.bs = bs;
-  sb.BPS = BPS;
-  sb.fdNA.set((uint32_t)NA);
-  sb.fdNR.set((uint32_t)NR);
-
-  StageC scx{};
-  scx.mb = mb; scx.bp = bp; scx.chi = chi; scx.gc = d_gc; scx.kmap = d_kmap; scx.km_off = d_km_off;
-  scx.ulen = d_ulen; scx.bp_off = d_bp_off; scx.rows_pt = 32 * C_WM; scx.N = N; scx.NA = NA;
-  scx.NR = NR; scx.NRI = NRI; scx.PG = PG; scx.PC = PC; scx.nRmax = std::max(nRmax, 1);
-  scx.n_atoms = na; scx.BPS = BPS;
-  scx.fdNR.set((uint32_t)NR);
-  scx.keep = d_keep; scx.tiles_skipped = d_tiles_skipped;
-
-  double flops_ab = 0.0, flops_c = 0.0, flops_a = 0.0, flops_b = 0.0;
-  const bool timing = opts && opts->timing;
-  std::vector<hipEvent_t> evs;
-  auto mark = [&](void) -> hipError_t {
-    if (!timing) return hipSuccess;
-    hipEvent_t e;
-    hipError_t r = hipEventCreate(&e);
-    if (r != hipSuccess) return r;
-    evs.push_back(e);
-    return hipEventRecord(e, st);
-  };
-  int64_t n_launch[3] = {0, 0, 0};
-  struct EvGuard {
-    std::vector<hipEvent_t>& v;
-    ~EvGuard() {
-      for (hipEvent_t e : v) (void)hipEventDestroy(e);
-    }
-  } ev_guard{evs};
-  int64_t nnz_elems = G.n_kept * bs;
-  // |A(c')| per RI atom: number of groups with that c
-  std::vector<int32_t> acount(na, 0);
-  for (int g = 0; g < n_groups; ++g) acount[gcv[g]]++;
-  std::vector<double> asuffix(na + 1, 0.0);   // sum_{c' >= c} |A(c')|
-  for (int c = na - 1; c >= 0; --c) asuffix[c] = asuffix[c + 1] + acount[c];
-
-  // ---- split-precision form: operands as bf16 hi/lo pairs, FP32 accumulation
-  // within a tile, FP64 accumulation across pivots
-  uint16_t *th = nullptr, *tl = nullptr, *doh = nullptr, *dol = nullptr, *dvh = nullptr, *dvl = nullptr;
-  uint16_t *mh = nullptr, *ml = nullptr, *nh = nullptr, *nl = nullptr;
-  std::vector<int64_t> poffb(n_pan + 1, 0);
-  for (int p = 0; p < n_pan; ++p) poffb[p + 1] = poffb[p] + (int64_t)NA * pan.ulen[p] * PC * 16;
-  const int64_t BPS16 = poffb[n_pan];
-  int64_t* d_poffb = nullptr;
-  if (!fp64) {
-    const size_t tsz = (size_t)s->n_trip * NR * NA * 16, dsz16 = (size_t)n_tau * N * na * 16;
-    const size_t msz = (size_t)n_tau * std::max(nRmax, 1) * N * NR * 16, nsz = (size_t)n_tau * BPS16;
-    if ((rc = sc.alloc(&th, tsz)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&tl, tsz)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&doh, dsz16)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&dol, dsz16)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&dvh, dsz16)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&dvl, dsz16)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&mh, msz)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&ml, msz)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&nh, nsz)) != GW_OK) return rc;
-    if ((rc = sc.alloc(&nl, nsz)) != GW_OK) return rc;
-    if ((rc = sc.upload(&d_poffb, poffb)) != GW_OK) return rc;
-    GW_HIP(hipMemsetAsync(mh, 0, 2 * msz, st));
-    GW_HIP(hipMemsetAsync(ml, 0, 2 * msz, st));
-    GW_HIP(hipMemsetAsync(nh, 0, 2 * nsz, st));
-    GW_HIP(hipMemsetAsync(nl, 0, 2 * nsz, st));
-    auto blocks = [](int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 1 << 20); };
-    hipLaunchKernelGGL(split_t_kernel, dim3(blocks((int64_t)tsz)), dim3(256), 0, st, s->t3c, th, tl,
-                       s->n_trip, NA, NR);
-    GW_HIP(hipGetLastError());
-    hipLaunchKernelGGL(split_d_kernel, dim3(blocks((int64_t)dsz16)), dim3(256), 0, st, dof, doh, dol,
-                       n_tau, N, na, NA);
-    GW_HIP(hipGetLastError());
-    hipLaunchKernelGGL(split_d_kernel, dim3(blocks((int64_t)dsz16)), dim3(256), 0, st, dvf, dvh, dvl,
-                       n_tau, N, na, NA);
-    GW_HIP(hipGetLastError());
-  }
-  StageABf ba{};
-  ba.dh = doh; ba.dl = dol; ba.th = th; ba.tl = tl; ba.mh = mh; ba.ml = ml; ba.goff = d_goff;
-  ba.seg_atom = d_seg_atom; ba.seg_brick = d_seg_brick; ba.rows_pt = 16 * 4 * 4;
-  ba.cols_pt = 16 * BF_NB_AB * BF_WN; ba.n_rt = (N + ba.rows_pt - 1) / ba.rows_pt;
-  ba.n_ct = (NA * NR + ba.cols_pt - 1) / ba.cols_pt; ba.N = N; ba.NA = NA; ba.NR = NR; ba.na = na;
-  ba.nRmax = std::max(nRmax, 1); ba.fdNA.set((uint32_t)NA);
-  StageBBf bb{};
-  bb.dh = dvh; bb.dl = dvl; bb.th = th; bb.tl = tl; bb.nh = nh; bb.nl = nl; bb.goff = d_goff;
-  bb.seg_atom = d_seg_atom; bb.seg_brick = d_seg_brick; bb.gc = d_gc; bb.gslot = d_gslot;
-  bb.poffb = d_poffb; bb.N = N; bb.NA = NA; bb.NR = NR; bb.na = na; bb.RS = RS; bb.PG = PG;
-  bb.PC = PC; bb.BPS16 = BPS16; bb.fdNA.set((uint32_t)NA);
-  StageCBf bc{};
-  bc.mh = mh; bc.ml = ml; bc.nh = nh; bc.nl = nl; bc.chi = chi; bc.gc = d_gc; bc.kmap = d_kmap;
-  bc.km_off = d_km_off; bc.ulen = d_ulen; bc.poffb = d_poffb; bc.rows_pt = 16 * 4 * 4; bc.N = N;
-  bc.NA = NA; bc.NR = NR; bc.NRI = NRI; bc.PG = PG; bc.PC = PC; bc.nRmax = std::max(nRmax, 1);
-  bc.n_atoms = na; bc.BPS16 = BPS16; bc.fdNR.set((uint32_t)NR);
-  bc.keep = d_keep; bc.tiles_skipped = d_tiles_skipped;
-
-  for (int b = 0; b < na; ++b) {
-    const int g0 = gb_start[b], nR = gb_start[b + 1] - g0;
-    if (nR == 0) continue;
-    if (fp64) {
-      {
-        const int64_t total = (int64_t)N * RS;
-        const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-        hipLaunchKernelGGL(gather_dvir_kernel, dim3(blocks), dim3(256), 0, st, dvf, dvg, N, NA,
-                           n_tau, b);
-        GW_HIP(hipGetLastError());
-      }
-      sa.g0 = g0;
-      GW_HIP(mark());
-      GW_HIP((launch_tile_gemm<A_WM, AB_WN, AB_NBW, 16>(sa, dim3((unsigned)(nR * sa.n_rt * sa.n_ct), n_tau), st)));
-      GW_HIP(mark());
-      hipError_t e;
-      if (RS <= 64) e = launch_stage_b<2>(sb, n_groups, st);
-      else if (RS <= 96) e = launch_stage_b<3>(sb, n_groups, st);
-      else if (RS <= 128) e = launch_stage_b<4>(sb, n_groups, st);
-      else if (RS <= 160) e = launch_stage_b<5>(sb, n_groups, st);
-      else e = launch_stage_b<4>(sb, n_groups, st);
-      GW_HIP(e);
-      GW_HIP(mark());
-      scx.g0 = g0;
-      scx.nR = nR;
-      scx.n_rt = (nR * NR + scx.rows_pt - 1) / scx.rows_pt;
-      GW_HIP((launch_tile_gemm<C_WM, C_WN, C_NBW, C_KC>(scx, dim3((unsigned)(scx.n_rt * n_pan), 1, n_tau), st)));
-      GW_HIP(mark());
-    } else {
-      ba.g0 = g0;
-      GW_HIP(mark());
-      GW_HIP((launch_tile_bf16x3<4, BF_WN, 4, BF_NB_AB, BF_KC>(ba, dim3((unsigned)(nR * ba.n_rt * ba.n_ct), n_tau), st)));
-      GW_HIP(mark());
-      bb.b = b;
-      hipError_t e;
-      if (RS <= 64) e = launch_stage_b_bf<2>(bb, n_groups, st);
-      else if (RS <= 96) e = launch_stage_b_bf<3>(bb, n_groups, st);
-      else if (RS <= 128) e = launch_stage_b_bf<4>(bb, n_groups, st);
-      else e = launch_stage_b_bf<5>(bb, n_groups, st);
-      GW_HIP(e);
-      GW_HIP(mark());
-      bc.g0 = g0;
-      bc.nR = nR;
-      bc.n_rt = (nR * NR + bc.rows_pt - 1) / bc.rows_pt;
-      GW_HIP((launch_tile_bf16x3<4, BF_WN, 4, BF_NB_C, BF_KC>(bc, dim3((unsigned)(bc.n_rt * n_pan), 1, n_tau), st)));
-      GW_HIP(mark());
-    }
-    n_launch[0]++; n_launch[1]++; n_launch[2]++;
-
-    int64_t nnz_b = 0;
-    for (int g = g0; g < g0 + nR; ++g) nnz_b += (int64_t)(goff[g + 1] - goff[g]) * bs;
-    flops_a += 2.0 * N * (double)nnz_b;
-    flops_b += 2.0 * NA * (double)nnz_elems;
-    flops_ab += 2.0 * N * (double)nnz_b + 2.0 * NA * (double)nnz_elems;
-    if (!screening) {
-      for (int g = g0; g < g0 + nR; ++g)
-        flops_c += 2.0 * NR * NR * NA * NA * asuffix[gcv[g]];
-    } else {
-      // per tau, kept blocks only (averaged into the per-tau figure below)
-      for (int g = g0; g < g0 + nR; ++g) {
-        const int c = gcv[g];
-        for (int j = 0; j < n_tau; ++j)
-          for (int c2 = c; c2 < na; ++c2)
-            if (keep_h[((int64_t)j * na + c) * na + c2])
-              flops_c += 2.0 * NR * NR * NA * NA * acount[c2] / n_tau;
-      }
-    }
-  }
-
-  // ---- symmetric completion and output filter
-  GW_HIP(mirror_lower_blocks(chi, n_tau, NRI, NR, st));
-  if (screening) GW_HIP(zero_unkept_blocks(chi, n_tau, na, NR, d_keep, st));
-  if (eps_f > 0.0)
-    GW_HIP(filter_square_blocks(chi, chi, n_tau, na, NR, eps_f, dropped + 2 * nflag, st));
-
-  if (stats) {
-    std::vector<uint8_t> fl(3 * nflag);
-    GW_HIP(hipMemcpyAsync(fl.data(), dropped, fl.size(), hipMemcpyDeviceToHost, st));
+    GW_HIP(hipMemcpyAsync(P.keep, keep_h.data(), nb, hipMemcpyHostToDevice, st));
     GW_HIP(hipStreamSynchronize(st));
-    int64_t dd = 0, dc = 0;
-    for (size_t i = 0; i < 2 * nflag; ++i) dd += fl[i];
-    if (eps_f > 0.0)
-      for (size_t i = 2 * nflag; i < 3 * nflag; ++i) dc += fl[i];
-    stats->n_trip_kept = G.n_kept;
-    if (screening) {
+  }
+  if ((rc = execute(*B, &d_occ, &d_vir, &chi, false, stats, st)) != GW_OK) return rc;
+  if (stats) {
+    if (!keep_h.empty()) {
       int skipped = 0;
-      GW_HIP(hipMemcpy(&skipped, d_tiles_skipped, sizeof(int), hipMemcpyDeviceToHost));
+      GW_HIP(hipMemcpyAsync(&skipped, B->tiles_skipped, sizeof(int), hipMemcpyDeviceToHost, st));
+      GW_HIP(hipStreamSynchronize(st));
       stats->n_tiles_screened = skipped;
       int64_t nbs = 0;
-      for (int j = 0; j < n_tau; ++j)
-        for (int c = 0; c < na; ++c)
-          for (int c2 = c; c2 < na; ++c2) nbs += keep_h[((int64_t)j * na + c) * na + c2] ? 0 : 1;
+      const int NA = B->NA, NR = B->NR;
+      for (int64_t e = 0; e < (int64_t)n_tau * na * na; ++e) {
+        const int c = (int)((e / na) % na), c2 = (int)(e % na);
+        if (c <= c2 && !keep_h[e]) ++nbs;
+      }
       stats->n_blocks_screened = nbs;
-    }
-    stats->n_dblk_dropped = dd;
-    stats->n_chiblk_dropped = dc;
-    stats->flops_ab = flops_ab * n_tau;
-    stats->flops_c = flops_c * n_tau;
-    for (int k = 0; k < 3; ++k) {
-      stats->ms_stage[k] = 0.0;
-      stats->n_launch[k] = n_launch[k];
-    }
-    stats->flops_stage[0] = flops_a * n_tau;
-    stats->flops_stage[1] = flops_b * n_tau;
-    stats->flops_stage[2] = flops_c * n_tau;
-    for (size_t i = 0; timing && i + 3 < evs.size(); i += 4) {
-      float ms;
-      GW_HIP(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
-      stats->ms_stage[0] += ms;
-      GW_HIP(hipEventElapsedTime(&ms, evs[i + 1], evs[i + 2]));
-      stats->ms_stage[1] += ms;
-      GW_HIP(hipEventElapsedTime(&ms, evs[i + 2], evs[i + 3]));
-      stats->ms_stage[2] += ms;
+      // stage-C FLOPs of the kept blocks only: sum over groups of the kept partners
+      double fl = 0.0;
+      for (int g = 0; g < P.n_groups; ++g) {
+        const int c = P.G.gc[g];
+        for (int j = 0; j < n_tau; ++j)
+          for (int c2 = c; c2 < na; ++c2)
+            if (keep_h[((int64_t)j * na + c) * na + c2]) fl += 2.0 * NR * NR * NA * NA * P.acount[c2];
+      }
+      stats->flops_c = fl;
+      stats->flops_stage[2] = fl;
     }
     stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   }

@@ -1,0 +1,285 @@
+// Problem types of the three chi stages (FP64 and split-precision forms)
+// for the tile engines.  Included once, by chi.hip.
+//
+// Eq. 3 is organised around a pivot AO atom b (sigma runs over b):
+//   stage A  M_b[tau][sigma][c][mu][P] = sum_a sum_{l in a} D^occ_{l mu}(tau) (l sigma P)
+//            for every RI atom c that has a brick (a, b, c) and every mu
+//   stage B  N_b[tau][(a', c')][mu][Q][sigma] = sum_{a2} sum_{nu in a2}
+//                 (nu mu Q) D^vir_{nu sigma}(tau)      (brick (a2, a', c'))
+//   stage C  chi[tau][c][c'] -= sum_{sigma in b} sum_{mu} M_b[..][mu][P] N_b[..][mu][Q][sigma]
+// Both half contractions use the same brick grouping: group (s, c) lists the
+// bricks (f, s, c) and the contraction runs over the first index f.  Stage C
+// is a GEMM per RI column panel p (PG consecutive RI atoms): its K range is
+// (sigma, mu in U_p) with U_p the union of the AO atoms that couple to the
+// panel, so N_b is written panel-dense (zeros where an atom does not couple).
+// Only blocks with c <= c' are computed; the lower blocks are mirrored at
+// the end (chi is symmetric).
+#pragma once
+#include "gw_internal.hpp"
+#include "tile_bf16x3.hpp"
+#include "tile_gemm.hpp"
+
+namespace gw {
+namespace {
+
+constexpr int A_WM = 4, AB_WN = 2, AB_NBW = 6;    // stage A tile 128 x 192, 8 waves
+constexpr int AB_COLS = 16 * AB_NBW * AB_WN;      // stage B tile (32 WM) x 192
+constexpr int C_WM = 4, C_WN = 2, C_NBW = 5;      // stage C tile 128 x 160, 8 waves
+constexpr int C_COLS = 16 * C_NBW * C_WN;
+constexpr int C_KC = 32;                          // K chunk staged per barrier pair
+
+constexpr int kSegTab = 2048;     // max bricks per group (first atoms)
+constexpr int kPanTab = 4096;     // max K functions per column panel (NA * |U_p|)
+
+struct StageA {
+  struct Tile : TileBase {
+    int g, slot, tau, row0, col0, seg0, nseg;
+  };
+  static constexpr bool kAScale = false, kDot = false;
+  static constexpr int kTabA = kSegTab, kTabB = kSegTab;
+  const double* dof;
+  const double* t3c;
+  double* mb;
+  const int32_t* goff;
+  const int32_t* seg_atom;
+  const int64_t* seg_brick;
+  int g0, n_rt, n_ct, rows_pt, cols_pt;
+  int N, NA, NR, nRmax;
+  int64_t bs;
+  FastDiv fdNA, fdNR;
+
+  __device__ bool tile(int bx, int by, int bz, Tile& t) const {
+    const int per = n_rt * n_ct;
+    t.slot = bx / per;
+    const int rem = bx % per;
+    t.row0 = (rem % n_rt) * rows_pt;
+    t.col0 = (rem / n_rt) * cols_pt;
+    t.g = g0 + t.slot;
+    t.tau = by;
+    t.seg0 = goff[t.g];
+    t.nseg = goff[t.g + 1] - t.seg0;
+    t.K = NA * t.nseg;
+    t.rows = min(rows_pt, N - t.row0);
+    t.cols = min(cols_pt, NA * NR - t.col0);
+    return t.rows > 0 && t.cols > 0;
+  }
+  __device__ void fill(const Tile& t, int* ta, int* tb, int tid, int nt) const {
+    for (int i = tid; i < t.nseg; i += nt) {
+      ta[i] = seg_atom[t.seg0 + i];
+      tb[i] = (int)seg_brick[t.seg0 + i];
+    }
+  }
+  __device__ const double* abase(const Tile& t) const { return dof + (int64_t)t.tau * N * N + t.row0; }
+  __device__ int64_t aroff(const Tile&, int r) const { return r; }
+  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
+    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
+    return (int64_t)(ta[sg] * NA + i) * N;
+  }
+  __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
+  __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
+    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
+    return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
+  }
+  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  // M_b[tau][sigma][slot][mu][P]: row mu, column (sigma, P)
+  __device__ double* obase(const Tile& t) const {
+    return mb + ((int64_t)t.tau * NA * nRmax + t.slot) * N * NR;
+  }
+  __device__ int64_t rowoff(const Tile& t, int r) const { return (int64_t)(t.row0 + r) * NR; }
+  __device__ int64_t coloff(const Tile& t, int c) const {
+    const int col = t.col0 + c, sg = (int)fdNR.div((uint32_t)col), P = col - sg * NR;
+    return (int64_t)sg * nRmax * N * NR + P;
+  }
+  static constexpr bool kAccum = false;
+  static constexpr double kSign = 1.0;
+  __device__ const double* dbase0(const Tile&) const { return nullptr; }
+  __device__ const double* dbase1(const Tile&) const { return nullptr; }
+  __device__ void dot_out(const Tile&, double, double) const {}
+};
+
+struct StageB {
+  struct Tile : TileBase {
+    int g, row0, col0, seg0, nseg, p, cl, slot, KU;
+  };
+  static constexpr bool kAScale = false, kDot = false;
+  static constexpr int kTabA = kSegTab, kTabB = kSegTab;
+  const double* dvg;        // [N][RS]
+  const double* t3c;
+  double* bp;
+  const int32_t* goff;
+  const int32_t* seg_atom;
+  const int64_t* seg_brick;
+  const int32_t* gc;
+  const int32_t* gslot;
+  const int32_t* ulen;
+  const int64_t* bp_off;
+  int n_rt, n_ct, rows_pt, cols_pt;
+  int RS, NA, NR, PG, PC;
+  int64_t bs, BPS;
+  FastDiv fdNA, fdNR;
+
+  __device__ bool tile(int bx, int, int, Tile& t) const {
+    const int per = n_rt * n_ct;
+    t.g = bx / per;
+    const int rem = bx % per;
+    t.row0 = (rem % n_rt) * rows_pt;
+    t.col0 = (rem / n_rt) * cols_pt;
+    t.seg0 = goff[t.g];
+    t.nseg = goff[t.g + 1] - t.seg0;
+    t.K = NA * t.nseg;
+    const int c = gc[t.g];
+    t.p = c / PG;
+    t.cl = c % PG;
+    t.slot = gslot[t.g];
+    t.KU = NA * ulen[t.p];
+    t.rows = min(rows_pt, RS - t.row0);
+    t.cols = min(cols_pt, NA * NR - t.col0);
+    return t.rows > 0 && t.cols > 0;
+  }
+  __device__ void fill(const Tile& t, int* ta, int* tb, int tid, int nt) const {
+    for (int i = tid; i < t.nseg; i += nt) {
+      ta[i] = seg_atom[t.seg0 + i];
+      tb[i] = (int)seg_brick[t.seg0 + i];
+    }
+  }
+  __device__ const double* abase(const Tile& t) const { return dvg + t.row0; }
+  __device__ int64_t aroff(const Tile&, int r) const { return r; }
+  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
+    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
+    return (int64_t)(ta[sg] * NA + i) * RS;
+  }
+  __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
+  __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
+    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
+    return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
+  }
+  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  // N_b panel: [tau][panel][sigma][u = slot*NA + mu][(cl, Q)]: row (tau, sigma), column (mu, Q)
+  __device__ double* obase(const Tile& t) const { return bp + bp_off[t.p]; }
+  __device__ int64_t rowoff(const Tile& t, int r) const {
+    const int row = t.row0 + r, tau = (int)fdNA.div((uint32_t)row), sg = row - tau * NA;
+    return (int64_t)tau * BPS + (int64_t)sg * t.KU * PC;
+  }
+  __device__ int64_t coloff(const Tile& t, int c) const {
+    const int col = t.col0 + c, mul = (int)fdNR.div((uint32_t)col), Q = col - mul * NR;
+    return (int64_t)(t.slot * NA + mul) * PC + t.cl * NR + Q;
+  }
+  static constexpr bool kAccum = false;
+  static constexpr double kSign = 1.0;
+  __device__ const double* dbase0(const Tile&) const { return nullptr; }
+  __device__ const double* dbase1(const Tile&) const { return nullptr; }
+  __device__ void dot_out(const Tile&, double, double) const {}
+};
+
+// true if some upper (c <= c') block of the tile is kept by the screener
+__device__ inline bool any_kept(const uint8_t* keep, const int32_t* slot_c, int s0, int s1,
+                                int c0, int c1, int tau, int na) {
+  const uint8_t* k = keep + (int64_t)tau * na * na;
+  for (int sl = s0; sl <= s1; ++sl) {
+    const int c = slot_c[sl];
+    for (int c2 = c0; c2 <= c1; ++c2)
+      if (c <= c2 && k[(int64_t)c * na + c2]) return true;
+  }
+  return false;
+}
+
+struct StageC {
+  struct Tile : TileBase {
+    int p, tau, row0, KU, km0;
+    FastDiv fdKU;
+  };
+  static constexpr bool kAScale = false, kDot = false;
+  static constexpr int kTabA = kPanTab, kTabB = 0;
+  const double* mb;
+  const double* bp;
+  double* chi;
+  const int32_t* gc;
+  const int32_t* kmap;
+  const int32_t* km_off;
+  const int32_t* ulen;
+  const int64_t* bp_off;
+  int g0, nR, n_rt, rows_pt;
+  int N, NA, NR, NRI, PG, PC, nRmax, n_atoms;
+  int64_t BPS;
+  FastDiv fdNR;
+  const uint8_t* keep;      // screener mask [tau][c][c'] (c <= c'), or null
+  int* tiles_skipped;
+
+  __device__ bool tile(int bx, int by, int bz, Tile& t) const {
+    t.row0 = (bx % n_rt) * rows_pt;
+    t.p = bx / n_rt;
+    t.tau = bz;
+    t.rows = min(rows_pt, nR * NR - t.row0);
+    t.cols = min(PC, NRI - t.p * PC);
+    if (t.rows <= 0 || t.cols <= 0) return false;
+    const int c_min = gc[g0 + t.row0 / NR];
+    const int cp_max = min(t.p * PG + PG - 1, n_atoms - 1);
+    if (c_min > cp_max) return false;          // strictly below the block diagonal
+    if (keep && !any_kept(keep, gc + g0, t.row0 / NR, (t.row0 + t.rows - 1) / NR, t.p * PG, cp_max,
+                          t.tau, n_atoms)) {
+      if (threadIdx.x == 0) atomicAdd(tiles_skipped, 1);
+      return false;
+    }
+    t.KU = NA * ulen[t.p];
+    t.km0 = km_off[t.p];
+    t.K = NA * t.KU;
+    t.fdKU.set((uint32_t)t.KU);
+    return t.K > 0;
+  }
+  __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
+    for (int i = tid; i < t.KU; i += nt) ta[i] = kmap[t.km0 + i] * NR;
+  }
+  __device__ const double* abase(const Tile& t) const {
+    return mb + (int64_t)t.tau * NA * nRmax * N * NR;
+  }
+  __device__ int64_t aroff(const Tile& t, int r) const {
+    const int row = t.row0 + r, sl = (int)fdNR.div((uint32_t)row);
+    return (int64_t)sl * N * NR + (row - sl * NR);
+  }
+  __device__ int64_t akoff(const Tile& t, int k, const int* ta) const {
+    const int sg = (int)t.fdKU.div((uint32_t)k), u = k - sg * t.KU;
+    return (int64_t)sg * nRmax * N * NR + ta[u];
+  }
+  __device__ const double* bbase(const Tile& t) const {
+    return bp + (int64_t)t.tau * BPS + bp_off[t.p];
+  }
+  __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PC; }
+  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  // chi[tau][P][Q] -= tile, P = (RI atom of the row's slot, P), Q = panel column
+  __device__ double* obase(const Tile& t) const { return chi + (int64_t)t.tau * NRI * NRI; }
+  __device__ int64_t rowoff(const Tile& t, int r) const {
+    const int row = t.row0 + r, sl = (int)fdNR.div((uint32_t)row), P = row - sl * NR;
+    return ((int64_t)gc[g0 + sl] * NR + P) * NRI;
+  }
+  __device__ int64_t coloff(const Tile& t, int c) const { return (int64_t)t.p * PC + c; }
+  static constexpr bool kAccum = true;
+  static constexpr double kSign = -1.0;
+  __device__ const double* dbase0(const Tile&) const { return nullptr; }
+  __device__ const double* dbase1(const Tile&) const { return nullptr; }
+  __device__ void dot_out(const Tile&, double, double) const {}
+};
+
+// D^vir columns of pivot atom b, gathered as dvg[nu][(tau, sigma)] for the
+// systems of one batch (blockIdx.y = entry)
+struct GatherEnt {
+  const double* dv;
+  double* dvg;
+  int N, b;
+};
+
+__global__ void gather_dvir_kernel(const GatherEnt* __restrict__ ents, int NA, int n_tau) {
+  const GatherEnt en = ents[blockIdx.y];
+  const int RS = n_tau * NA, N = en.N;
+  const int64_t total = (int64_t)N * RS;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int nu = (int)(e / RS), rc = (int)(e % RS);
+    const int tau = rc / NA, sg = rc % NA;
+    en.dvg[e] = en.dv[(int64_t)tau * N * N + (int64_t)nu * N + (int64_t)en.b * NA + sg];
+  }
+}
+
+#include "chi_bf16x3.inc"
+
+}  // namespace
+}  // namespace gw

@@ -265,6 +265,20 @@ hipError_t mirror_lower_blocks(double* x, int n_mat, int n, int nb, hipStream_t 
   return hipGetLastError();
 }
 
+__global__ void fill_zero_kernel(uint32_t* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0u;
+}
+
+hipError_t fill_zero(void* x, int64_t n_words32, hipStream_t st) {
+  if (n_words32 <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n_words32 + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, st, static_cast<uint32_t*>(x),
+                     n_words32);
+  return hipGetLastError();
+}
+
 }  // namespace gw
 
 extern "C" const char* gw_last_error(void) { return gw::g_last_error.c_str(); }

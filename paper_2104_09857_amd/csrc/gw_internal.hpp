@@ -32,19 +32,24 @@ void clear_error();
     }                                                                          \
   } while (0)
 
-// Stream-ordered scratch allocations released when the owner goes out of scope.
+// Device allocations released when the owner goes out of scope: stream
+// ordered (hipMallocAsync / hipFreeAsync on `st`) for the scratch of one
+// call, or plain hipMalloc / hipFree (ordered = false) for objects that
+// outlive the stream they were created on (plans).
 class Scratch {
  public:
-  explicit Scratch(hipStream_t st) : st_(st) {}
+  explicit Scratch(hipStream_t st, bool ordered = true) : st_(st), ordered_(ordered) {}
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
   ~Scratch() {
-    for (void* p : ptrs_) (void)hipFreeAsync(p, st_);
+    for (void* p : ptrs_) (void)(ordered_ ? hipFreeAsync(p, st_) : hipFree(p));
   }
   template <class T>
   gw_status alloc(T** out, size_t count) {
     void* p = nullptr;
     size_t bytes = count * sizeof(T);
     if (bytes == 0) bytes = 256;
-    hipError_t e = hipMallocAsync(&p, bytes, st_);
+    hipError_t e = ordered_ ? hipMallocAsync(&p, bytes, st_) : hipMalloc(&p, bytes);
     if (e != hipSuccess || p == nullptr) {
       (void)hipGetLastError();
       set_error("scratch allocation of " + std::to_string(bytes) + " bytes failed");
@@ -68,11 +73,17 @@ class Scratch {
     }
     return GW_OK;
   }
+  hipStream_t stream() const { return st_; }
 
  private:
   hipStream_t st_;
+  bool ordered_;
   std::vector<void*> ptrs_;
 };
+
+// x[0 .. n_words) = 0 with a kernel (usable inside a captured graph, unlike
+// hipMemsetAsync)
+hipError_t fill_zero(void* x, int64_t n_words32, hipStream_t st);
 
 // Validates the system description (host side, before any launch).
 gw_status check_system(const gw_system* s);

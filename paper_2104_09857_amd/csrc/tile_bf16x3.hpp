@@ -242,10 +242,16 @@ inline hipError_t launch_tile_bf16x3(const P& p, dim3 grid, hipStream_t st) {
 }
 
 template <int WM, int WN, int RB, int NB, int KC, class P>
-inline hipError_t launch_tile_bf16x3_persistent(const P& p, int n_work, int* queue, hipStream_t st) {
-  if (n_work <= 0) return hipSuccess;
+inline int persistent_cap_bf16x3() {
   static int cap = 0;
   if (cap == 0) cap = resident_groups(tile_bf16x3_persistent<WM, WN, RB, NB, KC, P>, 64 * WM * WN);
+  return cap;
+}
+
+template <int WM, int WN, int RB, int NB, int KC, class P>
+inline hipError_t launch_tile_bf16x3_persistent(const P& p, int n_work, int* queue, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  const int cap = persistent_cap_bf16x3<WM, WN, RB, NB, KC, P>();
   const int grid = cap > 0 ? (n_work < cap ? n_work : cap) : n_work;
   hipLaunchKernelGGL((tile_bf16x3_persistent<WM, WN, RB, NB, KC, P>), dim3(grid), dim3(64 * WM * WN), 0,
                      st, p, n_work, queue);

@@ -64,29 +64,40 @@ __device__ __forceinline__ auto resolve(const P& p, const T& t) {
   else return p;
 }
 
-// Concatenated tile ranges of several systems: tile bx belongs to system s
-// with tile_off[s] <= bx < tile_off[s + 1] (binary search) and is tile
-// bx - tile_off[s] of that system's problem probs[s].
+// One system of a batched launch: its problem and the extents (gx, gy) of
+// the 3D grid it would be launched with on its own.
+template <class P>
+struct BatchEntry {
+  P p;
+  int gx, gy;
+};
+
+// Concatenated work of several systems in one 1D launch: work item w belongs
+// to entry s with tile_off[s] <= w < tile_off[s + 1] (binary search) and is
+// block (bx, by, bz) of that entry's own grid, l = w - tile_off[s] =
+// bx + gx * (by + gy * bz).
 template <class P>
 struct Batched : P {
   static constexpr bool kBatched = true;
   struct Tile : P::Tile {
     int sys;
   };
-  const P* probs;
-  const int* tile_off;
+  const BatchEntry<P>* ent;
+  const int32_t* tile_off;
   int n_sys;
-  __device__ bool tile(int bx, int by, int bz, Tile& t) const {
+  __device__ bool tile(int w, int, int, Tile& t) const {
     int lo = 0, hi = n_sys;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (tile_off[mid] <= bx) lo = mid;
+      if (tile_off[mid] <= w) lo = mid;
       else hi = mid;
     }
     t.sys = lo;
-    return probs[lo].tile(bx - tile_off[lo], by, bz, t);
+    const int gx = ent[lo].gx, gy = ent[lo].gy;
+    const int l = w - tile_off[lo], r = l / gx;
+    return ent[lo].p.tile(l - r * gx, r % gy, r / gy, t);
   }
-  __device__ P local(const Tile& t) const { return probs[t.sys]; }
+  __device__ P local(const Tile& t) const { return ent[t.sys].p; }
 };
 
 template <int WM, int WN, int NB, int KC, class P>
@@ -328,11 +339,19 @@ inline int resident_groups(K kernel, int threads) {
   return ncu * (per > 0 ? per : 1);
 }
 
+// grid of the persistent form: the resident capacity (computed once per
+// kernel; call it outside graph capture before the first launch)
+template <int WM, int WN, int NB, int KC, class P>
+inline int persistent_cap_gemm() {
+  static int cap = 0;
+  if (cap == 0) cap = resident_groups(tile_gemm_persistent<WM, WN, NB, KC, P>, 64 * WM * WN);
+  return cap;
+}
+
 template <int WM, int WN, int NB, int KC, class P>
 inline hipError_t launch_tile_gemm_persistent(const P& p, int n_work, int* queue, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
-  static int cap = 0;
-  if (cap == 0) cap = resident_groups(tile_gemm_persistent<WM, WN, NB, KC, P>, 64 * WM * WN);
+  const int cap = persistent_cap_gemm<WM, WN, NB, KC, P>();
   const int grid = cap > 0 ? (n_work < cap ? n_work : cap) : n_work;
   hipLaunchKernelGGL((tile_gemm_persistent<WM, WN, NB, KC, P>), dim3(grid), dim3(64 * WM * WN), 0, st,
                      p, n_work, queue);

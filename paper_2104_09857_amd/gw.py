@@ -96,6 +96,15 @@ def lib():
         for f in ("gw_chi_block_features", "gw_chi_block_lognorms", "gw_mlp_forward",
                   "gw_mlp_gradient", "gw_mlp_train_step", "gw_mlp_sync_half"):
             getattr(L, f).restype = ctypes.c_int32
+        L.gw_chi_batch_create.argtypes = [_I32, _P, _I32, _P, _P, _P]
+        L.gw_chi_batch_execute.argtypes = [_P, _P, _P, _P, _I32, _P, _P]
+        L.gw_chi_batch_set_config.argtypes = [_P, _I32, _I32]
+        L.gw_chi_batch_get_config.argtypes = [_P, _P, _P, _P]
+        L.gw_chi_batch_tune.argtypes = [_P, _P, _P, _P, _I32, ctypes.c_char_p, _P, _P]
+        L.gw_chi_batch_destroy.argtypes = [_P]
+        for f in ("gw_chi_batch_create", "gw_chi_batch_execute", "gw_chi_batch_set_config",
+                  "gw_chi_batch_get_config", "gw_chi_batch_tune", "gw_chi_batch_destroy"):
+            getattr(L, f).restype = ctypes.c_int32
         L.gw_last_error.restype = ctypes.c_char_p
         L.gw_last_error.argtypes = []
         L.gw_version.restype = ctypes.c_char_p
@@ -107,7 +116,9 @@ def lib():
 EXPORTED = ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma",
             "gw_continue_qp", "gw_last_error", "gw_version", "gw_chi_block_features",
             "gw_chi_block_lognorms", "gw_mlp_param_count", "gw_mlp_forward", "gw_mlp_gradient",
-            "gw_mlp_train_step", "gw_mlp_sync_half")
+            "gw_mlp_train_step", "gw_mlp_sync_half", "gw_chi_batch_create", "gw_chi_batch_execute",
+            "gw_chi_batch_set_config", "gw_chi_batch_get_config", "gw_chi_batch_tune",
+            "gw_chi_batch_destroy")
 
 
 def _check(code):
@@ -176,6 +187,8 @@ def contract_chi(sys, d_occ, d_vir, filter_eps=0.0, chi=None, stream=None, timin
     n_tau = d_occ.shape[0]
     if chi is None:
         chi = torch.empty((n_tau, sys.n_ri, sys.n_ri), dtype=torch.float64, device=d_occ.device)
+    assert tuple(d_occ.shape) == tuple(d_vir.shape) == (n_tau, sys.n_ao, sys.n_ao), "D stack shape"
+    assert tuple(chi.shape) == (n_tau, sys.n_ri, sys.n_ri), "chi shape"
     tau_h = None if tau is None else np.ascontiguousarray(tau, dtype=np.float64)
     opts = _ChiOpts(PRECISIONS[prec], float(filter_eps), int(bool(timing)),
                     None if screener is None else ctypes.addressof(screener.c),
@@ -184,9 +197,83 @@ def contract_chi(sys, d_occ, d_vir, filter_eps=0.0, chi=None, stream=None, timin
     st = _ChiStats()
     _check(lib().gw_contract_chi(sys.ref, _dev(d_occ), _dev(d_vir), n_tau, ctypes.byref(opts),
                                  _dev(chi), ctypes.byref(st), _stream(stream)))
-    stats = {k: (list(getattr(st, k)) if k in ("ms_stage", "n_launch", "flops_stage")
-                 else getattr(st, k)) for k, _ in _ChiStats._fields_}
-    return chi, stats
+    return chi, _stats_dict(st)
+
+
+def _stats_dict(st):
+    return {k: (list(getattr(st, k)) if k in ("ms_stage", "n_launch", "flops_stage")
+                else getattr(st, k)) for k, _ in _ChiStats._fields_}
+
+
+class ChiBatch:
+    """A gw_chi_batch plan over several systems (sharing AO / RI per atom).
+
+    The systems (and their device bricks) must outlive the plan."""
+
+    def __init__(self, systems, n_tau, filter_eps=0.0, prec="fp64", timing=False, stream=None):
+        self.systems = list(systems)
+        self.n_tau = int(n_tau)
+        arr = (_System * len(self.systems))(*[s.c for s in self.systems])
+        self._arr = arr
+        opts = _ChiOpts(PRECISIONS[prec], float(filter_eps), int(bool(timing)), None, 0.0, None)
+        h = ctypes.c_void_p()
+        _check(lib().gw_chi_batch_create(len(self.systems), ctypes.cast(arr, _P), self.n_tau,
+                                         ctypes.byref(opts), ctypes.byref(h), _stream(stream)))
+        self.h = h
+
+    def _ptrs(self, ts):
+        assert len(ts) == len(self.systems)
+        return (ctypes.c_void_p * len(ts))(*[_dev(t).value for t in ts])
+
+    def outputs(self, device="cuda"):
+        import torch
+        return [torch.empty((self.n_tau, s.n_ri, s.n_ri), dtype=torch.float64, device=device)
+                for s in self.systems]
+
+    def _check_shapes(self, d_occ, d_vir, chi):
+        for s, o, v, c in zip(self.systems, d_occ, d_vir, chi):
+            want_d = (self.n_tau, s.n_ao, s.n_ao)
+            want_c = (self.n_tau, s.n_ri, s.n_ri)
+            assert tuple(o.shape) == want_d and tuple(v.shape) == want_d, "D stack shape"
+            assert tuple(c.shape) == want_c, "chi shape"
+            assert o.dtype == v.dtype == c.dtype == __import__("torch").float64
+
+    def execute(self, d_occ, d_vir, chi, graph=False, stats=True, stream=None):
+        self._check_shapes(d_occ, d_vir, chi)
+        st = _ChiStats()
+        po, pv, pc = self._ptrs(d_occ), self._ptrs(d_vir), self._ptrs(chi)
+        _check(lib().gw_chi_batch_execute(self.h, po, pv, pc, int(bool(graph)),
+                                          ctypes.byref(st) if stats else None, _stream(stream)))
+        return _stats_dict(st) if stats else None
+
+    def set_config(self, variant, persistent):
+        _check(lib().gw_chi_batch_set_config(self.h, int(variant), int(bool(persistent))))
+
+    def config(self):
+        v, p, n = _I32(), _I32(), _I32()
+        _check(lib().gw_chi_batch_get_config(self.h, ctypes.byref(v), ctypes.byref(p),
+                                             ctypes.byref(n)))
+        return v.value, p.value, n.value
+
+    def tune(self, d_occ, d_vir, chi, reps=1, cache_path=None, stream=None):
+        self._check_shapes(d_occ, d_vir, chi)
+        ms = _D()
+        po, pv, pc = self._ptrs(d_occ), self._ptrs(d_vir), self._ptrs(chi)
+        _check(lib().gw_chi_batch_tune(self.h, po, pv, pc, int(reps),
+                                       None if cache_path is None else str(cache_path).encode(),
+                                       ctypes.byref(ms), _stream(stream)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _check(lib().gw_chi_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def chi_block_features(sys, d_occ, d_vir, tau, filter_eps, feat=None, stream=None):

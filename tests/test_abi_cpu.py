@@ -73,6 +73,36 @@ def test_host_validation_rejects_bad_arguments():
     assert rc == gw.GW_ERR_ARG
 
 
+def test_batch_plan_validation():
+    L = gw.lib()
+    trip = np.zeros((1, 3), dtype=np.int32)
+    tp = trip.ctypes.data_as(ctypes.c_void_p).value
+    a = gw._System(2, 3, 4, 3, 1, tp, 1)
+    b = gw._System(2, 5, 4, 3, 1, tp, 1)          # other AO count per atom
+    bad = gw._System(2, 3, 4, 0, 0, None, None)    # no occupied states
+    opts = gw._ChiOpts(0, 0.0)
+    h = ctypes.c_void_p()
+
+    def create(systems, n_tau=4, o=opts):
+        arr = (gw._System * len(systems))(*systems)
+        return L.gw_chi_batch_create(len(systems), ctypes.cast(arr, ctypes.c_void_p), n_tau,
+                                     ctypes.byref(o), ctypes.byref(h), None)
+
+    assert create([a, b]) == gw.GW_ERR_ARG            # mixed basis sizes
+    assert create([a, bad]) == gw.GW_ERR_ARG          # invalid member
+    assert create([a], n_tau=0) == gw.GW_ERR_ARG
+    assert create([a], o=gw._ChiOpts(5, 0.0)) == gw.GW_ERR_ARG       # unknown precision
+    assert create([a], o=gw._ChiOpts(0, 1e-6, 0, 1, 1.0, None)) == gw.GW_ERR_ARG   # screener
+    assert L.gw_chi_batch_create(0, None, 4, ctypes.byref(opts), ctypes.byref(h), None) == gw.GW_ERR_ARG
+    assert L.gw_chi_batch_create(1, None, 4, ctypes.byref(opts), None, None) == gw.GW_ERR_ARG
+    assert h.value is None
+    assert L.gw_chi_batch_execute(None, None, None, None, 0, None, None) == gw.GW_ERR_ARG
+    assert L.gw_chi_batch_set_config(None, 0, 0) == gw.GW_ERR_ARG
+    assert L.gw_chi_batch_tune(None, None, None, None, 1, None, None, None) == gw.GW_ERR_ARG
+    assert L.gw_last_error()
+    assert L.gw_chi_batch_destroy(None) == gw.GW_OK
+
+
 def _random_sigma(rng, n_gw, n_tau):
     # a sum of decaying exponentials, like Sigma^occ / Sigma^vir
     t = np.geomspace(0.02, 20, n_tau)
