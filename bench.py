@@ -32,6 +32,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "chi+Sigma contraction TFLOP/s & time-to-QP; mixed/learned vs FP64 at 1 meV"
 PEAK_FP64_MFMA_TFLOPS = 78.6
+# dense MFMA peaks of MI355X by operand type of the chi contraction
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+DTYPE = {"fp64": "f64", "fp32": "f32 (FP32 MFMA and accumulation in a tile, FP64 across pivots)",
+         "bf16x3": "bf16x3 (bf16 hi/lo MFMA, FP32 accumulation in a tile, FP64 across pivots)"}
+STAGE_C_KERNEL = {"fp64": "tile_gemm_kernel<4,2,5,32,StageC<double>>",
+                  "fp32": "tile_gemm_kernel<4,2,5,32,StageC<float>>",
+                  "bf16x3": "tile_bf16x3_kernel<4,2,4,5,32,StageCBf>"}
 
 
 def log(*a):
@@ -116,12 +123,12 @@ def cpu_baseline(ctx, out, budget_s=20.0):
                       f"NumPy/OpenBLAS dense within the brick supports, {elapsed:.1f} s: {done}"}
 
 
-def setup_molecules(n_mol, seed=0):
+def setup_molecules(name, seed=0):
     import torch
     from gwinputs import configs, device as gdev
     from paper_2104_09857_amd import gw
     t0 = time.perf_counter()
-    ws = configs.molecules(n_mol, seed)
+    ws = configs.molecule_set(name, seed)
     ms = []
     for w in ws:
         s = w.system
@@ -135,7 +142,7 @@ def setup_molecules(n_mol, seed=0):
         ms.append(dict(w=w, s=s, sys=sysd, t3c=t3c, trip=trip, do=do, dv=dv))
     torch.cuda.synchronize()
     n = [m["s"].n_atoms for m in ms]
-    log(f"[setup] mol{n_mol}: atoms {min(n)}..{max(n)} (sum {sum(n)}), "
+    log(f"[setup] {name}: atoms {min(n)}..{max(n)} (sum {sum(n)}), "
         f"{sum(m['t3c'].numel() for m in ms) * 8 / 1e9:.1f} GB bricks, {time.perf_counter() - t0:.1f} s")
     return ms
 
@@ -145,8 +152,8 @@ def bench_batched(args):
     import tempfile
     import torch
     from paper_2104_09857_amd import gw
-    n_mol = int(args.workload[3:])
-    ms = setup_molecules(n_mol)
+    ms = setup_molecules(args.workload)
+    n_mol = len(ms)
     eps_f = ms[0]["s"].filter_eps
     n_tau = ms[0]["do"].shape[0]
     systems = [m["sys"] for m in ms]
@@ -218,13 +225,13 @@ def bench_batched(args):
     flops = st["flops_ab"] + st["flops_c"]
     c_ms, c_n, c_fl = st["ms_stage"][2], st["n_launch"][2], st["flops_stage"][2]
     achieved = (c_fl / max(c_n, 1)) / ((c_ms / max(c_n, 1)) / 1e3) / 1e12
-    peak = PEAK_FP64_MFMA_TFLOPS if args.prec == "fp64" else 2500.0
+    peak = PEAK[args.prec]
     n = [m["s"].n_atoms for m in ms]
     res = {
         "metric": METRIC, "value": flops / (graph_ms / 1e3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": graph_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "bf16x3 (fp32 accumulate, fp64 across tiles)",
+        "dtype": DTYPE[args.prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "form": "batched chi (gw_chi_batch, hipGraph)",
                    "n_mol": n_mol, "atoms_min": min(n), "atoms_max": max(n), "atoms_sum": sum(n),
@@ -252,10 +259,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="strip300")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "bf16x3"],
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
                     help="arithmetic of the timed chi contraction")
-    ap.add_argument("--no-compare", action="store_true",
-                    help="skip the extra untimed run of the other precision form")
+    ap.add_argument("--compare", default="fp32", choices=["fp64", "fp32", "bf16x3", "none"],
+                    help="arithmetic of an extra untimed run reported next to the main one")
+    ap.add_argument("--no-compare", action="store_true", help="same as --compare none")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--tune-cache", default=None, help="autotune cache file of the batched form")
     args = ap.parse_args()
@@ -307,7 +315,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "bf16x3 (fp32 accumulate, fp64 across tiles)",
+        "dtype": DTYPE[args.prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": s.n_atoms, "n_ao": s.n_ao, "n_ri": s.n_ri,
                    "n_occ": s.n_occ, "n_tau": ctx["w"].n_tau, "filter_eps": s.filter_eps,
@@ -322,30 +330,34 @@ def main():
                                  for f, m in zip(cs["flops_stage"], cs["ms_stage"])],
                       "launches": list(cs["n_launch"])},
         "e_qp": [float(x) for x in out["e_qp"]], "qp_status": [int(x) for x in out["status"]],
-        "roofline": {"kernel": "tile_gemm_kernel<4,2,5,32,StageC> (chi outer contraction)",
-                     "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
+        "roofline": {"kernel": STAGE_C_KERNEL[args.prec] + " (chi outer contraction)",
+                     "bound": "mfma", "achieved": achieved, "peak": PEAK[args.prec],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.prec],
                      "traffic": traffic, "launches": int(c_n), "avg_launch_ms": per_launch_ms},
     }
-    if not args.no_compare:
-        other = "bf16x3" if args.prec == "fp64" else "fp64"
+    other = None if args.no_compare or args.compare == "none" else args.compare
+    if other and other != args.prec:
         t1 = time.perf_counter()
         o2 = step(ctx, other)
         torch.cuda.synchronize()
         t2 = time.perf_counter() - t1
-        e64, e2 = (out, o2) if args.prec == "fp64" else (o2, out)
-        ok = (e64["status"] == 0) & (e2["status"] == 0)
-        de = np.abs(e2["e_qp"] - e64["e_qp"])[ok] * 27211.386245988 if args.prec == "fp64" else \
-            np.abs(out["e_qp"] - o2["e_qp"])[ok] * 27211.386245988
-        chi64 = (out if args.prec == "fp64" else o2)["ms"]["chi"]
-        chibf = (o2 if args.prec == "fp64" else out)["ms"]["chi"]
-        res["precision_form"] = {
-            "prec": "bf16x3", "chi_ms_fp64": chi64, "chi_ms_bf16x3": chibf,
-            "chi_speedup": chi64 / chibf,
-            "time_to_qp_s_other": t2, "other": other,
-            "max_abs_dE_meV_vs_fp64": float(de.max()) if de.size else None,
-            "dE_meV": [float(x) for x in de],
-            "status_bf16x3": [int(x) for x in (o2 if args.prec == "fp64" else out)["status"]]}
+        if args.prec == "fp64":
+            e64, eo = out, o2
+        elif other == "fp64":
+            e64, eo = o2, out
+        else:
+            e64 = eo = None
+        form = other if args.prec == "fp64" else args.prec
+        pf = {"prec": form, "chi_ms_" + args.prec: out["ms"]["chi"], "chi_ms_" + other: o2["ms"]["chi"],
+              "time_to_qp_s_" + other: t2}
+        if e64 is not None:
+            ok = (e64["status"] == 0) & (eo["status"] == 0)
+            de = np.abs(eo["e_qp"] - e64["e_qp"])[ok] * 27211.386245988
+            pf.update({"chi_speedup_vs_fp64": e64["ms"]["chi"] / eo["ms"]["chi"],
+                       "max_abs_dE_meV_vs_fp64": float(de.max()) if de.size else None,
+                       "dE_meV": [float(x) for x in de],
+                       "status_" + form: [int(x) for x in eo["status"]]})
+        res["precision_form"] = pf
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(ctx, out)
     print(json.dumps(res), flush=True)

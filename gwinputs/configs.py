@@ -13,7 +13,8 @@
                atoms at 2.5 bohr), filter 1e-8: a long quasi-1D system whose
                far output blocks fall below the filter.
   mol<M>       M independent molecules for the batched form: atom counts
-               drawn uniformly from [10, 40] (Philox uniform, stream 7),
+               drawn uniformly from [10, 40] (mol<M>:<lo>-<hi> for another
+               range; Philox uniform, stream 7),
                3D random sequential packings of number density 0.0148 / bohr^3
                with minimum distance 2.5 bohr, 13 AO / 40 RI per atom,
                decays 0.8 / 0.8 / 0.2, filter 1e-9, 12 tau, HOMO / LUMO.
@@ -86,6 +87,13 @@ def by_name(name: str, seed=0) -> Workload:
     if name.startswith("wire"):
         return wire(int(name[4:]), seed)
     raise KeyError(name)
+
+
+def molecule_set(name: str, seed=0) -> list:
+    """mol<M> (atom counts in [10, 40]) or mol<M>:<lo>-<hi>."""
+    head, _, rng = name.partition(":")
+    lo, hi = (10, 40) if not rng else (int(x) for x in rng.split("-"))
+    return molecules(int(head[3:]), seed, lo=lo, hi=hi)
 
 
 def grids_for(w: Workload, eps) -> ggrids.Grids:

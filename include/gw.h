@@ -52,10 +52,13 @@ enum {
   GW_ERR_BLAS = 6          /* rocBLAS / rocSOLVER returned an error          */
 };
 
-/* Arithmetic of the chi contraction: GW_FP64 (FP64 MFMA throughout) or
- * GW_BF16X3 (operands split into bf16 hi + lo, three bf16 MFMA products with
- * FP32 accumulation inside a tile, FP64 accumulation across tiles). */
-typedef enum { GW_FP64 = 0, GW_BF16X3 = 2 } gw_prec;
+/* Arithmetic of the chi contraction: GW_FP64 (FP64 MFMA throughout),
+ * GW_FP32 (operands and half-contracted tensors rounded to FP32, FP32 MFMA
+ * products with FP32 accumulation inside a tile, FP64 accumulation of chi
+ * across pivots) or GW_BF16X3 (operands split into bf16 hi + lo, three bf16
+ * MFMA products with FP32 accumulation inside a tile, FP64 accumulation
+ * across pivots). */
+typedef enum { GW_FP64 = 0, GW_FP32 = 1, GW_BF16X3 = 2 } gw_prec;
 
 /* One molecule / strip.  Atom-triple bricks (a, b, c) of the three-center
  * tensor (mu nu|P) (Eq. 4): mu on AO atom a, nu on AO atom b, P on RI atom c.

@@ -22,6 +22,7 @@
 #include <new>
 #include <numeric>
 #include <sstream>
+#include <type_traits>
 
 #include "chi_stages.hpp"
 
@@ -29,12 +30,12 @@ namespace gw {
 namespace {
 
 // stage-C tile variants: rows of a tile (columns are one 160-wide panel)
-//   FP64    0: <WM 4, KC 32> 128 rows   1: <WM 2, KC 32> 64 rows   2: <WM 4, KC 16> 128 rows
+//   FP64 and FP32  0: <WM 4, KC 32> 128 rows  1: <WM 2, KC 32> 64 rows  2: <WM 4, KC 16> 128 rows
 //   BF16x3  0: <WM 4, RB 4> 256 rows    1: <WM 4, RB 2> 128 rows   2: <WM 2, RB 4> 128 rows
 constexpr int kNVar = 3;
 int c_rows(int prec, int v) {
   static const int f64[kNVar] = {128, 64, 128}, bf[kNVar] = {256, 128, 128};
-  return prec == GW_FP64 ? f64[v] : bf[v];
+  return prec == GW_BF16X3 ? bf[v] : f64[v];
 }
 // stage-B waves (FP64) / row blocks (BF16x3) by the row count n_tau * NA
 int b_wm(int RS) { return RS <= 64 ? 2 : RS <= 96 ? 3 : RS <= 128 ? 4 : RS <= 160 ? 5 : 4; }
@@ -95,6 +96,21 @@ struct Table {
   }
 };
 
+// Buffers and problem descriptions of the FP64 (T = double) or FP32
+// (T = float) form of one system.
+template <class T>
+struct FBufs {
+  const T* dof = nullptr;      // filtered D^occ, D^vir in the operand type
+  const T* dvf = nullptr;
+  const T* t3c = nullptr;      // bricks in the operand type
+  T* dvg = nullptr;            // gathered D^vir columns of the pivot
+  T* mb = nullptr;             // M_b
+  T* bp = nullptr;             // N_b panels
+  StageA<T> sa{};
+  StageB<T> sb{};
+  StageC<T> sc{};
+};
+
 // One system of a plan.
 struct SysPlan {
   gw_system s{};
@@ -105,17 +121,35 @@ struct SysPlan {
   std::vector<int32_t> acount;
   std::vector<double> asuffix;
   double fl_a = 0.0, fl_b = 0.0, fl_c = 0.0;   // FLOPs per tau (all blocks)
-  double *dof = nullptr, *dvf = nullptr, *dvg = nullptr, *mb = nullptr, *bp = nullptr;
+  double *dof = nullptr, *dvf = nullptr;       // filtered D stacks (FP64)
+  float *dof32 = nullptr, *dvf32 = nullptr;    // their FP32 copies (FP32 form)
   uint8_t* dropped = nullptr;
   uint16_t *th = nullptr, *tl = nullptr, *doh = nullptr, *dol = nullptr, *dvh = nullptr, *dvl = nullptr;
   uint16_t *mh = nullptr, *ml = nullptr, *nh = nullptr, *nl = nullptr;
   uint8_t* keep = nullptr;          // screener mask (one-system calls only)
-  StageA sa{};
-  StageB sb{};
-  StageC sc{};
+  FBufs<double> f64;
+  FBufs<float> f32;
   StageABf ba{};
   StageBBf bb{};
   StageCBf bc{};
+};
+
+template <class T>
+FBufs<T>& bufs(SysPlan& P);
+template <>
+FBufs<double>& bufs<double>(SysPlan& P) { return P.f64; }
+template <>
+FBufs<float>& bufs<float>(SysPlan& P) { return P.f32; }
+
+// per-pivot-index launch tables of the FP64 / FP32 form
+template <class T>
+struct FTables {
+  Table<StageA<T>> tA;
+  Table<StageB<T>> tB;
+  Table<StageC<T>> tC;
+  std::vector<GatherEnt<T>> gath;
+  std::vector<int> gath0, gathn;
+  GatherEnt<T>* d_gath = nullptr;
 };
 
 }  // namespace
@@ -132,15 +166,11 @@ struct gw_chi_batch {
   std::vector<int> order;            // systems by decreasing size
   int variant = 0, persistent = 0;
   int RS = 0;
-  Table<StageA> tA;
-  Table<StageB> tB;
-  Table<StageC> tC;
+  FTables<double> t64;
+  FTables<float> t32;
   Table<StageABf> tAb;
   Table<StageBBf> tBb;
   Table<StageCBf> tCb;
-  std::vector<GatherEnt> gath;
-  std::vector<int> gath0, gathn;
-  GatherEnt* d_gath = nullptr;
   int* queues = nullptr;
   int n_queues = 0;
   int* tiles_skipped = nullptr;
@@ -169,6 +199,70 @@ struct gw_chi_batch {
 
 namespace gw {
 namespace {
+
+// device copies of a system's grouping and panel index arrays
+struct Index {
+  int32_t *goff, *seg_atom, *gc, *gslot, *ulen, *kmap, *km_off;
+  int64_t *seg_brick, *bp_off;
+};
+
+// scratch and problem descriptions of the FP64 / FP32 form of one system
+template <class T>
+gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index& ix, hipStream_t st) {
+  const int n_tau = B.n_tau, NA = B.NA, NR = B.NR, N = P.N, RS = n_tau * NA;
+  Scratch& M = B.mem;
+  FBufs<T>& F = bufs<T>(P);
+  gw_status rc;
+  if constexpr (std::is_same<T, double>::value) {
+    F.dof = P.dof;
+    F.dvf = P.dvf;
+    F.t3c = s->t3c;
+  } else {
+    // operands rounded to FP32 once: the bricks here, D(tau) at every execution
+    const size_t dsz = (size_t)n_tau * N * N, tsz = (size_t)s->n_trip * P.bs;
+    float* t32;
+    if ((rc = M.alloc(&P.dof32, dsz)) != GW_OK) return rc;
+    if ((rc = M.alloc(&P.dvf32, dsz)) != GW_OK) return rc;
+    if ((rc = M.alloc(&t32, tsz)) != GW_OK) return rc;
+    GW_HIP(to_f32(s->t3c, t32, (int64_t)tsz, st));
+    F.dof = P.dof32;
+    F.dvf = P.dvf32;
+    F.t3c = t32;
+  }
+  if ((rc = M.alloc(&F.dvg, (size_t)N * RS)) != GW_OK) return rc;
+  if ((rc = M.alloc(&F.mb, (size_t)n_tau * NA * P.nRmax * N * NR)) != GW_OK) return rc;
+  if ((rc = M.alloc(&F.bp, (size_t)n_tau * P.BPS)) != GW_OK) return rc;
+  // entries of N_b that no group writes stay zero for the life of the plan
+  GW_HIP(hipMemsetAsync(F.bp, 0, sizeof(T) * (size_t)n_tau * P.BPS, st));
+
+  StageA<T>& sa = F.sa;
+  sa.dof = F.dof; sa.t3c = F.t3c; sa.mb = F.mb; sa.goff = ix.goff; sa.seg_atom = ix.seg_atom;
+  sa.seg_brick = ix.seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = AB_COLS;
+  sa.n_rt = (N + sa.rows_pt - 1) / sa.rows_pt;
+  sa.n_ct = (NA * NR + sa.cols_pt - 1) / sa.cols_pt;
+  sa.N = N; sa.NA = NA; sa.NR = NR; sa.nRmax = P.nRmax; sa.bs = P.bs;
+  sa.fdNA.set((uint32_t)NA);
+  sa.fdNR.set((uint32_t)NR);
+
+  StageB<T>& sb = F.sb;
+  sb.dvg = F.dvg; sb.t3c = F.t3c; sb.bp = F.bp; sb.goff = ix.goff; sb.seg_atom = ix.seg_atom;
+  sb.seg_brick = ix.seg_brick; sb.gc = ix.gc; sb.gslot = ix.gslot; sb.ulen = ix.ulen;
+  sb.bp_off = ix.bp_off; sb.RS = RS; sb.NA = NA; sb.NR = NR; sb.PG = P.PG; sb.PC = P.PC;
+  sb.bs = P.bs; sb.BPS = P.BPS;
+  sb.rows_pt = 32 * b_wm(RS);
+  sb.cols_pt = AB_COLS;
+  sb.n_rt = (RS + sb.rows_pt - 1) / sb.rows_pt;
+  sb.n_ct = (NA * NR + sb.cols_pt - 1) / sb.cols_pt;
+  sb.fdNA.set((uint32_t)NA);
+  sb.fdNR.set((uint32_t)NR);
+
+  StageC<T>& sc = F.sc;
+  sc.mb = F.mb; sc.bp = F.bp; sc.gc = ix.gc; sc.kmap = ix.kmap; sc.km_off = ix.km_off;
+  sc.ulen = ix.ulen; sc.bp_off = ix.bp_off; sc.N = N; sc.NA = NA; sc.NR = NR; sc.NRI = P.NRI;
+  sc.PG = P.PG; sc.PC = P.PC; sc.nRmax = P.nRmax; sc.n_atoms = P.na; sc.BPS = P.BPS;
+  sc.fdNR.set((uint32_t)NR);
+  return GW_OK;
+}
 
 gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream_t st) {
   const int n_tau = B.n_tau, NA = B.NA, NR = B.NR;
@@ -235,39 +329,11 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
   if ((rc = M.upload(&d_km_off, P.pan.km_off)) != GW_OK) return rc;
   if ((rc = M.upload(&d_bp_off, P.pan.off)) != GW_OK) return rc;
 
+  const Index ix{d_goff, d_seg_atom, d_gc, d_gslot, d_ulen, d_kmap, d_km_off, d_seg_brick, d_bp_off};
   if (B.prec == GW_FP64) {
-    if ((rc = M.alloc(&P.dvg, (size_t)N * RS)) != GW_OK) return rc;
-    if ((rc = M.alloc(&P.mb, (size_t)n_tau * NA * P.nRmax * N * NR)) != GW_OK) return rc;
-    if ((rc = M.alloc(&P.bp, (size_t)n_tau * P.BPS)) != GW_OK) return rc;
-    // entries of N_b that no group writes stay zero for the life of the plan
-    GW_HIP(hipMemsetAsync(P.bp, 0, sizeof(double) * (size_t)n_tau * P.BPS, st));
-
-    StageA& sa = P.sa;
-    sa.dof = P.dof; sa.t3c = s->t3c; sa.mb = P.mb; sa.goff = d_goff; sa.seg_atom = d_seg_atom;
-    sa.seg_brick = d_seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = AB_COLS;
-    sa.n_rt = (N + sa.rows_pt - 1) / sa.rows_pt;
-    sa.n_ct = (NA * NR + sa.cols_pt - 1) / sa.cols_pt;
-    sa.N = N; sa.NA = NA; sa.NR = NR; sa.nRmax = P.nRmax; sa.bs = P.bs;
-    sa.fdNA.set((uint32_t)NA);
-    sa.fdNR.set((uint32_t)NR);
-
-    StageB& sb = P.sb;
-    sb.dvg = P.dvg; sb.t3c = s->t3c; sb.bp = P.bp; sb.goff = d_goff; sb.seg_atom = d_seg_atom;
-    sb.seg_brick = d_seg_brick; sb.gc = d_gc; sb.gslot = d_gslot; sb.ulen = d_ulen;
-    sb.bp_off = d_bp_off; sb.RS = RS; sb.NA = NA; sb.NR = NR; sb.PG = P.PG; sb.PC = P.PC;
-    sb.bs = P.bs; sb.BPS = P.BPS;
-    sb.rows_pt = 32 * b_wm(RS);
-    sb.cols_pt = AB_COLS;
-    sb.n_rt = (RS + sb.rows_pt - 1) / sb.rows_pt;
-    sb.n_ct = (NA * NR + sb.cols_pt - 1) / sb.cols_pt;
-    sb.fdNA.set((uint32_t)NA);
-    sb.fdNR.set((uint32_t)NR);
-
-    StageC& sc = P.sc;
-    sc.mb = P.mb; sc.bp = P.bp; sc.gc = d_gc; sc.kmap = d_kmap; sc.km_off = d_km_off;
-    sc.ulen = d_ulen; sc.bp_off = d_bp_off; sc.N = N; sc.NA = NA; sc.NR = NR; sc.NRI = P.NRI;
-    sc.PG = P.PG; sc.PC = P.PC; sc.nRmax = P.nRmax; sc.n_atoms = na; sc.BPS = P.BPS;
-    sc.fdNR.set((uint32_t)NR);
+    if ((rc = prepare_f<double>(B, P, s, ix, st)) != GW_OK) return rc;
+  } else if (B.prec == GW_FP32) {
+    if ((rc = prepare_f<float>(B, P, s, ix, st)) != GW_OK) return rc;
   } else {
     // split-precision form: operands as bf16 hi/lo pairs; T is split once per plan
     std::vector<int64_t> poffb(P.n_pan + 1, 0);
@@ -330,110 +396,135 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
   return GW_OK;
 }
 
+template <class T>
+FTables<T>& tabs(gw_chi_batch& B);
+template <>
+FTables<double>& tabs<double>(gw_chi_batch& B) { return B.t64; }
+template <>
+FTables<float>& tabs<float>(gw_chi_batch& B) { return B.t32; }
+template <class T>
+const FTables<T>& tabs(const gw_chi_batch& B) { return tabs<T>(const_cast<gw_chi_batch&>(B)); }
+
+// pivot atom index piv of system P: first group and group count (0: no work)
+inline int pivot_groups(const SysPlan& P, int piv, int& g0) {
+  if (piv >= P.na) return 0;
+  g0 = P.G.gb_start[piv];
+  return P.G.gb_start[piv + 1] - g0;
+}
+
 // tables of stages A and B (and the D^vir gathers) for every pivot index
-gw_status build_ab_tables(gw_chi_batch& B, hipStream_t st) {
+template <class T>
+gw_status ab_tables_f(gw_chi_batch& B, hipStream_t st) {
+  FTables<T>& F = tabs<T>(B);
   const int n_piv = B.max_na, n_tau = B.n_tau;
-  const bool fp64 = B.prec == GW_FP64;
-  if (fp64) {
-    B.tA.begin(n_piv);
-    B.tB.begin(n_piv);
-    B.gath.clear();
-    B.gath0.assign(n_piv, 0);
-    B.gathn.assign(n_piv, 0);
-  } else {
-    B.tAb.begin(n_piv);
-    B.tBb.begin(n_piv);
-  }
+  F.tA.begin(n_piv);
+  F.tB.begin(n_piv);
+  F.gath.clear();
+  F.gath0.assign(n_piv, 0);
+  F.gathn.assign(n_piv, 0);
   for (int piv = 0; piv < n_piv; ++piv) {
-    if (fp64) {
-      B.tA.open(piv);
-      B.tB.open(piv);
-      B.gath0[piv] = (int)B.gath.size();
-    } else {
-      B.tAb.open(piv);
-      B.tBb.open(piv);
-    }
+    F.tA.open(piv);
+    F.tB.open(piv);
+    F.gath0[piv] = (int)F.gath.size();
     for (int m : B.order) {
       SysPlan& P = B.sys[m];
-      if (piv >= P.na) continue;
-      const int g0 = P.G.gb_start[piv], nR = P.G.gb_start[piv + 1] - g0;
+      FBufs<T>& pb = bufs<T>(P);
+      int g0 = 0;
+      const int nR = pivot_groups(P, piv, g0);
       if (nR == 0) continue;
-      if (fp64) {
-        StageA a = P.sa;
-        a.g0 = g0;
-        B.tA.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
-        B.tB.add(piv, P.sb, P.n_groups * P.sb.n_rt * P.sb.n_ct, 1, 1);
-        B.gath.push_back(GatherEnt{P.dvf, P.dvg, P.N, piv});
-        B.gathn[piv]++;
-      } else {
-        StageABf a = P.ba;
-        a.g0 = g0;
-        B.tAb.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
-        StageBBf b = P.bb;
-        b.b = piv;
-        B.tBb.add(piv, b, P.n_groups * b.n_rt * b.n_ct, 1, 1);
-      }
+      StageA<T> a = pb.sa;
+      a.g0 = g0;
+      F.tA.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
+      F.tB.add(piv, pb.sb, P.n_groups * pb.sb.n_rt * pb.sb.n_ct, 1, 1);
+      F.gath.push_back(GatherEnt<T>{pb.dvf, pb.dvg, P.N, piv});
+      F.gathn[piv]++;
     }
   }
   gw_status rc;
-  if (fp64) {
-    if ((rc = B.tA.upload(B.mem, st)) != GW_OK) return rc;
-    if ((rc = B.tB.upload(B.mem, st)) != GW_OK) return rc;
-    if ((rc = B.mem.upload(&B.d_gath, B.gath)) != GW_OK) return rc;
-  } else {
-    if ((rc = B.tAb.upload(B.mem, st)) != GW_OK) return rc;
-    if ((rc = B.tBb.upload(B.mem, st)) != GW_OK) return rc;
+  if ((rc = F.tA.upload(B.mem, st)) != GW_OK) return rc;
+  if ((rc = F.tB.upload(B.mem, st)) != GW_OK) return rc;
+  return B.mem.upload(&F.d_gath, F.gath);
+}
+
+gw_status ab_tables_bf(gw_chi_batch& B, hipStream_t st) {
+  const int n_piv = B.max_na, n_tau = B.n_tau;
+  B.tAb.begin(n_piv);
+  B.tBb.begin(n_piv);
+  for (int piv = 0; piv < n_piv; ++piv) {
+    B.tAb.open(piv);
+    B.tBb.open(piv);
+    for (int m : B.order) {
+      SysPlan& P = B.sys[m];
+      int g0 = 0;
+      const int nR = pivot_groups(P, piv, g0);
+      if (nR == 0) continue;
+      StageABf a = P.ba;
+      a.g0 = g0;
+      B.tAb.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
+      StageBBf b = P.bb;
+      b.b = piv;
+      B.tBb.add(piv, b, P.n_groups * b.n_rt * b.n_ct, 1, 1);
+    }
   }
-  return GW_OK;
+  gw_status rc;
+  if ((rc = B.tAb.upload(B.mem, st)) != GW_OK) return rc;
+  return B.tBb.upload(B.mem, st);
+}
+
+gw_status build_ab_tables(gw_chi_batch& B, hipStream_t st) {
+  if (B.prec == GW_FP64) return ab_tables_f<double>(B, st);
+  if (B.prec == GW_FP32) return ab_tables_f<float>(B, st);
+  return ab_tables_bf(B, st);
 }
 
 // stage-C tables for the current variant and output pointers
-gw_status build_c_tables(gw_chi_batch& B, double* const* chi, hipStream_t st) {
+template <class C, class Get>
+void c_tables(gw_chi_batch& B, Table<C>& tab, Get get, double* const* chi) {
   const int n_piv = B.max_na, n_tau = B.n_tau, rows = c_rows(B.prec, B.variant);
-  const bool fp64 = B.prec == GW_FP64;
-  if (fp64) B.tC.begin(n_piv);
-  else B.tCb.begin(n_piv);
+  tab.begin(n_piv);
   for (int piv = 0; piv < n_piv; ++piv) {
-    if (fp64) B.tC.open(piv);
-    else B.tCb.open(piv);
+    tab.open(piv);
     for (int m : B.order) {
       SysPlan& P = B.sys[m];
-      if (piv >= P.na) continue;
-      const int g0 = P.G.gb_start[piv], nR = P.G.gb_start[piv + 1] - g0;
+      int g0 = 0;
+      const int nR = pivot_groups(P, piv, g0);
       if (nR == 0) continue;
       const int n_rt = (nR * B.NR + rows - 1) / rows;
-      if (fp64) {
-        StageC c = P.sc;
-        c.chi = chi[m];
-        c.g0 = g0;
-        c.nR = nR;
-        c.rows_pt = rows;
-        c.n_rt = n_rt;
-        c.keep = P.keep;
-        c.tiles_skipped = B.tiles_skipped;
-        B.tC.add(piv, c, n_rt * P.n_pan, 1, n_tau);
-      } else {
-        StageCBf c = P.bc;
-        c.chi = chi[m];
-        c.g0 = g0;
-        c.nR = nR;
-        c.rows_pt = rows;
-        c.n_rt = n_rt;
-        c.keep = P.keep;
-        c.tiles_skipped = B.tiles_skipped;
-        B.tCb.add(piv, c, n_rt * P.n_pan, 1, n_tau);
-      }
+      C c = get(P);
+      c.chi = chi[m];
+      c.g0 = g0;
+      c.nR = nR;
+      c.rows_pt = rows;
+      c.n_rt = n_rt;
+      c.keep = P.keep;
+      c.tiles_skipped = B.tiles_skipped;
+      tab.add(piv, c, n_rt * P.n_pan, 1, n_tau);
     }
   }
+}
+
+gw_status build_c_tables(gw_chi_batch& B, double* const* chi, hipStream_t st) {
+  gw_status rc;
+  if (B.prec == GW_FP64) {
+    c_tables(B, B.t64.tC, [](SysPlan& P) { return P.f64.sc; }, chi);
+    rc = B.t64.tC.upload(B.mem, st);
+  } else if (B.prec == GW_FP32) {
+    c_tables(B, B.t32.tC, [](SysPlan& P) { return P.f32.sc; }, chi);
+    rc = B.t32.tC.upload(B.mem, st);
+  } else {
+    c_tables(B, B.tCb, [](SysPlan& P) { return P.bc; }, chi);
+    rc = B.tCb.upload(B.mem, st);
+  }
+  if (rc != GW_OK) return rc;
   B.bound_chi.assign(chi, chi + B.n_sys);
   B.c_built_variant = B.variant;
-  return fp64 ? B.tC.upload(B.mem, st) : B.tCb.upload(B.mem, st);
+  return GW_OK;
 }
 
 // With queue == nullptr the call only computes the persistent grid size of
 // the kernel (done at plan creation, outside any graph capture).
 template <int WM, int WN, int NB, int KC, class P>
-hipError_t run_f64(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t st) {
+hipError_t run_mfma(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t st) {
   if (!queue) {
     (void)persistent_cap_gemm<WM, WN, NB, KC, Batched<P>>();
     return hipSuccess;
@@ -466,19 +557,27 @@ hipError_t run_bf(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t
               : launch_tile_bf16x3<WM, WN, RB, NB, KC>(b, dim3((unsigned)work), st);
 }
 
-hipError_t stage_b_f64(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+template <class T>
+hipError_t stage_a_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  return run_mfma<A_WM, AB_WN, AB_NBW, 16>(tabs<T>(B).tA, piv, pers, q, st);
+}
+template <class T>
+hipError_t stage_b_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  const auto& t = tabs<T>(B).tB;
   switch (b_wm(B.RS)) {
-    case 2: return run_f64<2, AB_WN, AB_NBW, 16>(B.tB, piv, pers, q, st);
-    case 3: return run_f64<3, AB_WN, AB_NBW, 16>(B.tB, piv, pers, q, st);
-    case 5: return run_f64<5, AB_WN, AB_NBW, 16>(B.tB, piv, pers, q, st);
-    default: return run_f64<4, AB_WN, AB_NBW, 16>(B.tB, piv, pers, q, st);
+    case 2: return run_mfma<2, AB_WN, AB_NBW, 16>(t, piv, pers, q, st);
+    case 3: return run_mfma<3, AB_WN, AB_NBW, 16>(t, piv, pers, q, st);
+    case 5: return run_mfma<5, AB_WN, AB_NBW, 16>(t, piv, pers, q, st);
+    default: return run_mfma<4, AB_WN, AB_NBW, 16>(t, piv, pers, q, st);
   }
 }
-hipError_t stage_c_f64(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+template <class T>
+hipError_t stage_c_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  const auto& t = tabs<T>(B).tC;
   switch (B.variant) {
-    case 1: return run_f64<2, C_WN, C_NBW, C_KC>(B.tC, piv, pers, q, st);
-    case 2: return run_f64<4, C_WN, C_NBW, 16>(B.tC, piv, pers, q, st);
-    default: return run_f64<4, C_WN, C_NBW, C_KC>(B.tC, piv, pers, q, st);
+    case 1: return run_mfma<2, C_WN, C_NBW, C_KC>(t, piv, pers, q, st);
+    case 2: return run_mfma<4, C_WN, C_NBW, 16>(t, piv, pers, q, st);
+    default: return run_mfma<4, C_WN, C_NBW, C_KC>(t, piv, pers, q, st);
   }
 }
 hipError_t stage_b_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
@@ -503,9 +602,13 @@ void prime(gw_chi_batch& B) {
   for (int v = 0; v < kNVar; ++v) {
     B.variant = v;
     if (B.prec == GW_FP64) {
-      (void)run_f64<A_WM, AB_WN, AB_NBW, 16>(B.tA, 0, true, nullptr, nullptr);
-      (void)stage_b_f64(B, 0, true, nullptr, nullptr);
-      (void)stage_c_f64(B, 0, true, nullptr, nullptr);
+      (void)stage_a_f<double>(B, 0, true, nullptr, nullptr);
+      (void)stage_b_f<double>(B, 0, true, nullptr, nullptr);
+      (void)stage_c_f<double>(B, 0, true, nullptr, nullptr);
+    } else if (B.prec == GW_FP32) {
+      (void)stage_a_f<float>(B, 0, true, nullptr, nullptr);
+      (void)stage_b_f<float>(B, 0, true, nullptr, nullptr);
+      (void)stage_c_f<float>(B, 0, true, nullptr, nullptr);
     } else {
       (void)run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, 0, true, nullptr, nullptr);
       (void)stage_b_bf(B, 0, true, nullptr, nullptr);
@@ -515,13 +618,38 @@ void prime(gw_chi_batch& B) {
   B.variant = v0;
 }
 
+// the three stages of pivot index piv, FP64 / FP32 form
+template <class T>
+gw_status pivot_f(gw_chi_batch& B, int piv, bool pers, int* q, std::vector<hipEvent_t>* ev,
+                  hipStream_t st) {
+  const FTables<T>& F = tabs<T>(B);
+  auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord((*ev)[4 * piv + k], st) : hipSuccess; };
+  if (F.gathn[piv] > 0) {
+    int64_t most = 0;
+    for (int e = 0; e < F.gathn[piv]; ++e)
+      most = std::max<int64_t>(most, (int64_t)F.gath[F.gath0[piv] + e].N * B.RS);
+    const unsigned bx = (unsigned)std::min<int64_t>((most + 255) / 256, 4096);
+    hipLaunchKernelGGL(gather_dvir_kernel<T>, dim3(bx, (unsigned)F.gathn[piv]), dim3(256), 0, st,
+                       F.d_gath + F.gath0[piv], B.NA, B.n_tau);
+    GW_HIP(hipGetLastError());
+  }
+  GW_HIP(mark(0));
+  GW_HIP(stage_a_f<T>(B, piv, pers, q, st));
+  GW_HIP(mark(1));
+  GW_HIP(stage_b_f<T>(B, piv, pers, q + 1, st));
+  GW_HIP(mark(2));
+  GW_HIP(stage_c_f<T>(B, piv, pers, q + 2, st));
+  GW_HIP(mark(3));
+  return GW_OK;
+}
+
 // Every launch of one execution, in stream order (no allocation, copy,
 // memset or synchronization: the sequence may be captured into a graph).
 // With `ev` (eager runs only) events bracket each stage of each pivot.
 gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const* vir,
                   double* const* chi, std::vector<hipEvent_t>* ev, hipStream_t st) {
   const int n_tau = B.n_tau, NA = B.NA, NR = B.NR;
-  const bool fp64 = B.prec == GW_FP64, pers = B.persistent != 0;
+  const bool pers = B.persistent != 0;
   GW_HIP(fill_zero(B.queues, B.n_queues, st));
   for (int m = 0; m < B.n_sys; ++m) {
     SysPlan& P = B.sys[m];
@@ -530,7 +658,10 @@ gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const
     if (P.s.n_trip == 0) continue;
     GW_HIP(filter_square_blocks(occ[m], P.dof, n_tau, P.na, NA, B.eps_f, P.dropped, st));
     GW_HIP(filter_square_blocks(vir[m], P.dvf, n_tau, P.na, NA, B.eps_f, P.dropped + nflag, st));
-    if (!fp64) {
+    if (B.prec == GW_FP32) {
+      GW_HIP(to_f32(P.dof, P.dof32, (int64_t)n_tau * P.N * P.N, st));
+      GW_HIP(to_f32(P.dvf, P.dvf32, (int64_t)n_tau * P.N * P.N, st));
+    } else if (B.prec == GW_BF16X3) {
       const int64_t dsz16 = (int64_t)n_tau * P.N * P.na * 16;
       const unsigned blocks = (unsigned)std::min<int64_t>((dsz16 + 255) / 256, 1 << 20);
       hipLaunchKernelGGL(split_d_kernel, dim3(blocks), dim3(256), 0, st, P.dof, P.doh, P.dol, n_tau,
@@ -546,23 +677,11 @@ gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const
   };
   for (int piv = 0; piv < B.max_na; ++piv) {
     int* q = B.queues + 3 * piv;
-    if (fp64) {
-      if (B.gathn[piv] > 0) {
-        int64_t most = 0;
-        for (int e = 0; e < B.gathn[piv]; ++e)
-          most = std::max<int64_t>(most, (int64_t)B.gath[B.gath0[piv] + e].N * n_tau * NA);
-        const unsigned bx = (unsigned)std::min<int64_t>((most + 255) / 256, 4096);
-        hipLaunchKernelGGL(gather_dvir_kernel, dim3(bx, (unsigned)B.gathn[piv]), dim3(256), 0, st,
-                           B.d_gath + B.gath0[piv], NA, n_tau);
-        GW_HIP(hipGetLastError());
-      }
-      GW_HIP(mark(piv, 0));
-      GW_HIP((run_f64<A_WM, AB_WN, AB_NBW, 16>(B.tA, piv, pers, q, st)));
-      GW_HIP(mark(piv, 1));
-      GW_HIP(stage_b_f64(B, piv, pers, q + 1, st));
-      GW_HIP(mark(piv, 2));
-      GW_HIP(stage_c_f64(B, piv, pers, q + 2, st));
-      GW_HIP(mark(piv, 3));
+    gw_status rc = GW_OK;
+    if (B.prec == GW_FP64) {
+      rc = pivot_f<double>(B, piv, pers, q, ev, st);
+    } else if (B.prec == GW_FP32) {
+      rc = pivot_f<float>(B, piv, pers, q, ev, st);
     } else {
       GW_HIP(mark(piv, 0));
       GW_HIP((run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, piv, pers, q, st)));
@@ -572,6 +691,7 @@ gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const
       GW_HIP(stage_c_bf(B, piv, pers, q + 2, st));
       GW_HIP(mark(piv, 3));
     }
+    if (rc != GW_OK) return rc;
   }
   // symmetric completion and output filter
   for (int m = 0; m < B.n_sys; ++m) {
@@ -674,8 +794,9 @@ gw_status execute(gw_chi_batch& B, const double* const* occ, const double* const
     for (int k = 0; k < 3; ++k) {
       int64_t nl = 0;
       for (int piv = 0; piv < B.max_na; ++piv)
-        nl += (B.prec == GW_FP64 ? (k == 0 ? B.tA.n[piv] : k == 1 ? B.tB.n[piv] : B.tC.n[piv])
-                                 : (k == 0 ? B.tAb.n[piv] : k == 1 ? B.tBb.n[piv] : B.tCb.n[piv])) > 0;
+        nl += (B.prec == GW_FP64   ? (k == 0 ? B.t64.tA.n[piv] : k == 1 ? B.t64.tB.n[piv] : B.t64.tC.n[piv])
+               : B.prec == GW_FP32 ? (k == 0 ? B.t32.tA.n[piv] : k == 1 ? B.t32.tB.n[piv] : B.t32.tC.n[piv])
+                                   : (k == 0 ? B.tAb.n[piv] : k == 1 ? B.tBb.n[piv] : B.tCb.n[piv])) > 0;
       stats->n_launch[k] = nl;
     }
     for (int piv = 0; timing && piv < B.max_na; ++piv)
@@ -699,7 +820,8 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   const double eps_f = opts ? opts->filter_eps : 0.0;
   GW_CHECK_ARG(std::isfinite(eps_f) && eps_f >= 0.0, "filter_eps must be finite and >= 0");
   const int prec = opts ? opts->prec : GW_FP64;
-  GW_CHECK_ARG(prec == GW_FP64 || prec == GW_BF16X3, "prec must be GW_FP64 or GW_BF16X3");
+  GW_CHECK_ARG(prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+               "prec must be GW_FP64, GW_FP32 or GW_BF16X3");
   gw_status rc;
   for (int m = 0; m < n_sys; ++m) {
     if ((rc = check_system(&systems[m])) != GW_OK) return rc;
@@ -752,7 +874,7 @@ std::string shape_key(const gw_chi_batch& B) {
   for (const SysPlan& P : B.sys) atoms += P.na;
   atoms /= B.n_sys;
   std::ostringstream k;
-  k << (B.prec == GW_FP64 ? "fp64" : "bf16x3") << "_ao" << B.NA << "_ri" << B.NR << "_tau" << B.n_tau
+  k << (B.prec == GW_FP64 ? "fp64" : B.prec == GW_FP32 ? "fp32" : "bf16x3") << "_ao" << B.NA << "_ri" << B.NR << "_tau" << B.n_tau
     << "_sys" << (int)std::lround(std::log2((double)B.n_sys)) << "_atoms"
     << (int)std::lround(2.0 * std::log2(std::max(1.0, atoms)));
   return k.str();

@@ -31,15 +31,19 @@ constexpr int C_KC = 32;                          // K chunk staged per barrier 
 constexpr int kSegTab = 2048;     // max bricks per group (first atoms)
 constexpr int kPanTab = 4096;     // max K functions per column panel (NA * |U_p|)
 
+// T: operand type (double: FP64 form, float: FP32 form)
+template <class T>
 struct StageA {
+  using In = T;
+  using Out = T;
   struct Tile : TileBase {
     int g, slot, tau, row0, col0, seg0, nseg;
   };
   static constexpr bool kAScale = false, kDot = false;
   static constexpr int kTabA = kSegTab, kTabB = kSegTab;
-  const double* dof;
-  const double* t3c;
-  double* mb;
+  const T* dof;
+  const T* t3c;
+  T* mb;
   const int32_t* goff;
   const int32_t* seg_atom;
   const int64_t* seg_brick;
@@ -69,20 +73,20 @@ struct StageA {
       tb[i] = (int)seg_brick[t.seg0 + i];
     }
   }
-  __device__ const double* abase(const Tile& t) const { return dof + (int64_t)t.tau * N * N + t.row0; }
+  __device__ const T* abase(const Tile& t) const { return dof + (int64_t)t.tau * N * N + t.row0; }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
   __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
     const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
     return (int64_t)(ta[sg] * NA + i) * N;
   }
-  __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
+  __device__ const T* bbase(const Tile& t) const { return t3c + t.col0; }
   __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
     const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
     return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
   }
-  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ T ascale(const Tile&, int) const { return T(1); }
   // M_b[tau][sigma][slot][mu][P]: row mu, column (sigma, P)
-  __device__ double* obase(const Tile& t) const {
+  __device__ T* obase(const Tile& t) const {
     return mb + ((int64_t)t.tau * NA * nRmax + t.slot) * N * NR;
   }
   __device__ int64_t rowoff(const Tile& t, int r) const { return (int64_t)(t.row0 + r) * NR; }
@@ -97,15 +101,18 @@ struct StageA {
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
+template <class T>
 struct StageB {
+  using In = T;
+  using Out = T;
   struct Tile : TileBase {
     int g, row0, col0, seg0, nseg, p, cl, slot, KU;
   };
   static constexpr bool kAScale = false, kDot = false;
   static constexpr int kTabA = kSegTab, kTabB = kSegTab;
-  const double* dvg;        // [N][RS]
-  const double* t3c;
-  double* bp;
+  const T* dvg;             // [N][RS]
+  const T* t3c;
+  T* bp;
   const int32_t* goff;
   const int32_t* seg_atom;
   const int64_t* seg_brick;
@@ -142,20 +149,20 @@ struct StageB {
       tb[i] = (int)seg_brick[t.seg0 + i];
     }
   }
-  __device__ const double* abase(const Tile& t) const { return dvg + t.row0; }
+  __device__ const T* abase(const Tile& t) const { return dvg + t.row0; }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
   __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
     const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
     return (int64_t)(ta[sg] * NA + i) * RS;
   }
-  __device__ const double* bbase(const Tile& t) const { return t3c + t.col0; }
+  __device__ const T* bbase(const Tile& t) const { return t3c + t.col0; }
   __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
     const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
     return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
   }
-  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ T ascale(const Tile&, int) const { return T(1); }
   // N_b panel: [tau][panel][sigma][u = slot*NA + mu][(cl, Q)]: row (tau, sigma), column (mu, Q)
-  __device__ double* obase(const Tile& t) const { return bp + bp_off[t.p]; }
+  __device__ T* obase(const Tile& t) const { return bp + bp_off[t.p]; }
   __device__ int64_t rowoff(const Tile& t, int r) const {
     const int row = t.row0 + r, tau = (int)fdNA.div((uint32_t)row), sg = row - tau * NA;
     return (int64_t)tau * BPS + (int64_t)sg * t.KU * PC;
@@ -183,15 +190,18 @@ __device__ inline bool any_kept(const uint8_t* keep, const int32_t* slot_c, int 
   return false;
 }
 
+template <class T>
 struct StageC {
+  using In = T;
+  using Out = double;
   struct Tile : TileBase {
     int p, tau, row0, KU, km0;
     FastDiv fdKU;
   };
   static constexpr bool kAScale = false, kDot = false;
   static constexpr int kTabA = kPanTab, kTabB = 0;
-  const double* mb;
-  const double* bp;
+  const T* mb;
+  const T* bp;
   double* chi;
   const int32_t* gc;
   const int32_t* kmap;
@@ -229,7 +239,7 @@ struct StageC {
   __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
     for (int i = tid; i < t.KU; i += nt) ta[i] = kmap[t.km0 + i] * NR;
   }
-  __device__ const double* abase(const Tile& t) const {
+  __device__ const T* abase(const Tile& t) const {
     return mb + (int64_t)t.tau * NA * nRmax * N * NR;
   }
   __device__ int64_t aroff(const Tile& t, int r) const {
@@ -240,11 +250,11 @@ struct StageC {
     const int sg = (int)t.fdKU.div((uint32_t)k), u = k - sg * t.KU;
     return (int64_t)sg * nRmax * N * NR + ta[u];
   }
-  __device__ const double* bbase(const Tile& t) const {
+  __device__ const T* bbase(const Tile& t) const {
     return bp + (int64_t)t.tau * BPS + bp_off[t.p];
   }
   __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PC; }
-  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ T ascale(const Tile&, int) const { return T(1); }
   // chi[tau][P][Q] -= tile, P = (RI atom of the row's slot, P), Q = panel column
   __device__ double* obase(const Tile& t) const { return chi + (int64_t)t.tau * NRI * NRI; }
   __device__ int64_t rowoff(const Tile& t, int r) const {
@@ -261,14 +271,16 @@ struct StageC {
 
 // D^vir columns of pivot atom b, gathered as dvg[nu][(tau, sigma)] for the
 // systems of one batch (blockIdx.y = entry)
+template <class T>
 struct GatherEnt {
-  const double* dv;
-  double* dvg;
+  const T* dv;
+  T* dvg;
   int N, b;
 };
 
-__global__ void gather_dvir_kernel(const GatherEnt* __restrict__ ents, int NA, int n_tau) {
-  const GatherEnt en = ents[blockIdx.y];
+template <class T>
+__global__ void gather_dvir_kernel(const GatherEnt<T>* __restrict__ ents, int NA, int n_tau) {
+  const GatherEnt<T> en = ents[blockIdx.y];
   const int RS = n_tau * NA, N = en.N;
   const int64_t total = (int64_t)N * RS;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -277,6 +289,20 @@ __global__ void gather_dvir_kernel(const GatherEnt* __restrict__ ents, int NA, i
     const int tau = rc / NA, sg = rc % NA;
     en.dvg[e] = en.dv[(int64_t)tau * N * N + (int64_t)nu * N + (int64_t)en.b * NA + sg];
   }
+}
+
+// FP64 -> FP32 copy of n elements (operands of the FP32 form)
+__global__ void to_f32_kernel(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+hipError_t to_f32(const double* x, float* y, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(to_f32_kernel, dim3(blocks), dim3(256), 0, st, x, y, n);
+  return hipGetLastError();
 }
 
 #include "chi_bf16x3.inc"

@@ -1,8 +1,10 @@
-// FP64 MFMA tile engine for gfx950 (CDNA4), shared by every contraction.
+// FP64 / FP32 MFMA tile engine for gfx950 (CDNA4), shared by every contraction.
 //
-// A workgroup of WM waves computes a (32*WM) x (16*NB) output tile
+// A workgroup of WM x WN waves computes a (32*WM) x (16*NB*WN) output tile
 //   C[r][c] = sum_k A(r, k) * B(k, c)
-// with v_mfma_f64_16x16x4f64.  Wave w owns rows [32w, 32w + 32) (two 16-row
+// with v_mfma_f64_16x16x4f64, or v_mfma_f32_16x16x4f32 when the problem's
+// operand type P::In is float (FP32 products, FP32 accumulation; P::Out is
+// the type of the output array, FP64 for an accumulated result).  Wave w owns rows [32w, 32w + 32) (two 16-row
 // MFMA blocks) and all NB 16-column blocks, i.e. 2*NB accumulators of four
 // doubles per lane.  K is staged through LDS in chunks of KC = 16: A as
 // As[k][r], B as Bs[k][c] (both with a pad that puts consecutive k rows in
@@ -20,6 +22,7 @@
 // so A(r, k) = abase[aroff(r) + akoff(k)] (* ascale(k)) and
 // B(k, c) = bbase[bkoff(k) + c]; entries outside rows/cols/K read as zero
 // (branch-free: out-of-range lanes load element 0 and discard it).
+// Operand and output types default to double (P::In, P::Out).
 // Output offsets are separable, out(r, c) at rowoff(t, r) + coloff(t, c):
 //   kDot == false: double* obase(t); the tile is stored (kAccum == false) or
 //                  added with factor kSign to what is there (kAccum == true)
@@ -36,8 +39,48 @@
 namespace gw {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
-__host__ __device__ constexpr int lds_stride(int n) { return n + (16 - n % 32 + 32) % 32; }
+// LDS row stride: consecutive k rows start 16 elements apart modulo the bank
+// width (32 doubles or 64 floats), so the four k rows read by one MFMA step
+// fall in different banks
+template <class T>
+__host__ __device__ constexpr int lds_stride(int n) {
+  constexpr int w = sizeof(T) == 8 ? 32 : 64;
+  return n + (16 - n % w + w) % w;
+}
+
+// operand / output element types of a problem (double unless it says otherwise)
+template <class P, class = void>
+struct in_type { using type = double; };
+template <class P>
+struct in_type<P, std::void_t<typename P::In>> { using type = typename P::In; };
+template <class P, class = void>
+struct out_type { using type = double; };
+template <class P>
+struct out_type<P, std::void_t<typename P::Out>> { using type = typename P::Out; };
+
+// one 16x16x4 MFMA step and the accumulator / output layout of each type
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using acc = dbl4;
+  __device__ static acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // lane l, element i -> row 4*i + l/16 (measured on gfx950), col l%16
+  __device__ static int row(int i, int lk) { return 4 * i + lk; }
+};
+template <>
+struct Mfma<float> {
+  using acc = flt4;
+  __device__ static acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // lane l, element i -> row 4*(l/16) + i, col l%16
+  __device__ static int row(int i, int lk) { return 4 * lk + i; }
+};
 
 // q = k / d for k * d < 2^32 (the hosts that size K check this)
 struct FastDiv {
@@ -102,14 +145,17 @@ struct Batched : P {
 
 template <int WM, int WN, int NB, int KC, class P>
 __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int bz) {
+  using TI = typename in_type<P>::type;
+  using TO = typename out_type<P>::type;
+  using MF = Mfma<TI>;
   constexpr int ROWS = 32 * WM, COLS = 16 * NB * WN, NT = 64 * WM * WN;
-  constexpr int AST = lds_stride(ROWS), BST = lds_stride(COLS);
+  constexpr int AST = lds_stride<TI>(ROWS), BST = lds_stride<TI>(COLS);
   constexpr int KSTEP = NT / ROWS;                    // k rows of A per pass of the threads
   constexpr int APT = KC / KSTEP;
   constexpr int BPT = (KC * COLS + NT - 1) / NT;
   static_assert(NT % ROWS == 0 && KC % KSTEP == 0, "A staging layout");
-  __shared__ double As[KC * AST];
-  __shared__ double Bs[KC * BST];
+  __shared__ TI As[KC * AST];
+  __shared__ TI Bs[KC * BST];
   __shared__ int tabA[P::kTabA > 0 ? P::kTabA : 1];
   __shared__ int tabB[P::kTabB > 0 ? P::kTabB : 1];
 
@@ -122,8 +168,8 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
   const auto lp = resolve(p, t);
   lp.fill(t, tabA, tabB, tid, NT);
   __syncthreads();
-  const double* __restrict__ abase = lp.abase(t);
-  const double* __restrict__ bbase = lp.bbase(t);
+  const TI* __restrict__ abase = lp.abase(t);
+  const TI* __restrict__ bbase = lp.bbase(t);
 
   // this thread's A row is fixed: r = tid % ROWS, k = tid / ROWS + KSTEP i
   const int ar = tid % ROWS;
@@ -131,8 +177,8 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
   const int64_t aro = arow_ok ? lp.aroff(t, ar) : 0;
   const int ak0 = tid / ROWS;
 
-  double ra[APT], rbv[BPT];
-  double ascl[P::kAScale ? APT : 1];
+  TI ra[APT], rbv[BPT];
+  TI ascl[P::kAScale ? APT : 1];
   uint32_t amask = 0u, bmask = 0u;
   const int kmax = t.K - 1;
   auto load = [&](int k0) {
@@ -175,23 +221,23 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
   auto stash = [&]() {
 #pragma unroll
     for (int i = 0; i < APT; ++i) {
-      double v = ra[i];
+      TI v = ra[i];
       if constexpr (P::kAScale) v *= ascl[i];
-      As[(ak0 + KSTEP * i) * AST + ar] = ((amask >> i) & 1u) ? v : 0.0;
+      As[(ak0 + KSTEP * i) * AST + ar] = ((amask >> i) & 1u) ? v : TI(0);
     }
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
       const int e = tid + i * NT;
       const int c = e % COLS, kl = e / COLS;
-      if (kl < KC) Bs[kl * BST + c] = ((bmask >> i) & 1u) ? rbv[i] : 0.0;
+      if (kl < KC) Bs[kl * BST + c] = ((bmask >> i) & 1u) ? rbv[i] : TI(0);
     }
   };
 
-  dbl4 acc[2][NB];
+  typename MF::acc acc[2][NB];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NB; ++j) acc[i][j] = typename MF::acc{0, 0, 0, 0};
 
   const int nch = (t.K + KC - 1) / KC;
   load(0);
@@ -203,13 +249,13 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
 #pragma unroll
     for (int kk = 0; kk < KC / 4; ++kk) {
       const int krow = 4 * kk + lk;
-      const double a0 = As[krow * AST + wm * 32 + lr];
-      const double a1 = As[krow * AST + wm * 32 + 16 + lr];
+      const TI a0 = As[krow * AST + wm * 32 + lr];
+      const TI a1 = As[krow * AST + wm * 32 + 16 + lr];
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
-        const double b = Bs[krow * BST + (wn * NB + cb) * 16 + lr];
-        acc[0][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][cb], 0, 0, 0);
-        acc[1][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][cb], 0, 0, 0);
+        const TI b = Bs[krow * BST + (wn * NB + cb) * 16 + lr];
+        acc[0][cb] = MF::step(a0, b, acc[0][cb]);
+        acc[1][cb] = MF::step(a1, b, acc[1][cb]);
       }
     }
     __syncthreads();
@@ -219,27 +265,25 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
     }
   }
 
-  // D layout of the 16x16x4 f64 MFMA on gfx950 (measured): lane l, element i
-  // -> row 4*i + l/16, col l%16
   int64_t ro[2][4];
   bool rv[2][4];
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int r = wm * 32 + rb * 16 + 4 * i + lk;
+      const int r = wm * 32 + rb * 16 + MF::row(i, lk);
       rv[rb][i] = r < t.rows;
       ro[rb][i] = rv[rb][i] ? lp.rowoff(t, r) : 0;
     }
   if constexpr (!P::kDot) {
-    double* __restrict__ ob = lp.obase(t);
+    TO* __restrict__ ob = lp.obase(t);
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
       const int c = (wn * NB + cb) * 16 + lr;
       const bool cv = c < t.cols;
       const int64_t co = cv ? lp.coloff(t, c) : 0;
       if constexpr (P::kAccum) {
-        double old[2][4];
+        TO old[2][4];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -248,13 +292,13 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (rv[rb][i] && cv) ob[ro[rb][i] + co] = old[rb][i] + P::kSign * acc[rb][cb][i];
+            if (rv[rb][i] && cv) ob[ro[rb][i] + co] = old[rb][i] + (TO)P::kSign * (TO)acc[rb][cb][i];
       } else {
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (rv[rb][i] && cv) ob[ro[rb][i] + co] = acc[rb][cb][i];
+            if (rv[rb][i] && cv) ob[ro[rb][i] + co] = (TO)acc[rb][cb][i];
       }
     }
   } else {
@@ -273,8 +317,8 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
           const bool ok = rv[rb][i] && cv;
           const int64_t e = ok ? ro[rb][i] + co : 0;
           const double x0 = d0[e], x1 = d1[e];
-          s0 += ok ? acc[rb][cb][i] * x0 : 0.0;
-          s1 += ok ? acc[rb][cb][i] * x1 : 0.0;
+          s0 += ok ? (double)acc[rb][cb][i] * x0 : 0.0;
+          s1 += ok ? (double)acc[rb][cb][i] * x1 : 0.0;
         }
     }
     // fixed-order block reduction (deterministic)

@@ -16,8 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libgw.so")
 
 GW_OK, GW_ERR_ARG, GW_ERR_HIP, GW_ERR_NOMEM, GW_ERR_NOT_SPD, GW_ERR_NO_CONVERGE, GW_ERR_BLAS = range(7)
 GW_FP64 = 0
+GW_FP32 = 1
 GW_BF16X3 = 2
-PRECISIONS = {"fp64": GW_FP64, "bf16x3": GW_BF16X3}
+PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "bf16x3": GW_BF16X3}
 
 
 class GWError(RuntimeError):

@@ -52,7 +52,7 @@ def _singles(ms, prec):
     return [gw.contract_chi(m["sys"], m["do"], m["dv"], m["s"].filter_eps, prec=prec)[0] for m in ms]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_batch_equals_single_calls(mols, prec):
     import torch
     from paper_2104_09857_amd import gw
