@@ -36,9 +36,18 @@ PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 DTYPE = {"fp64": "f64", "fp32": "f32 (FP32 MFMA and accumulation in a tile, FP64 across pivots)",
          "bf16x3": "bf16x3 (bf16 hi/lo MFMA, FP32 accumulation in a tile, FP64 across pivots)"}
-STAGE_C_KERNEL = {"fp64": "tile_gemm_kernel<4,2,5,32,StageC<double>>",
-                  "fp32": "tile_gemm_kernel<4,2,5,32,StageC<float>>",
-                  "bf16x3": "tile_bf16x3_kernel<4,2,4,5,32,StageCBf>"}
+_C_TILES = {"fp64": ["4,2,5,32", "2,2,5,32", "4,2,5,16"], "fp32": ["4,2,5,32", "2,2,5,32", "4,2,5,16"],
+            "bf16x3": ["4,2,4,5,32", "4,2,2,5,32", "2,2,4,5,32"]}
+_C_PROB = {"fp64": "StageC<double>", "fp32": "StageC<float>", "bf16x3": "StageCBf"}
+
+
+def stage_c_kernel(prec, variant, mask, batched=False):
+    """Name of the stage-C kernel a chi run launched (as rocprofv3 lists it)."""
+    eng = "tile_bf16x3" if prec == "bf16x3" else "tile_gemm"
+    prob = _C_PROB[prec]
+    if mask & 4:
+        return f"{eng}_persistent<{_C_TILES[prec][variant]},Batched<{prob}>>"
+    return f"{eng}_kernel<{_C_TILES[prec][variant]},{'Batched<' + prob + '>' if batched else prob}>"
 
 
 def log(*a):
@@ -244,7 +253,8 @@ def bench_batched(args):
                     "equal_to_single_calls": bool(same and same_graph),
                     "flops": flops, "stage_ms": [round(x, 2) for x in st["ms_stage"]],
                     "stage_launches": list(st["n_launch"])},
-        "roofline": {"kernel": "stage C (outer contraction), batched launches", "bound": "mfma",
+        "roofline": {"kernel": stage_c_kernel(args.prec, st["c_variant"], st["launch_mask"], True)
+                               + " (chi outer contraction, batched)", "bound": "mfma",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None, "launches": int(c_n), "avg_launch_ms": c_ms / max(c_n, 1)},
     }
@@ -330,7 +340,8 @@ def main():
                                  for f, m in zip(cs["flops_stage"], cs["ms_stage"])],
                       "launches": list(cs["n_launch"])},
         "e_qp": [float(x) for x in out["e_qp"]], "qp_status": [int(x) for x in out["status"]],
-        "roofline": {"kernel": STAGE_C_KERNEL[args.prec] + " (chi outer contraction)",
+        "roofline": {"kernel": stage_c_kernel(args.prec, cs["c_variant"], cs["launch_mask"])
+                               + " (chi outer contraction)",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK[args.prec],
                      "unit": "TFLOP/s", "frac": achieved / PEAK[args.prec],
                      "traffic": traffic, "launches": int(c_n), "avg_launch_ms": per_launch_ms},

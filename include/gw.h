@@ -127,6 +127,8 @@ typedef struct {
   double flops_stage[3];   /* algorithmic flops of each stage                 */
   int64_t n_blocks_screened; /* (c <= c', tau) output blocks the screener skipped */
   int64_t n_tiles_screened;  /* outer-contraction tiles skipped by the screener */
+  int32_t c_variant;       /* stage-C tile variant used (see gw_chi_batch_*)    */
+  int32_t launch_mask;     /* stages launched in the persistent form (bit k)    */
 } gw_chi_stats;
 
 /* Polarizability chi_PQ(tau_j) for all tau at once (Eq. 3), with the atom-block
@@ -172,15 +174,18 @@ gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double 
  *   synchronizes to read the filter counts.  Calls on one plan must not
  *   overlap (they share its scratch).
  * gw_chi_batch_set_config / get_config: stage-C tile variant
- *   (0 .. n_variants-1) and launch mode (persistent = 1: a resident grid
- *   takes tiles from a device queue, largest systems first; 0: one
- *   workgroup per tile).
+ *   (0 .. n_variants-1) and launch modes: persistent is a mask, bit k set =
+ *   stage k (0: A, 1: B, 2: C) runs as a resident grid that takes tiles from
+ *   per-XCD device queues, largest systems first; bit clear = one workgroup
+ *   per tile (XCD-aware tile order).  ARG error outside these ranges.
  * gw_chi_batch_tune: autotuner.  If cache_path (may be NULL) holds an entry
  *   for the plan's shape class (precision, AO/RI per atom, n_tau, log2 of
  *   the system count and of the mean atom count) that configuration is
- *   taken; otherwise every (variant, mode) is run reps times eagerly, the
- *   fastest is kept and appended to cache_path.  *ms_out (host, may be NULL)
- *   receives its time per execution.  Overwrites chi.
+ *   taken; otherwise every variant is run in both launch modes (reps timed
+ *   executions each, stage times from HIP events), each stage takes its
+ *   fastest mode and stage C its fastest variant, and the result is
+ *   appended to cache_path.  *ms_out (host, may be NULL) receives the time
+ *   per execution of the chosen configuration.  Overwrites chi.
  * gw_chi_batch_destroy: releases the plan (synchronizes the device). */
 typedef struct gw_chi_batch gw_chi_batch;
 

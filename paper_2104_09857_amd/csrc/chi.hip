@@ -620,7 +620,7 @@ void prime(gw_chi_batch& B) {
 
 // the three stages of pivot index piv, FP64 / FP32 form
 template <class T>
-gw_status pivot_f(gw_chi_batch& B, int piv, bool pers, int* q, std::vector<hipEvent_t>* ev,
+gw_status pivot_f(gw_chi_batch& B, int piv, int pers, int* q, std::vector<hipEvent_t>* ev,
                   hipStream_t st) {
   const FTables<T>& F = tabs<T>(B);
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord((*ev)[4 * piv + k], st) : hipSuccess; };
@@ -634,11 +634,11 @@ gw_status pivot_f(gw_chi_batch& B, int piv, bool pers, int* q, std::vector<hipEv
     GW_HIP(hipGetLastError());
   }
   GW_HIP(mark(0));
-  GW_HIP(stage_a_f<T>(B, piv, pers, q, st));
+  GW_HIP(stage_a_f<T>(B, piv, pers & 1, q, st));
   GW_HIP(mark(1));
-  GW_HIP(stage_b_f<T>(B, piv, pers, q + 1, st));
+  GW_HIP(stage_b_f<T>(B, piv, pers & 2, q + kXcds, st));
   GW_HIP(mark(2));
-  GW_HIP(stage_c_f<T>(B, piv, pers, q + 2, st));
+  GW_HIP(stage_c_f<T>(B, piv, pers & 4, q + 2 * kXcds, st));
   GW_HIP(mark(3));
   return GW_OK;
 }
@@ -649,7 +649,7 @@ gw_status pivot_f(gw_chi_batch& B, int piv, bool pers, int* q, std::vector<hipEv
 gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const* vir,
                   double* const* chi, std::vector<hipEvent_t>* ev, hipStream_t st) {
   const int n_tau = B.n_tau, NA = B.NA, NR = B.NR;
-  const bool pers = B.persistent != 0;
+  const int pers = B.persistent;     // bit k: stage k in the persistent form
   GW_HIP(fill_zero(B.queues, B.n_queues, st));
   for (int m = 0; m < B.n_sys; ++m) {
     SysPlan& P = B.sys[m];
@@ -676,7 +676,7 @@ gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const
     return ev ? hipEventRecord((*ev)[4 * piv + k], st) : hipSuccess;
   };
   for (int piv = 0; piv < B.max_na; ++piv) {
-    int* q = B.queues + 3 * piv;
+    int* q = B.queues + 3 * kXcds * piv;
     gw_status rc = GW_OK;
     if (B.prec == GW_FP64) {
       rc = pivot_f<double>(B, piv, pers, q, ev, st);
@@ -684,11 +684,11 @@ gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const
       rc = pivot_f<float>(B, piv, pers, q, ev, st);
     } else {
       GW_HIP(mark(piv, 0));
-      GW_HIP((run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, piv, pers, q, st)));
+      GW_HIP((run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, piv, pers & 1, q, st)));
       GW_HIP(mark(piv, 1));
-      GW_HIP(stage_b_bf(B, piv, pers, q + 1, st));
+      GW_HIP(stage_b_bf(B, piv, pers & 2, q + kXcds, st));
       GW_HIP(mark(piv, 2));
-      GW_HIP(stage_c_bf(B, piv, pers, q + 2, st));
+      GW_HIP(stage_c_bf(B, piv, pers & 4, q + 2 * kXcds, st));
       GW_HIP(mark(piv, 3));
     }
     if (rc != GW_OK) return rc;
@@ -805,6 +805,8 @@ gw_status execute(gw_chi_batch& B, const double* const* occ, const double* const
         GW_HIP(hipEventElapsedTime(&ms, B.ev[4 * piv + k], B.ev[4 * piv + k + 1]));
         stats->ms_stage[k] += ms;
       }
+    stats->c_variant = B.variant;
+    stats->launch_mask = B.persistent;
     stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return GW_OK;
@@ -846,6 +848,9 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   B->prec = prec;
   B->eps_f = eps_f;
   B->timing = opts && opts->timing;
+  // default tile configuration per precision (fastest measured for 13 AO / 40 RI per atom)
+  B->variant = prec == GW_FP64 ? 2 : 0;
+  B->persistent = prec == GW_FP32 ? 6 : 5;
   B->sys.resize(n_sys);
   for (int m = 0; m < n_sys; ++m) {
     if ((rc = prepare_sys(*B, B->sys[m], &systems[m], st)) != GW_OK) return rc;
@@ -857,7 +862,7 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   std::stable_sort(B->order.begin(), B->order.end(), [&](int x, int y) {
     return B->sys[x].fl_c + B->sys[x].fl_a > B->sys[y].fl_c + B->sys[y].fl_a;
   });
-  B->n_queues = 3 * std::max(B->max_na, 1);
+  B->n_queues = 3 * kXcds * std::max(B->max_na, 1);
   if ((rc = B->mem.alloc(&B->queues, B->n_queues)) != GW_OK) return rc;
   if ((rc = B->mem.alloc(&B->tiles_skipped, 1)) != GW_OK) return rc;
   GW_HIP(hipMemsetAsync(B->tiles_skipped, 0, sizeof(int), st));
@@ -906,8 +911,9 @@ extern "C" gw_status gw_chi_batch_set_config(gw_chi_batch* plan, int32_t variant
   clear_error();
   GW_CHECK_ARG(plan != nullptr, "plan must be non-null");
   GW_CHECK_ARG(variant >= 0 && variant < kNVar, "variant out of range");
+  GW_CHECK_ARG(persistent >= 0 && persistent <= 7, "persistent must be a mask of bits 0..2");
   plan->variant = variant;
-  plan->persistent = persistent ? 1 : 0;
+  plan->persistent = persistent;
   return GW_OK;
 }
 
@@ -939,55 +945,63 @@ extern "C" gw_status gw_chi_batch_tune(gw_chi_batch* plan, const double* const* 
       std::string k;
       int v = -1, pers = -1;
       double ms = 0.0;
-      if ((ls >> k >> v >> pers >> ms) && k == key && v >= 0 && v < kNVar) {
+      if ((ls >> k >> v >> pers >> ms) && k == key && v >= 0 && v < kNVar && pers >= 0 && pers <= 7) {
         plan->variant = v;
-        plan->persistent = pers ? 1 : 0;
+        plan->persistent = pers;
         if (ms_out) *ms_out = ms;
         return GW_OK;
       }
     }
   }
+  // every stage-C variant in both launch modes, stage times from HIP events;
+  // each stage takes its fastest mode (A, B: over all runs; C: with its variant)
   const bool timing = plan->timing;
-  plan->timing = false;
-  hipEvent_t e0, e1;
-  GW_HIP(hipEventCreate(&e0));
-  GW_HIP(hipEventCreate(&e1));
-  double best = -1.0;
-  int best_v = 0, best_p = 0;
+  plan->timing = true;
+  double best_a[2] = {1e300, 1e300}, best_b[2] = {1e300, 1e300}, best_c = 1e300;
+  int best_v = 0, best_pc = 0;
   for (int v = 0; v < kNVar && rc == GW_OK; ++v)
     for (int pers = 0; pers < 2 && rc == GW_OK; ++pers) {
       plan->variant = v;
-      plan->persistent = pers;
+      plan->persistent = pers ? 7 : 0;
       if ((rc = execute(*plan, d_occ, d_vir, chi, false, nullptr, st)) != GW_OK) break;  // warm-up
-      if (hipEventRecord(e0, st) != hipSuccess) { rc = GW_ERR_HIP; break; }
-      for (int r = 0; r < reps && rc == GW_OK; ++r) rc = execute(*plan, d_occ, d_vir, chi, false, nullptr, st);
-      if (rc != GW_OK) break;
-      float ms = 0.0f;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        rc = GW_ERR_HIP;
-        break;
+      double ms[3] = {0.0, 0.0, 0.0};
+      for (int r = 0; r < reps && rc == GW_OK; ++r) {
+        gw_chi_stats sx{};
+        rc = execute(*plan, d_occ, d_vir, chi, false, &sx, st);
+        for (int k = 0; k < 3; ++k) ms[k] += sx.ms_stage[k] / reps;
       }
-      const double per = ms / reps;
-      if (best < 0.0 || per < best) {
-        best = per;
+      best_a[pers] = std::min(best_a[pers], ms[0]);
+      best_b[pers] = std::min(best_b[pers], ms[1]);
+      if (ms[2] < best_c) {
+        best_c = ms[2];
         best_v = v;
-        best_p = pers;
+        best_pc = pers;
       }
     }
+  plan->timing = timing;
+  if (rc != GW_OK) return rc;
+  plan->variant = best_v;
+  plan->persistent = (best_a[1] < best_a[0] ? 1 : 0) | (best_b[1] < best_b[0] ? 2 : 0) | (best_pc ? 4 : 0);
+  // time of the chosen configuration (whole executions, eager)
+  hipEvent_t e0, e1;
+  GW_HIP(hipEventCreate(&e0));
+  GW_HIP(hipEventCreate(&e1));
+  float total = 0.0f;
+  hipError_t he = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && rc == GW_OK && he == hipSuccess; ++r)
+    rc = execute(*plan, d_occ, d_vir, chi, false, nullptr, st);
+  if (he == hipSuccess) he = hipEventRecord(e1, st);
+  if (he == hipSuccess) he = hipEventSynchronize(e1);
+  if (he == hipSuccess) he = hipEventElapsedTime(&total, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  plan->timing = timing;
-  if (rc != GW_OK) {
-    if (rc == GW_ERR_HIP) set_error("HIP error while timing the tile variants");
-    return rc;
-  }
-  plan->variant = best_v;
-  plan->persistent = best_p;
+  if (rc != GW_OK) return rc;
+  GW_HIP(he);
+  const double best = total / reps;
   if (ms_out) *ms_out = best;
   if (cache_path && *cache_path) {
     std::ofstream outf(cache_path, std::ios::app);
-    if (outf) outf << key << " " << best_v << " " << best_p << " " << best << "\n";
+    if (outf) outf << key << " " << plan->variant << " " << plan->persistent << " " << best << "\n";
   }
   return GW_OK;
 }

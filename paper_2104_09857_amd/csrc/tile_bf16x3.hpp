@@ -217,20 +217,29 @@ __device__ __forceinline__ void tile_bf16x3_body(const P& p, int bx, int by, int
 
 template <int WM, int WN, int RB, int NB, int KC, class P>
 __global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_kernel(P p) {
-  tile_bf16x3_body<WM, WN, RB, NB, KC>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+  int bx, by, bz;
+  grid_tile(bx, by, bz);
+  tile_bf16x3_body<WM, WN, RB, NB, KC>(p, bx, by, bz);
 }
 
-// persistent form (same queue protocol as tile_gemm_persistent)
+// persistent form (same per-XCD queue protocol as tile_gemm_persistent)
 template <int WM, int WN, int RB, int NB, int KC, class P>
 __global__ __launch_bounds__(64 * WM * WN) void tile_bf16x3_persistent(P p, int n_work, int* queue) {
   __shared__ int next;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
-    __syncthreads();
-    const int w = next;
-    if (w >= n_work) break;
-    tile_bf16x3_body<WM, WN, RB, NB, KC>(p, w, 0, 0);
+  const uint32_t q = (uint32_t)n_work / kXcds, r = (uint32_t)n_work % kXcds;
+  const uint32_t home = blockIdx.x % kXcds;
+  for (uint32_t j = 0; j < kXcds; ++j) {
+    const uint32_t x = (home + j) % kXcds;
+    const int start = (int)(x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q);
+    const int len = (int)(x < r ? q + 1 : q);
+    for (;;) {
+      __syncthreads();
+      if (threadIdx.x == 0) next = atomicAdd(queue + x, 1);
+      __syncthreads();
+      const int l = next;
+      if (l >= len) break;
+      tile_bf16x3_body<WM, WN, RB, NB, KC>(p, start + l, 0, 0);
+    }
   }
 }
 

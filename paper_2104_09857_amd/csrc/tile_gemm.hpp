@@ -345,24 +345,56 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
   }
 }
 
+// XCD-aware block order.  The dispatcher hands workgroup b (linear id over
+// x, then y, then z) to XCD b mod 8, and each XCD has its own L2.  Block b is
+// given tile number xcd_tile(b): XCD x works through the x-th contiguous
+// eighth of the tiles in order, so neighbouring tiles, which share operand
+// rows or panels, meet in the same L2.  A bijection on [0, n) for any n.
+constexpr int kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+  const uint32_t q = n / kXcds, r = n % kXcds, x = b % kXcds, l = b / kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+}
+__device__ __forceinline__ void grid_tile(int& bx, int& by, int& bz) {
+  const uint32_t gx = gridDim.x, gy = gridDim.y;
+  const uint32_t b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const uint32_t t = xcd_tile(b, gx * gy * gridDim.z);
+  bx = (int)(t % gx);
+  by = (int)((t / gx) % gy);
+  bz = (int)(t / (gx * gy));
+}
+
 template <int WM, int WN, int NB, int KC, class P>
 __global__ __launch_bounds__(64 * WM * WN) void tile_gemm_kernel(P p) {
-  tile_gemm_body<WM, WN, NB, KC>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+  int bx, by, bz;
+  grid_tile(bx, by, bz);
+  tile_gemm_body<WM, WN, NB, KC>(p, bx, by, bz);
 }
 
 // Persistent form: a grid sized to the resident capacity takes work items
-// 0 .. n_work-1 from a queue (an atomic counter, zero at launch) until it is
-// empty; every workgroup leaves once the counter has passed n_work.
+// 0 .. n_work-1 from kXcds queues (atomic counters queue[0..7], zero at
+// launch), one per contiguous eighth of the items.  A workgroup starts on the
+// queue of its own XCD (blockIdx.x mod 8, the dispatcher's round-robin), so
+// neighbouring items share an L2, and then helps the other queues in turn;
+// it leaves once every counter has passed its range, so every item is taken
+// exactly once and every workgroup exits.
 template <int WM, int WN, int NB, int KC, class P>
 __global__ __launch_bounds__(64 * WM * WN) void tile_gemm_persistent(P p, int n_work, int* queue) {
   __shared__ int next;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
-    __syncthreads();
-    const int w = next;
-    if (w >= n_work) break;
-    tile_gemm_body<WM, WN, NB, KC>(p, w, 0, 0);
+  const uint32_t q = (uint32_t)n_work / kXcds, r = (uint32_t)n_work % kXcds;
+  const uint32_t home = blockIdx.x % kXcds;
+  for (uint32_t j = 0; j < kXcds; ++j) {
+    const uint32_t x = (home + j) % kXcds;
+    const int start = (int)(x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q);
+    const int len = (int)(x < r ? q + 1 : q);
+    for (;;) {
+      __syncthreads();
+      if (threadIdx.x == 0) next = atomicAdd(queue + x, 1);
+      __syncthreads();
+      const int l = next;
+      if (l >= len) break;
+      tile_gemm_body<WM, WN, NB, KC>(p, start + l, 0, 0);
+    }
   }
 }
 

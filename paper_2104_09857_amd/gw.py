@@ -52,7 +52,8 @@ class _ChiStats(ctypes.Structure):
                 ("flops_c", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("ms_stage", ctypes.c_double * 3), ("n_launch", ctypes.c_int64 * 3),
                 ("flops_stage", ctypes.c_double * 3), ("n_blocks_screened", ctypes.c_int64),
-                ("n_tiles_screened", ctypes.c_int64)]
+                ("n_tiles_screened", ctypes.c_int64), ("c_variant", ctypes.c_int32),
+                ("launch_mask", ctypes.c_int32)]
 
 
 class _SigmaStats(ctypes.Structure):
@@ -248,7 +249,10 @@ class ChiBatch:
         return _stats_dict(st) if stats else None
 
     def set_config(self, variant, persistent):
-        _check(lib().gw_chi_batch_set_config(self.h, int(variant), int(bool(persistent))))
+        """persistent: mask of stages (bit 0 A, 1 B, 2 C) launched in the persistent
+        form; True means all three."""
+        mask = 7 if persistent is True else int(persistent)
+        _check(lib().gw_chi_batch_set_config(self.h, int(variant), mask))
 
     def config(self):
         v, p, n = _I32(), _I32(), _I32()
