@@ -1001,7 +1001,10 @@ extern "C" gw_status gw_chi_batch_tune(gw_chi_batch* plan, const double* const* 
   if (ms_out) *ms_out = best;
   if (cache_path && *cache_path) {
     std::ofstream outf(cache_path, std::ios::app);
-    if (outf) outf << key << " " << plan->variant << " " << plan->persistent << " " << best << "\n";
+    if (outf) {
+      outf.precision(10);
+      outf << key << " " << plan->variant << " " << plan->persistent << " " << best << "\n";
+    }
   }
   return GW_OK;
 }
