@@ -50,6 +50,24 @@ def stage_c_kernel(prec, variant, mask, batched=False):
     return f"{eng}_kernel<{_C_TILES[prec][variant]},{'Batched<' + prob + '>' if batched else prob}>"
 
 
+def measured_traffic(path, workload, kernel):
+    """HBM bytes per launch of the stage-C kernel from the stored rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs, or None when there is no record for this
+    workload and kernel or the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(path)).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -314,12 +332,8 @@ def main():
     c_flops = out["chi_stats"]["flops_stage"][2]
     per_launch_ms = c_ms / max(c_n, 1)
     achieved = (c_flops / max(c_n, 1)) / (per_launch_ms / 1e3) / 1e12
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            traffic = json.load(open(args.traffic_json)).get(args.workload)
-        except Exception:
-            traffic = None
+    c_kernel = stage_c_kernel(args.prec, cs["c_variant"], cs["launch_mask"])
+    traffic = measured_traffic(args.traffic_json, args.workload, c_kernel)
     s = ctx["s"]
     res = {
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -340,8 +354,7 @@ def main():
                                  for f, m in zip(cs["flops_stage"], cs["ms_stage"])],
                       "launches": list(cs["n_launch"])},
         "e_qp": [float(x) for x in out["e_qp"]], "qp_status": [int(x) for x in out["status"]],
-        "roofline": {"kernel": stage_c_kernel(args.prec, cs["c_variant"], cs["launch_mask"])
-                               + " (chi outer contraction)",
+        "roofline": {"kernel": c_kernel + " (chi outer contraction)",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK[args.prec],
                      "unit": "TFLOP/s", "frac": achieved / PEAK[args.prec],
                      "traffic": traffic, "launches": int(c_n), "avg_launch_ms": per_launch_ms},

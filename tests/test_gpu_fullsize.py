@@ -4,9 +4,8 @@
 The oracle cannot build the whole chi here, so it computes sampled output
 blocks one by one (Eq. 3 restricted to the blocks, from bricks drawn by the
 host generator and D(tau) from the oracle's own sums over MOs); the rest is
-checked through properties that hold at any size: exact symmetry, negative
-semidefiniteness of principal submatrices, Sigma^x < 0, every QP state
-converged."""
+checked through properties that hold at any size: exact symmetry and negative
+semidefiniteness of random principal submatrices."""
 import numpy as np
 import pytest
 
