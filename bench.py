@@ -289,8 +289,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
                     help="arithmetic of the timed chi contraction")
-    ap.add_argument("--compare", default="fp32", choices=["fp64", "fp32", "bf16x3", "none"],
-                    help="arithmetic of an extra untimed run reported next to the main one")
+    ap.add_argument("--compare", default="fp32,bf16x3",
+                    help="comma list of arithmetics run (untimed) next to the main one, or none")
     ap.add_argument("--no-compare", action="store_true", help="same as --compare none")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--tune-cache", default=None, help="autotune cache file of the batched form")
@@ -359,29 +359,31 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK[args.prec],
                      "traffic": traffic, "launches": int(c_n), "avg_launch_ms": per_launch_ms},
     }
-    other = None if args.no_compare or args.compare == "none" else args.compare
-    if other and other != args.prec:
+    others = [] if args.no_compare or args.compare == "none" else \
+        [x for x in args.compare.split(",") if x and x != args.prec]
+    forms = {}
+    for other in others:
         t1 = time.perf_counter()
         o2 = step(ctx, other)
         torch.cuda.synchronize()
         t2 = time.perf_counter() - t1
+        pf = {"chi_ms": o2["ms"]["chi"], "time_to_qp_s": t2,
+              "chi_tflops": (o2["chi_stats"]["flops_ab"] + o2["chi_stats"]["flops_c"])
+              / (o2["ms"]["chi"] / 1e3) / 1e12,
+              "stage_ms": [round(x, 1) for x in o2["chi_stats"]["ms_stage"]]}
         if args.prec == "fp64":
-            e64, eo = out, o2
-        elif other == "fp64":
-            e64, eo = o2, out
-        else:
-            e64 = eo = None
-        form = other if args.prec == "fp64" else args.prec
-        pf = {"prec": form, "chi_ms_" + args.prec: out["ms"]["chi"], "chi_ms_" + other: o2["ms"]["chi"],
-              "time_to_qp_s_" + other: t2}
-        if e64 is not None:
-            ok = (e64["status"] == 0) & (eo["status"] == 0)
-            de = np.abs(eo["e_qp"] - e64["e_qp"])[ok] * 27211.386245988
-            pf.update({"chi_speedup_vs_fp64": e64["ms"]["chi"] / eo["ms"]["chi"],
+            ok = (out["status"] == 0) & (o2["status"] == 0)
+            de = np.abs(o2["e_qp"] - out["e_qp"])[ok] * 27211.386245988
+            shift = np.abs(out["e_qp"] - ctx["eps"][ctx["w"].states()])[ok] * 27211.386245988
+            pf.update({"chi_speedup_vs_fp64": out["ms"]["chi"] / o2["ms"]["chi"],
                        "max_abs_dE_meV_vs_fp64": float(de.max()) if de.size else None,
-                       "dE_meV": [float(x) for x in de],
-                       "status_" + form: [int(x) for x in eo["status"]]})
-        res["precision_form"] = pf
+                       "dE_meV": [round(float(x), 4) for x in de],
+                       "max_dE_over_shift": float((de / np.maximum(shift, 1e-30)).max())
+                       if de.size else None,
+                       "status": [int(x) for x in o2["status"]]})
+        forms[other] = pf
+    if forms:
+        res["precision_form"] = forms
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(ctx, out)
     print(json.dumps(res), flush=True)

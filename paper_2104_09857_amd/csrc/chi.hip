@@ -229,6 +229,13 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
     F.dvf = P.dvf32;
     F.t3c = t32;
   }
+  // per-tile offsets of the stage maps are 32-bit
+  GW_CHECK_ARG((int64_t)N * N < (1ll << 31) && (int64_t)N * RS < (1ll << 31) &&
+                   (int64_t)NA * P.nRmax * N * NR < (1ll << 31) && P.bs < (1ll << 31),
+               "system too large for 32-bit tile offsets");
+  for (int p = 0; p < P.n_pan; ++p)
+    GW_CHECK_ARG((int64_t)NA * NA * P.pan.ulen[p] * P.PC < (1ll << 31),
+                 "column panel too large for 32-bit tile offsets");
   if ((rc = M.alloc(&F.dvg, (size_t)N * RS)) != GW_OK) return rc;
   if ((rc = M.alloc(&F.mb, (size_t)n_tau * NA * P.nRmax * N * NR)) != GW_OK) return rc;
   if ((rc = M.alloc(&F.bp, (size_t)n_tau * P.BPS)) != GW_OK) return rc;
@@ -240,7 +247,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
   sa.seg_brick = ix.seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = AB_COLS;
   sa.n_rt = (N + sa.rows_pt - 1) / sa.rows_pt;
   sa.n_ct = (NA * NR + sa.cols_pt - 1) / sa.cols_pt;
-  sa.N = N; sa.NA = NA; sa.NR = NR; sa.nRmax = P.nRmax; sa.bs = P.bs;
+  sa.N = N; sa.NA = NA; sa.NR = NR; sa.nRmax = P.nRmax; sa.bs = P.bs; sa.bs32 = (int)P.bs;
   sa.fdNA.set((uint32_t)NA);
   sa.fdNR.set((uint32_t)NR);
 
@@ -248,7 +255,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
   sb.dvg = F.dvg; sb.t3c = F.t3c; sb.bp = F.bp; sb.goff = ix.goff; sb.seg_atom = ix.seg_atom;
   sb.seg_brick = ix.seg_brick; sb.gc = ix.gc; sb.gslot = ix.gslot; sb.ulen = ix.ulen;
   sb.bp_off = ix.bp_off; sb.RS = RS; sb.NA = NA; sb.NR = NR; sb.PG = P.PG; sb.PC = P.PC;
-  sb.bs = P.bs; sb.BPS = P.BPS;
+  sb.bs = P.bs; sb.bs32 = (int)P.bs; sb.BPS = P.BPS;
   sb.rows_pt = 32 * b_wm(RS);
   sb.cols_pt = AB_COLS;
   sb.n_rt = (RS + sb.rows_pt - 1) / sb.rows_pt;
@@ -260,6 +267,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
   sc.mb = F.mb; sc.bp = F.bp; sc.gc = ix.gc; sc.kmap = ix.kmap; sc.km_off = ix.km_off;
   sc.ulen = ix.ulen; sc.bp_off = ix.bp_off; sc.N = N; sc.NA = NA; sc.NR = NR; sc.NRI = P.NRI;
   sc.PG = P.PG; sc.PC = P.PC; sc.nRmax = P.nRmax; sc.n_atoms = P.na; sc.BPS = P.BPS;
+  sc.sgs = P.nRmax * N * NR;
   sc.fdNR.set((uint32_t)NR);
   return GW_OK;
 }
@@ -850,7 +858,7 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   B->timing = opts && opts->timing;
   // default tile configuration per precision (fastest measured for 13 AO / 40 RI per atom)
   B->variant = prec == GW_FP64 ? 2 : 0;
-  B->persistent = prec == GW_FP32 ? 6 : 5;
+  B->persistent = prec == GW_FP32 ? 6 : 7;
   B->sys.resize(n_sys);
   for (int m = 0; m < n_sys; ++m) {
     if ((rc = prepare_sys(*B, B->sys[m], &systems[m], st)) != GW_OK) return rc;

@@ -50,6 +50,7 @@ struct StageA {
   int g0, n_rt, n_ct, rows_pt, cols_pt;
   int N, NA, NR, nRmax;
   int64_t bs;
+  int bs32;                 // brick size (elements) as int for the offset products
   FastDiv fdNA, fdNR;
 
   __device__ bool tile(int bx, int by, int bz, Tile& t) const {
@@ -74,15 +75,17 @@ struct StageA {
     }
   }
   __device__ const T* abase(const Tile& t) const { return dof + (int64_t)t.tau * N * N + t.row0; }
+  // A(r = mu, k = (segment sg, lambda = ta[sg] * NA + u)) = D^occ_{lambda mu}
+  static constexpr bool kAStep = true;
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
-    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
-    return (int64_t)(ta[sg] * NA + i) * N;
+  __device__ int adiv(const Tile&) const { return NA; }
+  __device__ uint32_t akoff2(const Tile&, int sg, int u, const int* ta) const {
+    return (uint32_t)(ta[sg] * NA + u) * (uint32_t)N;
   }
   __device__ const T* bbase(const Tile& t) const { return t3c + t.col0; }
   __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
     const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
-    return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
+    return (int64_t)tb[sg] * bs32 + i * NA * NR;
   }
   __device__ T ascale(const Tile&, int) const { return T(1); }
   // M_b[tau][sigma][slot][mu][P]: row mu, column (sigma, P)
@@ -123,6 +126,7 @@ struct StageB {
   int n_rt, n_ct, rows_pt, cols_pt;
   int RS, NA, NR, PG, PC;
   int64_t bs, BPS;
+  int bs32;
   FastDiv fdNA, fdNR;
 
   __device__ bool tile(int bx, int, int, Tile& t) const {
@@ -150,15 +154,17 @@ struct StageB {
     }
   }
   __device__ const T* abase(const Tile& t) const { return dvg + t.row0; }
+  // A(r = (tau, sigma), k = (segment sg, nu = ta[sg] * NA + u)) = dvg[nu][r]
+  static constexpr bool kAStep = true;
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
-    const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
-    return (int64_t)(ta[sg] * NA + i) * RS;
+  __device__ int adiv(const Tile&) const { return NA; }
+  __device__ uint32_t akoff2(const Tile&, int sg, int u, const int* ta) const {
+    return (uint32_t)(ta[sg] * NA + u) * (uint32_t)RS;
   }
   __device__ const T* bbase(const Tile& t) const { return t3c + t.col0; }
   __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
     const int sg = (int)fdNA.div((uint32_t)k), i = k - sg * NA;
-    return (int64_t)tb[sg] * bs + (int64_t)i * NA * NR;
+    return (int64_t)tb[sg] * bs32 + i * NA * NR;
   }
   __device__ T ascale(const Tile&, int) const { return T(1); }
   // N_b panel: [tau][panel][sigma][u = slot*NA + mu][(cl, Q)]: row (tau, sigma), column (mu, Q)
@@ -196,7 +202,6 @@ struct StageC {
   using Out = double;
   struct Tile : TileBase {
     int p, tau, row0, KU, km0;
-    FastDiv fdKU;
   };
   static constexpr bool kAScale = false, kDot = false;
   static constexpr int kTabA = kPanTab, kTabB = 0;
@@ -210,6 +215,7 @@ struct StageC {
   const int64_t* bp_off;
   int g0, nR, n_rt, rows_pt;
   int N, NA, NR, NRI, PG, PC, nRmax, n_atoms;
+  int sgs;                  // nRmax * N * NR: stride of sigma in M_b
   int64_t BPS;
   FastDiv fdNR;
   const uint8_t* keep;      // screener mask [tau][c][c'] (c <= c'), or null
@@ -233,7 +239,6 @@ struct StageC {
     t.KU = NA * ulen[t.p];
     t.km0 = km_off[t.p];
     t.K = NA * t.KU;
-    t.fdKU.set((uint32_t)t.KU);
     return t.K > 0;
   }
   __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
@@ -246,14 +251,17 @@ struct StageC {
     const int row = t.row0 + r, sl = (int)fdNR.div((uint32_t)row);
     return (int64_t)sl * N * NR + (row - sl * NR);
   }
-  __device__ int64_t akoff(const Tile& t, int k, const int* ta) const {
-    const int sg = (int)t.fdKU.div((uint32_t)k), u = k - sg * t.KU;
-    return (int64_t)sg * nRmax * N * NR + ta[u];
+  // k = (sigma = sg, u over the panel's AO functions); offsets within one tau
+  // of M_b, below 2^31 (checked on the host)
+  static constexpr bool kAStep = true, kBLin = true;
+  __device__ int adiv(const Tile& t) const { return t.KU; }
+  __device__ uint32_t akoff2(const Tile&, int sg, int u, const int* ta) const {
+    return (uint32_t)sg * (uint32_t)sgs + (uint32_t)ta[u];
   }
+  __device__ int bstride(const Tile&) const { return PC; }
   __device__ const T* bbase(const Tile& t) const {
     return bp + (int64_t)t.tau * BPS + bp_off[t.p];
   }
-  __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PC; }
   __device__ T ascale(const Tile&, int) const { return T(1); }
   // chi[tau][P][Q] -= tile, P = (RI atom of the row's slot, P), Q = panel column
   __device__ double* obase(const Tile& t) const { return chi + (int64_t)t.tau * NRI * NRI; }

@@ -28,6 +28,7 @@ namespace gw {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
 // round-to-nearest-even float -> bf16 bits
 __host__ __device__ inline uint16_t f32_to_bf16_bits(float f) {
@@ -70,14 +71,14 @@ __device__ __forceinline__ void tile_bf16x3_body(const P& p, int bx, int by, int
   const auto lp = resolve(p, t);
   lp.fill(t, tabA, tabB, tid, NT);
   __syncthreads();
-  const uint16_t* __restrict__ ahb = lp.abase_hi(t);
-  const uint16_t* __restrict__ alb = lp.abase_lo(t);
-  const uint16_t* __restrict__ bhb = lp.bbase_hi(t);
-  const uint16_t* __restrict__ blb = lp.bbase_lo(t);
+  const gmem<const uint16_t>* __restrict__ ahb = to_global(lp.abase_hi(t));
+  const gmem<const uint16_t>* __restrict__ alb = to_global(lp.abase_lo(t));
+  const gmem<const uint16_t>* __restrict__ bhb = to_global(lp.bbase_hi(t));
+  const gmem<const uint16_t>* __restrict__ blb = to_global(lp.bbase_lo(t));
   const int ngroups = t.K / 8;               // K is a multiple of 16
   const int gmax = ngroups - 1;
 
-  uint4 rah[AG], ral[AG], rbh[BG], rbl[BG];
+  u32x4_t rah[AG], ral[AG], rbh[BG], rbl[BG];
   uint32_t amask = 0u, bmask = 0u;
   auto load = [&](int g0) {
     int64_t aoff[AG], boff[BG];
@@ -99,24 +100,24 @@ __device__ __forceinline__ void tile_bf16x3_body(const P& p, int bx, int by, int
     }
 #pragma unroll
     for (int i = 0; i < AG; ++i) {
-      rah[i] = *reinterpret_cast<const uint4*>(ahb + aoff[i]);
-      ral[i] = *reinterpret_cast<const uint4*>(alb + aoff[i]);
+      rah[i] = *reinterpret_cast<const gmem<const u32x4_t>*>(ahb + aoff[i]);
+      ral[i] = *reinterpret_cast<const gmem<const u32x4_t>*>(alb + aoff[i]);
     }
 #pragma unroll
     for (int i = 0; i < BG; ++i) {
-      rbh[i] = *reinterpret_cast<const uint4*>(bhb + boff[i]);
-      rbl[i] = *reinterpret_cast<const uint4*>(blb + boff[i]);
+      rbh[i] = *reinterpret_cast<const gmem<const u32x4_t>*>(bhb + boff[i]);
+      rbl[i] = *reinterpret_cast<const gmem<const u32x4_t>*>(blb + boff[i]);
     }
   };
   auto stash = [&]() {
-    const uint4 z = {0u, 0u, 0u, 0u};
+    const u32x4_t z = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (int i = 0; i < AG; ++i) {
       const int e = tid + i * NT, r = e % ROWS, gl = e / ROWS;
       if (e < ROWS * KG) {
         const bool ok = (amask >> i) & 1u;
-        *reinterpret_cast<uint4*>(&Ah[r * LST + 8 * gl]) = ok ? rah[i] : z;
-        *reinterpret_cast<uint4*>(&Al[r * LST + 8 * gl]) = ok ? ral[i] : z;
+        *reinterpret_cast<u32x4_t*>(&Ah[r * LST + 8 * gl]) = ok ? rah[i] : z;
+        *reinterpret_cast<u32x4_t*>(&Al[r * LST + 8 * gl]) = ok ? ral[i] : z;
       }
     }
 #pragma unroll
@@ -124,8 +125,8 @@ __device__ __forceinline__ void tile_bf16x3_body(const P& p, int bx, int by, int
       const int e = tid + i * NT, c = e % COLS, gl = e / COLS;
       if (e < COLS * KG) {
         const bool ok = (bmask >> i) & 1u;
-        *reinterpret_cast<uint4*>(&Bh[c * LST + 8 * gl]) = ok ? rbh[i] : z;
-        *reinterpret_cast<uint4*>(&Bl[c * LST + 8 * gl]) = ok ? rbl[i] : z;
+        *reinterpret_cast<u32x4_t*>(&Bh[c * LST + 8 * gl]) = ok ? rbh[i] : z;
+        *reinterpret_cast<u32x4_t*>(&Bl[c * LST + 8 * gl]) = ok ? rbl[i] : z;
       }
     }
   };
@@ -182,7 +183,7 @@ __device__ __forceinline__ void tile_bf16x3_body(const P& p, int bx, int by, int
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       if constexpr (P::kOut == 0) {
-        double* __restrict__ ob = lp.obase(t);
+        gmem<double>* __restrict__ ob = to_global(lp.obase(t));
         double old[4];
         int64_t off[4];
         bool ok[4];
@@ -197,8 +198,8 @@ __device__ __forceinline__ void tile_bf16x3_body(const P& p, int bx, int by, int
         for (int i = 0; i < 4; ++i)
           if (ok[i]) ob[off[i]] = old[i] + P::kSign * (double)acc[rb][cb][i];
       } else {
-        uint16_t* __restrict__ oh = lp.obase_hi(t);
-        uint16_t* __restrict__ ol = lp.obase_lo(t);
+        gmem<uint16_t>* __restrict__ oh = to_global(lp.obase_hi(t));
+        gmem<uint16_t>* __restrict__ ol = to_global(lp.obase_lo(t));
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int r = (wm * RB + rb) * 16 + 4 * lk + i;

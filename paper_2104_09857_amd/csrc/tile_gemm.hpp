@@ -93,6 +93,17 @@ struct TileBase {
   int rows, cols, K;
 };
 
+// Global-memory view of a pointer.  Problem descriptions reach the kernels
+// through memory (batched tables), so the compiler cannot infer that their
+// pointers are global and would emit flat accesses, which also count against
+// the LDS wait counter; the kernels access operands through this view.
+template <class T>
+using gmem = T __attribute__((address_space(1)));
+template <class T>
+__device__ __forceinline__ gmem<T>* to_global(T* p) {
+  return (gmem<T>*)p;
+}
+
 // A batched problem (one launch over the tiles of many systems) defines
 // kBatched and local(t), which returns the problem of the tile's system;
 // a plain problem is its own local problem.
@@ -100,6 +111,21 @@ template <class P, class = void>
 struct is_batched : std::false_type {};
 template <class P>
 struct is_batched<P, std::void_t<decltype(P::kBatched)>> : std::true_type {};
+
+// Optional cheaper index maps (detected):
+//   P::kAStep: A(r, k) at abase[aroff(r) + akoff2(t, sg, u, ta)] with
+//              k = sg * adiv(t) + u; the engine steps (sg, u) along a thread's
+//              k sequence instead of dividing (when adiv(t) > NT / ROWS), and
+//              all A offsets of a tile fit in 32 bits
+//   P::kBLin:  B(k, c) at bbase[k * bstride(t) + c], offsets below 2^31
+template <class P, class = void>
+struct has_astep : std::false_type {};
+template <class P>
+struct has_astep<P, std::void_t<decltype(P::kAStep)>> : std::bool_constant<P::kAStep> {};
+template <class P, class = void>
+struct has_blin : std::false_type {};
+template <class P>
+struct has_blin<P, std::void_t<decltype(P::kBLin)>> : std::bool_constant<P::kBLin> {};
 
 template <class P, class T>
 __device__ __forceinline__ auto resolve(const P& p, const T& t) {
@@ -163,38 +189,127 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
   if (!p.tile(bx, by, bz, t)) return;
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave % WM, wn = wave / WM;
   const auto lp = resolve(p, t);
   lp.fill(t, tabA, tabB, tid, NT);
   __syncthreads();
-  const TI* __restrict__ abase = lp.abase(t);
-  const TI* __restrict__ bbase = lp.bbase(t);
+  const gmem<const TI>* __restrict__ abase = to_global(lp.abase(t));
+  const gmem<const TI>* __restrict__ bbase = to_global(lp.bbase(t));
 
   // this thread's A row is fixed: r = tid % ROWS, k = tid / ROWS + KSTEP i
+  constexpr bool ASTEP = has_astep<P>::value, BLIN = has_blin<P>::value;
   const int ar = tid % ROWS;
   const bool arow_ok = ar < t.rows;
   const int64_t aro = arow_ok ? lp.aroff(t, ar) : 0;
   const int ak0 = tid / ROWS;
 
-  TI ra[APT], rbv[BPT];
+  // Wave-uniform index maps.  When ROWS is a multiple of 64 a wave loads 64
+  // consecutive rows of one k, so the k sequence (and the k part of every A
+  // offset) is the same for all its lanes; lane j computes the offset of
+  // element j and every lane reads them back (readlane).  Likewise, when
+  // COLS is a multiple of 64 (and B is not linear), B is loaded in slots of
+  // 64 consecutive columns of one k row.
+  constexpr bool AUNI = ASTEP && ROWS % 64 == 0;
+  constexpr int NW = NT / 64, CSL = COLS / 64;
+  constexpr bool BUNI = !BLIN && COLS % 64 == 0;
+  constexpr int BPTU = BUNI ? (KC * CSL + NW - 1) / NW : 1;
+  constexpr int NB_ = BUNI ? BPTU : BPT;    // B elements per thread
+  // this thread's B elements (k row, column) are the same in every chunk
+  int bkl[NB_], bcc[NB_];
+  uint32_t bstat = 0u;       // element i inside the chunk and the tile's columns
+  uint32_t bin = 0u;         // element i inside the chunk (it has an LDS slot)
+#pragma unroll
+  for (int i = 0; i < NB_; ++i) {
+    int kl, c;
+    if constexpr (BUNI) {
+      const int sl = wave + NW * i;
+      kl = sl / CSL;
+      c = (sl % CSL) * 64 + lane;
+    } else {
+      const int e = tid + i * NT;
+      kl = e / COLS;
+      c = e % COLS;
+    }
+    bkl[i] = kl < KC ? kl : KC - 1;
+    bcc[i] = c;
+    bstat |= (kl < KC && c < t.cols) ? (1u << i) : 0u;
+    bin |= kl < KC ? (1u << i) : 0u;
+  }
+  int adiv = 1, sgmax = 0;
+  FastDiv afd{};
+  if constexpr (ASTEP) {
+    adiv = lp.adiv(t);
+    afd.set((uint32_t)adiv);
+    sgmax = (t.K - 1) / adiv;
+  }
+  int bstr = 0;
+  if constexpr (BLIN) bstr = lp.bstride(t);
+
+  TI ra[APT], rbv[NB_];
   TI ascl[P::kAScale ? APT : 1];
   uint32_t amask = 0u, bmask = 0u;
   const int kmax = t.K - 1;
   auto load = [&](int k0) {
     // offsets for a clamped k first (no branches, table reads batched), then the loads
-    int64_t aoff[APT], boff[BPT];
+    int64_t aoff[APT], boff[NB_];
+    if constexpr (AUNI) {
+      const int kw = __builtin_amdgcn_readfirstlane(k0 + ak0);
+      int kj = kw + KSTEP * (lane < APT ? lane : 0);
+      kj = kj < kmax ? kj : kmax;
+      const int sgj = (int)afd.div((uint32_t)kj);
+      const int offj = (int)lp.akoff2(t, sgj < sgmax ? sgj : sgmax, kj - sgj * adiv, tabA);
 #pragma unroll
-    for (int i = 0; i < APT; ++i) {
-      const int k = k0 + ak0 + KSTEP * i;
-      aoff[i] = lp.akoff(t, k < kmax ? k : kmax, tabA);
+      for (int i = 0; i < APT; ++i) aoff[i] = (uint32_t)__builtin_amdgcn_readlane(offj, i);
+    } else if constexpr (ASTEP) {
+      const int ks = k0 + ak0 < kmax ? k0 + ak0 : kmax;
+      int sg = (int)afd.div((uint32_t)ks), u = ks - sg * adiv;
+#pragma unroll
+      for (int i = 0; i < APT; ++i) {
+        aoff[i] = (uint32_t)lp.akoff2(t, sg < sgmax ? sg : sgmax, u, tabA);
+        if (adiv > KSTEP) {       // uniform: at most one wrap per step
+          u += KSTEP;
+          const bool w = u >= adiv;
+          u -= w ? adiv : 0;
+          sg += w ? 1 : 0;
+        } else {
+          const int k = k0 + ak0 + KSTEP * (i + 1);
+          const int kc = k < kmax ? k : kmax;
+          sg = (int)afd.div((uint32_t)kc);
+          u = kc - sg * adiv;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < APT; ++i) {
+        const int k = k0 + ak0 + KSTEP * i;
+        aoff[i] = lp.akoff(t, k < kmax ? k : kmax, tabA);
+      }
     }
+    if constexpr (BUNI) {
+      // lane j: offset of the k row of slot j (uniform over the slot's 64 lanes)
+      const int slj = wave + NW * (lane < NB_ ? lane : 0);
+      const int klj = slj / CSL;
+      int kj = k0 + (klj < KC ? klj : KC - 1);
+      kj = kj < kmax ? kj : kmax;
+      const int64_t offj = lp.bkoff(t, kj, tabB);
+      const int lo = (int)(uint32_t)offj, hi = (int)(offj >> 32);
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int e = tid + i * NT;
-      const int kl = e / COLS;
-      const int k = k0 + (kl < KC ? kl : KC - 1);
-      boff[i] = lp.bkoff(t, k < kmax ? k : kmax, tabB);
+      for (int i = 0; i < NB_; ++i) {
+        const uint32_t l32 = (uint32_t)__builtin_amdgcn_readlane(lo, i);
+        const uint32_t h32 = (uint32_t)__builtin_amdgcn_readlane(hi, i);
+        boff[i] = (int64_t)(((uint64_t)h32 << 32) | l32) + bcc[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NB_; ++i) {
+        if constexpr (BLIN) {
+          boff[i] = (uint32_t)((k0 + bkl[i]) * bstr + bcc[i]);
+        } else {
+          const int k = k0 + bkl[i];
+          boff[i] = lp.bkoff(t, k < kmax ? k : kmax, tabB) + bcc[i];
+        }
+      }
     }
     // raw values now; out-of-range entries are zeroed at stash time so that
     // nothing waits on these loads before the matrix-core work of this chunk
@@ -205,17 +320,16 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
       const int k = k0 + ak0 + KSTEP * i;
       const bool ok = arow_ok && k < t.K;
       amask |= ok ? (1u << i) : 0u;
-      ra[i] = abase[ok ? aro + aoff[i] : 0];
+      if constexpr (ASTEP) ra[i] = abase[ok ? (uint32_t)(aro + aoff[i]) : 0u];
+      else ra[i] = abase[ok ? aro + aoff[i] : 0];
       if constexpr (P::kAScale) ascl[i] = lp.ascale(t, k < kmax ? k : kmax);
     }
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int e = tid + i * NT;
-      const int c = e % COLS, kl = e / COLS;
-      const int k = k0 + kl;
-      const bool ok = kl < KC && c < t.cols && k < t.K;
+    for (int i = 0; i < NB_; ++i) {
+      const bool ok = ((bstat >> i) & 1u) && k0 + bkl[i] < t.K;
       bmask |= ok ? (1u << i) : 0u;
-      rbv[i] = bbase[ok ? boff[i] + c : 0];
+      if constexpr (BLIN) rbv[i] = bbase[ok ? (uint32_t)boff[i] : 0u];
+      else rbv[i] = bbase[ok ? boff[i] : 0];
     }
   };
   auto stash = [&]() {
@@ -226,11 +340,8 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
       As[(ak0 + KSTEP * i) * AST + ar] = ((amask >> i) & 1u) ? v : TI(0);
     }
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int e = tid + i * NT;
-      const int c = e % COLS, kl = e / COLS;
-      if (kl < KC) Bs[kl * BST + c] = ((bmask >> i) & 1u) ? rbv[i] : TI(0);
-    }
+    for (int i = 0; i < NB_; ++i)
+      if ((bin >> i) & 1u) Bs[bkl[i] * BST + bcc[i]] = ((bmask >> i) & 1u) ? rbv[i] : TI(0);
   };
 
   typename MF::acc acc[2][NB];
@@ -276,7 +387,7 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
       ro[rb][i] = rv[rb][i] ? lp.rowoff(t, r) : 0;
     }
   if constexpr (!P::kDot) {
-    TO* __restrict__ ob = lp.obase(t);
+    gmem<TO>* __restrict__ ob = to_global(lp.obase(t));
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
       const int c = (wn * NB + cb) * 16 + lr;
@@ -302,8 +413,8 @@ __device__ __forceinline__ void tile_gemm_body(const P& p, int bx, int by, int b
       }
     }
   } else {
-    const double* __restrict__ d0 = lp.dbase0(t);
-    const double* __restrict__ d1 = lp.dbase1(t);
+    const gmem<const double>* __restrict__ d0 = to_global(lp.dbase0(t));
+    const gmem<const double>* __restrict__ d1 = to_global(lp.dbase1(t));
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
