@@ -140,7 +140,10 @@ typedef struct {
  * mirrored).  stats (host, may be NULL) is filled.  The call is synchronous:
  * it reads the kept-brick mask on the host first and releases its scratch
  * (plain device allocations) before returning.  It runs the batched form
- * below on one system, eagerly, with the default tile variant. */
+ * below on one system, eagerly, with the default tile configuration of the
+ * precision (the fastest measured on gfx950 for 13 AO / 40 RI per atom:
+ * FP64 stage-C variant 2 with all stages persistent, FP32 variant 0 with
+ * stages B and C persistent, BF16x3 variant 0 with all stages persistent). */
 gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double *d_vir,
                           int32_t n_tau, const gw_chi_opts *opts, double *chi,
                           gw_chi_stats *stats, hipStream_t stream);
