@@ -12,6 +12,9 @@
   wire<N>      the strip generator on a ribbon one atom wide (a chain of N
                atoms at 2.5 bohr), filter 1e-8: a long quasi-1D system whose
                far output blocks fall below the filter.
+  ribbon<N>    the 7-wide strip with 5 AO / 12 RI per atom, filter 1e-8: the
+               long-ribbon geometry (e.g. ribbon1734, 620 bohr long) for the
+               learned-screener measurement at a basis that allows exact runs.
   mol<M>       M independent molecules for the batched form: atom counts
                drawn uniformly from [10, 40] (mol<M>:<lo>-<hi> for another
                range; Philox uniform, stream 7),
@@ -54,6 +57,14 @@ def strip(n_atoms: int, seed=0, filter_eps=1e-9, n_ao=13, n_ri=40, n_tau=12,
     return Workload(f"strip{n_atoms}", s, n_tau, n_tau, n_below, n_above)
 
 
+def ribbon(n_atoms: int, seed=0, filter_eps=1e-8, n_tau=12) -> Workload:
+    """The 7-wide strip generator with 5 AO / 12 RI per atom and filter 1e-8:
+    the geometry of the long-ribbon (1734-atom) screening workload at a basis
+    small enough for exact reference runs on one GPU."""
+    s = gsys.System(gsys.strip(n_atoms), 5, 12, 0.8, 0.8, 0.2, filter_eps, seed=seed)
+    return Workload(f"ribbon{n_atoms}", s, n_tau, n_tau, 5, 5)
+
+
 def wire(n_atoms: int, seed=0, filter_eps=1e-8, n_tau=12) -> Workload:
     s = gsys.System(gsys.strip(n_atoms, width=1), 13, 40, 0.8, 0.8, 0.2, filter_eps, seed=seed)
     return Workload(f"wire{n_atoms}", s, n_tau, n_tau, 5, 5)
@@ -86,6 +97,8 @@ def by_name(name: str, seed=0) -> Workload:
         return strip(int(name[5:]), seed)
     if name.startswith("wire"):
         return wire(int(name[4:]), seed)
+    if name.startswith("ribbon"):
+        return ribbon(int(name[6:]), seed)
     raise KeyError(name)
 
 

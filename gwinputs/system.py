@@ -145,11 +145,23 @@ class System:
         """
         na = self.n_atoms
         size = np.sqrt(float(self.n_ao_atom * self.n_ao_atom * self.n_ri_atom))
+        # the perimeter s is at least 2 d_ac and 2 d_bc, so only atoms within
+        # s_max / 2 of c can take part (s_max: the largest perimeter whose bound
+        # reaches the filter; a relative slack keeps rounding on the safe side)
+        if self.filter_eps > 0.0:
+            s_max = np.log(philox.Z_MAX * size / self.filter_eps) / self.k_t
+            reach = 0.5 * s_max * (1.0 + 1e-9) + 1e-9
+        else:
+            reach = np.inf
         out = []
         for c in range(na):
-            s = self.dist + (self.dist[:, c][:, None] + self.dist[:, c][None, :])
+            idx = np.nonzero(self.dist[:, c] <= reach)[0]
+            d = self.dist[np.ix_(idx, idx)]
+            dc = self.dist[idx, c]
+            s = d + (dc[:, None] + dc[None, :])
             bound = philox.Z_MAX * size * np.exp(-self.k_t * s)
-            b_idx, a_idx = np.nonzero((bound >= self.filter_eps).T)
+            b_sub, a_sub = np.nonzero((bound >= self.filter_eps).T)
+            a_idx, b_idx = idx[a_sub], idx[b_sub]
             trip = np.stack([a_idx, b_idx, np.full_like(a_idx, c)], axis=1)
             out.append(trip)
         return np.ascontiguousarray(np.concatenate(out).astype(np.int32))
