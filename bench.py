@@ -12,6 +12,14 @@ Sigma for HOMO-4 .. LUMO+4.  Inputs are seeded and synthetic (gwinputs).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload strip300]
 
+Workload ribbon<N> (e.g. ribbon1734, 5 AO / 12 RI per atom, filter 1e-8)
+measures the learned block screener: the network is trained on the GPU on
+exact runs of ribbon300 and ribbon600, its safety band calibrated on
+ribbon900, and chi of ribbon<N> is timed exact and screened in FP64 and in
+BF16x3, with the skipped blocks audited against an exact run without the
+output filter, and the QP energies of the screened BF16x3 chain compared
+with the plain FP64 chain.
+
 Workload mol<M> (e.g. mol64) times the batched form instead: one step = one
 execution of a gw_chi_batch plan (chi for all tau of M molecules of 10-40
 atoms, captured in a hipGraph, tile variant and launch mode autotuned),
@@ -280,6 +288,127 @@ def bench_batched(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_screened(args):
+    """The learned block screener on a long ribbon (see the module docstring)."""
+    import torch
+    from gwinputs import configs, device as gdev
+    from paper_2104_09857_amd import gw, pipeline, screener
+
+    def prepare(name):
+        w = configs.by_name(name)
+        s = w.system
+        C, eps = s.mean_field()
+        g = configs.grids_for(w, eps)
+        mu = configs.mu_fermi(eps, s.n_occ)
+        trip = s.triples()
+        t3c = gdev.bricks_on_device(s, trip)
+        sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c)
+        Cd = torch.as_tensor(C, device="cuda")
+        do, dv = gw.build_gt(sysd, Cd, eps, mu, g.tau)
+        return dict(w=w, s=s, C=C, Cd=Cd, eps=eps, g=g, mu=mu, sys=sysd, do=do, dv=dv)
+
+    def timed_chi(m, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chi, st = gw.contract_chi(m["sys"], m["do"], m["dv"], m["s"].filter_eps, tau=m["g"].tau, **kw)
+        torch.cuda.synchronize()
+        return chi, st, (time.perf_counter() - t0) * 1e3
+
+    t_all = time.perf_counter()
+    Xs, ts = [], []
+    for name in ("ribbon300", "ribbon600"):
+        m = prepare(name)
+        chi, _, ms = timed_chi(m)
+        X, t = screener.samples(m["sys"], m["do"], m["dv"], chi, m["g"].tau, m["s"].filter_eps)
+        Xs.append(X)
+        ts.append(t)
+        log(f"[screen] training data {name}: {X.shape[0]} blocks, exact chi {ms:.0f} ms")
+        del chi, m
+    eps_f = configs.by_name("ribbon300").system.filter_eps
+    sc = screener.BlockScreener(11)
+    t0 = time.perf_counter()
+    hist = sc.fit(torch.cat(Xs), torch.cat(ts), filter_eps=eps_f, steps=3000, batch=4096, lr=2e-3,
+                  alpha=8.0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del Xs, ts
+    mv = prepare("ribbon900")
+    chi, _, _ = timed_chi(mv)
+    Xv, tv = screener.samples(mv["sys"], mv["do"], mv["dv"], chi, mv["g"].tau, eps_f)
+    margin = sc.calibrate(Xv, tv, eps_f)
+    del chi, mv, Xv, tv
+    log(f"[screen] trained {train_s:.1f} s (loss {hist[0][1]:.3g} -> {hist[-1][1]:.3g}), "
+        f"band {margin:.2f} decades")
+
+    m = prepare(args.workload)
+    s = m["s"]
+    res = {}
+    ref_unf, _, _ = timed_chi(m, keep_small_blocks=True)          # exact, nothing zeroed
+    lg_ref = gw.chi_block_lognorms(m["sys"], ref_unf)
+    del ref_unf
+    for prec in ("fp64", "bf16x3"):
+        exact = timed_chi(m, prec=prec, timing=True)[0]           # warm-up
+        del exact
+        exact, st_e, ms_e = timed_chi(m, prec=prec, timing=True)
+        scr = timed_chi(m, prec=prec, timing=True, screener=sc.net, screen_margin=margin)[0]
+        del scr
+        scr, st_s, ms_s = timed_chi(m, prec=prec, timing=True, screener=sc.net, screen_margin=margin)
+        same = bool(torch.equal(scr, exact))
+        del exact, scr
+        scr_unf, _, _ = timed_chi(m, prec=prec, screener=sc.net, screen_margin=margin,
+                                  keep_small_blocks=True)
+        lg_s = gw.chi_block_lognorms(m["sys"], scr_unf)
+        del scr_unf
+        skipped = (lg_s < -29) & (lg_ref >= -29)
+        blk = torch.pow(10.0, lg_ref.double())                       # exact block norms
+        skipped_mass = float(torch.sqrt((blk[skipped] ** 2).sum()) / torch.sqrt((blk ** 2).sum()))
+        res[prec] = {"chi_ms_exact": ms_e, "chi_ms_screened": ms_s,
+                     "stage_c_ms_exact": st_e["ms_stage"][2], "stage_c_ms_screened": st_s["ms_stage"][2],
+                     "flops_c_exact": st_e["flops_c"], "flops_c_screened": st_s["flops_c"],
+                     "blocks_screened": int(st_s["n_blocks_screened"]),
+                     "blocks_total": int(s.n_atoms * (s.n_atoms + 1) // 2 * m["w"].n_tau),
+                     "tiles_screened": int(st_s["n_tiles_screened"]),
+                     "max_skipped_log10_norm": float(lg_ref[skipped].max()) if bool(skipped.any()) else None,
+                     "skipped_mass_rel": skipped_mass,
+                     "equal_to_exact": same}
+        log(f"[screen] {prec}: exact {ms_e:.0f} ms, screened {ms_s:.0f} ms, "
+            f"{res[prec]['blocks_screened']} blocks skipped, equal {res[prec]['equal_to_exact']}")
+        torch.cuda.empty_cache()
+    # QP: plain FP64 chain vs BF16x3 + screener chain
+    V = torch.as_tensor(s.coulomb(), device="cuda")
+    g = m["g"]
+    a = (m["sys"], m["Cd"], m["eps"], m["mu"], V, g.tau, g.omega, g.cos_w, g.sin_w, g.icos_w,
+         m["w"].states(), s.filter_eps)
+    o64 = pipeline.g0w0(*a, events=True)
+    o64 = {k: o64[k] for k in ("e_qp", "status", "ms")}
+    torch.cuda.empty_cache()
+    omx = pipeline.g0w0(*a, events=True, prec="bf16x3", screener=sc.net, screen_margin=margin)
+    ok = (o64["status"] == 0) & (omx["status"] == 0)
+    de = np.abs(omx["e_qp"] - o64["e_qp"])[ok] * 27211.386245988
+    f64, fmx = res["fp64"], res["bf16x3"]
+    out = {
+        "metric": METRIC, "value": f64["chi_ms_exact"] / fmx["chi_ms_screened"],
+        "unit": "x (chi time, plain FP64 / BF16x3 + learned screener)", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": fmx["chi_ms_screened"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3 + fp64 reference", "data": "synthetic",
+        "config": {"workload": args.workload, "n_atoms": s.n_atoms, "n_ao": s.n_ao, "n_ri": s.n_ri,
+                   "filter_eps": s.filter_eps, "n_tau": m["w"].n_tau,
+                   "train": ["ribbon300", "ribbon600"], "calibrate": "ribbon900"},
+        "screener": {"band_decades": margin, "train_s": train_s, "loss_first_last": [hist[0][1], hist[-1][1]]},
+        "chi": res,
+        "speedup": {"fp64_screened": f64["chi_ms_exact"] / f64["chi_ms_screened"],
+                    "bf16x3": f64["chi_ms_exact"] / fmx["chi_ms_exact"],
+                    "bf16x3_screened": f64["chi_ms_exact"] / fmx["chi_ms_screened"]},
+        "qp": {"dE_meV_bf16x3_screened_vs_fp64": [round(float(x), 4) for x in de],
+               "max_abs_dE_meV": float(de.max()) if de.size else None,
+               "status_fp64": [int(x) for x in o64["status"]], "status_mixed": [int(x) for x in omx["status"]],
+               "time_to_qp_s_fp64": sum(o64["ms"].values()) / 1e3,
+               "time_to_qp_s_mixed": sum(omx["ms"].values()) / 1e3},
+        "wall_s": time.perf_counter() - t_all,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,6 +432,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload.startswith("mol"):
         bench_batched(args)
+        return
+    if args.workload.startswith("ribbon"):
+        bench_screened(args)
         return
     ctx = setup(args.workload)
     for i in range(args.warmup):

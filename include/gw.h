@@ -112,6 +112,9 @@ typedef struct {
                               computed nor kept (zero); needs filter_eps > 0   */
   double screen_margin;    /* decades of safety band below the filter          */
   const double *screen_tau;/* host [n_tau] tau values (screener feature)       */
+  int32_t keep_small_blocks; /* 1: skip the output filter (chi blocks below
+                              filter_eps are kept; for audits of the skipped
+                              mass); 0: the filter of the computational details */
 } gw_chi_opts;
 
 typedef struct {

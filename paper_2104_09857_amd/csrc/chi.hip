@@ -161,6 +161,7 @@ struct gw_chi_batch {
   int n_sys = 0, n_tau = 0, NA = 0, NR = 0, prec = GW_FP64, max_na = 0;
   double eps_f = 0.0;
   bool timing = false;
+  bool out_filter = true;            // zero chi blocks below eps_f at the end
   Scratch mem;
   std::vector<SysPlan> sys;
   std::vector<int> order;            // systems by decreasing size
@@ -708,7 +709,7 @@ gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const
     const size_t nflag = (size_t)n_tau * P.na * P.na;
     GW_HIP(mirror_lower_blocks(chi[m], n_tau, P.NRI, NR, st));
     if (P.keep) GW_HIP(zero_unkept_blocks(chi[m], n_tau, P.na, NR, P.keep, st));
-    if (B.eps_f > 0.0)
+    if (B.eps_f > 0.0 && B.out_filter)
       GW_HIP(filter_square_blocks(chi[m], chi[m], n_tau, P.na, NR, B.eps_f, P.dropped + 2 * nflag, st));
   }
   return GW_OK;
@@ -782,7 +783,7 @@ gw_status execute(gw_chi_batch& B, const double* const* occ, const double* const
       GW_HIP(hipStreamSynchronize(st));
       if (P.s.n_trip > 0) {
         for (size_t i = 0; i < 2 * nflag; ++i) dd += fl[i];
-        if (B.eps_f > 0.0)
+        if (B.eps_f > 0.0 && B.out_filter)
           for (size_t i = 2 * nflag; i < 3 * nflag; ++i) dc += fl[i];
       }
       kept += P.G.n_kept;
@@ -856,6 +857,7 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   B->prec = prec;
   B->eps_f = eps_f;
   B->timing = opts && opts->timing;
+  B->out_filter = !(opts && opts->keep_small_blocks);
   // default tile configuration per precision (fastest measured for 13 AO / 40 RI per atom)
   B->variant = prec == GW_FP64 ? 2 : 0;
   B->persistent = prec == GW_FP32 ? 6 : 7;
@@ -1084,14 +1086,19 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
         if (c <= c2 && !keep_h[e]) ++nbs;
       }
       stats->n_blocks_screened = nbs;
-      // stage-C FLOPs of the kept blocks only: sum over groups of the kept partners
+      // stage-C FLOPs of the kept blocks only: every group with RI atom c pairs
+      // with the kept partners c2 >= c, each of |A(c2)| groups
+      std::vector<double> kept_a((size_t)n_tau * na, 0.0);   // [j][c]: sum of |A(c2)| over kept c2
+      for (int j = 0; j < n_tau; ++j)
+        for (int c = 0; c < na; ++c) {
+          double a = 0.0;
+          const uint8_t* k = &keep_h[((int64_t)j * na + c) * na];
+          for (int c2 = c; c2 < na; ++c2) a += k[c2] ? P.acount[c2] : 0;
+          kept_a[(size_t)j * na + c] = a;
+        }
       double fl = 0.0;
-      for (int g = 0; g < P.n_groups; ++g) {
-        const int c = P.G.gc[g];
-        for (int j = 0; j < n_tau; ++j)
-          for (int c2 = c; c2 < na; ++c2)
-            if (keep_h[((int64_t)j * na + c) * na + c2]) fl += 2.0 * NR * NR * NA * NA * P.acount[c2];
-      }
+      for (int g = 0; g < P.n_groups; ++g)
+        for (int j = 0; j < n_tau; ++j) fl += 2.0 * NR * NR * NA * NA * kept_a[(size_t)j * na + P.G.gc[g]];
       stats->flops_c = fl;
       stats->flops_stage[2] = fl;
     }

@@ -43,7 +43,7 @@ class _Mlp(ctypes.Structure):
 class _ChiOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("filter_eps", ctypes.c_double), ("timing", ctypes.c_int32),
                 ("screener", ctypes.c_void_p), ("screen_margin", ctypes.c_double),
-                ("screen_tau", ctypes.c_void_p)]
+                ("screen_tau", ctypes.c_void_p), ("keep_small_blocks", ctypes.c_int32)]
 
 
 class _ChiStats(ctypes.Structure):
@@ -184,7 +184,7 @@ def build_gt(sys, C, eps, mu_f, tau, d_occ=None, d_vir=None, stream=None):
 
 
 def contract_chi(sys, d_occ, d_vir, filter_eps=0.0, chi=None, stream=None, timing=False,
-                 prec="fp64", screener=None, screen_margin=1.0, tau=None):
+                 prec="fp64", screener=None, screen_margin=1.0, tau=None, keep_small_blocks=False):
     import torch
     n_tau = d_occ.shape[0]
     if chi is None:
@@ -195,7 +195,8 @@ def contract_chi(sys, d_occ, d_vir, filter_eps=0.0, chi=None, stream=None, timin
     opts = _ChiOpts(PRECISIONS[prec], float(filter_eps), int(bool(timing)),
                     None if screener is None else ctypes.addressof(screener.c),
                     float(screen_margin),
-                    None if tau_h is None else tau_h.ctypes.data_as(ctypes.c_void_p).value)
+                    None if tau_h is None else tau_h.ctypes.data_as(ctypes.c_void_p).value,
+                    int(bool(keep_small_blocks)))
     st = _ChiStats()
     _check(lib().gw_contract_chi(sys.ref, _dev(d_occ), _dev(d_vir), n_tau, ctypes.byref(opts),
                                  _dev(chi), ctypes.byref(st), _stream(stream)))

@@ -12,7 +12,7 @@ from . import gw
 
 def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_eps,
          spin=2.0, vxc=None, window=0.0, stream=None, events=False, chi_timing=False,
-         prec="fp64"):
+         prec="fp64", screener=None, screen_margin=1.0):
     import torch
     st = torch.cuda.current_stream() if stream is None else stream
     ev = {}
@@ -30,7 +30,8 @@ def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_
     d0, _ = gw.build_gt(sys, C, eps, mu_f, [0.0], d_vir=False, stream=st)
     mark("gt")
     chi, chi_stats = gw.contract_chi(sys, d_occ, d_vir, filter_eps, stream=st, timing=chi_timing,
-                                     prec=prec)
+                                     prec=prec, screener=screener, screen_margin=screen_margin,
+                                     tau=tau)
     mark("chi")
     wc = gw.screen_w(sys, chi, V, cos_w, icos_w, spin, stream=st)
     mark("screen")
