@@ -97,7 +97,7 @@ def setup(name, seed=0):
     V = torch.as_tensor(s.coulomb(), device="cuda")
     Cd = torch.as_tensor(C, device="cuda")
     torch.cuda.synchronize()
-    sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c)
+    sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c, s.xyz)
     log(f"[setup] device inputs ready ({t3c.numel() * 8 / 1e9:.1f} GB bricks), "
         f"{time.perf_counter() - t0:.1f} s")
     return dict(w=w, s=s, C=C, eps=eps, g=g, mu=mu, trip=trip, sys=sysd, Cd=Cd, V=V, t3c=t3c)
@@ -172,7 +172,7 @@ def setup_molecules(name, seed=0):
         mu = configs.mu_fermi(eps, s.n_occ)
         trip = s.triples()
         t3c = gdev.bricks_on_device(s, trip)
-        sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c)
+        sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c, s.xyz)
         do, dv = gw.build_gt(sysd, torch.as_tensor(C, device="cuda"), eps, mu, g.tau)
         ms.append(dict(w=w, s=s, sys=sysd, t3c=t3c, trip=trip, do=do, dv=dv))
     torch.cuda.synchronize()
@@ -302,7 +302,7 @@ def bench_screened(args):
         mu = configs.mu_fermi(eps, s.n_occ)
         trip = s.triples()
         t3c = gdev.bricks_on_device(s, trip)
-        sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c)
+        sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c, s.xyz)
         Cd = torch.as_tensor(C, device="cuda")
         do, dv = gw.build_gt(sysd, Cd, eps, mu, g.tau)
         return dict(w=w, s=s, C=C, Cd=Cd, eps=eps, g=g, mu=mu, sys=sysd, do=do, dv=dv)
@@ -316,9 +316,11 @@ def bench_screened(args):
 
     t_all = time.perf_counter()
     Xs, ts = [], []
+    # targets: block norms of the exact contraction without the output filter
+    # (continuous through the threshold, unlike the filtered output)
     for name in ("ribbon300", "ribbon600"):
         m = prepare(name)
-        chi, _, ms = timed_chi(m)
+        chi, _, ms = timed_chi(m, keep_small_blocks=True)
         X, t = screener.samples(m["sys"], m["do"], m["dv"], chi, m["g"].tau, m["s"].filter_eps)
         Xs.append(X)
         ts.append(t)
@@ -333,7 +335,7 @@ def bench_screened(args):
     train_s = time.perf_counter() - t0
     del Xs, ts
     mv = prepare("ribbon900")
-    chi, _, _ = timed_chi(mv)
+    chi, _, _ = timed_chi(mv, keep_small_blocks=True)
     Xv, tv = screener.samples(mv["sys"], mv["do"], mv["dv"], chi, mv["g"].tau, eps_f)
     margin = sc.calibrate(Xv, tv, eps_f)
     del chi, mv, Xv, tv
@@ -342,17 +344,17 @@ def bench_screened(args):
 
     m = prepare(args.workload)
     s = m["s"]
+    log(f"[screen] {args.workload} ready ({s.n_atoms} atoms)")
     res = {}
-    ref_unf, _, _ = timed_chi(m, keep_small_blocks=True)          # exact, nothing zeroed
+    ref_unf, _, ms_ref = timed_chi(m, keep_small_blocks=True)     # exact, nothing zeroed (warms up)
     lg_ref = gw.chi_block_lognorms(m["sys"], ref_unf)
     del ref_unf
+    log(f"[screen] exact unfiltered chi {ms_ref:.0f} ms")
     for prec in ("fp64", "bf16x3"):
-        exact = timed_chi(m, prec=prec, timing=True)[0]           # warm-up
-        del exact
         exact, st_e, ms_e = timed_chi(m, prec=prec, timing=True)
-        scr = timed_chi(m, prec=prec, timing=True, screener=sc.net, screen_margin=margin)[0]
-        del scr
+        log(f"[screen] {prec} exact {ms_e:.0f} ms")
         scr, st_s, ms_s = timed_chi(m, prec=prec, timing=True, screener=sc.net, screen_margin=margin)
+        log(f"[screen] {prec} screened {ms_s:.0f} ms")
         same = bool(torch.equal(scr, exact))
         del exact, scr
         scr_unf, _, _ = timed_chi(m, prec=prec, screener=sc.net, screen_margin=margin,
@@ -381,8 +383,10 @@ def bench_screened(args):
          m["w"].states(), s.filter_eps)
     o64 = pipeline.g0w0(*a, events=True)
     o64 = {k: o64[k] for k in ("e_qp", "status", "ms")}
+    log(f"[screen] FP64 chain {sum(o64['ms'].values()) / 1e3:.1f} s")
     torch.cuda.empty_cache()
     omx = pipeline.g0w0(*a, events=True, prec="bf16x3", screener=sc.net, screen_margin=margin)
+    log(f"[screen] BF16x3 + screener chain {sum(omx['ms'].values()) / 1e3:.1f} s")
     ok = (o64["status"] == 0) & (omx["status"] == 0)
     de = np.abs(omx["e_qp"] - o64["e_qp"])[ok] * 27211.386245988
     f64, fmx = res["fp64"], res["bf16x3"]

@@ -73,8 +73,9 @@ typedef struct {
   int64_t n_trip;
   const int32_t *trip;     /* host [n_trip][3] = (a, b, c)                   */
   const double *t3c;       /* dev  [n_trip][ao][ao][ri]                      */
-  const double *xyz;       /* host [n_atoms][3] bohr, or NULL (only used as a
-                              screener feature)                               */
+  const double *xyz;       /* host [n_atoms][3] bohr, or NULL; only the block
+                              screener uses it (distance feature) and then
+                              requires it                                     */
 } gw_system;
 
 /* Block screener network (beyond the paper): a perceptron x (F) -> 64 -> 64
@@ -265,7 +266,8 @@ gw_status gw_continue_qp(int32_t n_gw, const double *sig_occ, const double *sig_
  * (distance/10 bohr, log10 tau, log10 ||T_c||, log10 ||T_c'||,
  *  log10 ||D^occ_{cc'}(tau)||, log10 ||D^vir_{cc'}(tau)||) with norms over the
  * kept bricks of RI atom c and over the (c, c') atom blocks of D (1e-30 added
- * inside every log).  tau: host [n_tau]. */
+ * inside every log).  tau: host [n_tau].  s->xyz must be set (GW_ERR_ARG
+ * otherwise: without it the distance feature would be zero). */
 gw_status gw_chi_block_features(const gw_system *s, const double *d_occ, const double *d_vir,
                                 int32_t n_tau, const double *tau, double filter_eps, float *feat,
                                 hipStream_t stream);

@@ -189,6 +189,7 @@ extern "C" gw_status gw_chi_block_features(const gw_system* s, const double* d_o
   gw_status rc = check_system(s);
   if (rc != GW_OK) return rc;
   GW_CHECK_ARG(d_occ && d_vir && tau && feat, "null argument");
+  GW_CHECK_ARG(s->xyz, "block features need the atom coordinates (gw_system.xyz)");
   GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
   GW_CHECK_ARG(std::isfinite(filter_eps) && filter_eps >= 0, "filter_eps must be >= 0");
   const int na = s->n_atoms, NA = s->ao_per_atom;
@@ -209,16 +210,15 @@ extern "C" gw_status gw_chi_block_features(const gw_system* s, const double* d_o
   for (int64_t i : G.seg_brick) tn2[s->trip[3 * i + 2]] += bn[i] * bn[i];
   std::vector<float> tnorm(na), dist((size_t)na * na, 0.f);
   for (int c = 0; c < na; ++c) tnorm[c] = (float)std::sqrt(tn2[c]);
-  if (s->xyz)
-    for (int a = 0; a < na; ++a)
-      for (int b = 0; b < na; ++b) {
-        double d2 = 0;
-        for (int k = 0; k < 3; ++k) {
-          const double d = s->xyz[3 * a + k] - s->xyz[3 * b + k];
-          d2 += d * d;
-        }
-        dist[(size_t)a * na + b] = (float)std::sqrt(d2);
+  for (int a = 0; a < na; ++a)
+    for (int b = 0; b < na; ++b) {
+      double d2 = 0;
+      for (int k = 0; k < 3; ++k) {
+        const double d = s->xyz[3 * a + k] - s->xyz[3 * b + k];
+        d2 += d * d;
       }
+      dist[(size_t)a * na + b] = (float)std::sqrt(d2);
+    }
   float *d_tn, *d_dist, *dno, *dnv;
   double* d_tau;
   if ((rc = sc.upload(&d_tn, tnorm)) != GW_OK) return rc;

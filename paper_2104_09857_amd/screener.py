@@ -44,7 +44,14 @@ def unpack(p):
 
 
 def samples(sys, d_occ, d_vir, chi, tau, filter_eps):
-    """(X [n, 6], t [n]) device tensors for the upper blocks of every tau."""
+    """(X [n, 6], t [n]) device tensors for the upper blocks of every tau.
+
+    chi should be the exact contraction without the output filter
+    (contract_chi(..., keep_small_blocks=True)): its block norms are
+    continuous through the threshold, whereas the filtered output jumps from
+    just above the threshold to zero, a cliff the regression cannot follow
+    (blocks just above it are then under-predicted by the depth of the
+    target floor)."""
     import torch
     feat = gw.chi_block_features(sys, d_occ, d_vir, tau, filter_eps)
     lgn = gw.chi_block_lognorms(sys, chi)

@@ -46,6 +46,11 @@ def test_host_validation_rejects_bad_arguments():
     for f in (-1.0, float("nan")):
         o = gw._ChiOpts(0, f)
         assert L.gw_contract_chi(ctypes.byref(sys_ok), 1, 1, 1, ctypes.byref(o), 1, None, None) == gw.GW_ERR_ARG
+    # block features need the atom coordinates (distance feature)
+    tau1 = np.array([0.1])
+    rc = L.gw_chi_block_features(ctypes.byref(sys_ok), 1, 1, 1, tau1.ctypes.data_as(ctypes.c_void_p),
+                                 0.0, 1, None)
+    assert rc == gw.GW_ERR_ARG and b"coordinates" in L.gw_last_error()
     # build_gt: unsorted eps and negative tau are rejected
     eps = np.array([0.3, -0.1, 0.2, 0.5, 0.6, 0.7])
     tau = np.array([0.1])

@@ -70,6 +70,10 @@ def wires():
     for n in (60, 90, 120, 160):
         r = _wire_run(n)
         r["chi"], r["st"] = gw.contract_chi(r["sys"], r["do"], r["dv"], r["s"].filter_eps)
+        # the same contraction without the output filter: block norms that are
+        # continuous through the threshold (training targets, audit)
+        r["chi_u"], _ = gw.contract_chi(r["sys"], r["do"], r["dv"], r["s"].filter_eps,
+                                        keep_small_blocks=True)
         out[n] = r
     return out
 
@@ -101,7 +105,7 @@ def test_trained_screener_audit_and_gain(wires):
     Xs, ts = [], []
     for n in (60, 90):
         r = wires[n]
-        X, t = screener.samples(r["sys"], r["do"], r["dv"], r["chi"], r["g"].tau, r["s"].filter_eps)
+        X, t = screener.samples(r["sys"], r["do"], r["dv"], r["chi_u"], r["g"].tau, r["s"].filter_eps)
         Xs.append(X)
         ts.append(t)
     sc = screener.BlockScreener(7)
@@ -111,7 +115,7 @@ def test_trained_screener_audit_and_gain(wires):
     assert hist[-1][1] < 0.2 * hist[0][1]
     # safety band calibrated on a held-out wire, then applied to a longer one
     rv = wires[120]
-    Xv, tv = screener.samples(rv["sys"], rv["do"], rv["dv"], rv["chi"], rv["g"].tau,
+    Xv, tv = screener.samples(rv["sys"], rv["do"], rv["dv"], rv["chi_u"], rv["g"].tau,
                               rv["s"].filter_eps)
     margin = sc.calibrate(Xv, tv, rv["s"].filter_eps)
     print("calibrated margin (decades)", margin, flush=True)
@@ -120,12 +124,13 @@ def test_trained_screener_audit_and_gain(wires):
     chi_s, st = gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=sc.net,
                                 screen_margin=margin, tau=r["g"].tau)
     exact = r["chi"]
-    lg = gw.chi_block_lognorms(r["sys"], exact).cpu().numpy()
+    lg = gw.chi_block_lognorms(r["sys"], r["chi_u"]).cpu().numpy()     # unfiltered exact norms
     lgs = gw.chi_block_lognorms(r["sys"], chi_s).cpu().numpy()
     skipped = (lgs < -29) & (lg >= -29)          # zero in the screened run, nonzero in the exact one
     total = st["n_blocks_screened"]
-    print("screened blocks", total, "tiles", st["n_tiles_screened"], "max skipped log10 norm",
-          lg[skipped].max() if skipped.any() else None, flush=True)
+    na, nt = s.n_atoms, r["do"].shape[0]
+    print("screened blocks", total, "of", nt * na * (na + 1) // 2, "tiles", st["n_tiles_screened"],
+          "max skipped log10 norm", lg[skipped].max() if skipped.any() else None, flush=True)
     assert total > 0 and st["n_tiles_screened"] > 0
     # audit: every skipped block lies below the filter (the exact output filter would
     # have zeroed it too), so the screened chi equals the exact filtered chi
