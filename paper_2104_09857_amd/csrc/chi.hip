@@ -39,6 +39,9 @@ int c_rows(int prec, int v) {
 }
 // stage-B waves (FP64) / row blocks (BF16x3) by the row count n_tau * NA
 int b_wm(int RS) { return RS <= 64 ? 2 : RS <= 96 ? 3 : RS <= 128 ? 4 : RS <= 160 ? 5 : 4; }
+// stage-A/B column blocks per wave by the column count NA * NR of one RI
+// atom block: 64-wide tiles for small bases, 192-wide otherwise
+int ab_nb(int cols) { return cols <= 16 * AB_NBN * AB_WN ? AB_NBN : AB_NBW; }
 int b_rb(int RS) { return RS <= 64 ? 2 : RS <= 96 ? 3 : RS <= 128 ? 4 : 5; }
 
 // Work of one stage at every pivot index, for a batched launch.
@@ -167,6 +170,7 @@ struct gw_chi_batch {
   std::vector<int> order;            // systems by decreasing size
   int variant = 0, persistent = 0;
   int RS = 0;
+  int ab_nb = AB_NBW;      // 16-column blocks per wave of the stage-A/B tiles
   FTables<double> t64;
   FTables<float> t32;
   Table<StageABf> tAb;
@@ -200,6 +204,11 @@ struct gw_chi_batch {
 
 namespace gw {
 namespace {
+
+// BF16x3 stage-A/B column blocks per wave (same rule as the FP64 / FP32 form)
+int bf_ab_nb(const gw_chi_batch& B) {
+  return B.NA * B.NR <= 16 * BF_NB_ABN * BF_WN ? BF_NB_ABN : BF_NB_AB;
+}
 
 // device copies of a system's grouping and panel index arrays
 struct Index {
@@ -245,7 +254,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
 
   StageA<T>& sa = F.sa;
   sa.dof = F.dof; sa.t3c = F.t3c; sa.mb = F.mb; sa.goff = ix.goff; sa.seg_atom = ix.seg_atom;
-  sa.seg_brick = ix.seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = AB_COLS;
+  sa.seg_brick = ix.seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = 16 * B.ab_nb * AB_WN;
   sa.n_rt = (N + sa.rows_pt - 1) / sa.rows_pt;
   sa.n_ct = (NA * NR + sa.cols_pt - 1) / sa.cols_pt;
   sa.N = N; sa.NA = NA; sa.NR = NR; sa.nRmax = P.nRmax; sa.bs = P.bs; sa.bs32 = (int)P.bs;
@@ -258,7 +267,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
   sb.bp_off = ix.bp_off; sb.RS = RS; sb.NA = NA; sb.NR = NR; sb.PG = P.PG; sb.PC = P.PC;
   sb.bs = P.bs; sb.bs32 = (int)P.bs; sb.BPS = P.BPS;
   sb.rows_pt = 32 * b_wm(RS);
-  sb.cols_pt = AB_COLS;
+  sb.cols_pt = 16 * B.ab_nb * AB_WN;
   sb.n_rt = (RS + sb.rows_pt - 1) / sb.rows_pt;
   sb.n_ct = (NA * NR + sb.cols_pt - 1) / sb.cols_pt;
   sb.fdNA.set((uint32_t)NA);
@@ -378,7 +387,7 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     StageABf& ba = P.ba;
     ba.dh = P.doh; ba.dl = P.dol; ba.th = P.th; ba.tl = P.tl; ba.mh = P.mh; ba.ml = P.ml;
     ba.goff = d_goff; ba.seg_atom = d_seg_atom; ba.seg_brick = d_seg_brick;
-    ba.rows_pt = 16 * 4 * 4; ba.cols_pt = 16 * BF_NB_AB * BF_WN;
+    ba.rows_pt = 16 * 4 * 4; ba.cols_pt = 16 * bf_ab_nb(B) * BF_WN;
     ba.n_rt = (N + ba.rows_pt - 1) / ba.rows_pt;
     ba.n_ct = (NA * NR + ba.cols_pt - 1) / ba.cols_pt;
     ba.N = N; ba.NA = NA; ba.NR = NR; ba.na = na; ba.nRmax = P.nRmax;
@@ -390,7 +399,7 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     bb.gslot = d_gslot; bb.poffb = d_poffb; bb.N = N; bb.NA = NA; bb.NR = NR; bb.na = na;
     bb.RS = RS; bb.PG = P.PG; bb.PC = P.PC; bb.BPS16 = P.BPS16;
     bb.rows_pt = 16 * b_rb(RS) * 2;
-    bb.cols_pt = 16 * BF_NB_AB * BF_WN;
+    bb.cols_pt = 16 * bf_ab_nb(B) * BF_WN;
     bb.n_rt = (RS + bb.rows_pt - 1) / bb.rows_pt;
     bb.n_ct = (NA * NR + bb.cols_pt - 1) / bb.cols_pt;
     bb.fdNA.set((uint32_t)NA);
@@ -568,17 +577,22 @@ hipError_t run_bf(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t
 
 template <class T>
 hipError_t stage_a_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  if (B.ab_nb == AB_NBN) return run_mfma<A_WM, AB_WN, AB_NBN, 16>(tabs<T>(B).tA, piv, pers, q, st);
   return run_mfma<A_WM, AB_WN, AB_NBW, 16>(tabs<T>(B).tA, piv, pers, q, st);
+}
+template <int NB, class Tab>
+hipError_t stage_b_rows(const gw_chi_batch& B, const Tab& t, int piv, bool pers, int* q, hipStream_t st) {
+  switch (b_wm(B.RS)) {
+    case 2: return run_mfma<2, AB_WN, NB, 16>(t, piv, pers, q, st);
+    case 3: return run_mfma<3, AB_WN, NB, 16>(t, piv, pers, q, st);
+    case 5: return run_mfma<5, AB_WN, NB, 16>(t, piv, pers, q, st);
+    default: return run_mfma<4, AB_WN, NB, 16>(t, piv, pers, q, st);
+  }
 }
 template <class T>
 hipError_t stage_b_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
-  const auto& t = tabs<T>(B).tB;
-  switch (b_wm(B.RS)) {
-    case 2: return run_mfma<2, AB_WN, AB_NBW, 16>(t, piv, pers, q, st);
-    case 3: return run_mfma<3, AB_WN, AB_NBW, 16>(t, piv, pers, q, st);
-    case 5: return run_mfma<5, AB_WN, AB_NBW, 16>(t, piv, pers, q, st);
-    default: return run_mfma<4, AB_WN, AB_NBW, 16>(t, piv, pers, q, st);
-  }
+  if (B.ab_nb == AB_NBN) return stage_b_rows<AB_NBN>(B, tabs<T>(B).tB, piv, pers, q, st);
+  return stage_b_rows<AB_NBW>(B, tabs<T>(B).tB, piv, pers, q, st);
 }
 template <class T>
 hipError_t stage_c_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
@@ -589,13 +603,22 @@ hipError_t stage_c_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStrea
     default: return run_mfma<4, C_WN, C_NBW, C_KC>(t, piv, pers, q, st);
   }
 }
-hipError_t stage_b_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+hipError_t stage_a_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  if (bf_ab_nb(B) == BF_NB_ABN) return run_bf<4, BF_WN, 4, BF_NB_ABN, BF_KC>(B.tAb, piv, pers, q, st);
+  return run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, piv, pers, q, st);
+}
+template <int NB>
+hipError_t stage_b_bf_rows(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
   switch (b_rb(B.RS)) {
-    case 2: return run_bf<2, BF_WN, 2, BF_NB_AB, BF_KC>(B.tBb, piv, pers, q, st);
-    case 3: return run_bf<2, BF_WN, 3, BF_NB_AB, BF_KC>(B.tBb, piv, pers, q, st);
-    case 4: return run_bf<2, BF_WN, 4, BF_NB_AB, BF_KC>(B.tBb, piv, pers, q, st);
-    default: return run_bf<2, BF_WN, 5, BF_NB_AB, BF_KC>(B.tBb, piv, pers, q, st);
+    case 2: return run_bf<2, BF_WN, 2, NB, BF_KC>(B.tBb, piv, pers, q, st);
+    case 3: return run_bf<2, BF_WN, 3, NB, BF_KC>(B.tBb, piv, pers, q, st);
+    case 4: return run_bf<2, BF_WN, 4, NB, BF_KC>(B.tBb, piv, pers, q, st);
+    default: return run_bf<2, BF_WN, 5, NB, BF_KC>(B.tBb, piv, pers, q, st);
   }
+}
+hipError_t stage_b_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  if (bf_ab_nb(B) == BF_NB_ABN) return stage_b_bf_rows<BF_NB_ABN>(B, piv, pers, q, st);
+  return stage_b_bf_rows<BF_NB_AB>(B, piv, pers, q, st);
 }
 hipError_t stage_c_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
   switch (B.variant) {
@@ -619,7 +642,7 @@ void prime(gw_chi_batch& B) {
       (void)stage_b_f<float>(B, 0, true, nullptr, nullptr);
       (void)stage_c_f<float>(B, 0, true, nullptr, nullptr);
     } else {
-      (void)run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, 0, true, nullptr, nullptr);
+      (void)stage_a_bf(B, 0, true, nullptr, nullptr);
       (void)stage_b_bf(B, 0, true, nullptr, nullptr);
       (void)stage_c_bf(B, 0, true, nullptr, nullptr);
     }
@@ -693,7 +716,7 @@ gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const
       rc = pivot_f<float>(B, piv, pers, q, ev, st);
     } else {
       GW_HIP(mark(piv, 0));
-      GW_HIP((run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, piv, pers & 1, q, st)));
+      GW_HIP(stage_a_bf(B, piv, pers & 1, q, st));
       GW_HIP(mark(piv, 1));
       GW_HIP(stage_b_bf(B, piv, pers & 2, q + kXcds, st));
       GW_HIP(mark(piv, 2));
@@ -854,6 +877,7 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   B->NA = NA;
   B->NR = NR;
   B->RS = n_tau * NA;
+  B->ab_nb = ab_nb(NA * NR);
   B->prec = prec;
   B->eps_f = eps_f;
   B->timing = opts && opts->timing;

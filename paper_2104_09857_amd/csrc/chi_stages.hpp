@@ -23,7 +23,7 @@ namespace gw {
 namespace {
 
 constexpr int A_WM = 4, AB_WN = 2, AB_NBW = 6;    // stage A tile 128 x 192, 8 waves
-constexpr int AB_COLS = 16 * AB_NBW * AB_WN;      // stage B tile (32 WM) x 192
+constexpr int AB_NBN = 2;                         // narrow stage-A/B tiles: 64 columns
 constexpr int C_WM = 4, C_WN = 2, C_NBW = 5;      // stage C tile 128 x 160, 8 waves
 constexpr int C_COLS = 16 * C_NBW * C_WN;
 constexpr int C_KC = 32;                          // K chunk staged per barrier pair

@@ -4,7 +4,8 @@ Workloads: the 12-atom chain (dense, no filter, 8 AO / 20 RI per atom) and a
 22-atom ribbon with 13 AO / 40 RI per atom and a 1e-5 filter: 286 AO (three
 128-row tiles, ragged) and 880 RI (5.5 column panels of 160, ragged), with
 dropped bricks, so the tiling, the panel unions and the filters are all
-exercised.  Tolerances: 1e-12 relative (max-norm) for the contractions,
+exercised; and a 21-atom ribbon with 5 AO / 12 RI per atom (the narrow
+stage-A/B tiles of small bases).  Tolerances: 1e-12 relative (max-norm) for the contractions,
 1e-10 for the screening (Cholesky solves), 1e-9 Ha for QP energies from the
 same Sigma, 1e-6 Ha for the whole chain."""
 import numpy as np
@@ -17,9 +18,14 @@ from oracle import gt as ogt, chi as ochi, screen as oscreen, sigma as osig, qp 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=["chain12", "strip22"])
+@pytest.fixture(scope="module", params=["chain12", "strip22", "strip21_small_basis"])
 def case(request):
-    inp = get_inputs("chain12") if request.param == "chain12" else get_inputs("strip22", filter_eps=1e-5)
+    if request.param == "chain12":
+        inp = get_inputs("chain12")
+    elif request.param == "strip22":
+        inp = get_inputs("strip22", filter_eps=1e-5)
+    else:      # 5 AO / 12 RI per atom (narrow stage-A/B tiles), 6 tau
+        inp = get_inputs("strip21", n_ao=5, n_ri=12, filter_eps=1e-4, n_tau=6)
     s = inp.s
     d = device_inputs(inp)
     ref = ochain.g0w0(inp.C, inp.eps, s.n_occ, inp.t3c, inp.V, s.ao_off, s.ri_off, inp.grids,

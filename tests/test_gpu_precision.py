@@ -25,9 +25,14 @@ pytestmark = pytest.mark.gpu
 HA_MEV = 27211.386245988
 
 
-@pytest.fixture(scope="module", params=["chain12", "strip22"])
+@pytest.fixture(scope="module", params=["chain12", "strip22", "strip21_small_basis"])
 def case(request):
-    inp = get_inputs("chain12") if request.param == "chain12" else get_inputs("strip22", filter_eps=1e-5)
+    if request.param == "chain12":
+        inp = get_inputs("chain12")
+    elif request.param == "strip22":
+        inp = get_inputs("strip22", filter_eps=1e-5)
+    else:      # 5 AO / 12 RI per atom: the narrow stage-A/B tiles
+        inp = get_inputs("strip21", n_ao=5, n_ri=12, filter_eps=1e-4, n_tau=6)
     s = inp.s
     ref = ochain.g0w0(inp.C, inp.eps, s.n_occ, inp.t3c, inp.V, s.ao_off, s.ri_off, inp.grids,
                       inp.states, s.filter_eps)
