@@ -15,10 +15,11 @@ Sigma for HOMO-4 .. LUMO+4.  Inputs are seeded and synthetic (gwinputs).
 Workload ribbon<N> (e.g. ribbon1734, 5 AO / 12 RI per atom, filter 1e-8)
 measures the learned block screener: the network is trained on the GPU on
 exact runs of ribbon300 and ribbon600, its safety band calibrated on
-ribbon900, and chi of ribbon<N> is timed exact and screened in FP64 and in
-BF16x3, with the skipped blocks audited against an exact run without the
-output filter, and the QP energies of the screened BF16x3 chain compared
-with the plain FP64 chain.
+ribbon900, and chi of ribbon<N> is timed exact and screened in FP64, FP32
+and BF16x3, with the skipped blocks audited against an exact run without
+the output filter, and the QP energies of the screened FP32 and BF16x3
+chains compared with the plain FP64 chain (value: plain FP64 chi time over
+screened FP32 chi time).
 
 Workload mol<M> (e.g. mol64) times the batched form instead: one step = one
 execution of a gw_chi_batch plan (chi for all tau of M molecules of 10-40
@@ -350,33 +351,34 @@ def bench_screened(args):
     lg_ref = gw.chi_block_lognorms(m["sys"], ref_unf)
     del ref_unf
     log(f"[screen] exact unfiltered chi {ms_ref:.0f} ms")
-    for prec in ("fp64", "bf16x3"):
+    # audit: the keep mask depends on the features only, so one screened run
+    # without the output filter shows every skipped block for all precisions
+    scr_unf, _, _ = timed_chi(m, screener=sc.net, screen_margin=margin, keep_small_blocks=True)
+    lg_s = gw.chi_block_lognorms(m["sys"], scr_unf)
+    del scr_unf
+    skipped = (lg_s < -29) & (lg_ref >= -29)
+    blk = torch.pow(10.0, lg_ref.double())                           # exact block norms
+    audit = {"blocks_skipped_nonzero": int(skipped.sum()),
+             "max_skipped_log10_norm": float(lg_ref[skipped].max()) if bool(skipped.any()) else None,
+             "skipped_mass_rel": float(torch.sqrt((blk[skipped] ** 2).sum()) / torch.sqrt((blk ** 2).sum()))}
+    del lg_s, blk, skipped
+    log(f"[screen] audit {audit}")
+    for prec in ("fp64", "fp32", "bf16x3"):
         exact, st_e, ms_e = timed_chi(m, prec=prec, timing=True)
         log(f"[screen] {prec} exact {ms_e:.0f} ms")
         scr, st_s, ms_s = timed_chi(m, prec=prec, timing=True, screener=sc.net, screen_margin=margin)
         log(f"[screen] {prec} screened {ms_s:.0f} ms")
         same = bool(torch.equal(scr, exact))
         del exact, scr
-        scr_unf, _, _ = timed_chi(m, prec=prec, screener=sc.net, screen_margin=margin,
-                                  keep_small_blocks=True)
-        lg_s = gw.chi_block_lognorms(m["sys"], scr_unf)
-        del scr_unf
-        skipped = (lg_s < -29) & (lg_ref >= -29)
-        blk = torch.pow(10.0, lg_ref.double())                       # exact block norms
-        skipped_mass = float(torch.sqrt((blk[skipped] ** 2).sum()) / torch.sqrt((blk ** 2).sum()))
         res[prec] = {"chi_ms_exact": ms_e, "chi_ms_screened": ms_s,
-                     "stage_c_ms_exact": st_e["ms_stage"][2], "stage_c_ms_screened": st_s["ms_stage"][2],
+                     "stage_ms_exact": st_e["ms_stage"], "stage_ms_screened": st_s["ms_stage"],
                      "flops_c_exact": st_e["flops_c"], "flops_c_screened": st_s["flops_c"],
                      "blocks_screened": int(st_s["n_blocks_screened"]),
                      "blocks_total": int(s.n_atoms * (s.n_atoms + 1) // 2 * m["w"].n_tau),
                      "tiles_screened": int(st_s["n_tiles_screened"]),
-                     "max_skipped_log10_norm": float(lg_ref[skipped].max()) if bool(skipped.any()) else None,
-                     "skipped_mass_rel": skipped_mass,
                      "equal_to_exact": same}
-        log(f"[screen] {prec}: exact {ms_e:.0f} ms, screened {ms_s:.0f} ms, "
-            f"{res[prec]['blocks_screened']} blocks skipped, equal {res[prec]['equal_to_exact']}")
         torch.cuda.empty_cache()
-    # QP: plain FP64 chain vs BF16x3 + screener chain
+    # QP: plain FP64 chain vs the screened FP32 and BF16x3 chains
     V = torch.as_tensor(s.coulomb(), device="cuda")
     g = m["g"]
     a = (m["sys"], m["Cd"], m["eps"], m["mu"], V, g.tau, g.omega, g.cos_w, g.sin_w, g.icos_w,
@@ -384,30 +386,37 @@ def bench_screened(args):
     o64 = pipeline.g0w0(*a, events=True)
     o64 = {k: o64[k] for k in ("e_qp", "status", "ms")}
     log(f"[screen] FP64 chain {sum(o64['ms'].values()) / 1e3:.1f} s")
-    torch.cuda.empty_cache()
-    omx = pipeline.g0w0(*a, events=True, prec="bf16x3", screener=sc.net, screen_margin=margin)
-    log(f"[screen] BF16x3 + screener chain {sum(omx['ms'].values()) / 1e3:.1f} s")
-    ok = (o64["status"] == 0) & (omx["status"] == 0)
-    de = np.abs(omx["e_qp"] - o64["e_qp"])[ok] * 27211.386245988
-    f64, fmx = res["fp64"], res["bf16x3"]
+    shift = np.abs(o64["e_qp"] - m["eps"][m["w"].states()]) * 27211.386245988
+    qp = {"shift_meV_fp64": [round(float(x), 1) for x in shift],
+          "status_fp64": [int(x) for x in o64["status"]],
+          "time_to_qp_s_fp64": sum(o64["ms"].values()) / 1e3}
+    for prec in ("fp32", "bf16x3"):
+        torch.cuda.empty_cache()
+        omx = pipeline.g0w0(*a, events=True, prec=prec, screener=sc.net, screen_margin=margin)
+        log(f"[screen] {prec} + screener chain {sum(omx['ms'].values()) / 1e3:.1f} s")
+        ok = (o64["status"] == 0) & (omx["status"] == 0)
+        de = np.where(ok, np.abs(omx["e_qp"] - o64["e_qp"]) * 27211.386245988, np.nan)
+        qp[prec + "_screened"] = {
+            "dE_meV_vs_fp64": [round(float(x), 4) for x in de],
+            "max_abs_dE_meV": float(np.nanmax(de)) if ok.any() else None,
+            "max_dE_over_shift": float(np.nanmax(de / np.maximum(shift, 1e-30))) if ok.any() else None,
+            "status": [int(x) for x in omx["status"]],
+            "time_to_qp_s": sum(omx["ms"].values()) / 1e3}
+    f64, fmx = res["fp64"], res["fp32"]
     out = {
         "metric": METRIC, "value": f64["chi_ms_exact"] / fmx["chi_ms_screened"],
-        "unit": "x (chi time, plain FP64 / BF16x3 + learned screener)", "n_gpus": 1, "steps": 1,
+        "unit": "x (chi time, plain FP64 / FP32 + learned screener)", "n_gpus": 1, "steps": 1,
         "warmup": 1, "ms_per_step": fmx["chi_ms_screened"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3 + fp64 reference", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 + fp64 reference", "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": s.n_atoms, "n_ao": s.n_ao, "n_ri": s.n_ri,
                    "filter_eps": s.filter_eps, "n_tau": m["w"].n_tau,
                    "train": ["ribbon300", "ribbon600"], "calibrate": "ribbon900"},
         "screener": {"band_decades": margin, "train_s": train_s, "loss_first_last": [hist[0][1], hist[-1][1]]},
+        "audit": audit,
         "chi": res,
-        "speedup": {"fp64_screened": f64["chi_ms_exact"] / f64["chi_ms_screened"],
-                    "bf16x3": f64["chi_ms_exact"] / fmx["chi_ms_exact"],
-                    "bf16x3_screened": f64["chi_ms_exact"] / fmx["chi_ms_screened"]},
-        "qp": {"dE_meV_bf16x3_screened_vs_fp64": [round(float(x), 4) for x in de],
-               "max_abs_dE_meV": float(de.max()) if de.size else None,
-               "status_fp64": [int(x) for x in o64["status"]], "status_mixed": [int(x) for x in omx["status"]],
-               "time_to_qp_s_fp64": sum(o64["ms"].values()) / 1e3,
-               "time_to_qp_s_mixed": sum(omx["ms"].values()) / 1e3},
+        "speedup_vs_fp64_exact": {p + sfx: f64["chi_ms_exact"] / res[p]["chi_ms_" + key]
+                                  for p in res for sfx, key in (("", "exact"), ("_screened", "screened"))},
+        "qp": qp,
         "wall_s": time.perf_counter() - t_all,
     }
     print(json.dumps(out), flush=True)
