@@ -146,8 +146,10 @@ typedef struct {
  * (plain device allocations) before returning.  It runs the batched form
  * below on one system, eagerly, with the default tile configuration of the
  * precision (the fastest measured on gfx950 for 13 AO / 40 RI per atom:
- * FP64 stage-C variant 2 with all stages persistent, FP32 variant 0 with
- * stages B and C persistent, BF16x3 variant 0 with all stages persistent). */
+ * FP64 stage-C variant 2 with all stages persistent, FP32 variant 3 (the
+ * direct-to-LDS outer contraction; variant 0 when ri_per_atom is not a
+ * multiple of 4) with stages B and C persistent, BF16x3 variant 0 with all
+ * stages persistent). */
 gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double *d_vir,
                           int32_t n_tau, const gw_chi_opts *opts, double *chi,
                           gw_chi_stats *stats, hipStream_t stream);
@@ -184,11 +186,13 @@ gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double 
  *   (0 .. n_variants-1) and launch modes: persistent is a mask, bit k set =
  *   stage k (0: A, 1: B, 2: C) runs as a resident grid that takes tiles from
  *   per-XCD device queues, largest systems first; bit clear = one workgroup
- *   per tile (XCD-aware tile order).  ARG error outside these ranges.
+ *   per tile (XCD-aware tile order).  ARG error outside these ranges, and
+ *   for variant 3 of FP64 / FP32 plans when ri_per_atom is not a multiple of
+ *   2 / 4 (its operands are copied into LDS 16 bytes at a time).
  * gw_chi_batch_tune: autotuner.  If cache_path (may be NULL) holds an entry
  *   for the plan's shape class (precision, AO/RI per atom, n_tau, log2 of
  *   the system count and of the mean atom count) that configuration is
- *   taken; otherwise every variant is run in both launch modes (reps timed
+ *   taken; otherwise every usable variant is run in both launch modes (reps timed
  *   executions each, stage times from HIP events), each stage takes its
  *   fastest mode and stage C its fastest variant, and the result is
  *   appended to cache_path.  *ms_out (host, may be NULL) receives the time

@@ -31,11 +31,23 @@ namespace {
 
 // stage-C tile variants: rows of a tile (columns are one 160-wide panel)
 //   FP64 and FP32  0: <WM 4, KC 32> 128 rows  1: <WM 2, KC 32> 64 rows  2: <WM 4, KC 16> 128 rows
+//                  3: direct-to-LDS copies three chunks deep, two workgroups per CU:
+//                     FP64 <WM 2, WN 5, NB 2, KC 8> 64 rows (10 waves of 32 x 32),
+//                     FP32 <WM 4, WN 2, NB 5, KC 16> 128 rows; needs NR a multiple of
+//                     2 (FP64) / 4 (FP32)
 //   BF16x3  0: <WM 4, RB 4> 256 rows    1: <WM 4, RB 2> 128 rows   2: <WM 2, RB 4> 128 rows
-constexpr int kNVar = 3;
+//           3: <WM 4, RB 3> 192 rows
+constexpr int kNVar = 4;
 int c_rows(int prec, int v) {
-  static const int f64[kNVar] = {128, 64, 128}, bf[kNVar] = {256, 128, 128};
-  return prec == GW_BF16X3 ? bf[v] : f64[v];
+  static const int f64[kNVar] = {128, 64, 128, 64}, f32[kNVar] = {128, 64, 128, 128},
+                   bf[kNVar] = {256, 128, 128, 192};
+  return prec == GW_BF16X3 ? bf[v] : prec == GW_FP32 ? f32[v] : f64[v];
+}
+// stage-C variant usable for this precision and RI block size
+bool variant_ok(int prec, int NR, int v) {
+  if (v < 0 || v >= kNVar) return false;
+  if (v == 3 && prec != GW_BF16X3) return NR % (prec == GW_FP64 ? 2 : 4) == 0;
+  return true;
 }
 // stage-B waves (FP64) / row blocks (BF16x3) by the row count n_tau * NA
 int b_wm(int RS) { return RS <= 64 ? 2 : RS <= 96 ? 3 : RS <= 128 ? 4 : RS <= 160 ? 5 : 4; }
@@ -558,6 +570,24 @@ hipError_t run_mfma(const Table<P>& T, int piv, bool pers, int* queue, hipStream
               : launch_tile_gemm<WM, WN, NB, KC>(b, dim3((unsigned)work), st);
 }
 
+// the same for the direct-to-LDS form of the outer contraction
+template <int WM, int WN, int NB, int KC, int S, class P>
+hipError_t run_dma(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t st) {
+  if (!queue) {
+    (void)persistent_cap_dma<WM, WN, NB, KC, S, Batched<P>>();
+    return hipSuccess;
+  }
+  const int work = T.work[piv];
+  if (T.n[piv] == 0 || work == 0) return hipSuccess;
+  if (!pers && T.n[piv] == 1) {
+    const BatchEntry<P>& e = T.ent[T.ent0[piv]];
+    return launch_tile_dma<WM, WN, NB, KC, S>(e.p, dim3(e.gx, e.gy, work / (e.gx * e.gy)), st);
+  }
+  const Batched<P> b = T.at(piv);
+  return pers ? launch_tile_dma_persistent<WM, WN, NB, KC, S>(b, work, queue, st)
+              : launch_tile_dma<WM, WN, NB, KC, S>(b, dim3((unsigned)work), st);
+}
+
 template <int WM, int WN, int RB, int NB, int KC, class P>
 hipError_t run_bf(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t st) {
   if (!queue) {
@@ -600,6 +630,9 @@ hipError_t stage_c_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStrea
   switch (B.variant) {
     case 1: return run_mfma<2, C_WN, C_NBW, C_KC>(t, piv, pers, q, st);
     case 2: return run_mfma<4, C_WN, C_NBW, 16>(t, piv, pers, q, st);
+    case 3:
+      if constexpr (std::is_same<T, double>::value) return run_dma<2, 5, 2, 8, 3>(t, piv, pers, q, st);
+      else return run_dma<4, C_WN, C_NBW, 16, 3>(t, piv, pers, q, st);
     default: return run_mfma<4, C_WN, C_NBW, C_KC>(t, piv, pers, q, st);
   }
 }
@@ -624,6 +657,7 @@ hipError_t stage_c_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStre
   switch (B.variant) {
     case 1: return run_bf<4, BF_WN, 2, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
     case 2: return run_bf<2, BF_WN, 4, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
+    case 3: return run_bf<4, BF_WN, 3, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
     default: return run_bf<4, BF_WN, 4, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
   }
 }
@@ -883,7 +917,7 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   B->timing = opts && opts->timing;
   B->out_filter = !(opts && opts->keep_small_blocks);
   // default tile configuration per precision (fastest measured for 13 AO / 40 RI per atom)
-  B->variant = prec == GW_FP64 ? 2 : 0;
+  B->variant = prec == GW_FP64 ? 2 : prec == GW_FP32 && variant_ok(prec, NR, 3) ? 3 : 0;
   B->persistent = prec == GW_FP32 ? 6 : 7;
   B->sys.resize(n_sys);
   for (int m = 0; m < n_sys; ++m) {
@@ -945,6 +979,8 @@ extern "C" gw_status gw_chi_batch_set_config(gw_chi_batch* plan, int32_t variant
   clear_error();
   GW_CHECK_ARG(plan != nullptr, "plan must be non-null");
   GW_CHECK_ARG(variant >= 0 && variant < kNVar, "variant out of range");
+  GW_CHECK_ARG(variant_ok(plan->prec, plan->NR, variant),
+               "stage-C variant 3 needs ri_per_atom a multiple of 2 (FP64) or 4 (FP32)");
   GW_CHECK_ARG(persistent >= 0 && persistent <= 7, "persistent must be a mask of bits 0..2");
   plan->variant = variant;
   plan->persistent = persistent;
@@ -979,7 +1015,8 @@ extern "C" gw_status gw_chi_batch_tune(gw_chi_batch* plan, const double* const* 
       std::string k;
       int v = -1, pers = -1;
       double ms = 0.0;
-      if ((ls >> k >> v >> pers >> ms) && k == key && v >= 0 && v < kNVar && pers >= 0 && pers <= 7) {
+      if ((ls >> k >> v >> pers >> ms) && k == key && variant_ok(plan->prec, plan->NR, v) && pers >= 0 &&
+          pers <= 7) {
         plan->variant = v;
         plan->persistent = pers;
         if (ms_out) *ms_out = ms;
@@ -995,6 +1032,7 @@ extern "C" gw_status gw_chi_batch_tune(gw_chi_batch* plan, const double* const* 
   int best_v = 0, best_pc = 0;
   for (int v = 0; v < kNVar && rc == GW_OK; ++v)
     for (int pers = 0; pers < 2 && rc == GW_OK; ++pers) {
+      if (!variant_ok(plan->prec, plan->NR, v)) continue;
       plan->variant = v;
       plan->persistent = pers ? 7 : 0;
       if ((rc = execute(*plan, d_occ, d_vir, chi, false, nullptr, st)) != GW_OK) break;  // warm-up

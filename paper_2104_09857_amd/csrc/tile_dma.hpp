@@ -1,0 +1,268 @@
+// Direct-to-LDS form of the tile engine for problems whose A offsets step in k
+// (kAStep) and whose B is a linear panel (kBLin): the outer contraction of chi.
+//
+// The register-staged engine (tile_gemm.hpp) loads each K chunk into
+// registers, waits, and writes it to LDS; its prefetch registers, their
+// addresses and the unrolled operand reads put an FP64 128 x 160 tile at ~200
+// VGPRs, one workgroup per CU.  Here the load units copy global memory
+// straight into LDS (global_load_lds, 16 bytes per lane), S chunks deep, so no
+// operand passes through registers and two workgroups fit on a CU.
+//
+// Layout of one stage: A chunk [KC][ROWS], B chunk [KC][COLS], both without
+// padding; k row k is stored rotated by 16 elements when k is odd (element e
+// of the row at position (e + 16 (k & 1)) mod width), which puts the k rows
+// read by one matrix-core step into different LDS banks, as the padded rows
+// of the register-staged engine do.  A copy instruction fills 64 * EPL
+// consecutive LDS elements (EPL = 16 bytes / element size); each lane fetches
+// the EPL global elements that the rotation places at its position, which
+// are consecutive in global memory as long as ROWS / COLS and the problem's
+// row blocks are multiples of EPL (the host checks NR % EPL == 0).
+//
+// Rows and columns outside the tile are copied from a clamped valid address
+// (they only reach outputs that are not stored); K rows past t.K are copied
+// from row K - 1 and zeroed in the A operand of the last chunk.
+#pragma once
+
+#include "tile_gemm.hpp"
+
+namespace gw {
+
+// s_waitcnt with vmcnt(n) (n < 16) and no wait on the other counters
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 16, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
+
+template <int WM, int WN, int NB, int KC, int S, class P>
+__device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz) {
+  using TI = typename in_type<P>::type;
+  using TO = typename out_type<P>::type;
+  using MF = Mfma<TI>;
+  static_assert(has_astep<P>::value && has_blin<P>::value, "direct-to-LDS form needs kAStep and kBLin");
+  constexpr int ROWS = 32 * WM, COLS = 16 * NB * WN, NT = 64 * WM * WN, NW = NT / 64;
+  constexpr int EPL = 16 / (int)sizeof(TI), PER = 64 * EPL;
+  constexpr int ACH = KC * ROWS, BCH = KC * COLS;
+  constexpr int NCA = ACH / PER, NCB = BCH / PER, NC = NCA + NCB;   // copies per chunk
+  constexpr int CPW = (NC + NW - 1) / NW, CMIN = NC / NW;            // copies per wave (max, min)
+  constexpr int ROT = 16;
+  static_assert(ACH % PER == 0 && BCH % PER == 0 && ROWS % EPL == 0 && COLS % EPL == 0, "copy layout");
+  static_assert(KC % 4 == 0 && S >= 2 && CMIN >= 1, "pipeline shape");
+  __shared__ __attribute__((aligned(16))) TI As[S][ACH];
+  __shared__ __attribute__((aligned(16))) TI Bs[S][BCH];
+  __shared__ int tabA[P::kTabA > 0 ? P::kTabA : 1];
+  __shared__ int tabB[1];
+
+  typename P::Tile t;
+  if (!p.tile(bx, by, bz, t)) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave % WM, wn = wave / WM;
+  const auto lp = resolve(p, t);
+  lp.fill(t, tabA, tabB, tid, NT);
+  __syncthreads();
+  const gmem<const TI>* __restrict__ abase = to_global(lp.abase(t));
+  const gmem<const TI>* __restrict__ bbase = to_global(lp.bbase(t));
+  const int adiv = lp.adiv(t), bstr = lp.bstride(t);
+  const int kmax = t.K - 1;
+  FastDiv afd{};
+  afd.set((uint32_t)adiv);
+  const int sgmax = kmax / adiv;
+
+  // copies of this wave: copy c = wave + NW * j (A copies first, then B); for
+  // each, the k row inside the chunk, the LDS offset inside the stage and the
+  // lane's fixed part of the global offset (A: row offset, B: k row * stride
+  // + column)
+  int ck[CPW], cl[CPW];
+  uint32_t cg[CPW];
+  bool cb_[CPW];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int c = wave + NW * j < NC ? wave + NW * j : NC - 1;
+    const bool isb = c >= NCA;
+    const int e = (isb ? c - NCA : c) * PER + lane * EPL;   // element of the chunk
+    const int width = isb ? COLS : ROWS;
+    const int k = e / width, pos = e % width;
+    int x = pos - ROT * (k & 1);
+    x += x < 0 ? width : 0;                                   // row / column in the tile
+    ck[j] = k;
+    cl[j] = (isb ? c - NCA : c) * PER;
+    cb_[j] = isb;
+    if (isb) {
+      cg[j] = (uint32_t)(k * bstr + (x < t.cols ? x : 0));
+    } else {
+      cg[j] = x < t.rows ? (uint32_t)lp.aroff(t, x) : (uint32_t)lp.aroff(t, 0);
+    }
+  }
+  const int nmine = wave + NW * (CPW - 1) < NC ? CPW : CPW - 1;
+
+  auto issue = [&](int ch, int stg) {
+    const int k0 = ch * KC;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      if (j < nmine) {
+        int k = k0 + ck[j];
+        k = k < kmax ? k : kmax;
+        if (cb_[j]) {
+          const gmem<const TI>* g = bbase + (cg[j] + (uint32_t)((k - ck[j]) * bstr));
+          __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                           (void __attribute__((address_space(3)))*)(&Bs[stg][cl[j]]),
+                                           16, 0, 0);
+        } else {
+          const int sg = (int)afd.div((uint32_t)k), u = k - sg * adiv;
+          const uint32_t ko = lp.akoff2(t, sg < sgmax ? sg : sgmax, u, tabA);
+          const gmem<const TI>* g = abase + (cg[j] + ko);
+          __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                           (void __attribute__((address_space(3)))*)(&As[stg][cl[j]]),
+                                           16, 0, 0);
+        }
+      }
+    }
+  };
+
+  typename MF::acc acc[2][NB];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = typename MF::acc{0, 0, 0, 0};
+
+  // LDS offsets of this lane's operands inside a stage (k row 4 kk + lk has
+  // the parity of lk)
+  const int lr = lane & 15, lk = lane >> 4, rot = ROT * (lk & 1);
+  const int a0o = lk * ROWS + ((wm * 32 + lr + rot) % ROWS);
+  const int a1o = lk * ROWS + ((wm * 32 + 16 + lr + rot) % ROWS);
+  int bo[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) bo[cb] = lk * COLS + (((wn * NB + cb) * 16 + lr + rot) % COLS);
+
+  const int nch = (t.K + KC - 1) / KC;
+#pragma unroll
+  for (int s = 0; s + 1 < S; ++s)
+    if (s < nch) issue(s, s);
+  for (int ch = 0; ch < nch; ++ch) {
+    // this wave's copies of chunk ch have landed (later chunks may still be
+    // in flight); then every wave's have, and stage (ch + S - 1) % S is free
+    if (S > 2 && ch + S - 2 < nch) wait_vm<CMIN * (S > 2 ? S - 2 : 0)>();
+    else wait_vm<0>();
+    __syncthreads();
+    if (ch + S - 1 < nch) issue(ch + S - 1, (ch + S - 1) % S);
+    const int stg = ch % S;
+    const TI* as = As[stg];
+    const TI* bs = Bs[stg];
+    const int kv = t.K - ch * KC;            // valid k rows of this chunk
+    if (kv >= KC) {
+#pragma unroll
+      for (int kk = 0; kk < KC / 4; ++kk) {
+        const TI a0 = as[kk * 4 * ROWS + a0o];
+        const TI a1 = as[kk * 4 * ROWS + a1o];
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+          const TI b = bs[kk * 4 * COLS + bo[cb]];
+          acc[0][cb] = MF::step(a0, b, acc[0][cb]);
+          acc[1][cb] = MF::step(a1, b, acc[1][cb]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KC / 4; ++kk) {
+        const bool ok = 4 * kk + lk < kv;
+        const TI a0 = ok ? as[kk * 4 * ROWS + a0o] : TI(0);
+        const TI a1 = ok ? as[kk * 4 * ROWS + a1o] : TI(0);
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+          const TI b = bs[kk * 4 * COLS + bo[cb]];
+          acc[0][cb] = MF::step(a0, b, acc[0][cb]);
+          acc[1][cb] = MF::step(a1, b, acc[1][cb]);
+        }
+      }
+    }
+  }
+
+  // epilogue one 16-row block at a time (keeps the live registers of the
+  // accumulators, row offsets and old values within the occupancy budget)
+  gmem<TO>* __restrict__ ob = to_global(lp.obase(t));
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+    int64_t ro[4];
+    bool rv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm * 32 + rb * 16 + MF::row(i, lk);
+      rv[i] = r < t.rows;
+      ro[i] = rv[i] ? lp.rowoff(t, r) : 0;
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      const int c = (wn * NB + cb) * 16 + lr;
+      const bool cv = c < t.cols;
+      const int64_t co = cv ? lp.coloff(t, c) : 0;
+      if constexpr (P::kAccum) {
+        TO old[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) old[i] = ob[(rv[i] && cv) ? ro[i] + co : 0];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (rv[i] && cv) ob[ro[i] + co] = old[i] + (TO)P::kSign * (TO)acc[rb][cb][i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (rv[i] && cv) ob[ro[i] + co] = (TO)acc[rb][cb][i];
+      }
+    }
+  }
+}
+
+template <int WM, int WN, int NB, int KC, int S, class P>
+__global__ __launch_bounds__(64 * WM * WN) void tile_dma_kernel(P p) {
+  int bx, by, bz;
+  grid_tile(bx, by, bz);
+  tile_dma_body<WM, WN, NB, KC, S>(p, bx, by, bz);
+}
+
+// persistent form: the work queues of tile_gemm_persistent
+template <int WM, int WN, int NB, int KC, int S, class P>
+__global__ __launch_bounds__(64 * WM * WN) void tile_dma_persistent(P p, int n_work, int* queue) {
+  __shared__ int next;
+  const uint32_t q = (uint32_t)n_work / kXcds, r = (uint32_t)n_work % kXcds;
+  const uint32_t home = blockIdx.x % kXcds;
+  for (uint32_t j = 0; j < kXcds; ++j) {
+    const uint32_t x = (home + j) % kXcds;
+    const int start = (int)(x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q);
+    const int len = (int)(x < r ? q + 1 : q);
+    for (;;) {
+      __syncthreads();
+      if (threadIdx.x == 0) next = atomicAdd(queue + x, 1);
+      __syncthreads();
+      const int l = next;
+      if (l >= len) break;
+      tile_dma_body<WM, WN, NB, KC, S>(p, start + l, 0, 0);
+    }
+  }
+}
+
+template <int WM, int WN, int NB, int KC, int S, class P>
+inline hipError_t launch_tile_dma(const P& p, dim3 grid, hipStream_t st) {
+  if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
+  hipLaunchKernelGGL((tile_dma_kernel<WM, WN, NB, KC, S, P>), grid, dim3(64 * WM * WN), 0, st, p);
+  return hipGetLastError();
+}
+
+template <int WM, int WN, int NB, int KC, int S, class P>
+inline int persistent_cap_dma() {
+  static int cap = 0;
+  if (cap == 0) cap = resident_groups(tile_dma_persistent<WM, WN, NB, KC, S, P>, 64 * WM * WN);
+  return cap;
+}
+
+template <int WM, int WN, int NB, int KC, int S, class P>
+inline hipError_t launch_tile_dma_persistent(const P& p, int n_work, int* queue, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  const int cap = persistent_cap_dma<WM, WN, NB, KC, S, P>();
+  const int grid = cap > 0 ? (n_work < cap ? n_work : cap) : n_work;
+  hipLaunchKernelGGL((tile_dma_persistent<WM, WN, NB, KC, S, P>), dim3(grid), dim3(64 * WM * WN), 0, st,
+                     p, n_work, queue);
+  return hipGetLastError();
+}
+
+}  // namespace gw
