@@ -45,14 +45,16 @@ PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 DTYPE = {"fp64": "f64", "fp32": "f32 (FP32 MFMA and accumulation in a tile, FP64 across pivots)",
          "bf16x3": "bf16x3 (bf16 hi/lo MFMA, FP32 accumulation in a tile, FP64 across pivots)"}
-_C_TILES = {"fp64": ["4,2,5,32", "2,2,5,32", "4,2,5,16"], "fp32": ["4,2,5,32", "2,2,5,32", "4,2,5,16"],
-            "bf16x3": ["4,2,4,5,32", "4,2,2,5,32", "2,2,4,5,32"]}
+_C_TILES = {"fp64": ["4,2,5,32", "2,2,5,32", "4,2,5,16", "2,5,2,8,3"],
+            "fp32": ["4,2,5,32", "2,2,5,32", "4,2,5,16", "4,2,5,16,3"],
+            "bf16x3": ["4,2,4,5,32", "4,2,2,5,32", "2,2,4,5,32", "4,2,3,5,32"]}
 _C_PROB = {"fp64": "StageC<double>", "fp32": "StageC<float>", "bf16x3": "StageCBf"}
 
 
 def stage_c_kernel(prec, variant, mask, batched=False):
-    """Name of the stage-C kernel a chi run launched (as rocprofv3 lists it)."""
-    eng = "tile_bf16x3" if prec == "bf16x3" else "tile_gemm"
+    """Name of the stage-C kernel a chi run launched (as rocprofv3 lists it);
+    variant 3 of FP64 / FP32 is the direct-to-LDS engine (tile_dma)."""
+    eng = "tile_bf16x3" if prec == "bf16x3" else "tile_dma" if variant == 3 else "tile_gemm"
     prob = _C_PROB[prec]
     if mask & 4:
         return f"{eng}_persistent<{_C_TILES[prec][variant]},Batched<{prob}>>"
@@ -65,10 +67,11 @@ def measured_traffic(path, workload, kernel):
     workload and kernel or the kernel sources changed since it was taken."""
     import hashlib
     try:
-        rec = json.load(open(path)).get(workload)
+        recs = json.load(open(path)).get(workload) or []
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("kernel") != kernel:
+    rec = next((r for r in recs if r.get("kernel") == kernel), None)
+    if rec is None:
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
