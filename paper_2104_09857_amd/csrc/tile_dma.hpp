@@ -9,10 +9,12 @@
 // operand passes through registers and two workgroups fit on a CU.
 //
 // Layout of one stage: A chunk [KC][ROWS], B chunk [KC][COLS], both without
-// padding; k row k is stored rotated by 16 elements when k is odd (element e
-// of the row at position (e + 16 (k & 1)) mod width), which puts the k rows
-// read by one matrix-core step into different LDS banks, as the padded rows
-// of the register-staged engine do.  A copy instruction fills 64 * EPL
+// padding; k row k of width W is stored rotated (element e at position
+// (e + rot(k)) mod W) with rot(k) = (16 (k mod G) - k W) mod BW, BW the bank
+// width in elements (32 doubles, 64 floats) and G = BW / 16: the k rows read
+// by one matrix-core step then start 16 elements apart modulo the bank
+// width, in different LDS banks, as the padded rows of the register-staged
+// engine do.  A copy instruction fills 64 * EPL
 // consecutive LDS elements (EPL = 16 bytes / element size); each lane fetches
 // the EPL global elements that the rotation places at its position, which
 // are consecutive in global memory as long as ROWS / COLS and the problem's
@@ -45,8 +47,9 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
   constexpr int ACH = KC * ROWS, BCH = KC * COLS;
   constexpr int NCA = ACH / PER, NCB = BCH / PER, NC = NCA + NCB;   // copies per chunk
   constexpr int CPW = (NC + NW - 1) / NW, CMIN = NC / NW;            // copies per wave (max, min)
-  constexpr int ROT = 16;
-  static_assert(ACH % PER == 0 && BCH % PER == 0 && ROWS % EPL == 0 && COLS % EPL == 0, "copy layout");
+  constexpr int BW = sizeof(TI) == 8 ? 32 : 64, G = BW / 16;
+  auto rot = [](int k, int w) { return ((16 * (k % G) - (k * w) % BW) % BW + BW) % BW; };
+  static_assert(ACH % PER == 0 && BCH % PER == 0 && ROWS % 16 == 0 && COLS % 16 == 0, "copy layout");
   static_assert(KC % 4 == 0 && S >= 2 && CMIN >= 1, "pipeline shape");
   __shared__ __attribute__((aligned(16))) TI As[S][ACH];
   __shared__ __attribute__((aligned(16))) TI Bs[S][BCH];
@@ -84,7 +87,7 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
     const int e = (isb ? c - NCA : c) * PER + lane * EPL;   // element of the chunk
     const int width = isb ? COLS : ROWS;
     const int k = e / width, pos = e % width;
-    int x = pos - ROT * (k & 1);
+    int x = pos - rot(k, width);
     x += x < 0 ? width : 0;                                   // row / column in the tile
     ck[j] = k;
     cl[j] = (isb ? c - NCA : c) * PER;
@@ -128,13 +131,13 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
     for (int j = 0; j < NB; ++j) acc[i][j] = typename MF::acc{0, 0, 0, 0};
 
   // LDS offsets of this lane's operands inside a stage (k row 4 kk + lk has
-  // the parity of lk)
-  const int lr = lane & 15, lk = lane >> 4, rot = ROT * (lk & 1);
-  const int a0o = lk * ROWS + ((wm * 32 + lr + rot) % ROWS);
-  const int a1o = lk * ROWS + ((wm * 32 + 16 + lr + rot) % ROWS);
+  // the rotation of row lk: 4 kk W is a multiple of the bank width)
+  const int lr = lane & 15, lk = lane >> 4, ra = rot(lk, ROWS), rbo = rot(lk, COLS);
+  const int a0o = lk * ROWS + ((wm * 32 + lr + ra) % ROWS);
+  const int a1o = lk * ROWS + ((wm * 32 + 16 + lr + ra) % ROWS);
   int bo[NB];
 #pragma unroll
-  for (int cb = 0; cb < NB; ++cb) bo[cb] = lk * COLS + (((wn * NB + cb) * 16 + lr + rot) % COLS);
+  for (int cb = 0; cb < NB; ++cb) bo[cb] = lk * COLS + (((wn * NB + cb) * 16 + lr + rbo) % COLS);
 
   const int nch = (t.K + KC - 1) / KC;
 #pragma unroll
