@@ -148,8 +148,9 @@ typedef struct {
  * precision (the fastest measured on gfx950 for 13 AO / 40 RI per atom:
  * FP64 stage-C variant 2 with all stages persistent, FP32 variant 3 (the
  * direct-to-LDS outer contraction; variant 0 when ri_per_atom is not a
- * multiple of 4) with stages B and C persistent, BF16x3 variant 0 with all
- * stages persistent). */
+ * multiple of 4) with stages B and C persistent (stage B as a grid when the
+ * basis has at most 64 AO x RI functions per atom pair), BF16x3 variant 0
+ * with all stages persistent). */
 gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double *d_vir,
                           int32_t n_tau, const gw_chi_opts *opts, double *chi,
                           gw_chi_stats *stats, hipStream_t stream);

@@ -183,6 +183,7 @@ struct gw_chi_batch {
   int variant = 0, persistent = 0;
   int RS = 0;
   int ab_nb = AB_NBW;      // 16-column blocks per wave of the stage-A/B tiles
+  bool b_dma = false;      // FP32 stage B on the direct-to-LDS engine
   FTables<double> t64;
   FTables<float> t32;
   Table<StageABf> tAb;
@@ -619,8 +620,23 @@ hipError_t stage_b_rows(const gw_chi_batch& B, const Tab& t, int piv, bool pers,
     default: return run_mfma<4, AB_WN, NB, 16>(t, piv, pers, q, st);
   }
 }
+template <int NB, class Tab>
+hipError_t stage_b_dma_rows(const gw_chi_batch& B, const Tab& t, int piv, bool pers, int* q, hipStream_t st) {
+  switch (b_wm(B.RS)) {
+    case 2: return run_dma<2, AB_WN, NB, 16, 2>(t, piv, pers, q, st);
+    case 3: return run_dma<3, AB_WN, NB, 16, 2>(t, piv, pers, q, st);
+    case 5: return run_dma<5, AB_WN, NB, 16, 2>(t, piv, pers, q, st);
+    default: return run_dma<4, AB_WN, NB, 16, 2>(t, piv, pers, q, st);
+  }
+}
 template <class T>
 hipError_t stage_b_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (B.b_dma) {
+      if (B.ab_nb == AB_NBN) return stage_b_dma_rows<AB_NBN>(B, tabs<T>(B).tB, piv, pers, q, st);
+      return stage_b_dma_rows<AB_NBW>(B, tabs<T>(B).tB, piv, pers, q, st);
+    }
+  }
   if (B.ab_nb == AB_NBN) return stage_b_rows<AB_NBN>(B, tabs<T>(B).tB, piv, pers, q, st);
   return stage_b_rows<AB_NBW>(B, tabs<T>(B).tB, piv, pers, q, st);
 }
@@ -912,13 +928,18 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   B->NR = NR;
   B->RS = n_tau * NA;
   B->ab_nb = ab_nb(NA * NR);
+  // 16-byte copies need the rows of the gathered D^vir (n_tau * NA floats) and
+  // the brick rows (NA * NR floats) in whole groups of four
+  B->b_dma = prec == GW_FP32 && NR % 4 == 0 && (n_tau * NA) % 4 == 0;
   B->prec = prec;
   B->eps_f = eps_f;
   B->timing = opts && opts->timing;
   B->out_filter = !(opts && opts->keep_small_blocks);
   // default tile configuration per precision (fastest measured for 13 AO / 40 RI per atom)
   B->variant = prec == GW_FP64 ? 2 : prec == GW_FP32 && variant_ok(prec, NR, 3) ? 3 : 0;
-  B->persistent = prec == GW_FP32 ? 6 : 7;
+  // FP32: stage A as a grid; stage B persistent on the wide tiles, a grid on
+  // the narrow ones (measured on 13/40 and 5/12 bases)
+  B->persistent = prec == GW_FP32 ? (B->ab_nb == AB_NBN ? 4 : 6) : 7;
   B->sys.resize(n_sys);
   for (int m = 0; m < n_sys; ++m) {
     if ((rc = prepare_sys(*B, B->sys[m], &systems[m], st)) != GW_OK) return rc;

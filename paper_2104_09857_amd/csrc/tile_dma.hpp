@@ -1,5 +1,6 @@
 // Direct-to-LDS form of the tile engine for problems whose A offsets step in k
-// (kAStep) and whose B is a linear panel (kBLin): the outer contraction of chi.
+// (kAStep): the outer contraction of chi (B a linear panel, kBLin) and the
+// D^vir half contraction (B rows gathered from the bricks through a table).
 //
 // The register-staged engine (tile_gemm.hpp) loads each K chunk into
 // registers, waits, and writes it to LDS; its prefetch registers, their
@@ -41,7 +42,8 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
   using TI = typename in_type<P>::type;
   using TO = typename out_type<P>::type;
   using MF = Mfma<TI>;
-  static_assert(has_astep<P>::value && has_blin<P>::value, "direct-to-LDS form needs kAStep and kBLin");
+  static_assert(has_astep<P>::value, "direct-to-LDS form needs kAStep");
+  constexpr bool BLIN = has_blin<P>::value;
   constexpr int ROWS = 32 * WM, COLS = 16 * NB * WN, NT = 64 * WM * WN, NW = NT / 64;
   constexpr int EPL = 16 / (int)sizeof(TI), PER = 64 * EPL;
   constexpr int ACH = KC * ROWS, BCH = KC * COLS;
@@ -54,7 +56,7 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
   __shared__ __attribute__((aligned(16))) TI As[S][ACH];
   __shared__ __attribute__((aligned(16))) TI Bs[S][BCH];
   __shared__ int tabA[P::kTabA > 0 ? P::kTabA : 1];
-  __shared__ int tabB[1];
+  __shared__ int tabB[P::kTabB > 0 ? P::kTabB : 1];
 
   typename P::Tile t;
   if (!p.tile(bx, by, bz, t)) return;
@@ -67,7 +69,9 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
   __syncthreads();
   const gmem<const TI>* __restrict__ abase = to_global(lp.abase(t));
   const gmem<const TI>* __restrict__ bbase = to_global(lp.bbase(t));
-  const int adiv = lp.adiv(t), bstr = lp.bstride(t);
+  const int adiv = lp.adiv(t);
+  int bstr = 0;
+  if constexpr (BLIN) bstr = lp.bstride(t);
   const int kmax = t.K - 1;
   FastDiv afd{};
   afd.set((uint32_t)adiv);
@@ -75,8 +79,8 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
 
   // copies of this wave: copy c = wave + NW * j (A copies first, then B); for
   // each, the k row inside the chunk, the LDS offset inside the stage and the
-  // lane's fixed part of the global offset (A: row offset, B: k row * stride
-  // + column)
+  // lane's fixed part of the global offset (A: row offset; B: k row * stride
+  // + column for a linear panel, the column for a gathered one)
   int ck[CPW], cl[CPW];
   uint32_t cg[CPW];
   bool cb_[CPW];
@@ -93,7 +97,7 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
     cl[j] = (isb ? c - NCA : c) * PER;
     cb_[j] = isb;
     if (isb) {
-      cg[j] = (uint32_t)(k * bstr + (x < t.cols ? x : 0));
+      cg[j] = (uint32_t)((BLIN ? k * bstr : 0) + (x < t.cols ? x : 0));
     } else {
       cg[j] = x < t.rows ? (uint32_t)lp.aroff(t, x) : (uint32_t)lp.aroff(t, 0);
     }
@@ -108,7 +112,9 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
         int k = k0 + ck[j];
         k = k < kmax ? k : kmax;
         if (cb_[j]) {
-          const gmem<const TI>* g = bbase + (cg[j] + (uint32_t)((k - ck[j]) * bstr));
+          const gmem<const TI>* g;
+          if constexpr (BLIN) g = bbase + (cg[j] + (uint32_t)((k - ck[j]) * bstr));
+          else g = bbase + (lp.bkoff(t, k, tabB) + cg[j]);
           __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
                                            (void __attribute__((address_space(3)))*)(&Bs[stg][cl[j]]),
                                            16, 0, 0);
