@@ -184,6 +184,7 @@ struct gw_chi_batch {
   int RS = 0;
   int ab_nb = AB_NBW;      // 16-column blocks per wave of the stage-A/B tiles
   bool b_dma = false;      // FP32 stage B on the direct-to-LDS engine
+  bool a_dma = false;      // FP32 stage A on the direct-to-LDS engine
   FTables<double> t64;
   FTables<float> t32;
   Table<StageABf> tAb;
@@ -580,10 +581,8 @@ hipError_t run_dma(const Table<P>& T, int piv, bool pers, int* queue, hipStream_
   }
   const int work = T.work[piv];
   if (T.n[piv] == 0 || work == 0) return hipSuccess;
-  if (!pers && T.n[piv] == 1) {
-    const BatchEntry<P>& e = T.ent[T.ent0[piv]];
-    return launch_tile_dma<WM, WN, NB, KC, S>(e.p, dim3(e.gx, e.gy, work / (e.gx * e.gy)), st);
-  }
+  // grid launches go through the batched form too: reading the problem from
+  // the table keeps the kernel at fewer registers (two workgroups per CU)
   const Batched<P> b = T.at(piv);
   return pers ? launch_tile_dma_persistent<WM, WN, NB, KC, S>(b, work, queue, st)
               : launch_tile_dma<WM, WN, NB, KC, S>(b, dim3((unsigned)work), st);
@@ -608,6 +607,12 @@ hipError_t run_bf(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t
 
 template <class T>
 hipError_t stage_a_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (B.a_dma) {
+      if (B.ab_nb == AB_NBN) return run_dma<A_WM, AB_WN, AB_NBN, 16, 2>(tabs<T>(B).tA, piv, pers, q, st);
+      return run_dma<A_WM, AB_WN, AB_NBW, 16, 2>(tabs<T>(B).tA, piv, pers, q, st);
+    }
+  }
   if (B.ab_nb == AB_NBN) return run_mfma<A_WM, AB_WN, AB_NBN, 16>(tabs<T>(B).tA, piv, pers, q, st);
   return run_mfma<A_WM, AB_WN, AB_NBW, 16>(tabs<T>(B).tA, piv, pers, q, st);
 }
@@ -941,7 +946,11 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   // the narrow ones (measured on 13/40 and 5/12 bases)
   B->persistent = prec == GW_FP32 ? (B->ab_nb == AB_NBN ? 4 : 6) : 7;
   B->sys.resize(n_sys);
+  // FP32 stage A copies D^occ rows 16 bytes at a time: every system needs
+  // n_ao (the row length) and NR in whole groups of four floats
+  B->a_dma = prec == GW_FP32 && NR % 4 == 0;
   for (int m = 0; m < n_sys; ++m) {
+    B->a_dma = B->a_dma && ((int64_t)systems[m].n_atoms * NA) % 4 == 0;
     if ((rc = prepare_sys(*B, B->sys[m], &systems[m], st)) != GW_OK) return rc;
     B->max_na = std::max(B->max_na, systems[m].n_atoms);
   }
