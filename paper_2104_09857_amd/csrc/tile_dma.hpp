@@ -37,6 +37,17 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt(0x0F70 | N);
 }
 
+// Workgroup barrier without the memory fence of __syncthreads (whose release
+// waits for every outstanding load, here the copies of the chunks ahead).
+// The waits the pipeline needs are explicit (wait_vm); LDS needs no cache
+// maintenance; the empty asm statements keep the compiler from moving LDS
+// accesses across the barrier.
+__device__ __forceinline__ void stage_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <int WM, int WN, int NB, int KC, int S, class P>
 __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz) {
   using TI = typename in_type<P>::type;
@@ -154,7 +165,7 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
     // in flight); then every wave's have, and stage (ch + S - 1) % S is free
     if (S > 2 && ch + S - 2 < nch) wait_vm<CMIN * (S > 2 ? S - 2 : 0)>();
     else wait_vm<0>();
-    __syncthreads();
+    stage_barrier();
     if (ch + S - 1 < nch) issue(ch + S - 1, (ch + S - 1) % S);
     const int stg = ch % S;
     const TI* as = As[stg];
