@@ -138,6 +138,7 @@ struct SysPlan {
   double fl_a = 0.0, fl_b = 0.0, fl_c = 0.0;   // FLOPs per tau (all blocks)
   double *dof = nullptr, *dvf = nullptr;       // filtered D stacks (FP64)
   float *dof32 = nullptr, *dvf32 = nullptr;    // their FP32 copies (FP32 form)
+  int ld32 = 0;                                // row stride of dof32 (N rounded up to 4)
   uint8_t* dropped = nullptr;
   uint16_t *th = nullptr, *tl = nullptr, *doh = nullptr, *dol = nullptr, *dvh = nullptr, *dvl = nullptr;
   uint16_t *mh = nullptr, *ml = nullptr, *nh = nullptr, *nl = nullptr;
@@ -245,7 +246,8 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
     // operands rounded to FP32 once: the bricks here, D(tau) at every execution
     const size_t dsz = (size_t)n_tau * N * N, tsz = (size_t)s->n_trip * P.bs;
     float* t32;
-    if ((rc = M.alloc(&P.dof32, dsz)) != GW_OK) return rc;
+    // D^occ rows padded to a multiple of 4 floats (16-byte copies of stage A)
+    if ((rc = M.alloc(&P.dof32, (size_t)n_tau * N * P.ld32)) != GW_OK) return rc;
     if ((rc = M.alloc(&P.dvf32, dsz)) != GW_OK) return rc;
     if ((rc = M.alloc(&t32, tsz)) != GW_OK) return rc;
     GW_HIP(to_f32(s->t3c, t32, (int64_t)tsz, st));
@@ -254,7 +256,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
     F.t3c = t32;
   }
   // per-tile offsets of the stage maps are 32-bit
-  GW_CHECK_ARG((int64_t)N * N < (1ll << 31) && (int64_t)N * RS < (1ll << 31) &&
+  GW_CHECK_ARG((int64_t)N * P.ld32 < (1ll << 31) && (int64_t)N * RS < (1ll << 31) &&
                    (int64_t)NA * P.nRmax * N * NR < (1ll << 31) && P.bs < (1ll << 31),
                "system too large for 32-bit tile offsets");
   for (int p = 0; p < P.n_pan; ++p)
@@ -272,6 +274,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
   sa.n_rt = (N + sa.rows_pt - 1) / sa.rows_pt;
   sa.n_ct = (NA * NR + sa.cols_pt - 1) / sa.cols_pt;
   sa.N = N; sa.NA = NA; sa.NR = NR; sa.nRmax = P.nRmax; sa.bs = P.bs; sa.bs32 = (int)P.bs;
+  sa.lda = std::is_same<T, float>::value ? P.ld32 : N;
   sa.fdNA.set((uint32_t)NA);
   sa.fdNR.set((uint32_t)NR);
 
@@ -301,6 +304,7 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
   P.s = *s;
   P.na = s->n_atoms;
   P.N = P.na * NA;
+  P.ld32 = (P.N + 3) / 4 * 4;
   P.NRI = P.na * NR;
   P.bs = (int64_t)NA * NA * NR;
   const int na = P.na, N = P.N;
@@ -581,8 +585,14 @@ hipError_t run_dma(const Table<P>& T, int piv, bool pers, int* queue, hipStream_
   }
   const int work = T.work[piv];
   if (T.n[piv] == 0 || work == 0) return hipSuccess;
-  // grid launches go through the batched form too: reading the problem from
-  // the table keeps the kernel at fewer registers (two workgroups per CU)
+  // a one-system grid launch of a narrow tile takes the problem in its
+  // arguments (many small tiles: no table search per tile); wide tiles go
+  // through the batched form, whose kernel needs fewer registers (two
+  // workgroups per CU)
+  if (NB <= AB_NBN && !pers && T.n[piv] == 1) {
+    const BatchEntry<P>& e = T.ent[T.ent0[piv]];
+    return launch_tile_dma<WM, WN, NB, KC, S>(e.p, dim3(e.gx, e.gy, work / (e.gx * e.gy)), st);
+  }
   const Batched<P> b = T.at(piv);
   return pers ? launch_tile_dma_persistent<WM, WN, NB, KC, S>(b, work, queue, st)
               : launch_tile_dma<WM, WN, NB, KC, S>(b, dim3((unsigned)work), st);
@@ -746,7 +756,7 @@ gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const
     GW_HIP(filter_square_blocks(occ[m], P.dof, n_tau, P.na, NA, B.eps_f, P.dropped, st));
     GW_HIP(filter_square_blocks(vir[m], P.dvf, n_tau, P.na, NA, B.eps_f, P.dropped + nflag, st));
     if (B.prec == GW_FP32) {
-      GW_HIP(to_f32(P.dof, P.dof32, (int64_t)n_tau * P.N * P.N, st));
+      GW_HIP(to_f32_rows(P.dof, P.dof32, (int64_t)n_tau * P.N, P.N, P.ld32, st));
       GW_HIP(to_f32(P.dvf, P.dvf32, (int64_t)n_tau * P.N * P.N, st));
     } else if (B.prec == GW_BF16X3) {
       const int64_t dsz16 = (int64_t)n_tau * P.N * P.na * 16;
@@ -946,11 +956,10 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   // the narrow ones (measured on 13/40 and 5/12 bases)
   B->persistent = prec == GW_FP32 ? (B->ab_nb == AB_NBN ? 4 : 6) : 7;
   B->sys.resize(n_sys);
-  // FP32 stage A copies D^occ rows 16 bytes at a time: every system needs
-  // n_ao (the row length) and NR in whole groups of four floats
+  // FP32 stage A copies D^occ rows 16 bytes at a time (rows padded to four
+  // floats in the plan's FP32 copy) and brick rows of NA * NR floats
   B->a_dma = prec == GW_FP32 && NR % 4 == 0;
   for (int m = 0; m < n_sys; ++m) {
-    B->a_dma = B->a_dma && ((int64_t)systems[m].n_atoms * NA) % 4 == 0;
     if ((rc = prepare_sys(*B, B->sys[m], &systems[m], st)) != GW_OK) return rc;
     B->max_na = std::max(B->max_na, systems[m].n_atoms);
   }

@@ -49,6 +49,7 @@ struct StageA {
   const int64_t* seg_brick;
   int g0, n_rt, n_ct, rows_pt, cols_pt;
   int N, NA, NR, nRmax;
+  int lda;                  // row stride of the D^occ stack (N, or N padded to 4 in FP32)
   int64_t bs;
   int bs32;                 // brick size (elements) as int for the offset products
   FastDiv fdNA, fdNR;
@@ -74,13 +75,13 @@ struct StageA {
       tb[i] = (int)seg_brick[t.seg0 + i];
     }
   }
-  __device__ const T* abase(const Tile& t) const { return dof + (int64_t)t.tau * N * N + t.row0; }
+  __device__ const T* abase(const Tile& t) const { return dof + (int64_t)t.tau * N * lda + t.row0; }
   // A(r = mu, k = (segment sg, lambda = ta[sg] * NA + u)) = D^occ_{lambda mu}
   static constexpr bool kAStep = true;
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
   __device__ int adiv(const Tile&) const { return NA; }
   __device__ uint32_t akoff2(const Tile&, int sg, int u, const int* ta) const {
-    return (uint32_t)(ta[sg] * NA + u) * (uint32_t)N;
+    return (uint32_t)(ta[sg] * NA + u) * (uint32_t)lda;
   }
   __device__ const T* bbase(const Tile& t) const { return t3c + t.col0; }
   __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
@@ -310,6 +311,26 @@ hipError_t to_f32(const double* x, float* y, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1 << 20);
   hipLaunchKernelGGL(to_f32_kernel, dim3(blocks), dim3(256), 0, st, x, y, n);
+  return hipGetLastError();
+}
+
+// rows of n_rows x n_cols FP64 matrices to FP32 rows of stride ld >= n_cols,
+// the padding set to zero
+__global__ void to_f32_rows_kernel(const double* __restrict__ x, float* __restrict__ y, int64_t rows,
+                                   int n_cols, int ld) {
+  const int64_t total = rows * ld;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / ld;
+    const int c = (int)(i - r * ld);
+    y[i] = c < n_cols ? (float)x[r * n_cols + c] : 0.f;
+  }
+}
+
+hipError_t to_f32_rows(const double* x, float* y, int64_t rows, int n_cols, int ld, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((rows * ld + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(to_f32_rows_kernel, dim3(blocks), dim3(256), 0, st, x, y, rows, n_cols, ld);
   return hipGetLastError();
 }
 
