@@ -94,10 +94,13 @@ typedef struct {
 } gw_mlp;
 
 /* Imaginary-time density matrices (Eq. 2).
- * C: dev [n_ao][n_ao], row n = MO n (orthonormal AO basis); eps: host [n_ao]
- * ascending; tau: host [n_tau] >= 0.  Writes d_occ, d_vir: dev
- * [n_tau][n_ao][n_ao].  Either output may be NULL to skip it.
- * Errors: GW_ERR_ARG for bad sizes, unsorted eps, negative/non-finite tau. */
+ * C: dev [n_ao][n_ao], row n = MO n (orthonormal AO basis); eps: host [n_ao],
+ * the first n_occ occupied, each occupied level below mu_f and each virtual
+ * level above it (in any order otherwise: an evGW update may reorder levels);
+ * tau: host [n_tau] >= 0.  Writes d_occ, d_vir: dev [n_tau][n_ao][n_ao].
+ * Either output may be NULL to skip it.
+ * Errors: GW_ERR_ARG for bad sizes, non-finite eps, occupied (virtual) levels
+ * not below (above) mu_f, negative/non-finite tau. */
 gw_status gw_build_gt(const gw_system *s, const double *C, const double *eps, double mu_f,
                       int32_t n_tau, const double *tau, double *d_occ, double *d_vir,
                       hipStream_t stream);
@@ -266,6 +269,23 @@ gw_status gw_continue_qp(int32_t n_gw, const double *sig_occ, const double *sig_
                          const int32_t *is_occ, double mu_f, int32_t n_tau, int32_t n_w,
                          const double *omega, const double *cos_w, const double *sin_w,
                          const gw_qp_opts *opts, double *e_qp, int32_t *state_status);
+
+/* Eigenvalue self-consistent GW (evGW; the paper's step after Eq. 12: the QP
+ * energies replace the mean-field levels in the Green's function, Eq. 2, and
+ * the cycle repeats until they are self-consistent), host only: the energies
+ * of the next Green's function.  eps0: [n_mo] mean-field energies, the first
+ * n_occ occupied; states / e_qp: [n_gw] computed states (distinct, in
+ * [0, n_mo)) and their QP energies.  eps_out[i] (host [n_mo]) = e_qp of state
+ * i if computed, else eps0[i] + the mean correction e_qp - eps0 of the computed
+ * states of its class (occupied i < n_occ, virtual otherwise; no shift for a
+ * class without computed states).  *mu_out = midpoint of the highest occupied
+ * and the lowest virtual eps_out.  The QP equation of the next cycle keeps
+ * eps0 and v^xc.  ARG error for invalid arguments or non-finite e_qp;
+ * GW_ERR_NO_CONVERGE (eps_out and *mu_out filled) when an occupied level ends
+ * at or above a virtual one: the Green's function of Eq. 2 would not decay. */
+gw_status gw_evgw_update(int32_t n_mo, int32_t n_occ, const double *eps0, int32_t n_gw,
+                         const int32_t *states, const double *e_qp, double *eps_out,
+                         double *mu_out);
 
 /* Screener features of every output block: dev [n_tau][n_atoms][n_atoms][6] =
  * (distance/10 bohr, log10 tau, log10 ||T_c||, log10 ||T_c'||,

@@ -81,7 +81,8 @@ extern "C" gw_status gw_build_gt(const gw_system* s, const double* C, const doub
   GW_CHECK_ARG(std::isfinite(mu_f), "mu_f must be finite");
   for (int i = 0; i < N; ++i) {
     GW_CHECK_ARG(std::isfinite(eps[i]), "eps must be finite");
-    GW_CHECK_ARG(i == 0 || eps[i] >= eps[i - 1], "eps must be ascending");
+    GW_CHECK_ARG(i < s->n_occ ? eps[i] < mu_f : eps[i] > mu_f,
+                 "occupied levels must lie below mu_f and virtual levels above it");
   }
   for (int j = 0; j < n_tau; ++j) GW_CHECK_ARG(std::isfinite(tau[j]) && tau[j] >= 0.0, "tau must be finite and >= 0");
 

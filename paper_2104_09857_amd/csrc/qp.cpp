@@ -9,6 +9,7 @@
 // (and their z derivatives).  Virtual states use nodes +i w_k, occupied
 // states -i w_k with conjugated values.  Newton-Raphson from E = eps_n on
 //   f(E) = E - eps_n + vxc_n - sig_x_n - Re Sigma^c_n(E - mu_F).
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <string>
@@ -120,4 +121,46 @@ extern "C" gw_status gw_continue_qp(int32_t n_gw, const double* sig_occ, const d
   }
   if (ret != GW_OK) gw::set_error("Newton did not converge for at least one state");
   return ret;
+}
+
+extern "C" gw_status gw_evgw_update(int32_t n_mo, int32_t n_occ, const double* eps0, int32_t n_gw,
+                                    const int32_t* states, const double* e_qp, double* eps_out,
+                                    double* mu_out) {
+  gw::clear_error();
+  if (n_mo < 2 || n_occ < 1 || n_occ >= n_mo || n_gw < 1 || n_gw > n_mo || !eps0 || !states ||
+      !e_qp || !eps_out || !mu_out) {
+    gw::set_error("gw_evgw_update: invalid argument");
+    return GW_ERR_ARG;
+  }
+  std::vector<char> seen((size_t)n_mo, 0);
+  double d_occ = 0.0, d_vir = 0.0;
+  int n_o = 0, n_v = 0;
+  for (int n = 0; n < n_gw; ++n) {
+    const int i = states[n];
+    if (i < 0 || i >= n_mo || seen[i] || !std::isfinite(e_qp[n]) || !std::isfinite(eps0[i])) {
+      gw::set_error("gw_evgw_update: states must be distinct indices in [0, n_mo) with finite energies");
+      return GW_ERR_ARG;
+    }
+    seen[i] = 1;
+    if (i < n_occ) {
+      d_occ += e_qp[n] - eps0[i];
+      ++n_o;
+    } else {
+      d_vir += e_qp[n] - eps0[i];
+      ++n_v;
+    }
+  }
+  d_occ = n_o ? d_occ / n_o : 0.0;
+  d_vir = n_v ? d_vir / n_v : 0.0;
+  for (int i = 0; i < n_mo; ++i) eps_out[i] = eps0[i] + (i < n_occ ? d_occ : d_vir);
+  for (int n = 0; n < n_gw; ++n) eps_out[states[n]] = e_qp[n];
+  double homo = eps_out[0], lumo = eps_out[n_occ];
+  for (int i = 1; i < n_occ; ++i) homo = std::max(homo, eps_out[i]);
+  for (int i = n_occ + 1; i < n_mo; ++i) lumo = std::min(lumo, eps_out[i]);
+  *mu_out = 0.5 * (homo + lumo);
+  if (!(homo < lumo)) {
+    gw::set_error("gw_evgw_update: an occupied level ends at or above a virtual one");
+    return GW_ERR_NO_CONVERGE;
+  }
+  return GW_OK;
 }

@@ -84,8 +84,9 @@ def lib():
                                         _P, _P]
         L.gw_continue_qp.argtypes = [_I32, _P, _P, _P, _P, _P, _P, _D, _I32, _I32, _P, _P, _P, _P,
                                      _P, _P]
+        L.gw_evgw_update.argtypes = [_I32, _I32, _P, _I32, _P, _P, _P, _P]
         for f in ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma",
-                  "gw_continue_qp"):
+                  "gw_continue_qp", "gw_evgw_update"):
             getattr(L, f).restype = ctypes.c_int32
         L.gw_chi_block_features.argtypes = [_P, _P, _P, _I32, _P, _D, _P, _P]
         L.gw_chi_block_lognorms.argtypes = [_P, _P, _I32, _P, _P]
@@ -120,7 +121,7 @@ EXPORTED = ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma"
             "gw_chi_block_lognorms", "gw_mlp_param_count", "gw_mlp_forward", "gw_mlp_gradient",
             "gw_mlp_train_step", "gw_mlp_sync_half", "gw_chi_batch_create", "gw_chi_batch_execute",
             "gw_chi_batch_set_config", "gw_chi_batch_get_config", "gw_chi_batch_tune",
-            "gw_chi_batch_destroy")
+            "gw_chi_batch_destroy", "gw_evgw_update")
 
 
 def _check(code):
@@ -367,6 +368,19 @@ def contract_sigma(sys, states, C, d_occ, d_vir, d_occ0, wc, V, filter_eps=0.0, 
                                    so.ctypes.data_as(_P), sv.ctypes.data_as(_P),
                                    sx.ctypes.data_as(_P), ctypes.byref(stats), _stream(stream)))
     return so, sv, sx, {"flops": stats.flops, "ms_total": stats.ms_total}
+
+
+def evgw_update(eps0, n_occ, states, e_qp):
+    """gw_evgw_update: (energies of the next Green's function, mu_F); raises
+    GWError when an occupied level ends at or above a virtual one."""
+    e0, e0_p = _host(eps0)
+    stt, st_p = _host(states, np.int32)
+    eq, eq_p = _host(e_qp)
+    out = np.zeros(len(e0))
+    mu = ctypes.c_double(0.0)
+    _check(lib().gw_evgw_update(len(e0), int(n_occ), e0_p, len(stt), st_p, eq_p,
+                                out.ctypes.data_as(_P), ctypes.byref(mu)))
+    return out, mu.value
 
 
 def continue_qp(sig_occ, sig_vir, sig_x, eps_n, vxc_n, is_occ, mu_f, omega, cos_w, sin_w,

@@ -12,7 +12,10 @@ from . import gw
 
 def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_eps,
          spin=2.0, vxc=None, window=0.0, stream=None, events=False, chi_timing=False,
-         prec="fp64", screener=None, screen_margin=1.0):
+         prec="fp64", screener=None, screen_margin=1.0, eps_g=None, mu_g=None):
+    """The chain of library calls.  eps_g / mu_g (optional): energies and
+    energy zero of the Green's function (Eq. 2) when they differ from the
+    mean-field eps / mu_f, which the QP equation keeps (an evGW step)."""
     import torch
     st = torch.cuda.current_stream() if stream is None else stream
     ev = {}
@@ -25,9 +28,12 @@ def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_
 
     states = np.asarray(states, dtype=np.int32)
     eps = np.asarray(eps, dtype=np.float64)
+    if eps_g is None:
+        eps_g, mu_g = eps, mu_f
+    eps_g = np.asarray(eps_g, dtype=np.float64)
     mark("start")
-    d_occ, d_vir = gw.build_gt(sys, C, eps, mu_f, tau, stream=st)
-    d0, _ = gw.build_gt(sys, C, eps, mu_f, [0.0], d_vir=False, stream=st)
+    d_occ, d_vir = gw.build_gt(sys, C, eps_g, mu_g, tau, stream=st)
+    d0, _ = gw.build_gt(sys, C, eps_g, mu_g, [0.0], d_vir=False, stream=st)
     mark("gt")
     chi, chi_stats = gw.contract_chi(sys, d_occ, d_vir, filter_eps, stream=st, timing=chi_timing,
                                      prec=prec, screener=screener, screen_margin=screen_margin,
@@ -40,7 +46,7 @@ def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_
     mark("sigma")
     vxc = np.zeros(len(states)) if vxc is None else np.asarray(vxc, dtype=np.float64)
     is_occ = (states < sys.c.n_occ).astype(np.int32)
-    e_qp, status = gw.continue_qp(so, sv, sx, eps[states], vxc, is_occ, mu_f, omega, cos_w, sin_w,
+    e_qp, status = gw.continue_qp(so, sv, sx, eps[states], vxc, is_occ, mu_g, omega, cos_w, sin_w,
                                   window)
     mark("qp")
     out = dict(d_occ=d_occ, d_vir=d_vir, chi=chi, wc=wc, sig_occ=so, sig_vir=sv, sig_x=sx,
@@ -49,4 +55,36 @@ def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_
         st.synchronize()
         names = list(ev)
         out["ms"] = {names[i]: ev[names[i - 1]].elapsed_time(ev[names[i]]) for i in range(1, len(names))}
+    return out
+
+
+def evgw(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_eps, tol=1e-6,
+         max_iter=20, **kw):
+    """Eigenvalue self-consistent GW (the paper's step after Eq. 12): G0W0
+    chains whose Green's function takes the energies of gw_evgw_update (QP
+    energies of the computed states, scissor shift for the others), repeated
+    until max |e_qp change| < tol.  The grids stay those of the mean field.
+    Returns the last chain's outputs with e_qp history, step count and
+    whether it converged."""
+    eps = np.asarray(eps, dtype=np.float64)
+    states = np.asarray(states, dtype=np.int32)
+    n_occ = sys.c.n_occ
+    eps_g, mu_g = eps, mu_f
+    history, prev, out, converged = [], None, None, False
+    for _ in range(max_iter):
+        out = g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_eps,
+                   eps_g=eps_g, mu_g=mu_g, **kw)
+        e = out["e_qp"]
+        history.append(e)
+        if np.any(out["status"] != 0):
+            break
+        if prev is not None and np.abs(e - prev).max() < tol:
+            converged = True
+            break
+        try:
+            eps_g, mu_g = gw.evgw_update(eps, n_occ, states, e)
+        except gw.GWError:
+            break
+        prev = e
+    out.update(history=history, steps=len(history), converged=converged, eps_g=eps_g, mu_g=mu_g)
     return out

@@ -51,17 +51,17 @@ def test_host_validation_rejects_bad_arguments():
     rc = L.gw_chi_block_features(ctypes.byref(sys_ok), 1, 1, 1, tau1.ctypes.data_as(ctypes.c_void_p),
                                  0.0, 1, None)
     assert rc == gw.GW_ERR_ARG and b"coordinates" in L.gw_last_error()
-    # build_gt: unsorted eps and negative tau are rejected
+    # build_gt: an occupied level above mu_f, and a negative tau, are rejected
     eps = np.array([0.3, -0.1, 0.2, 0.5, 0.6, 0.7])
     tau = np.array([0.1])
     rc = L.gw_build_gt(ctypes.byref(sys_ok), 1, eps.ctypes.data_as(ctypes.c_void_p), 0.0, 1,
                        tau.ctypes.data_as(ctypes.c_void_p), 1, 1, None)
     assert rc == gw.GW_ERR_ARG
     eps.sort()
-    tau[0] = -1.0
-    rc = L.gw_build_gt(ctypes.byref(sys_ok), 1, eps.ctypes.data_as(ctypes.c_void_p), 0.0, 1,
+    tau[0] = -1.0                       # levels around mu_f = 0.4 are valid, tau is not
+    rc = L.gw_build_gt(ctypes.byref(sys_ok), 1, eps.ctypes.data_as(ctypes.c_void_p), 0.4, 1,
                        tau.ctypes.data_as(ctypes.c_void_p), 1, 1, None)
-    assert rc == gw.GW_ERR_ARG
+    assert rc == gw.GW_ERR_ARG and b"tau" in L.gw_last_error()
     # screen_w: too many tau points, non-positive spin
     cw = np.zeros(64 * 64)
     for n_tau, spin in ((40, 2.0), (4, 0.0)):
@@ -146,3 +146,35 @@ def test_continue_qp_reports_non_convergence():
     assert st[0] in (gw.GW_OK, gw.GW_ERR_NO_CONVERGE)
     with pytest.raises(gw.GWError):
         gw.continue_qp(so, so, np.zeros(1), np.zeros(1), np.zeros(1), np.array([0]), 0.0, -om, cw, sw)
+
+
+def test_evgw_update_matches_oracle():
+    """gw_evgw_update (host) against the oracle's update rule on random level
+    sets, the crossing failure and invalid arguments."""
+    from oracle import evgw as oev
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        n_mo = int(rng.integers(4, 40))
+        n_occ = int(rng.integers(1, n_mo))
+        eps0 = np.sort(rng.normal(size=n_mo))
+        eps0[n_occ:] += 3.0                       # a gap
+        k = int(rng.integers(1, min(n_mo, 8) + 1))
+        states = np.sort(rng.choice(n_mo, size=k, replace=False)).astype(np.int32)
+        e_qp = eps0[states] + 0.3 * rng.normal(size=k)
+        ref = oev.update_energies(eps0, n_occ, states, e_qp)
+        if ref is None:
+            with pytest.raises(gw.GWError):
+                gw.evgw_update(eps0, n_occ, states, e_qp)
+            continue
+        out, mu = gw.evgw_update(eps0, n_occ, states, e_qp)
+        np.testing.assert_allclose(out, ref, rtol=0, atol=1e-14)
+        assert mu == pytest.approx(0.5 * (ref[:n_occ].max() + ref[n_occ:].min()), abs=1e-14)
+    eps0 = np.array([-2.0, -1.0, 1.0, 2.0])
+    with pytest.raises(gw.GWError):            # HOMO pushed above the LUMO
+        gw.evgw_update(eps0, 2, [1, 2], [1.5, 1.2])
+    with pytest.raises(gw.GWError):            # repeated state
+        gw.evgw_update(eps0, 2, [1, 1], [-1.1, -1.2])
+    with pytest.raises(gw.GWError):            # state out of range
+        gw.evgw_update(eps0, 2, [4], [0.0])
+    with pytest.raises(gw.GWError):            # non-finite QP energy
+        gw.evgw_update(eps0, 2, [1], [float("nan")])
