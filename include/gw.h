@@ -249,6 +249,17 @@ gw_status gw_contract_sigma(const gw_system *s, int32_t n_gw, const int32_t *sta
                             const double *d_occ0, const double *wc, const double *V,
                             int32_t n_tau, double filter_eps, double *sig_occ, double *sig_vir,
                             double *sig_x, gw_sigma_stats *stats, hipStream_t stream);
+/* The same with the precision of the per-slot products (the bulk of
+ * Eq. 10-11): GW_FP64 (= gw_contract_sigma) or GW_FP32 (precision form:
+ * W^c(tau_j), V and B^n rounded to FP32, FP32 products and tile sums, the
+ * tile dots with D summed in FP64; the half transform to B^n stays FP64).
+ * ARG error for GW_BF16X3. */
+gw_status gw_contract_sigma_prec(const gw_system *s, int32_t n_gw, const int32_t *states,
+                                 const double *C, const double *d_occ, const double *d_vir,
+                                 const double *d_occ0, const double *wc, const double *V,
+                                 int32_t n_tau, double filter_eps, int32_t prec, double *sig_occ,
+                                 double *sig_vir, double *sig_x, gw_sigma_stats *stats,
+                                 hipStream_t stream);
 
 typedef struct {
   double pade_window;      /* use only nodes with w_k <= window; <= 0: all    */

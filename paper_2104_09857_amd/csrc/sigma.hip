@@ -11,6 +11,7 @@
 // product (K = Q) and the final contraction (K = P).
 #include <chrono>
 #include <cmath>
+#include <type_traits>
 
 #include "gw_internal.hpp"
 #include "tile_gemm.hpp"
@@ -95,15 +96,19 @@ struct HalfProblem {
 };
 
 // Z[n][P][nu] = sum_{k in panel q} W[Q(k)][P] * Fp[n][q][k][nu - q*PCa]
+// (operands and Z in T: double, or float in the FP32 form)
+template <class T>
 struct ZProblem {
+  using In = T;
+  using Out = T;
   struct Tile : TileBase {
     int row0, q, n, km0;
   };
   static constexpr bool kAScale = false, kDot = false;
   static constexpr int kTabA = kPanTab, kTabB = 0;
-  const double* w;          // [NRI][NRI] symmetric
-  const double* fp;
-  double* z;                // [n_gw][NRI][N]
+  const T* w;               // [NRI][NRI] symmetric
+  const T* fp;
+  T* z;                     // [n_gw][NRI][N]
   const int32_t* kmap;
   const int32_t* km_off;
   const int32_t* ulen;
@@ -124,13 +129,13 @@ struct ZProblem {
   __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
     for (int i = tid; i < t.K; i += nt) ta[i] = kmap[t.km0 + i];
   }
-  __device__ const double* abase(const Tile& t) const { return w + t.row0; }
+  __device__ const T* abase(const Tile& t) const { return w + t.row0; }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
   __device__ int64_t akoff(const Tile&, int k, const int* ta) const { return (int64_t)ta[k] * NRI; }
-  __device__ const double* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
+  __device__ const T* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
   __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PCa; }
-  __device__ double ascale(const Tile&, int) const { return 1.0; }
-  __device__ double* obase(const Tile& t) const {
+  __device__ T ascale(const Tile&, int) const { return T(1); }
+  __device__ T* obase(const Tile& t) const {
     return z + ((int64_t)t.n * NRI + t.row0) * N + (int64_t)t.q * PCa;
   }
   __device__ int64_t rowoff(const Tile&, int r) const { return (int64_t)r * N; }
@@ -143,14 +148,17 @@ struct ZProblem {
 };
 
 // sum_{nu mu} D[nu][mu] * sum_{k in panel q} Z[n][P(k)][nu] Fp[n][q][k][mu - q*PCa]
+// (Z, Fp in T; the tile products meet D and are summed in FP64)
+template <class T>
 struct DotProblem {
+  using In = T;
   struct Tile : TileBase {
     int row0, q, n, km0, tile_id;
   };
   static constexpr bool kAScale = false, kDot = true;
   static constexpr int kTabA = kPanTab, kTabB = 0;
-  const double* z;
-  const double* fp;
+  const T* z;
+  const T* fp;
   const double* d0;         // [N][N]
   const double* d1;         // [N][N]
   double* partial;          // [n_gw][n_tiles][2]
@@ -180,7 +188,7 @@ struct DotProblem {
     }
     return true;
   }
-  __device__ const double* abase(const Tile& t) const {
+  __device__ const T* abase(const Tile& t) const {
     return z + (int64_t)t.n * NRI * N + t.row0;
   }
   __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
@@ -188,9 +196,9 @@ struct DotProblem {
   }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
   __device__ int64_t akoff(const Tile&, int k, const int* ta) const { return (int64_t)ta[k] * N; }
-  __device__ const double* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
+  __device__ const T* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
   __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PCa; }
-  __device__ double ascale(const Tile&, int) const { return 1.0; }
+  __device__ T ascale(const Tile&, int) const { return T(1); }
   __device__ double* obase(const Tile&) const { return nullptr; }
   __device__ const double* dbase0(const Tile& t) const { return d0 + (int64_t)t.row0 * N + (int64_t)t.q * PCa; }
   __device__ const double* dbase1(const Tile& t) const { return d1 + (int64_t)t.row0 * N + (int64_t)t.q * PCa; }
@@ -214,6 +222,18 @@ __global__ void gather_rows_kernel(const double* __restrict__ C, const int32_t* 
   }
 }
 
+__global__ void round_f32_kernel(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+hipError_t round_f32(const double* x, float* y, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(round_f32_kernel, dim3(blocks), dim3(256), 0, st, x, y, n);
+  return hipGetLastError();
+}
+
 template <int WM>
 hipError_t launch_half(HalfProblem hp, int n_groups, hipStream_t st) {
   hp.rows_pt = 32 * WM;
@@ -228,13 +248,15 @@ hipError_t launch_half(HalfProblem hp, int n_groups, hipStream_t st) {
 
 using namespace gw;
 
-extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const int32_t* states,
-                                       const double* C, const double* d_occ, const double* d_vir,
-                                       const double* d_occ0, const double* wc, const double* V,
-                                       int32_t n_tau, double filter_eps, double* sig_occ,
-                                       double* sig_vir, double* sig_x, gw_sigma_stats* stats,
-                                       hipStream_t st) {
+extern "C" gw_status gw_contract_sigma_prec(const gw_system* s, int32_t n_gw, const int32_t* states,
+                                            const double* C, const double* d_occ, const double* d_vir,
+                                            const double* d_occ0, const double* wc, const double* V,
+                                            int32_t n_tau, double filter_eps, int32_t prec,
+                                            double* sig_occ, double* sig_vir, double* sig_x,
+                                            gw_sigma_stats* stats, hipStream_t st) {
   clear_error();
+  GW_CHECK_ARG(prec == GW_FP64 || prec == GW_FP32, "the Sigma contraction runs in FP64 or FP32");
+  const bool f32 = prec == GW_FP32;
   const auto t_start = std::chrono::steady_clock::now();
   gw_status rc = check_system(s);
   if (rc != GW_OK) return rc;
@@ -266,7 +288,8 @@ extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const i
   for (int q = 0; q < n_pan; ++q)
     GW_CHECK_ARG(NR * pan.ulen[q] <= kPanTab, "too many RI atoms coupled to one AO column panel");
 
-  double *dof, *dvf, *d0f, *cg, *fp, *z, *partial;
+  double *dof, *dvf, *d0f, *cg, *fp, *z = nullptr, *partial;
+  float *fp32 = nullptr, *z32 = nullptr, *w32 = nullptr;   // FP32 form
   int32_t* d_states;
   const size_t dsz = (size_t)n_tau * N * N;
   if ((rc = sc.alloc(&dof, dsz)) != GW_OK) return rc;
@@ -274,7 +297,13 @@ extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const i
   if ((rc = sc.alloc(&d0f, (size_t)N * N)) != GW_OK) return rc;
   if ((rc = sc.alloc(&cg, (size_t)N * n_gw)) != GW_OK) return rc;
   if ((rc = sc.alloc(&fp, (size_t)n_gw * std::max<int64_t>(FPS, 1))) != GW_OK) return rc;
-  if ((rc = sc.alloc(&z, (size_t)n_gw * NRI * N)) != GW_OK) return rc;
+  if (f32) {
+    if ((rc = sc.alloc(&fp32, (size_t)n_gw * std::max<int64_t>(FPS, 1))) != GW_OK) return rc;
+    if ((rc = sc.alloc(&z32, (size_t)n_gw * NRI * N)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&w32, (size_t)NRI * NRI)) != GW_OK) return rc;
+  } else {
+    if ((rc = sc.alloc(&z, (size_t)n_gw * NRI * N)) != GW_OK) return rc;
+  }
   const int z_rt = (NRI + 32 * Z_WM - 1) / (32 * Z_WM);
   const int y_rt = (N + 32 * Z_WM - 1) / (32 * Z_WM);
   const int n_tiles = y_rt * n_pan;
@@ -298,7 +327,8 @@ extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const i
   GW_HIP(filter_square_blocks(d_occ0, d0f, 1, na, NA, filter_eps, nullptr, st));
   GW_HIP(hipMemsetAsync(fp, 0, sizeof(double) * (size_t)n_gw * std::max<int64_t>(FPS, 1), st));
   // panels without coupled RI atoms never write their Z columns; those stay 0
-  GW_HIP(hipMemsetAsync(z, 0, sizeof(double) * (size_t)n_gw * NRI * N, st));
+  if (f32) GW_HIP(hipMemsetAsync(z32, 0, sizeof(float) * (size_t)n_gw * NRI * N, st));
+  else GW_HIP(hipMemsetAsync(z, 0, sizeof(double) * (size_t)n_gw * NRI * N, st));
   {
     const int64_t total = (int64_t)N * n_gw;
     const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
@@ -318,23 +348,41 @@ extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const i
     GW_HIP(e);
   }
 
-  ZProblem zp{};
-  zp.fp = fp; zp.z = z; zp.kmap = d_kmap; zp.km_off = d_km_off; zp.ulen = d_ulen; zp.poff = d_poff;
-  zp.n_rt = z_rt; zp.rows_pt = 32 * Z_WM; zp.NRI = NRI; zp.N = N; zp.NR = NR; zp.PCa = PCa;
-  zp.FPS = FPS;
-  DotProblem dp{};
-  dp.z = z; dp.fp = fp; dp.kmap = d_kmap; dp.km_off = d_km_off; dp.ulen = d_ulen; dp.poff = d_poff;
-  dp.n_rt = y_rt; dp.n_tiles = n_tiles; dp.rows_pt = 32 * Z_WM; dp.NRI = NRI; dp.N = N; dp.NR = NR;
-  dp.PCa = PCa; dp.FPS = FPS;
-
-  for (int j = 0; j < n_slots; ++j) {
-    const bool xslot = (j == n_tau);
-    zp.w = xslot ? V : wc + (int64_t)j * NRI * NRI;
-    GW_HIP((launch_tile_gemm<Z_WM, Z_WN, Z_NBW, 16>(zp, dim3((unsigned)(z_rt * n_pan), 1, n_gw), st)));
-    dp.d0 = xslot ? d0f : dof + (int64_t)j * N * N;
-    dp.d1 = xslot ? d0f : dvf + (int64_t)j * N * N;
-    dp.partial = partial + (size_t)j * n_gw * n_tiles * 2;
-    GW_HIP((launch_tile_gemm<Z_WM, Z_WN, Z_NBW, 16>(dp, dim3((unsigned)n_tiles, 1, n_gw), st)));
+  // per slot (tau_j, then the exchange slot with W := V, D := D^occ(0)): Z = W B^n
+  // and the dots with D^occ / D^vir, in FP64 or, in the FP32 form, with W,
+  // B^n and Z rounded to FP32 (FP32 products and tile sums, FP64 dot sums)
+  auto slots = [&](auto tag, auto* fpx, auto* zx, auto* wx) -> gw_status {
+    using T = decltype(tag);
+    ZProblem<T> zp{};
+    zp.fp = fpx; zp.z = zx; zp.kmap = d_kmap; zp.km_off = d_km_off; zp.ulen = d_ulen; zp.poff = d_poff;
+    zp.n_rt = z_rt; zp.rows_pt = 32 * Z_WM; zp.NRI = NRI; zp.N = N; zp.NR = NR; zp.PCa = PCa;
+    zp.FPS = FPS;
+    DotProblem<T> dp{};
+    dp.z = zx; dp.fp = fpx; dp.kmap = d_kmap; dp.km_off = d_km_off; dp.ulen = d_ulen; dp.poff = d_poff;
+    dp.n_rt = y_rt; dp.n_tiles = n_tiles; dp.rows_pt = 32 * Z_WM; dp.NRI = NRI; dp.N = N; dp.NR = NR;
+    dp.PCa = PCa; dp.FPS = FPS;
+    for (int j = 0; j < n_slots; ++j) {
+      const bool xslot = (j == n_tau);
+      const double* w = xslot ? V : wc + (int64_t)j * NRI * NRI;
+      if constexpr (std::is_same<T, float>::value) {
+        GW_HIP(round_f32(w, wx, (int64_t)NRI * NRI, st));
+        zp.w = wx;
+      } else {
+        zp.w = w;
+      }
+      GW_HIP((launch_tile_gemm<Z_WM, Z_WN, Z_NBW, 16>(zp, dim3((unsigned)(z_rt * n_pan), 1, n_gw), st)));
+      dp.d0 = xslot ? d0f : dof + (int64_t)j * N * N;
+      dp.d1 = xslot ? d0f : dvf + (int64_t)j * N * N;
+      dp.partial = partial + (size_t)j * n_gw * n_tiles * 2;
+      GW_HIP((launch_tile_gemm<Z_WM, Z_WN, Z_NBW, 16>(dp, dim3((unsigned)n_tiles, 1, n_gw), st)));
+    }
+    return GW_OK;
+  };
+  if (f32) {
+    GW_HIP(round_f32(fp, fp32, (int64_t)n_gw * std::max<int64_t>(FPS, 1), st));
+    if ((rc = slots(0.0f, fp32, z32, w32)) != GW_OK) return rc;
+  } else {
+    if ((rc = slots(0.0, fp, z, (double*)nullptr)) != GW_OK) return rc;
   }
 
   std::vector<double> hp((size_t)n_slots * n_gw * n_tiles * 2);
@@ -363,4 +411,14 @@ extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const i
     stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   }
   return GW_OK;
+}
+
+extern "C" gw_status gw_contract_sigma(const gw_system* s, int32_t n_gw, const int32_t* states,
+                                       const double* C, const double* d_occ, const double* d_vir,
+                                       const double* d_occ0, const double* wc, const double* V,
+                                       int32_t n_tau, double filter_eps, double* sig_occ,
+                                       double* sig_vir, double* sig_x, gw_sigma_stats* stats,
+                                       hipStream_t st) {
+  return gw_contract_sigma_prec(s, n_gw, states, C, d_occ, d_vir, d_occ0, wc, V, n_tau, filter_eps,
+                                GW_FP64, sig_occ, sig_vir, sig_x, stats, st);
 }

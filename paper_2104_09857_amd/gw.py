@@ -80,6 +80,9 @@ def lib():
         L.gw_build_gt.argtypes = [_P, _P, _P, _D, _I32, _P, _P, _P, _P]
         L.gw_contract_chi.argtypes = [_P, _P, _P, _I32, _P, _P, _P, _P]
         L.gw_screen_w.argtypes = [_P, _P, _P, _I32, _I32, _P, _P, _D, _P, _P]
+        L.gw_contract_sigma_prec.argtypes = [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _I32, _D, _I32,
+                                             _P, _P, _P, _P, _P]
+        L.gw_contract_sigma_prec.restype = ctypes.c_int32
         L.gw_contract_sigma.argtypes = [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _I32, _D, _P, _P, _P,
                                         _P, _P]
         L.gw_continue_qp.argtypes = [_I32, _P, _P, _P, _P, _P, _P, _D, _I32, _I32, _P, _P, _P, _P,
@@ -121,7 +124,7 @@ EXPORTED = ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma"
             "gw_chi_block_lognorms", "gw_mlp_param_count", "gw_mlp_forward", "gw_mlp_gradient",
             "gw_mlp_train_step", "gw_mlp_sync_half", "gw_chi_batch_create", "gw_chi_batch_execute",
             "gw_chi_batch_set_config", "gw_chi_batch_get_config", "gw_chi_batch_tune",
-            "gw_chi_batch_destroy", "gw_evgw_update")
+            "gw_chi_batch_destroy", "gw_evgw_update", "gw_contract_sigma_prec")
 
 
 def _check(code):
@@ -356,17 +359,23 @@ def screen_w(sys, chi, V, cos_w, icos_w, spin=2.0, wc=None, stream=None):
     return wc
 
 
-def contract_sigma(sys, states, C, d_occ, d_vir, d_occ0, wc, V, filter_eps=0.0, stream=None):
+def contract_sigma(sys, states, C, d_occ, d_vir, d_occ0, wc, V, filter_eps=0.0, stream=None,
+                   prec="fp64"):
+    """prec "fp64" (gw_contract_sigma) or "fp32" (gw_contract_sigma_prec)."""
     st_h, st_p = _host(states, np.int32)
     n_gw, n_tau = len(st_h), d_occ.shape[0]
     so = np.zeros((n_gw, n_tau))
     sv = np.zeros((n_gw, n_tau))
     sx = np.zeros(n_gw)
     stats = _SigmaStats()
-    _check(lib().gw_contract_sigma(sys.ref, n_gw, st_p, _dev(C), _dev(d_occ), _dev(d_vir),
-                                   _dev(d_occ0), _dev(wc), _dev(V), n_tau, float(filter_eps),
-                                   so.ctypes.data_as(_P), sv.ctypes.data_as(_P),
-                                   sx.ctypes.data_as(_P), ctypes.byref(stats), _stream(stream)))
+    args = (sys.ref, n_gw, st_p, _dev(C), _dev(d_occ), _dev(d_vir), _dev(d_occ0), _dev(wc), _dev(V),
+            n_tau, float(filter_eps))
+    outs = (so.ctypes.data_as(_P), sv.ctypes.data_as(_P), sx.ctypes.data_as(_P), ctypes.byref(stats),
+            _stream(stream))
+    if prec == "fp64":
+        _check(lib().gw_contract_sigma(*args, *outs))
+    else:
+        _check(lib().gw_contract_sigma_prec(*args, PRECISIONS[prec], *outs))
     return so, sv, sx, {"flops": stats.flops, "ms_total": stats.ms_total}
 
 

@@ -12,9 +12,13 @@ from . import gw
 
 def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_eps,
          spin=2.0, vxc=None, window=0.0, stream=None, events=False, chi_timing=False,
-         prec="fp64", screener=None, screen_margin=1.0, eps_g=None, mu_g=None):
-    """The chain of library calls.  eps_g / mu_g (optional): energies and
-    energy zero of the Green's function (Eq. 2) when they differ from the
+         prec="fp64", screener=None, screen_margin=1.0, eps_g=None, mu_g=None,
+         sigma_prec="fp64"):
+    """The chain of library calls.  prec: arithmetic of the chi contraction;
+    sigma_prec: of the Sigma products ("fp64" or "fp32"; FP64 by default: the
+    Pade continuation and Newton of the QP step lose a state here and there
+    to the last digits of an FP32 Sigma).  eps_g / mu_g (optional): energies
+    and energy zero of the Green's function (Eq. 2) when they differ from the
     mean-field eps / mu_f, which the QP equation keeps (an evGW step)."""
     import torch
     st = torch.cuda.current_stream() if stream is None else stream
@@ -42,7 +46,7 @@ def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_
     wc = gw.screen_w(sys, chi, V, cos_w, icos_w, spin, stream=st)
     mark("screen")
     so, sv, sx, sig_stats = gw.contract_sigma(sys, states, C, d_occ, d_vir, d0, wc, V, filter_eps,
-                                              stream=st)
+                                              stream=st, prec=sigma_prec)
     mark("sigma")
     vxc = np.zeros(len(states)) if vxc is None else np.asarray(vxc, dtype=np.float64)
     is_occ = (states < sys.c.n_occ).astype(np.int32)

@@ -9,6 +9,9 @@ random-walk error ~sqrt(K) 2^-24.  Together ~1e-5 of the magnitude
 contraction |chi|_abs = sum |M| |N| (the same sums with |T| and |D|); the
 bound checked is 5e-5 of its maximum, and |dE| <= 1 meV + 1e-5 |E_QP - eps|.
 
+The Sigma products have an FP32 form too (test_sigma_fp32_error_bound); the
+chains below keep them in FP64.
+
 FP32: operands and stage outputs rounded to FP32 (2^-24 relative), FP32
 products and sums: the random walk sqrt(K) 2^-24 ~ 1e-5 of |chi|_abs at
 K = 2e4 dominates; the bound checked is 1e-5 of its maximum, and
@@ -77,6 +80,29 @@ def test_chi_error_bound(case, prec):
     assert err.max() <= CHI_BOUND[prec] * absx.max()
     # and it is not the FP64 result
     assert err.max() > 0
+
+
+def test_sigma_fp32_error_bound(case):
+    """FP32 form of the Sigma products (gw_contract_sigma_prec): W^c, V and
+    B^n rounded to FP32 (2^-24), FP32 products and tile sums over
+    K = NR |U_q| <= 1e4 terms, FP64 sums of the tile dots: a few 1e-6 of the
+    largest value (bound 2e-5); the exchange term (no cancellation of
+    screened terms) 1e-6.  Same inputs as the FP64 parity test."""
+    import torch
+    from paper_2104_09857_amd import gw
+    from gpu_common import rel
+    from oracle import gt as ogt
+    inp, d, ref = case
+    s = inp.s
+    print("case", inp.w.name, flush=True)
+    d0, _ = ogt.density_matrices(inp.C, inp.eps, s.n_occ, inp.mu_f, [0.0])
+    cu = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+    so, sv, sx, _ = gw.contract_sigma(d["sys"], inp.states, d["C"], cu(ref.d_occ), cu(ref.d_vir),
+                                      cu(d0[0]), cu(ref.wc_tau), d["V"], s.filter_eps, prec="fp32")
+    e = (rel(so, ref.sig_occ), rel(sv, ref.sig_vir), rel(sx, ref.sig_x))
+    print("case", inp.w.name, "rel err occ / vir / x", e, flush=True)
+    assert e[0] < 2e-5 and e[1] < 2e-5 and e[2] < 1e-6
+    assert e[2] > 0          # and it is not the FP64 result
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
