@@ -32,6 +32,7 @@ from . import philox
 STREAM_H = 1
 STREAM_H_DIAG = 2
 STREAM_T = 3
+STREAM_SPIN = 4
 SPACING = 2.5          # bohr
 STRIP_WIDTH = 7
 
@@ -124,6 +125,18 @@ class System:
         """(C [n_mo][n_ao] row per MO, eps ascending) from eigh(H)."""
         w, v = np.linalg.eigh(self.hamiltonian())
         return np.ascontiguousarray(v.T), w
+
+    def mean_field_spin(self, delta: float):
+        """Spin-polarized mean field: H_up/dn = H +/- delta * diag(z), z a
+        normal draw per AO function (stream STREAM_SPIN); returns
+        ((C_up, eps_up), (C_dn, eps_dn)).  delta = 0 gives the closed shell."""
+        h = self.hamiltonian()
+        z = philox.normal(self.seed, stream_id(STREAM_SPIN, self.sys_id), np.arange(self.n_ao))
+        out = []
+        for sgn in (1.0, -1.0):
+            w, v = np.linalg.eigh(h + sgn * delta * np.diag(z))
+            out.append((np.ascontiguousarray(v.T), w))
+        return tuple(out)
 
     # ---- V
     def coulomb(self) -> np.ndarray:

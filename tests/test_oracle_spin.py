@@ -1,0 +1,63 @@
+"""The open-shell oracle (oracle/spin.py) against fixed points that do not
+come from it: the closed-shell limit (equal channels, spin factor 2 of the
+pinned closed-shell chain), the exchange of the channels, and each channel's
+chi(tau) against its MO closed form (Eq. 3 summed over occupied-virtual pairs
+of that channel).  Input: the 12-atom chain with a spin-dependent potential
+of 0.05 Ha per AO (gwinputs System.mean_field_spin)."""
+import numpy as np
+import pytest
+
+from conftest import get_inputs
+from oracle import chain as ochain, chi as ochi, spin as ospin
+
+DELTA = 0.05
+
+
+@pytest.fixture(scope="module")
+def spin_inputs():
+    inp = get_inputs("chain12")
+    up, dn = inp.s.mean_field_spin(DELTA)
+    return inp, up, dn
+
+
+def _run(inp, up, dn, n_up, n_dn, st_up, st_dn):
+    s = inp.s
+    return ospin.g0w0_spin((up[0], up[1], n_up), (dn[0], dn[1], n_dn), inp.t3c, inp.V, s.ao_off,
+                           s.ri_off, inp.grids, st_up, st_dn, s.filter_eps)
+
+
+def test_closed_shell_limit(spin_inputs):
+    inp, _, _ = spin_inputs
+    s = inp.s
+    r = _run(inp, (inp.C, inp.eps), (inp.C, inp.eps), s.n_occ, s.n_occ, inp.states, inp.states)
+    ref = ochain.g0w0(inp.C, inp.eps, s.n_occ, inp.t3c, inp.V, s.ao_off, s.ri_off, inp.grids,
+                      inp.states, s.filter_eps)
+    np.testing.assert_allclose(r.chi_up + r.chi_dn, 2.0 * ref.chi_tau, rtol=0,
+                               atol=1e-12 * np.abs(ref.chi_tau).max())
+    np.testing.assert_allclose(r.wc_tau, ref.wc_tau, rtol=0, atol=1e-10 * np.abs(ref.wc_tau).max())
+    for e in r.e_qp:
+        np.testing.assert_allclose(e, ref.e_qp, rtol=0, atol=1e-9)
+
+
+def test_channel_exchange_and_mo_form(spin_inputs):
+    inp, up, dn = spin_inputs
+    s = inp.s
+    n_up, n_dn = s.n_occ + 1, s.n_occ - 1
+    st_up = np.array([n_up - 1, n_up])
+    st_dn = np.array([n_dn - 1, n_dn])
+    a = _run(inp, up, dn, n_up, n_dn, st_up, st_dn)
+    b = _run(inp, dn, up, n_dn, n_up, st_dn, st_up)
+    np.testing.assert_allclose(a.chi_up, b.chi_dn, rtol=0, atol=0)
+    np.testing.assert_allclose(a.wc_tau, b.wc_tau, rtol=0, atol=1e-12 * np.abs(a.wc_tau).max())
+    np.testing.assert_allclose(a.e_qp[0], b.e_qp[1], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(a.e_qp[1], b.e_qp[0], rtol=0, atol=1e-9)
+    assert np.all(a.status[0] == 0) and np.all(a.status[1] == 0)
+    # each channel's chi(tau) is its MO closed form
+    for chi, (C, eps), n_occ in ((a.chi_up, up, n_up), (a.chi_dn, dn, n_dn)):
+        iap = ochi.mo_integrals(C, inp.t3c, n_occ).reshape(-1, s.n_ri)
+        delta = (eps[None, n_occ:] - eps[:n_occ, None]).ravel()
+        for j, tau in enumerate(inp.grids.tau):
+            ref = -(iap * np.exp(-delta * tau)[:, None]).T @ iap
+            assert np.abs(chi[j] - ref).max() <= 1e-11 * np.abs(ref).max()
+    # the two channels differ (the potential splits them)
+    assert np.abs(a.e_qp[0] - b.e_qp[0]).max() > 1e-6
