@@ -126,15 +126,17 @@ class System:
         w, v = np.linalg.eigh(self.hamiltonian())
         return np.ascontiguousarray(v.T), w
 
-    def mean_field_spin(self, delta: float):
-        """Spin-polarized mean field: H_up/dn = H +/- delta * diag(z), z a
-        normal draw per AO function (stream STREAM_SPIN); returns
-        ((C_up, eps_up), (C_dn, eps_dn)).  delta = 0 gives the closed shell."""
+    def mean_field_spin(self, delta: float, zeeman: float = 0.0):
+        """Spin-polarized mean field: H_up/dn = H +/- (delta * diag(z) - zeeman),
+        z a normal draw per AO function (stream STREAM_SPIN): delta splits the
+        orbitals of the channels, zeeman shifts the up levels down and the
+        down levels up uniformly.  Returns ((C_up, eps_up), (C_dn, eps_dn));
+        delta = zeeman = 0 gives the closed shell."""
         h = self.hamiltonian()
         z = philox.normal(self.seed, stream_id(STREAM_SPIN, self.sys_id), np.arange(self.n_ao))
         out = []
         for sgn in (1.0, -1.0):
-            w, v = np.linalg.eigh(h + sgn * delta * np.diag(z))
+            w, v = np.linalg.eigh(h + sgn * (delta * np.diag(z) - zeeman * np.eye(self.n_ao)))
             out.append((np.ascontiguousarray(v.T), w))
         return tuple(out)
 

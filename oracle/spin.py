@@ -39,8 +39,13 @@ class SpinChain:
 
 
 def mu_common(eps_up, n_up, eps_dn, n_dn):
+    """Midpoint of the highest occupied and lowest virtual level of both
+    channels; the occupied levels of both must lie below the virtual levels
+    of both, else the Green's function of Eq. 2 grows with tau."""
     homo = max(np.max(eps_up[:n_up]), np.max(eps_dn[:n_dn]))
     lumo = min(np.min(eps_up[n_up:]), np.min(eps_dn[n_dn:]))
+    if not homo < lumo:
+        raise ValueError("an occupied level of one channel lies above a virtual level")
     return 0.5 * (homo + lumo)
 
 

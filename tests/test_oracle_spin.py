@@ -3,7 +3,9 @@ come from it: the closed-shell limit (equal channels, spin factor 2 of the
 pinned closed-shell chain), the exchange of the channels, and each channel's
 chi(tau) against its MO closed form (Eq. 3 summed over occupied-virtual pairs
 of that channel).  Input: the 12-atom chain with a spin-dependent potential
-of 0.05 Ha per AO (gwinputs System.mean_field_spin)."""
+of 0.05 Ha per AO (gwinputs System.mean_field_spin): equal occupations (the
+broken-symmetry singlet the paper runs its ribbons as) and, with a uniform
+0.09 Ha Zeeman split, one electron moved from the down to the up channel."""
 import numpy as np
 import pytest
 
@@ -11,13 +13,13 @@ from conftest import get_inputs
 from oracle import chain as ochain, chi as ochi, spin as ospin
 
 DELTA = 0.05
+ZEEMAN = 0.09
+CASES = {"singlet": (0.0, 0), "triplet": (ZEEMAN, 1)}
 
 
 @pytest.fixture(scope="module")
-def spin_inputs():
-    inp = get_inputs("chain12")
-    up, dn = inp.s.mean_field_spin(DELTA)
-    return inp, up, dn
+def chain():
+    return get_inputs("chain12")
 
 
 def _run(inp, up, dn, n_up, n_dn, st_up, st_dn):
@@ -26,8 +28,8 @@ def _run(inp, up, dn, n_up, n_dn, st_up, st_dn):
                            s.ri_off, inp.grids, st_up, st_dn, s.filter_eps)
 
 
-def test_closed_shell_limit(spin_inputs):
-    inp, _, _ = spin_inputs
+def test_closed_shell_limit(chain):
+    inp = chain
     s = inp.s
     r = _run(inp, (inp.C, inp.eps), (inp.C, inp.eps), s.n_occ, s.n_occ, inp.states, inp.states)
     ref = ochain.g0w0(inp.C, inp.eps, s.n_occ, inp.t3c, inp.V, s.ao_off, s.ri_off, inp.grids,
@@ -39,10 +41,23 @@ def test_closed_shell_limit(spin_inputs):
         np.testing.assert_allclose(e, ref.e_qp, rtol=0, atol=1e-9)
 
 
-def test_channel_exchange_and_mo_form(spin_inputs):
-    inp, up, dn = spin_inputs
+def test_occupation_check(chain):
+    """Without the Zeeman split the moved electron sits above the down
+    channel's lowest virtual level: no common Fermi level exists."""
+    inp = chain
     s = inp.s
-    n_up, n_dn = s.n_occ + 1, s.n_occ - 1
+    up, dn = s.mean_field_spin(DELTA)
+    with pytest.raises(ValueError):
+        _run(inp, up, dn, s.n_occ + 1, s.n_occ - 1, [s.n_occ], [s.n_occ - 1])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_channel_exchange_and_mo_form(chain, name):
+    inp = chain
+    s = inp.s
+    zeeman, moved = CASES[name]
+    up, dn = s.mean_field_spin(DELTA, zeeman)
+    n_up, n_dn = s.n_occ + moved, s.n_occ - moved
     st_up = np.array([n_up - 1, n_up])
     st_dn = np.array([n_dn - 1, n_dn])
     a = _run(inp, up, dn, n_up, n_dn, st_up, st_dn)
