@@ -229,6 +229,18 @@ gw_status gw_chi_batch_destroy(gw_chi_batch *plan);
 gw_status gw_screen_w(const gw_system *s, const double *chi, const double *V, int32_t n_tau,
                       int32_t n_w, const double *cos_w, const double *icos_w, double spin,
                       double *wc, hipStream_t stream);
+/* Open-shell (spin-polarized) screening: gw_screen_w with chi = chi_up +
+ * chi_dn and spin factor 1.  chi_up, chi_dn: dev [n_tau][n_ri][n_ri], the
+ * per-channel polarizabilities of gw_contract_chi (two systems sharing the
+ * bricks, each with its channel's n_occ, the Green's functions built with one
+ * common mu_F); read only, caller-owned.  The sum is taken inside the cosine
+ * transform; nothing else differs from gw_screen_w (same workspace, errors
+ * and stream semantics), plus GW_ERR_ARG for a null chi_up or chi_dn.  The
+ * paper writes Eqs. 5-9 for a closed shell and runs its nanoribbons as
+ * open-shell singlets (computational details): two channels, one W. */
+gw_status gw_screen_w_spins(const gw_system *s, const double *chi_up, const double *chi_dn,
+                            const double *V, int32_t n_tau, int32_t n_w, const double *cos_w,
+                            const double *icos_w, double *wc, hipStream_t stream);
 
 typedef struct {
   double flops;            /* algorithmic flops of the self-energy products   */

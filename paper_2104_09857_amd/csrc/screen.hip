@@ -23,9 +23,10 @@ namespace {
 constexpr int kMaxStack = 32;
 
 // out[k][e] = sum_j coef[k][j] in[j][e] for a stack of n_in matrices of n2 elements
-__global__ void stack_transform_kernel(const double* __restrict__ in, double* __restrict__ out,
-                                       const double* __restrict__ coef, int n_in, int n_out,
-                                       int64_t n2) {
+// out[k] = sum_j coef[k][j] (in[j] + in2[j]) (in2 may be null)
+__global__ void stack_transform_kernel(const double* __restrict__ in, const double* __restrict__ in2,
+                                       double* __restrict__ out, const double* __restrict__ coef,
+                                       int n_in, int n_out, int64_t n2) {
   extern __shared__ double cs[];
   for (int i = threadIdx.x; i < n_in * n_out; i += blockDim.x) cs[i] = coef[i];
   __syncthreads();
@@ -33,7 +34,8 @@ __global__ void stack_transform_kernel(const double* __restrict__ in, double* __
        e += (int64_t)gridDim.x * blockDim.x) {
     double v[kMaxStack];
 #pragma unroll
-    for (int j = 0; j < kMaxStack; ++j) v[j] = j < n_in ? in[(int64_t)j * n2 + e] : 0.0;
+    for (int j = 0; j < kMaxStack; ++j)
+      v[j] = j < n_in ? in[(int64_t)j * n2 + e] + (in2 ? in2[(int64_t)j * n2 + e] : 0.0) : 0.0;
     for (int k = 0; k < n_out; ++k) {
       double s = 0.0;
 #pragma unroll
@@ -54,11 +56,11 @@ __global__ void one_minus_kernel(const double* __restrict__ a, double* __restric
   }
 }
 
-hipError_t stack_transform(const double* in, double* out, const double* coef_dev, int n_in,
-                           int n_out, int64_t n2, hipStream_t st) {
+hipError_t stack_transform(const double* in, const double* in2, double* out, const double* coef_dev,
+                           int n_in, int n_out, int64_t n2, hipStream_t st) {
   const unsigned blocks = (unsigned)std::min<int64_t>((n2 + 255) / 256, 16384);
   hipLaunchKernelGGL(stack_transform_kernel, dim3(blocks), dim3(256),
-                     sizeof(double) * n_in * n_out, st, in, out, coef_dev, n_in, n_out, n2);
+                     sizeof(double) * n_in * n_out, st, in, in2, out, coef_dev, n_in, n_out, n2);
   return hipGetLastError();
 }
 
@@ -102,10 +104,11 @@ gw_status get_handle(hipStream_t st, rocblas_handle* h) {
 
 using namespace gw;
 
-extern "C" gw_status gw_screen_w(const gw_system* s, const double* chi, const double* V,
-                                 int32_t n_tau, int32_t n_w, const double* cos_w,
-                                 const double* icos_w, double spin, double* wc, hipStream_t st) {
-  clear_error();
+namespace {
+// W^c from chi + chi2 (chi2 may be null), spin factor `spin` (Eqs. 5-9)
+gw_status screen_impl(const gw_system* s, const double* chi, const double* chi2, const double* V,
+                      int32_t n_tau, int32_t n_w, const double* cos_w, const double* icos_w,
+                      double spin, double* wc, hipStream_t st) {
   GW_CHECK_ARG(s != nullptr && s->n_atoms > 0 && s->ri_per_atom > 0, "bad system");
   const int64_t n64 = (int64_t)s->n_atoms * s->ri_per_atom;
   GW_CHECK_ARG(n64 < 46341, "n_ri too large for 32-bit BLAS indexing");
@@ -145,7 +148,7 @@ extern "C" gw_status gw_screen_w(const gw_system* s, const double* chi, const do
   GW_BLAS(rocsolver_dpotrf(h, rocblas_fill_lower, n, L, n, info + n_w));
 
   // chi(i w_k) for all k
-  GW_HIP(stack_transform(chi, S, coef, n_tau, n_w, n2, st));
+  GW_HIP(stack_transform(chi, chi2, S, coef, n_tau, n_w, n2, st));
   const double one = 1.0;
   const unsigned eb = (unsigned)std::min<int64_t>((n2 + 255) / 256, 16384);
   for (int k = 0; k < n_w; ++k) {
@@ -168,7 +171,7 @@ extern "C" gw_status gw_screen_w(const gw_system* s, const double* chi, const do
                           rocblas_diagonal_non_unit, n, n, &one, L, n, T1, n, X, n));
   }
   // W^c(tau_j)
-  GW_HIP(stack_transform(S, wc, coef + (size_t)n_w * n_tau, n_w, n_tau, n2, st));
+  GW_HIP(stack_transform(S, nullptr, wc, coef + (size_t)n_w * n_tau, n_w, n_tau, n2, st));
 
   std::vector<rocblas_int> hinfo(n_w + 1);
   GW_HIP(hipMemcpyAsync(hinfo.data(), info, sizeof(rocblas_int) * (n_w + 1), hipMemcpyDeviceToHost, st));
@@ -184,4 +187,21 @@ extern "C" gw_status gw_screen_w(const gw_system* s, const double* chi, const do
       return GW_ERR_NOT_SPD;
     }
   return GW_OK;
+}
+}  // namespace
+
+extern "C" gw_status gw_screen_w(const gw_system* s, const double* chi, const double* V,
+                                 int32_t n_tau, int32_t n_w, const double* cos_w,
+                                 const double* icos_w, double spin, double* wc, hipStream_t st) {
+  clear_error();
+  return screen_impl(s, chi, nullptr, V, n_tau, n_w, cos_w, icos_w, spin, wc, st);
+}
+
+extern "C" gw_status gw_screen_w_spins(const gw_system* s, const double* chi_up,
+                                       const double* chi_dn, const double* V, int32_t n_tau,
+                                       int32_t n_w, const double* cos_w, const double* icos_w,
+                                       double* wc, hipStream_t st) {
+  clear_error();
+  GW_CHECK_ARG(chi_up && chi_dn, "null pointer argument");
+  return screen_impl(s, chi_up, chi_dn, V, n_tau, n_w, cos_w, icos_w, 1.0, wc, st);
 }

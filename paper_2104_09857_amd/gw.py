@@ -88,6 +88,8 @@ def lib():
         L.gw_continue_qp.argtypes = [_I32, _P, _P, _P, _P, _P, _P, _D, _I32, _I32, _P, _P, _P, _P,
                                      _P, _P]
         L.gw_evgw_update.argtypes = [_I32, _I32, _P, _I32, _P, _P, _P, _P]
+        L.gw_screen_w_spins.argtypes = [_P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P]
+        L.gw_screen_w_spins.restype = ctypes.c_int32
         for f in ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma",
                   "gw_continue_qp", "gw_evgw_update"):
             getattr(L, f).restype = ctypes.c_int32
@@ -124,7 +126,7 @@ EXPORTED = ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma"
             "gw_chi_block_lognorms", "gw_mlp_param_count", "gw_mlp_forward", "gw_mlp_gradient",
             "gw_mlp_train_step", "gw_mlp_sync_half", "gw_chi_batch_create", "gw_chi_batch_execute",
             "gw_chi_batch_set_config", "gw_chi_batch_get_config", "gw_chi_batch_tune",
-            "gw_chi_batch_destroy", "gw_evgw_update", "gw_contract_sigma_prec")
+            "gw_chi_batch_destroy", "gw_evgw_update", "gw_contract_sigma_prec", "gw_screen_w_spins")
 
 
 def _check(code):
@@ -356,6 +358,21 @@ def screen_w(sys, chi, V, cos_w, icos_w, spin=2.0, wc=None, stream=None):
         wc = torch.empty_like(chi)
     _check(lib().gw_screen_w(sys.ref, _dev(chi), _dev(V), n_tau, n_w, cw_p, iw_p, float(spin),
                              _dev(wc), _stream(stream)))
+    return wc
+
+
+def screen_w_spins(sys, chi_up, chi_dn, V, cos_w, icos_w, wc=None, stream=None):
+    """gw_screen_w_spins: W^c from chi_up + chi_dn (open shell, spin factor 1)."""
+    import torch
+    cw, cw_p = _host(cos_w)
+    iw, iw_p = _host(icos_w)
+    n_w, n_tau = cw.shape
+    if chi_up.shape != chi_dn.shape:
+        raise ValueError("chi_up and chi_dn must have the same shape")
+    if wc is None:
+        wc = torch.empty_like(chi_up)
+    _check(lib().gw_screen_w_spins(sys.ref, _dev(chi_up), _dev(chi_dn), _dev(V), n_tau, n_w, cw_p,
+                                   iw_p, _dev(wc), _stream(stream)))
     return wc
 
 

@@ -92,3 +92,43 @@ def evgw(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_
         prev = e
     out.update(history=history, steps=len(history), converged=converged, eps_g=eps_g, mu_g=mu_g)
     return out
+
+
+def g0w0_spin(sys_up, sys_dn, C_up, C_dn, eps_up, eps_dn, V, tau, omega, cos_w, sin_w, icos_w,
+              states_up, states_dn, filter_eps, vxc_up=None, vxc_dn=None, window=0.0, stream=None,
+              prec="fp64", sigma_prec="fp64"):
+    """Open-shell G0W0: one Green's function and chi per spin channel (sys_up
+    and sys_dn share the bricks and differ in n_occ), W from chi_up + chi_dn
+    with spin factor 1 (gw_screen_w_spins), Sigma and the QP equation per
+    channel.  The energy zero is the midpoint of the highest occupied and the
+    lowest virtual level over both channels.  Returns per-channel outputs
+    and the common mu_F."""
+    import torch
+    st = torch.cuda.current_stream() if stream is None else stream
+    chans = ((sys_up, C_up, np.asarray(eps_up, dtype=np.float64), states_up, vxc_up),
+             (sys_dn, C_dn, np.asarray(eps_dn, dtype=np.float64), states_dn, vxc_dn))
+    homo = max(e[:s.c.n_occ].max() for s, _, e, _, _ in chans)
+    lumo = min(e[s.c.n_occ:].min() for s, _, e, _, _ in chans)
+    if not homo < lumo:
+        raise ValueError("an occupied level of one channel lies above a virtual level")
+    mu_f = 0.5 * (homo + lumo)
+    ds, chis = [], []
+    for sysc, C, eps, _, _ in chans:
+        d_occ, d_vir = gw.build_gt(sysc, C, eps, mu_f, tau, stream=st)
+        d0, _ = gw.build_gt(sysc, C, eps, mu_f, [0.0], d_vir=False, stream=st)
+        chi, _ = gw.contract_chi(sysc, d_occ, d_vir, filter_eps, stream=st, prec=prec)
+        ds.append((d_occ, d_vir, d0))
+        chis.append(chi)
+    wc = gw.screen_w_spins(sys_up, chis[0], chis[1], V, cos_w, icos_w, stream=st)
+    out = dict(chi_up=chis[0], chi_dn=chis[1], wc=wc, mu_f=mu_f)
+    for tag, (sysc, C, eps, states, vxc), (d_occ, d_vir, d0) in zip(("up", "dn"), chans, ds):
+        states = np.asarray(states, dtype=np.int32)
+        so, sv, sx, _ = gw.contract_sigma(sysc, states, C, d_occ, d_vir, d0, wc, V, filter_eps,
+                                          stream=st, prec=sigma_prec)
+        vxc = np.zeros(len(states)) if vxc is None else np.asarray(vxc, dtype=np.float64)
+        is_occ = (states < sysc.c.n_occ).astype(np.int32)
+        e_qp, status = gw.continue_qp(so, sv, sx, eps[states], vxc, is_occ, mu_f, omega, cos_w,
+                                      sin_w, window)
+        out["e_qp_" + tag] = e_qp
+        out["status_" + tag] = status
+    return out
