@@ -15,6 +15,12 @@ Sigma for HOMO-4 .. LUMO+4.  Inputs are seeded and synthetic (gwinputs).
 --evgw SCALE times eigenvalue self-consistent GW on the workload instead,
 its three-center tensor scaled by SCALE (e.g. --workload strip84 --evgw 0.02).
 
+--open-shell DELTA times open-shell G0W0 instead: two spin channels of the
+workload's mean field split by a spin-dependent potential of DELTA Ha per AO
+(equal occupations, the broken-symmetry singlet), one chi per channel and one
+W, next to the closed-shell chain on the same inputs (--t3c-scale scales the
+three-center tensor, e.g. 0.02 for eV-sized shifts).
+
 Workload ribbon<N> (e.g. ribbon1734, 5 AO / 12 RI per atom, filter 1e-8)
 measures the learned block screener: the network is trained on the GPU on
 exact runs of ribbon300 and ribbon600, its safety band calibrated on
@@ -163,6 +169,63 @@ def bench_evgw(args):
                  "gap_eV_evgw": float((hist[-1][lumo] - hist[-1][homo]) * ha_ev),
                  "max_change_meV_per_step": [float(np.abs(hist[i] - hist[i - 1]).max() * ha_ev * 1e3)
                                              for i in range(1, len(hist))]},
+    }
+    print(json.dumps(res), flush=True)
+
+
+def bench_open_shell(args):
+    """Open-shell G0W0 (see the module docstring): time-to-QP per step of
+    pipeline.g0w0_spin after one untimed chain, and of one closed-shell chain
+    on the same inputs."""
+    import torch
+    from paper_2104_09857_amd import gw, pipeline
+    ctx = setup(args.workload)
+    ctx["t3c"].mul_(args.t3c_scale)
+    g, s, states = ctx["g"], ctx["s"], ctx["w"].states()
+    up, dn = s.mean_field_spin(args.open_shell)
+    cu = torch.as_tensor(up[0], device="cuda")
+    cd = torch.as_tensor(dn[0], device="cuda")
+    sys_dn = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, ctx["trip"], ctx["t3c"], s.xyz)
+    torch.cuda.synchronize()
+
+    def spin_step():
+        return pipeline.g0w0_spin(ctx["sys"], sys_dn, cu, cd, up[1], dn[1], ctx["V"], g.tau, g.omega,
+                                  g.cos_w, g.sin_w, g.icos_w, states, states, s.filter_eps,
+                                  prec=args.prec)
+
+    t0 = time.perf_counter()
+    spin_step()
+    torch.cuda.synchronize()
+    log(f"[open-shell] warm-up {time.perf_counter() - t0:.1f} s")
+    walls = []
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        out = spin_step()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        log(f"[open-shell] step {i} {walls[-1]:.2f} s")
+    t0 = time.perf_counter()
+    closed = step(ctx, args.prec)
+    torch.cuda.synchronize()
+    closed_s = time.perf_counter() - t0
+    log(f"[open-shell] closed-shell chain {closed_s:.2f} s")
+    ha_ev = 27.211386245988
+    wall = float(np.mean(walls))
+    res = {
+        "metric": METRIC, "value": wall, "unit": "s (open-shell G0W0 time-to-QP)", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": wall * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "paper_context": PAPER_CONTEXT, "dtype": DTYPE[args.prec], "data": "synthetic",
+        "config": {"workload": args.workload, "n_atoms": s.n_atoms, "n_ao": s.n_ao, "n_ri": s.n_ri,
+                   "filter_eps": s.filter_eps, "n_tau": ctx["w"].n_tau, "spin_delta": args.open_shell,
+                   "t3c_scale": args.t3c_scale},
+        "open_shell": {
+            "closed_shell_s": closed_s, "ratio_to_closed_shell": wall / closed_s,
+            "status_ok": bool(np.all(out["status_up"] == 0) and np.all(out["status_dn"] == 0)),
+            "shift_eV_up": [round(float(x), 4) for x in (out["e_qp_up"] - up[1][states]) * ha_ev],
+            "shift_eV_dn": [round(float(x), 4) for x in (out["e_qp_dn"] - dn[1][states]) * ha_ev],
+            "shift_eV_closed": [round(float(x), 4)
+                                for x in (closed["e_qp"] - ctx["eps"][states]) * ha_ev]},
     }
     print(json.dumps(res), flush=True)
 
@@ -493,6 +556,10 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotune cache file of the batched form")
     ap.add_argument("--evgw", type=float, default=None, metavar="SCALE",
                     help="time evGW instead, the three-center tensor scaled by SCALE")
+    ap.add_argument("--open-shell", type=float, default=None, metavar="DELTA",
+                    help="time open-shell G0W0 instead, channels split by DELTA Ha per AO")
+    ap.add_argument("--t3c-scale", type=float, default=1.0,
+                    help="scale of the three-center tensor in the --open-shell mode")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -508,6 +575,9 @@ def main():
         return
     if args.evgw is not None:
         bench_evgw(args)
+        return
+    if args.open_shell is not None:
+        bench_open_shell(args)
         return
     ctx = setup(args.workload)
     for i in range(args.warmup):
