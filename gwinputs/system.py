@@ -140,6 +140,39 @@ class System:
             out.append((np.ascontiguousarray(v.T), w))
         return tuple(out)
 
+    # ---- non-orthogonal bases
+    def gaussian_metric(self, n_per_atom: int, atom_of: np.ndarray, ov_max: float = 0.4,
+                        ov_min: float = 0.05) -> np.ndarray:
+        """Overlap matrix of normalized s-type Gaussians, n_per_atom of them on
+        every atom: function p of an atom has exponent alpha_p, geometric from
+        the value whose overlap with its copy on a neighbour at SPACING is
+        ov_max down to the value where it is ov_min.  Functions of different
+        p are taken as orthogonal (as components of different angular
+        momentum would be on one centre), so
+        S[(a, p), (b, q)] = delta_pq exp(-alpha_p d_ab^2 / 2):
+        symmetric positive definite (a Gaussian kernel per p), unit diagonal."""
+        lo, hi = -2.0 * np.log(ov_max) / SPACING ** 2, -2.0 * np.log(ov_min) / SPACING ** 2
+        alpha = lo * (hi / lo) ** (np.arange(n_per_atom) / max(n_per_atom - 1, 1))
+        p = np.tile(np.arange(n_per_atom), self.n_atoms)
+        d = self.dist[atom_of[:, None], atom_of[None, :]]
+        return np.where(p[:, None] == p[None, :], np.exp(-0.5 * alpha[p][:, None] * d * d), 0.0)
+
+    def ri_metric(self) -> np.ndarray:
+        """RI overlap S_PQ (Eq. 5): the Gaussian metric over the RI functions."""
+        return self.gaussian_metric(self.n_ri_atom, self.ri_atom)
+
+    def ao_metric(self) -> np.ndarray:
+        """AO overlap: the Gaussian metric over the AO functions."""
+        return self.gaussian_metric(self.n_ao_atom, self.ao_atom, ov_max=0.3)
+
+    def mean_field_nonorth(self, s_ao: np.ndarray):
+        """(C, eps) of H C = S C eps in the non-orthogonal AO basis of overlap
+        s_ao: rows of C are the MOs, C s_ao C^T = 1."""
+        lc = np.linalg.cholesky(s_ao)
+        linv = np.linalg.inv(lc)
+        w, v = np.linalg.eigh(linv @ self.hamiltonian() @ linv.T)
+        return np.ascontiguousarray((linv.T @ v).T), w
+
     # ---- V
     def coulomb(self) -> np.ndarray:
         d = self.dist[self.ri_atom[:, None], self.ri_atom[None, :]]
