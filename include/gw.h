@@ -241,6 +241,21 @@ gw_status gw_screen_w(const gw_system *s, const double *chi, const double *V, in
 gw_status gw_screen_w_spins(const gw_system *s, const double *chi_up, const double *chi_dn,
                             const double *V, int32_t n_tau, int32_t n_w, const double *cos_w,
                             const double *icos_w, double *wc, hipStream_t stream);
+/* Screening with a non-orthogonal RI basis (Eq. 5 and the definitions after
+ * Eqs. 10 and 11): with the RI overlap S_PQ the dielectric function takes
+ * chi~ = S^-1 chi S^-1, and the self-energies take W~^c = S^-1 W^c S^-1 and
+ * V~ = S^-1 V S^-1.  S_ri: dev [n_ri][n_ri], symmetric positive definite,
+ * read only, caller-owned.  wc_tilde: dev [n_tau][n_ri][n_ri], overwritten
+ * with W~^c(tau_j), to be passed to gw_contract_sigma as its wc; v_tilde: dev
+ * [n_ri][n_ri] or NULL, overwritten with V~, to be passed to
+ * gw_contract_sigma as its V.  Other arguments, workspace and stream
+ * semantics as gw_screen_w; no output may alias an input.  Errors as
+ * gw_screen_w, plus GW_ERR_ARG for a null S_ri and GW_ERR_NOT_SPD when S is
+ * not positive definite.  S_ri = 1 gives gw_screen_w's W^c (and V~ = V). */
+gw_status gw_screen_w_metric(const gw_system *s, const double *chi, const double *V,
+                             const double *S_ri, int32_t n_tau, int32_t n_w, const double *cos_w,
+                             const double *icos_w, double spin, double *wc_tilde,
+                             double *v_tilde, hipStream_t stream);
 
 typedef struct {
   double flops;            /* algorithmic flops of the self-energy products   */

@@ -13,13 +13,16 @@ from . import gw
 def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_eps,
          spin=2.0, vxc=None, window=0.0, stream=None, events=False, chi_timing=False,
          prec="fp64", screener=None, screen_margin=1.0, eps_g=None, mu_g=None,
-         sigma_prec="fp64"):
+         sigma_prec="fp64", S_ri=None):
     """The chain of library calls.  prec: arithmetic of the chi contraction;
     sigma_prec: of the Sigma products ("fp64" or "fp32"; FP64 by default: the
     Pade continuation and Newton of the QP step lose a state here and there
     to the last digits of an FP32 Sigma).  eps_g / mu_g (optional): energies
     and energy zero of the Green's function (Eq. 2) when they differ from the
-    mean-field eps / mu_f, which the QP equation keeps (an evGW step)."""
+    mean-field eps / mu_f, which the QP equation keeps (an evGW step).  S_ri
+    (optional, device [n_ri][n_ri]): RI overlap metric (Eq. 5); the
+    self-energies then take W~^c and V~ (gw_screen_w_metric).  C may belong
+    to a non-orthogonal AO basis (C S_ao C^T = 1) with no other change."""
     import torch
     st = torch.cuda.current_stream() if stream is None else stream
     ev = {}
@@ -43,10 +46,13 @@ def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_
                                      prec=prec, screener=screener, screen_margin=screen_margin,
                                      tau=tau)
     mark("chi")
-    wc = gw.screen_w(sys, chi, V, cos_w, icos_w, spin, stream=st)
+    if S_ri is None:
+        wc, v_sig = gw.screen_w(sys, chi, V, cos_w, icos_w, spin, stream=st), V
+    else:
+        wc, v_sig = gw.screen_w_metric(sys, chi, V, S_ri, cos_w, icos_w, spin, stream=st)
     mark("screen")
-    so, sv, sx, sig_stats = gw.contract_sigma(sys, states, C, d_occ, d_vir, d0, wc, V, filter_eps,
-                                              stream=st, prec=sigma_prec)
+    so, sv, sx, sig_stats = gw.contract_sigma(sys, states, C, d_occ, d_vir, d0, wc, v_sig,
+                                              filter_eps, stream=st, prec=sigma_prec)
     mark("sigma")
     vxc = np.zeros(len(states)) if vxc is None else np.asarray(vxc, dtype=np.float64)
     is_occ = (states < sys.c.n_occ).astype(np.int32)

@@ -68,6 +68,14 @@ def test_host_validation_rejects_bad_arguments():
         rc = L.gw_screen_w(ctypes.byref(sys_ok), 1, 1, n_tau, 4, cw.ctypes.data_as(ctypes.c_void_p),
                            cw.ctypes.data_as(ctypes.c_void_p), ctypes.c_double(spin), 1, None)
         assert rc == gw.GW_ERR_ARG
+    # screen_w_metric: null S, too many tau points; screen_w_spins: null chi_dn
+    p = cw.ctypes.data_as(ctypes.c_void_p)
+    for S, n_tau in ((None, 4), (1, 40)):
+        rc = L.gw_screen_w_metric(ctypes.byref(sys_ok), 1, 1, S, n_tau, 4, p, p,
+                                  ctypes.c_double(2.0), 1, None, None)
+        assert rc == gw.GW_ERR_ARG
+    rc = L.gw_screen_w_spins(ctypes.byref(sys_ok), 1, None, 1, 4, 4, p, p, 1, None)
+    assert rc == gw.GW_ERR_ARG
     # contract_sigma: state out of range
     st = np.array([7], dtype=np.int32)
     so = np.zeros(4)
