@@ -70,6 +70,16 @@ def wire(n_atoms: int, seed=0, filter_eps=1e-8, n_tau=12) -> Workload:
     return Workload(f"wire{n_atoms}", s, n_tau, n_tau, 5, 5)
 
 
+def bulk(n: int, seed=0, filter_eps=1e-9, n_ao=8, n_ri=20, n_tau=12) -> Workload:
+    """Periodic Gamma-point cell: n^3 atoms on the simple cubic lattice in a
+    cube of side n * SPACING, minimum-image distances for H and the tensor; V
+    is the periodic Coulomb matrix of the RI charges (System.ri_charges)."""
+    xyz = gsys.cubic_lattice(n)
+    s = gsys.System(xyz, n_ao, n_ri, 0.8, 0.8, 0.2, filter_eps, seed=seed,
+                    cell=np.full(3, n * gsys.SPACING))
+    return Workload(f"bulk{n}", s, n_tau, n_tau, 5, 5)
+
+
 STREAM_SIZES = 7
 STREAM_PACKING = 8
 
@@ -99,6 +109,8 @@ def by_name(name: str, seed=0) -> Workload:
         return wire(int(name[4:]), seed)
     if name.startswith("ribbon"):
         return ribbon(int(name[6:]), seed)
+    if name.startswith("bulk"):
+        return bulk(int(name[4:]), seed)
     raise KeyError(name)
 
 

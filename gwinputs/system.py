@@ -57,6 +57,23 @@ def strip(n_atoms: int, width: int = STRIP_WIDTH, spacing: float = SPACING) -> n
     return xyz
 
 
+def cubic_lattice(n: int, spacing: float = SPACING) -> np.ndarray:
+    """n^3 atoms on a simple cubic lattice, atom (i, j, k) at spacing*(i, j, k),
+    i slowest; the periodic cell of the bulk workloads is the cube of side
+    n*spacing."""
+    k = np.arange(n)
+    return np.stack(np.meshgrid(k, k, k, indexing="ij"), -1).reshape(-1, 3) * float(spacing)
+
+
+def fibonacci_sphere(n: int, radius: float) -> np.ndarray:
+    """n nearly uniform points on a sphere (golden-angle spiral)."""
+    i = np.arange(n) + 0.5
+    polar = np.arccos(1.0 - 2.0 * i / n)
+    azim = np.pi * (1.0 + 5.0 ** 0.5) * i
+    return radius * np.stack([np.cos(azim) * np.sin(polar), np.sin(azim) * np.sin(polar),
+                              np.cos(polar)], axis=1)
+
+
 def packing(n_atoms: int, seed: int, stream: int, density: float = 0.0148,
             d_min: float = SPACING, max_tries: int = 200000) -> np.ndarray:
     """Random sequential addition in a cube of the given number density."""
@@ -93,6 +110,7 @@ class System:
     seed: int = 0
     sys_id: int = 0
     n_occ: Optional[int] = None
+    cell: Optional[np.ndarray] = None   # orthorhombic periodic cell (box lengths), or None
 
     def __post_init__(self):
         self.n_atoms = self.xyz.shape[0]
@@ -102,7 +120,14 @@ class System:
             self.n_occ = self.n_ao // 2
         self.ao_off = np.arange(self.n_atoms + 1, dtype=np.int32) * self.n_ao_atom
         self.ri_off = np.arange(self.n_atoms + 1, dtype=np.int32) * self.n_ri_atom
-        self.dist = atom_distances(self.xyz)
+        if self.cell is None:
+            self.dist = atom_distances(self.xyz)
+        else:
+            # minimum-image distances of the periodic cell
+            self.cell = np.asarray(self.cell, dtype=np.float64)
+            diff = self.xyz[:, None, :] - self.xyz[None, :, :]
+            diff -= self.cell * np.round(diff / self.cell)
+            self.dist = np.sqrt((diff * diff).sum(-1))
         self.ao_atom = np.repeat(np.arange(self.n_atoms), self.n_ao_atom)
         self.ri_atom = np.repeat(np.arange(self.n_atoms), self.n_ri_atom)
 
@@ -172,6 +197,18 @@ class System:
         linv = np.linalg.inv(lc)
         w, v = np.linalg.eigh(linv @ self.hamiltonian() @ linv.T)
         return np.ascontiguousarray((linv.T @ v).T), w
+
+    def ri_charges(self, radius: float = 0.8, alpha_lo: float = 0.5, alpha_hi: float = 2.0):
+        """RI functions as normalized Gaussian charges for the periodic
+        Coulomb matrix: function p of atom a centred at xyz[a] + o_p (o_p on a
+        sphere of the given radius, standing in for the angular structure of a
+        real RI basis) with exponent alpha_p geometric in [alpha_lo, alpha_hi].
+        Returns (centres [n_ri][3], alpha [n_ri])."""
+        nr = self.n_ri_atom
+        alpha = alpha_lo * (alpha_hi / alpha_lo) ** (np.arange(nr) / max(nr - 1, 1))
+        off = fibonacci_sphere(nr, radius)
+        centres = (self.xyz[:, None, :] + off[None, :, :]).reshape(-1, 3)
+        return np.ascontiguousarray(centres), np.tile(alpha, self.n_atoms)
 
     # ---- V
     def coulomb(self) -> np.ndarray:
