@@ -257,6 +257,33 @@ gw_status gw_screen_w_metric(const gw_system *s, const double *chi, const double
                              const double *icos_w, double spin, double *wc_tilde,
                              double *v_tilde, hipStream_t stream);
 
+/* Coulomb matrix of a periodic Gamma-point cell (Eq. 8; the paper obtains V
+ * for periodic cells by Ewald summation).  The RI functions are normalized
+ * Gaussian charges: centres host [n_ri][3] (bohr), alpha host [n_ri] (> 0),
+ * in the orthorhombic cell with box lengths cell host [3] (bohr), with a
+ * neutralizing background (G = 0 left out):
+ *   V_PQ = (4 pi/Omega) sum_{G != 0} e^{-G^2/4a_P} e^{-G^2/4a_Q} cos(G.(R_P - R_Q)) / G^2.
+ * Computed by an Ewald split with parameter eta (0: chosen by a cost model;
+ * else 0 < eta < sqrt(min alpha / 2)): a real-space erf sum over lattice
+ * images, a reciprocal sum as one FP64 GEMM, and the background constant;
+ * terms below tol (0 < tol <= 1e-6; 1e-17 for full FP64) are dropped.  V:
+ * dev [n_ri][n_ri], overwritten (symmetric).  info: host, optional (NULL),
+ * receives the parameters used.  Synchronous on stream; the workspace
+ * (n_ri x 2 n_g doubles) is allocated stream-ordered and freed.  Errors:
+ * GW_ERR_ARG for bad sizes, pointers, exponents, cell, tol or eta, or a
+ * split whose image box or reciprocal list exceeds the bounds; GW_ERR_NOMEM,
+ * GW_ERR_BLAS, GW_ERR_HIP. */
+typedef struct {
+  double eta;     /* splitting parameter used                          */
+  double r_cut;   /* real-space cutoff (bohr)                           */
+  double g_cut;   /* reciprocal cutoff (1/bohr)                         */
+  int32_t n_g;    /* reciprocal vectors in the half space               */
+  int32_t n_img;  /* lattice images within r_cut (estimate)             */
+} gw_coulomb_info;
+gw_status gw_coulomb_periodic(int32_t n_ri, const double *centres, const double *alpha,
+                              const double *cell, double eta, double tol, double *V,
+                              gw_coulomb_info *info, hipStream_t stream);
+
 typedef struct {
   double flops;            /* algorithmic flops of the self-energy products   */
   double ms_total;

@@ -92,6 +92,8 @@ def lib():
         L.gw_screen_w_spins.restype = ctypes.c_int32
         L.gw_screen_w_metric.argtypes = [_P, _P, _P, _P, _I32, _I32, _P, _P, _D, _P, _P, _P]
         L.gw_screen_w_metric.restype = ctypes.c_int32
+        L.gw_coulomb_periodic.argtypes = [_I32, _P, _P, _P, _D, _D, _P, _P, _P]
+        L.gw_coulomb_periodic.restype = ctypes.c_int32
         for f in ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma",
                   "gw_continue_qp", "gw_evgw_update"):
             getattr(L, f).restype = ctypes.c_int32
@@ -129,7 +131,7 @@ EXPORTED = ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma"
             "gw_mlp_train_step", "gw_mlp_sync_half", "gw_chi_batch_create", "gw_chi_batch_execute",
             "gw_chi_batch_set_config", "gw_chi_batch_get_config", "gw_chi_batch_tune",
             "gw_chi_batch_destroy", "gw_evgw_update", "gw_contract_sigma_prec", "gw_screen_w_spins",
-            "gw_screen_w_metric")
+            "gw_screen_w_metric", "gw_coulomb_periodic")
 
 
 def _check(code):
@@ -396,6 +398,31 @@ def screen_w_metric(sys, chi, V, S_ri, cos_w, icos_w, spin=2.0, wc=None, v_tilde
     _check(lib().gw_screen_w_metric(sys.ref, _dev(chi), _dev(V), _dev(S_ri), n_tau, n_w, cw_p, iw_p,
                                     float(spin), _dev(wc), _dev(vt), _stream(stream)))
     return wc, vt
+
+
+class _CoulombInfo(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("r_cut", ctypes.c_double), ("g_cut", ctypes.c_double),
+                ("n_g", ctypes.c_int32), ("n_img", ctypes.c_int32)]
+
+
+def coulomb_periodic(centres, alpha, cell, eta=0.0, tol=1e-17, V=None, device="cuda",
+                     stream=None):
+    """gw_coulomb_periodic: (V on the device, parameters used) for Gaussian RI
+    charges in an orthorhombic periodic cell."""
+    import torch
+    c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
+    a = np.ascontiguousarray(alpha, dtype=np.float64).ravel()
+    cl = np.ascontiguousarray(cell, dtype=np.float64).ravel()
+    n = len(a)
+    if c.shape[0] != n or cl.shape != (3,):
+        raise ValueError("centres [n][3], alpha [n] and cell [3] expected")
+    if V is None:
+        V = torch.empty((n, n), dtype=torch.float64, device=device)
+    info = _CoulombInfo()
+    _check(lib().gw_coulomb_periodic(n, c.ctypes.data_as(_P), a.ctypes.data_as(_P),
+                                     cl.ctypes.data_as(_P), float(eta), float(tol), _dev(V),
+                                     ctypes.byref(info), _stream(stream)))
+    return V, {k: getattr(info, k) for k, _ in _CoulombInfo._fields_}
 
 
 def contract_sigma(sys, states, C, d_occ, d_vir, d_occ0, wc, V, filter_eps=0.0, stream=None,

@@ -76,6 +76,19 @@ def test_host_validation_rejects_bad_arguments():
         assert rc == gw.GW_ERR_ARG
     rc = L.gw_screen_w_spins(ctypes.byref(sys_ok), 1, None, 1, 4, 4, p, p, 1, None)
     assert rc == gw.GW_ERR_ARG
+    # coulomb_periodic: bad cell, non-positive exponent, eta beyond sqrt(min alpha / 2),
+    # loose tol, an image box beyond the bound
+    cen = np.zeros(6)
+    good_a, good_c = np.array([0.5, 1.0]), np.array([5.0, 5.0, 5.0])
+    for a_, c_, eta, tol in ((good_a, np.array([5.0, 0.0, 5.0]), 0.0, 1e-17),
+                             (np.array([0.5, -1.0]), good_c, 0.0, 1e-17),
+                             (good_a, good_c, 0.6, 1e-17), (good_a, good_c, 0.0, 1e-3),
+                             (good_a, good_c, 1e-4, 1e-17)):
+        rc = L.gw_coulomb_periodic(2, cen.ctypes.data_as(ctypes.c_void_p),
+                                   a_.ctypes.data_as(ctypes.c_void_p),
+                                   c_.ctypes.data_as(ctypes.c_void_p), ctypes.c_double(eta),
+                                   ctypes.c_double(tol), 1, None, None)
+        assert rc == gw.GW_ERR_ARG
     # contract_sigma: state out of range
     st = np.array([7], dtype=np.int32)
     so = np.zeros(4)
