@@ -375,9 +375,12 @@ EwaldPlan ewald_plan(double eta, const double* cell, double omega, double tol) {
     g = 2.0 * eta * std::sqrt(std::max(std::log(std::max(arg, 1.0)), 0.0));
   }
   pl.g_cut = g * 1.02;
-  pl.nx = (int)std::ceil(pl.r_cut / cell[0] + 0.5);
-  pl.ny = (int)std::ceil(pl.r_cut / cell[1] + 0.5);
-  pl.nz = (int)std::ceil(pl.r_cut / cell[2] + 0.5);
+  // images per direction, clamped before the int conversion (the caller
+  // rejects boxes beyond its bound)
+  auto n_img_dir = [&](double l) { return (int)std::min(std::ceil(pl.r_cut / l + 0.5), 1.0e6); };
+  pl.nx = n_img_dir(cell[0]);
+  pl.ny = n_img_dir(cell[1]);
+  pl.nz = n_img_dir(cell[2]);
   const double ball = 4.0 / 3.0 * kPi * pl.r_cut * pl.r_cut * pl.r_cut;
   pl.n_img = std::min<int64_t>((int64_t)(2 * pl.nx + 1) * (2 * pl.ny + 1) * (2 * pl.nz + 1),
                                (int64_t)(ball / omega) + 1);

@@ -83,7 +83,8 @@ def test_host_validation_rejects_bad_arguments():
     for a_, c_, eta, tol in ((good_a, np.array([5.0, 0.0, 5.0]), 0.0, 1e-17),
                              (np.array([0.5, -1.0]), good_c, 0.0, 1e-17),
                              (good_a, good_c, 0.6, 1e-17), (good_a, good_c, 0.0, 1e-3),
-                             (good_a, good_c, 1e-4, 1e-17)):
+                             (good_a, good_c, 1e-4, 1e-17),
+                             (good_a, np.array([1e-12, 5.0, 5.0]), 0.0, 1e-17)):
         rc = L.gw_coulomb_periodic(2, cen.ctypes.data_as(ctypes.c_void_p),
                                    a_.ctypes.data_as(ctypes.c_void_p),
                                    c_.ctypes.data_as(ctypes.c_void_p), ctypes.c_double(eta),
