@@ -278,7 +278,7 @@ typedef struct {
   double r_cut;   /* real-space cutoff (bohr)                           */
   double g_cut;   /* reciprocal cutoff (1/bohr)                         */
   int32_t n_g;    /* reciprocal vectors in the half space               */
-  int32_t n_img;  /* lattice images within r_cut (estimate)             */
+  int32_t n_img;  /* lattice images each element of V visits            */
 } gw_coulomb_info;
 gw_status gw_coulomb_periodic(int32_t n_ri, const double *centres, const double *alpha,
                               const double *cell, double eta, double tol, double *V,

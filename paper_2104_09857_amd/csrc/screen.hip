@@ -314,12 +314,17 @@ __device__ inline double short_range(double smu, double eta, double r) {
   return d / r;
 }
 
+// images: n_img lattice vectors (x, y, z) whose distance to the box of
+// minimum-image displacements is within r_cut (the only ones that can be)
 __global__ void ewald_real_kernel(const double* __restrict__ centres, const double* __restrict__ alpha,
-                                  int n_ri, double lx, double ly, double lz, int nx, int ny, int nz,
-                                  double eta, double r_cut, double inv_omega, double* __restrict__ V) {
+                                  int n_ri, double lx, double ly, double lz,
+                                  const double* __restrict__ images, int n_img, double eta,
+                                  double r_cut, double inv_omega, double* __restrict__ V) {
+  // the real-space part is symmetric in (P, Q): element (p, q >= p) adds
+  // to V_pq and V_qp (each pair owned by one thread)
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int p = blockIdx.y;
-  if (q >= n_ri) return;
+  if (q >= n_ri || q < p) return;
   const double ap = alpha[p], aq = alpha[q];
   const double mu = ap * aq / (ap + aq);
   const double smu = sqrt(mu);
@@ -331,21 +336,14 @@ __global__ void ewald_real_kernel(const double* __restrict__ centres, const doub
   dz -= lz * rint(dz / lz);
   const double rc2 = r_cut * r_cut;
   double acc = 0.0;
-  for (int i = -nx; i <= nx; ++i) {
-    const double x = dx + i * lx;
-    for (int j = -ny; j <= ny; ++j) {
-      const double y = dy + j * ly;
-      const double xy = x * x + y * y;
-      if (xy > rc2) continue;
-      for (int k = -nz; k <= nz; ++k) {
-        const double z = dz + k * lz;
-        const double r2 = xy + z * z;
-        if (r2 <= rc2) acc += short_range(smu, eta, sqrt(r2));
-      }
-    }
+  for (int m = 0; m < n_img; ++m) {
+    const double x = dx + images[3 * m], y = dy + images[3 * m + 1], z = dz + images[3 * m + 2];
+    const double r2 = x * x + y * y + z * z;
+    if (r2 <= rc2) acc += short_range(smu, eta, sqrt(r2));
   }
   acc -= kPi * inv_omega * (1.0 / (eta * eta) - 1.0 / mu);
   V[(int64_t)p * n_ri + q] += acc;
+  if (q != p) V[(int64_t)q * n_ri + p] += acc;
 }
 
 // x with erfc(x) <= tol
@@ -442,6 +440,23 @@ extern "C" gw_status gw_coulomb_periodic(int32_t n_ri, const double* centres, co
         gw4.insert(gw4.end(), {gx, gy, gz, std::sqrt(w)});
       }
   const int n_g = (int)(gw4.size() / 4);
+  // lattice images that can lie within r_cut of a minimum-image displacement
+  // (|d_i| <= l_i / 2): distance from the image to that box at most r_cut
+  std::vector<double> img;
+  const double l[3] = {cell[0], cell[1], cell[2]};
+  for (int i = -pl.nx; i <= pl.nx; ++i)
+    for (int j = -pl.ny; j <= pl.ny; ++j)
+      for (int k = -pl.nz; k <= pl.nz; ++k) {
+        const int n[3] = {i, j, k};
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          const double e = std::max(0.0, std::abs(n[a]) * l[a] - 0.5 * l[a]);
+          d2 += e * e;
+        }
+        if (d2 <= pl.r_cut * pl.r_cut * (1.0 + 1e-12))
+          img.insert(img.end(), {i * l[0], j * l[1], k * l[2]});
+      }
+  const int n_list = (int)(img.size() / 3);
   const int64_t f_elems = (int64_t)n_ri * 2 * std::max(n_g, 1);
   GW_CHECK_ARG(f_elems * 8 <= (int64_t)16 << 30,
                "reciprocal sum too large for the workspace (give a smaller eta)");
@@ -450,7 +465,7 @@ extern "C" gw_status gw_coulomb_periodic(int32_t n_ri, const double* centres, co
     info->r_cut = pl.r_cut;
     info->g_cut = pl.g_cut;
     info->n_g = n_g;
-    info->n_img = (int32_t)std::min<int64_t>(pl.n_img, INT32_MAX);
+    info->n_img = n_list;
   }
 
   rocblas_handle h;
@@ -458,9 +473,10 @@ extern "C" gw_status gw_coulomb_periodic(int32_t n_ri, const double* centres, co
   if (rc != GW_OK) return rc;
   Scratch sc(st);
   std::vector<double> cen(centres, centres + 3 * (size_t)n_ri), alp(alpha, alpha + n_ri);
-  double *cen_d, *alp_d, *gw_d = nullptr, *F = nullptr;
+  double *cen_d, *alp_d, *img_d, *gw_d = nullptr, *F = nullptr;
   if ((rc = sc.upload(&cen_d, cen)) != GW_OK) return rc;
   if ((rc = sc.upload(&alp_d, alp)) != GW_OK) return rc;
+  if ((rc = sc.upload(&img_d, img)) != GW_OK) return rc;
   const int64_t n2 = (int64_t)n_ri * n_ri;
   if (n_g > 0) {
     if ((rc = sc.upload(&gw_d, gw4)) != GW_OK) return rc;
@@ -475,8 +491,9 @@ extern "C" gw_status gw_coulomb_periodic(int32_t n_ri, const double* centres, co
   } else {
     GW_HIP(hipMemsetAsync(V, 0, sizeof(double) * n2, st));
   }
+  // one block row per p; blocks entirely left of the diagonal exit at once
   hipLaunchKernelGGL(ewald_real_kernel, dim3((n_ri + 255) / 256, n_ri), dim3(256), 0, st, cen_d,
-                     alp_d, n_ri, cell[0], cell[1], cell[2], pl.nx, pl.ny, pl.nz, pl.eta, pl.r_cut,
+                     alp_d, n_ri, cell[0], cell[1], cell[2], img_d, n_list, pl.eta, pl.r_cut,
                      1.0 / omega, V);
   GW_HIP(hipGetLastError());
   GW_HIP(hipStreamSynchronize(st));
