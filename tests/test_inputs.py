@@ -79,3 +79,35 @@ def test_grid_weights_fit_their_targets(chain12):
         assert np.max(np.abs(fit / true - 1)) < 0.5
     lap = (e @ g.lap_w) * x
     assert np.max(np.abs(lap - 1)) < 0.5
+
+
+def test_non_orthogonal_and_periodic_inputs():
+    """Gaussian metrics are SPD with unit diagonal; the generalized
+    eigenvectors are S_ao-orthonormal; a periodic cell has symmetric
+    minimum-image distances no longer than half its diagonal; the RI charges
+    sit off the atoms on their sphere."""
+    from gwinputs import configs
+    s = configs.chain12().system
+    for S in (s.ri_metric(), s.ao_metric()):
+        np.testing.assert_allclose(S, S.T, rtol=0, atol=0)
+        np.testing.assert_allclose(np.diag(S), 1.0, rtol=0, atol=0)
+        assert np.linalg.eigvalsh(S).min() > 0.05
+    Sa = s.ao_metric()
+    C, eps = s.mean_field_nonorth(Sa)
+    np.testing.assert_allclose(C @ Sa @ C.T, np.eye(s.n_ao), rtol=0, atol=1e-12)
+    assert np.all(np.diff(eps) >= 0)
+    b = configs.bulk(3, n_ao=5, n_ri=12).system
+    np.testing.assert_allclose(b.dist, b.dist.T, rtol=0, atol=0)
+    assert b.dist.max() <= 0.5 * np.linalg.norm(b.cell) + 1e-12
+    # atoms (0, 0, 0) and (2, 0, 0) are neighbours through the cell boundary
+    assert abs(b.dist[0, 18] - 2.5) < 1e-12
+    R, a = b.ri_charges()
+    assert R.shape == (b.n_ri, 3) and a.shape == (b.n_ri,)
+    off = R.reshape(b.n_atoms, b.n_ri_atom, 3) - b.xyz[:, None, :]
+    np.testing.assert_allclose(np.linalg.norm(off, axis=-1), 0.8, rtol=0, atol=1e-12)
+    assert a.min() == 0.5 and abs(a.max() - 2.0) < 1e-12
+    # open-shell inputs: delta = zeeman = 0 gives the closed shell
+    (cu, eu), (cd, ed) = s.mean_field_spin(0.0)
+    C0, e0 = s.mean_field()
+    np.testing.assert_allclose(eu, e0, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(ed, e0, rtol=0, atol=1e-12)
