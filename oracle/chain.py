@@ -1,5 +1,8 @@
 """The whole G0W0 chain on dense arrays, plus the canonical O(N^4) forms.
 
+Test infrastructure (the oracle): used only by tests/, __graft_entry__.smoke()
+and the CPU baseline of bench.py, never by the product path.
+
 ``g0w0`` runs every step of the oracle in the paper's order (Eq. 2 -> Eq. 3
 -> Eqs. 5-9 -> Eqs. 10-11 -> transforms, Pade, Eq. 12) and returns every
 intermediate, so that each piece of the HIP path can be compared with it.

@@ -1,5 +1,8 @@
 """Polarizability chi_PQ(tau) (Eq. 3), FP64.
 
+Test infrastructure (the oracle): used only by tests/, __graft_entry__.smoke()
+and the CPU baseline of bench.py, never by the product path.
+
 * ``chi_eq3``: the printed contraction order of Eq. 3 on dense arrays:
   first the two inner sums (over lambda with D^occ, over nu with D^vir), then
   the outer sum over mu and sigma.  Returns the per-spin chi (negative
@@ -14,7 +17,7 @@
 
 Pinned by: chi_eq3 == chi_mo (brute force on small systems), symmetry,
 negative semidefiniteness, mu_F invariance, MO sign-flip invariance, the
-cosine-transform closed form and the Laplace closed form (test_oracle_*.py).
+cosine-transform closed form and the Laplace closed form (tests/test_oracle_gt_chi.py).
 """
 from __future__ import annotations
 

@@ -1,6 +1,7 @@
 """Eigenvalue self-consistent GW (evGW) on the oracle chain, FP64.
 
-Test infrastructure (the oracle): only tests/ may use it.
+Test infrastructure (the oracle): used only by tests/, __graft_entry__.smoke()
+and the CPU baseline of bench.py, never by the product path.
 
 evGW as the paper defines it right after the QP equation (Eq. 12; the dashed
 arrow of its workflow figure): the QP energies replace the mean-field levels

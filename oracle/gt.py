@@ -1,7 +1,13 @@
 """Imaginary-time density matrices (Eq. 2), FP64, plain sums over MOs.
 
-Pinned by: idempotency and trace of D^occ(0), D^occ(0) + D^vir(0) = 1 (S = 1),
-the semigroup law D(t1) D(t2) = D(t1 + t2), symmetry and positivity.
+Test infrastructure (the oracle): used only by tests/, __graft_entry__.smoke()
+and the CPU baseline of bench.py, never by the product path.
+
+Pinned by (tests/test_oracle_gt_chi.py): idempotency and trace of D^occ(0),
+D^occ(0) + D^vir(0) = 1 (S = 1), the semigroup law D(t1) D(t2) = D(t1 + t2),
+symmetry and positivity; with a non-orthogonal AO basis the metric forms
+D S D = D, tr(D S) = n_occ and (D^occ + D^vir)(0) S = 1
+(tests/test_oracle_metric.py).
 """
 from __future__ import annotations
 

@@ -1,6 +1,7 @@
 """G0W0 with non-orthogonal bases, FP64.
 
-Test infrastructure (the oracle): only tests/ may use it.
+Test infrastructure (the oracle): used only by tests/, __graft_entry__.smoke()
+and the CPU baseline of bench.py, never by the product path.
 
 RI overlap metric (Eq. 5 and the definitions after Eqs. 10 and 11): with the
 RI overlap S_PQ, the polarizability entering the dielectric function is

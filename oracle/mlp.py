@@ -10,7 +10,7 @@ skipped wrongly), and the Adam update (Kingma & Ba, ICLR 2015):
     p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 
 Pinned by: gradients against central finite differences of the loss
-(test_oracle_mlp.py); the GPU kernels are then checked against this module.
+(tests/test_oracle_mlp.py); the GPU kernels are then checked against this module.
 """
 from __future__ import annotations
 

@@ -1,6 +1,7 @@
 """Coulomb matrix of a periodic Gamma-point cell, FP64.
 
-Test infrastructure (the oracle): only tests/ may use it.
+Test infrastructure (the oracle): used only by tests/, __graft_entry__.smoke()
+and the CPU baseline of bench.py, never by the product path.
 
 For periodic cells the paper obtains V of Eq. 8 by Ewald summation.  Reading:
 the RI functions are normalized Gaussian charges rho_P (exponent alpha_P,

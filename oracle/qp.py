@@ -1,5 +1,8 @@
 """From Sigma(tau) to quasiparticle energies (transforms, Pade, Eq. 12), FP64.
 
+Test infrastructure (the oracle): used only by tests/, __graft_entry__.smoke()
+and the CPU baseline of bench.py, never by the product path.
+
 * ``sigma_iw``: Sigma^c_n(i w_k) = sum_j c_kj (S^vir - S^occ)(tau_j)
                                   + i sum_j s_kj (S^vir + S^occ)(tau_j).
 * ``thiele_coeffs`` / ``thiele_eval``: Pade interpolant as a Thiele continued
@@ -15,7 +18,7 @@
 
 Pinned by: exact reproduction of rational data by the continued fraction,
 Sigma^c = 0 giving eps - vxc + Sigma^x, and the polynomial root of a one-pole
-Sigma^c (test_oracle_qp.py).
+Sigma^c (tests/test_oracle_screen_sigma_qp.py).
 """
 from __future__ import annotations
 

@@ -1,5 +1,8 @@
 """Screening: chi(i w), dielectric matrix, W^c(i w) and W^c(tau) (Eqs. 5-9), FP64.
 
+Test infrastructure (the oracle): used only by tests/, __graft_entry__.smoke()
+and the CPU baseline of bench.py, never by the product path.
+
 RI overlap metric S = 1 (the synthetic tensor plays the role of (mu nu P)),
 so chi~ = chi and W~ = W (Eqs. 5-6).  Step by step:
 
@@ -11,7 +14,7 @@ so chi~ = chi and W~ = W (Eqs. 5-6).  Step by step:
 
 Pinned by: eig(eps) >= 1, W^c negative semidefinite, the Cholesky route equal
 to the V^{1/2} route, chi = 0 giving W^c = 0, and the single-pole closed form
-of the self-energy built on top (test_oracle_screen.py, test_oracle_sigma.py).
+of the self-energy built on top (tests/test_oracle_screen_sigma_qp.py).
 """
 from __future__ import annotations
 

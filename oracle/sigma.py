@@ -1,5 +1,8 @@
 """Diagonal self-energy pieces (Eqs. 10-11), FP64.
 
+Test infrastructure (the oracle): used only by tests/, __graft_entry__.smoke()
+and the CPU baseline of bench.py, never by the product path.
+
   B^n_{mu P}     = sum_nu C_{n nu} (nu mu P)                 half transform
   Z^n_{P nu}     = sum_Q W_PQ B^n_{nu Q}                      inner sum of Eq. 10
   S^occ_n(tau)   = sum_{mu nu} D^occ_{mu nu}(tau) sum_P B^n_{mu P} Z^n_{P nu}
@@ -9,7 +12,7 @@
 Pinned by: AO contraction == MO form (brute force),
 S^occ_n(tau) = sum_i exp(eps_bar_i tau) sum_PQ (ni|P) W_PQ (Q|in), likewise
 for the virtual part, Sigma^x_n = -sum_i (ni|P) V_PQ (Q|in) <= 0, and the
-single-pole closed form of Sigma^c(i w) (test_oracle_sigma.py).
+single-pole closed form of Sigma^c(i w) (tests/test_oracle_screen_sigma_qp.py).
 """
 from __future__ import annotations
 

@@ -1,6 +1,7 @@
 """Open-shell (spin-polarized) G0W0 on the oracle pieces, FP64.
 
-Test infrastructure (the oracle): only tests/ may use it.
+Test infrastructure (the oracle): used only by tests/, __graft_entry__.smoke()
+and the CPU baseline of bench.py, never by the product path.
 
 The paper runs its nanoribbons as open-shell singlets (computational
 details) and writes the equations for a closed shell.  Readings for two
