@@ -39,7 +39,7 @@ namespace {
 //           3: <WM 4, RB 3> 192 rows
 constexpr int kNVar = 4;
 int c_rows(int prec, int v) {
-  static const int f64[kNVar] = {128, 64, 128, 64}, f32[kNVar] = {128, 64, 128, 128},
+  static const int f64[kNVar] = {128, 64, 128, 128}, f32[kNVar] = {128, 64, 128, 128},
                    bf[kNVar] = {256, 128, 128, 192};
   return prec == GW_BF16X3 ? bf[v] : prec == GW_FP32 ? f32[v] : f64[v];
 }
@@ -662,7 +662,7 @@ hipError_t stage_c_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStrea
     case 1: return run_mfma<2, C_WN, C_NBW, C_KC>(t, piv, pers, q, st);
     case 2: return run_mfma<4, C_WN, C_NBW, 16>(t, piv, pers, q, st);
     case 3:
-      if constexpr (std::is_same<T, double>::value) return run_dma<2, 5, 2, 8, 3>(t, piv, pers, q, st);
+      if constexpr (std::is_same<T, double>::value) return run_dma<4, 2, 5, 24, 2>(t, piv, pers, q, st);
       else return run_dma<4, C_WN, C_NBW, 16, 3>(t, piv, pers, q, st);
     default: return run_mfma<4, C_WN, C_NBW, C_KC>(t, piv, pers, q, st);
   }
