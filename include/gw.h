@@ -149,9 +149,10 @@ typedef struct {
  * (plain device allocations) before returning.  It runs the batched form
  * below on one system, eagerly, with the default tile configuration of the
  * precision (the fastest measured on gfx950 for 13 AO / 40 RI per atom:
- * FP64 stage-C variant 2 with all stages persistent, FP32 variant 3 (the
- * direct-to-LDS outer contraction; variant 0 when ri_per_atom is not a
- * multiple of 4) with stages B and C persistent (stage B as a grid when the
+ * FP64 stage-C variant 3 (the direct-to-LDS outer contraction; variant 2
+ * when ri_per_atom is odd) with all stages persistent, FP32 variant 3
+ * (variant 0 when ri_per_atom is not a multiple of 4) with stages B and C
+ * persistent (stage B as a grid when the
  * basis has at most 64 AO x RI functions per atom pair), BF16x3 variant 0
  * with all stages persistent). */
 gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double *d_vir,

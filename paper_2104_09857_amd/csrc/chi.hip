@@ -662,7 +662,7 @@ hipError_t stage_c_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStrea
     case 1: return run_mfma<2, C_WN, C_NBW, C_KC>(t, piv, pers, q, st);
     case 2: return run_mfma<4, C_WN, C_NBW, 16>(t, piv, pers, q, st);
     case 3:
-      if constexpr (std::is_same<T, double>::value) return run_dma<4, 2, 5, 24, 2>(t, piv, pers, q, st);
+      if constexpr (std::is_same<T, double>::value) return run_dma<4, 2, 5, 32, 2>(t, piv, pers, q, st);
       else return run_dma<4, C_WN, C_NBW, 16, 3>(t, piv, pers, q, st);
     default: return run_mfma<4, C_WN, C_NBW, C_KC>(t, piv, pers, q, st);
   }
@@ -951,7 +951,9 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   B->timing = opts && opts->timing;
   B->out_filter = !(opts && opts->keep_small_blocks);
   // default tile configuration per precision (fastest measured for 13 AO / 40 RI per atom)
-  B->variant = prec == GW_FP64 ? 2 : prec == GW_FP32 && variant_ok(prec, NR, 3) ? 3 : 0;
+  // direct-to-LDS outer contraction (variant 3) when the RI block size allows
+  // its 16-byte copies; else the register-staged tiles
+  B->variant = variant_ok(prec, NR, 3) && prec != GW_BF16X3 ? 3 : prec == GW_FP64 ? 2 : 0;
   // FP32: stage A as a grid; stage B persistent on the wide tiles, a grid on
   // the narrow ones (measured on 13/40 and 5/12 bases)
   B->persistent = prec == GW_FP32 ? (B->ab_nb == AB_NBN ? 4 : 6) : 7;

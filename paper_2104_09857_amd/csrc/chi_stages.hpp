@@ -29,7 +29,10 @@ constexpr int C_COLS = 16 * C_NBW * C_WN;
 constexpr int C_KC = 32;                          // K chunk staged per barrier pair
 
 constexpr int kSegTab = 2048;     // max bricks per group (first atoms)
-constexpr int kPanTab = 4096;     // max K functions per column panel (NA * |U_p|)
+// max K functions per column panel (NA * |U_p|); sized so that the FP64
+// direct-to-LDS outer contraction with 32-deep K chunks (144 KB of operand
+// stages) and this table fit in the 160 KB of LDS
+constexpr int kPanTab = 3968;
 
 // T: operand type (double: FP64 form, float: FP32 form)
 template <class T>

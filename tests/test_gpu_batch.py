@@ -181,14 +181,16 @@ def test_empty_member():
 
 def test_direct_to_lds_variant_needs_aligned_ri_blocks():
     """Variant 3 copies operands into LDS 16 bytes at a time: an FP64 plan
-    with an odd RI count per atom rejects it, and the default configuration
-    of an FP32 plan with such a count falls back to variant 0."""
+    with an odd RI count per atom rejects it and defaults to variant 2, and
+    the default configuration of an FP32 plan with such a count falls back to
+    variant 0."""
     import torch
     from paper_2104_09857_amd import gw
     from gwinputs import configs
     ws = configs.molecules(2, seed=6, lo=3, hi=5, filter_eps=1e-6, n_tau=2, n_ao=4, n_ri=13)
     ms = _setup(ws)
     plan = gw.ChiBatch([m["sys"] for m in ms], 2, 1e-6)
+    assert plan.config()[0] == 2          # FP64 default without variant 3
     with pytest.raises(gw.GWError):
         plan.set_config(3, 7)
     plan.set_config(2, 7)
