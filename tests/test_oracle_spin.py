@@ -76,3 +76,27 @@ def test_channel_exchange_and_mo_form(chain, name):
             assert np.abs(chi[j] - ref).max() <= 1e-11 * np.abs(ref).max()
     # the two channels differ (the potential splits them)
     assert np.abs(a.e_qp[0] - b.e_qp[0]).max() > 1e-6
+
+
+def test_with_ri_metric(chain):
+    """Equal channels with an RI overlap reproduce the pinned metric chain
+    (spin factor 2); S = 1 gives the form without S."""
+    from oracle import metric as omet
+    inp = chain
+    s = inp.s
+    S = s.ri_metric()
+    r = ospin.g0w0_spin((inp.C, inp.eps, s.n_occ), (inp.C, inp.eps, s.n_occ), inp.t3c, inp.V,
+                        s.ao_off, s.ri_off, inp.grids, inp.states, inp.states, s.filter_eps, S=S)
+    ref = omet.g0w0_metric(inp.C, inp.eps, s.n_occ, inp.t3c, inp.V, S, s.ao_off, s.ri_off,
+                           inp.grids, inp.states, s.filter_eps)
+    np.testing.assert_allclose(r.wc_tau, ref.wc_tau, rtol=0, atol=1e-10 * np.abs(ref.wc_tau).max())
+    for e in r.e_qp:
+        np.testing.assert_allclose(e, ref.e_qp, rtol=0, atol=1e-9)
+    up, dn = s.mean_field_spin(DELTA)
+    st = np.array([s.n_occ - 1, s.n_occ])
+    a = _run(inp, up, dn, s.n_occ, s.n_occ, st, st)
+    b = ospin.g0w0_spin((up[0], up[1], s.n_occ), (dn[0], dn[1], s.n_occ), inp.t3c, inp.V,
+                        s.ao_off, s.ri_off, inp.grids, st, st, s.filter_eps, S=np.eye(s.n_ri))
+    np.testing.assert_allclose(b.wc_tau, a.wc_tau, rtol=0, atol=1e-12 * np.abs(a.wc_tau).max())
+    np.testing.assert_allclose(b.e_qp[0], a.e_qp[0], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(b.e_qp[1], a.e_qp[1], rtol=0, atol=1e-10)
