@@ -257,6 +257,15 @@ gw_status gw_screen_w_metric(const gw_system *s, const double *chi, const double
                              const double *S_ri, int32_t n_tau, int32_t n_w, const double *cos_w,
                              const double *icos_w, double spin, double *wc_tilde,
                              double *v_tilde, hipStream_t stream);
+/* Both at once, as the paper's open-shell ribbons need (overlap-metric RI,
+ * two spin channels): gw_screen_w_metric of chi = chi_up + chi_dn with spin
+ * factor 1 (chi_up, chi_dn as for gw_screen_w_spins).  Outputs, errors and
+ * stream semantics as gw_screen_w_metric. */
+gw_status gw_screen_w_spins_metric(const gw_system *s, const double *chi_up,
+                                   const double *chi_dn, const double *V, const double *S_ri,
+                                   int32_t n_tau, int32_t n_w, const double *cos_w,
+                                   const double *icos_w, double *wc_tilde, double *v_tilde,
+                                   hipStream_t stream);
 
 /* Coulomb matrix of a periodic Gamma-point cell (Eq. 8; the paper obtains V
  * for periodic cells by Ewald summation).  The RI functions are normalized

@@ -271,6 +271,17 @@ extern "C" gw_status gw_screen_w_spins(const gw_system* s, const double* chi_up,
   return screen_impl(s, chi_up, chi_dn, V, nullptr, n_tau, n_w, cos_w, icos_w, 1.0, wc, nullptr, st);
 }
 
+extern "C" gw_status gw_screen_w_spins_metric(const gw_system* s, const double* chi_up,
+                                              const double* chi_dn, const double* V,
+                                              const double* S_ri, int32_t n_tau, int32_t n_w,
+                                              const double* cos_w, const double* icos_w,
+                                              double* wc_tilde, double* v_tilde, hipStream_t st) {
+  clear_error();
+  GW_CHECK_ARG(chi_up && chi_dn && S_ri, "null pointer argument");
+  return screen_impl(s, chi_up, chi_dn, V, S_ri, n_tau, n_w, cos_w, icos_w, 1.0, wc_tilde, v_tilde,
+                     st);
+}
+
 // ---------------------------------------------------------------------------
 // Periodic Coulomb matrix (Eq. 8 for a periodic Gamma-point cell, obtained by
 // Ewald summation).  RI functions are normalized Gaussian charges (exponent

@@ -92,6 +92,8 @@ def lib():
         L.gw_screen_w_spins.restype = ctypes.c_int32
         L.gw_screen_w_metric.argtypes = [_P, _P, _P, _P, _I32, _I32, _P, _P, _D, _P, _P, _P]
         L.gw_screen_w_metric.restype = ctypes.c_int32
+        L.gw_screen_w_spins_metric.argtypes = [_P, _P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P]
+        L.gw_screen_w_spins_metric.restype = ctypes.c_int32
         L.gw_coulomb_periodic.argtypes = [_I32, _P, _P, _P, _D, _D, _P, _P, _P]
         L.gw_coulomb_periodic.restype = ctypes.c_int32
         for f in ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma",
@@ -131,7 +133,7 @@ EXPORTED = ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma"
             "gw_mlp_train_step", "gw_mlp_sync_half", "gw_chi_batch_create", "gw_chi_batch_execute",
             "gw_chi_batch_set_config", "gw_chi_batch_get_config", "gw_chi_batch_tune",
             "gw_chi_batch_destroy", "gw_evgw_update", "gw_contract_sigma_prec", "gw_screen_w_spins",
-            "gw_screen_w_metric", "gw_coulomb_periodic")
+            "gw_screen_w_metric", "gw_coulomb_periodic", "gw_screen_w_spins_metric")
 
 
 def _check(code):
@@ -397,6 +399,27 @@ def screen_w_metric(sys, chi, V, S_ri, cos_w, icos_w, spin=2.0, wc=None, v_tilde
     vt = torch.empty_like(V) if v_tilde is True else (None if v_tilde is False else v_tilde)
     _check(lib().gw_screen_w_metric(sys.ref, _dev(chi), _dev(V), _dev(S_ri), n_tau, n_w, cw_p, iw_p,
                                     float(spin), _dev(wc), _dev(vt), _stream(stream)))
+    return wc, vt
+
+
+def screen_w_spins_metric(sys, chi_up, chi_dn, V, S_ri, cos_w, icos_w, wc=None, v_tilde=True,
+                          stream=None):
+    """gw_screen_w_spins_metric: (W~^c, V~) from chi_up + chi_dn with the RI
+    overlap S_ri (spin factor 1)."""
+    import torch
+    cw, cw_p = _host(cos_w)
+    iw, iw_p = _host(icos_w)
+    n_w, n_tau = cw.shape
+    n = sys.n_ri
+    if chi_up.shape != chi_dn.shape or tuple(chi_up.shape) != (n_tau, n, n) or \
+            tuple(S_ri.shape) != (n, n) or tuple(V.shape) != (n, n):
+        raise ValueError("chi_up, chi_dn, V and S_ri shapes must match the system and grids")
+    if wc is None:
+        wc = torch.empty_like(chi_up)
+    vt = torch.empty_like(V) if v_tilde is True else (None if v_tilde is False else v_tilde)
+    _check(lib().gw_screen_w_spins_metric(sys.ref, _dev(chi_up), _dev(chi_dn), _dev(V), _dev(S_ri),
+                                          n_tau, n_w, cw_p, iw_p, _dev(wc), _dev(vt),
+                                          _stream(stream)))
     return wc, vt
 
 

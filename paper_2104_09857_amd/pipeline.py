@@ -102,13 +102,14 @@ def evgw(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_
 
 def g0w0_spin(sys_up, sys_dn, C_up, C_dn, eps_up, eps_dn, V, tau, omega, cos_w, sin_w, icos_w,
               states_up, states_dn, filter_eps, vxc_up=None, vxc_dn=None, window=0.0, stream=None,
-              prec="fp64", sigma_prec="fp64"):
+              prec="fp64", sigma_prec="fp64", S_ri=None):
     """Open-shell G0W0: one Green's function and chi per spin channel (sys_up
     and sys_dn share the bricks and differ in n_occ), W from chi_up + chi_dn
     with spin factor 1 (gw_screen_w_spins), Sigma and the QP equation per
     channel.  The energy zero is the midpoint of the highest occupied and the
-    lowest virtual level over both channels.  Returns per-channel outputs
-    and the common mu_F."""
+    lowest virtual level over both channels.  S_ri (optional): RI overlap
+    metric, the self-energies then take W~^c and V~.  Returns per-channel
+    outputs and the common mu_F."""
     import torch
     st = torch.cuda.current_stream() if stream is None else stream
     chans = ((sys_up, C_up, np.asarray(eps_up, dtype=np.float64), states_up, vxc_up),
@@ -125,12 +126,16 @@ def g0w0_spin(sys_up, sys_dn, C_up, C_dn, eps_up, eps_dn, V, tau, omega, cos_w, 
         chi, _ = gw.contract_chi(sysc, d_occ, d_vir, filter_eps, stream=st, prec=prec)
         ds.append((d_occ, d_vir, d0))
         chis.append(chi)
-    wc = gw.screen_w_spins(sys_up, chis[0], chis[1], V, cos_w, icos_w, stream=st)
+    if S_ri is None:
+        wc, v_sig = gw.screen_w_spins(sys_up, chis[0], chis[1], V, cos_w, icos_w, stream=st), V
+    else:
+        wc, v_sig = gw.screen_w_spins_metric(sys_up, chis[0], chis[1], V, S_ri, cos_w, icos_w,
+                                             stream=st)
     out = dict(chi_up=chis[0], chi_dn=chis[1], wc=wc, mu_f=mu_f)
     for tag, (sysc, C, eps, states, vxc), (d_occ, d_vir, d0) in zip(("up", "dn"), chans, ds):
         states = np.asarray(states, dtype=np.int32)
-        so, sv, sx, _ = gw.contract_sigma(sysc, states, C, d_occ, d_vir, d0, wc, V, filter_eps,
-                                          stream=st, prec=sigma_prec)
+        so, sv, sx, _ = gw.contract_sigma(sysc, states, C, d_occ, d_vir, d0, wc, v_sig,
+                                          filter_eps, stream=st, prec=sigma_prec)
         vxc = np.zeros(len(states)) if vxc is None else np.asarray(vxc, dtype=np.float64)
         is_occ = (states < sysc.c.n_occ).astype(np.int32)
         e_qp, status = gw.continue_qp(so, sv, sx, eps[states], vxc, is_occ, mu_f, omega, cos_w,

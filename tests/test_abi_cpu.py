@@ -76,6 +76,8 @@ def test_host_validation_rejects_bad_arguments():
         assert rc == gw.GW_ERR_ARG
     rc = L.gw_screen_w_spins(ctypes.byref(sys_ok), 1, None, 1, 4, 4, p, p, 1, None)
     assert rc == gw.GW_ERR_ARG
+    rc = L.gw_screen_w_spins_metric(ctypes.byref(sys_ok), 1, 1, 1, None, 4, 4, p, p, 1, None, None)
+    assert rc == gw.GW_ERR_ARG
     # coulomb_periodic: bad cell, non-positive exponent, eta beyond sqrt(min alpha / 2),
     # loose tol, an image box beyond the bound
     cen = np.zeros(6)

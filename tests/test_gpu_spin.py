@@ -91,3 +91,31 @@ def test_screen_w_spins_is_screen_w_of_the_sum():
     assert np.abs(w1 - w2).max() <= 1e-12 * np.abs(w1).max()
     with pytest.raises(ValueError):
         gw.screen_w_spins(sysd, a.cuda(), b[:-1].cuda(), V, g.cos_w, g.icos_w)
+
+
+def test_open_shell_with_ri_metric_matches_oracle():
+    """The paper's ribbon setting: open-shell singlet with the overlap-metric
+    RI (gw_screen_w_spins_metric), chain12, tensor scaled by 0.02."""
+    import torch
+    from paper_2104_09857_amd import gw, pipeline
+    inp = get_inputs("chain12")
+    s, g = inp.s, inp.grids
+    up, dn = s.mean_field_spin(DELTA)
+    S = s.ri_metric()
+    st = np.array([s.n_occ - 1, s.n_occ], dtype=np.int32)
+    t3 = ochi.dense_from_bricks(inp.trip, inp.bricks * SCALE, s.ao_off, s.ri_off, s.n_ao, s.n_ri,
+                                s.filter_eps)
+    ref = ospin.g0w0_spin((up[0], up[1], s.n_occ), (dn[0], dn[1], s.n_occ), t3, inp.V, s.ao_off,
+                          s.ri_off, g, st, st, s.filter_eps, S=S)
+    t3c = torch.as_tensor(inp.bricks * SCALE, device="cuda")
+    sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, inp.trip, t3c)
+    dev = lambda a: torch.as_tensor(a, device="cuda")
+    out = pipeline.g0w0_spin(sysd, sysd, dev(up[0]), dev(dn[0]), up[1], dn[1], dev(inp.V), g.tau,
+                             g.omega, g.cos_w, g.sin_w, g.icos_w, st, st, s.filter_eps,
+                             S_ri=dev(S))
+    torch.cuda.synchronize()
+    wc = out["wc"].cpu().numpy()
+    assert np.abs(wc - ref.wc_tau).max() <= 1e-10 * np.abs(ref.wc_tau).max()
+    assert np.all(out["status_up"] == 0) and np.all(out["status_dn"] == 0)
+    np.testing.assert_allclose(out["e_qp_up"], ref.e_qp[0], rtol=0, atol=1e-6)
+    np.testing.assert_allclose(out["e_qp_dn"], ref.e_qp[1], rtol=0, atol=1e-6)
