@@ -202,3 +202,55 @@ def test_evgw_update_matches_oracle():
         gw.evgw_update(eps0, 2, [4], [0.0])
     with pytest.raises(gw.GWError):            # non-finite QP energy
         gw.evgw_update(eps0, 2, [1], [float("nan")])
+
+
+def test_coulomb_periodic_host_plan():
+    """The Ewald plan of gw_coulomb_periodic (filled into gw_coulomb_info on
+    the host before any device work; the call then stops at the missing GPU
+    here): the reciprocal vectors are the half space of the lattice within
+    g_cut, each +-G pair once; the real-space images are those whose distance
+    to the box of minimum-image displacements is within r_cut; and the
+    split parameter honours eta < sqrt(min alpha / 2)."""
+    import math
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("with a GPU the call would go on to launch kernels on the dummy output; "
+                    "the device side is covered by tests/test_gpu_periodic.py")
+    L = gw.lib()
+    cell = np.array([7.5, 8.0, 9.5])
+    rng = np.random.default_rng(2)
+    cen = rng.uniform(0, 1, (6, 3)) * cell
+    alpha = np.array([0.5, 0.8, 1.0, 1.3, 2.0, 0.6])
+    for eta in (0.0, 0.3):
+        info = gw._CoulombInfo()
+        rc = L.gw_coulomb_periodic(6, cen.ctypes.data_as(ctypes.c_void_p),
+                                   alpha.ctypes.data_as(ctypes.c_void_p),
+                                   cell.ctypes.data_as(ctypes.c_void_p), ctypes.c_double(eta),
+                                   ctypes.c_double(1e-17), 1, ctypes.byref(info), None)
+        assert rc in (gw.GW_OK, gw.GW_ERR_HIP)
+        assert 0 < info.eta < math.sqrt(alpha.min() / 2)
+        if eta > 0:
+            assert info.eta == eta
+        b = 2 * np.pi / cell
+        m = np.ceil(info.g_cut / b).astype(int)
+        n_g = 0
+        for i in range(-m[0], m[0] + 1):
+            for j in range(-m[1], m[1] + 1):
+                for k in range(-m[2], m[2] + 1):
+                    g2 = (i * b[0]) ** 2 + (j * b[1]) ** 2 + (k * b[2]) ** 2
+                    if 0 < g2 <= info.g_cut ** 2:
+                        n_g += 1
+        assert info.n_g * 2 == n_g
+        n = np.ceil(info.r_cut / cell + 0.5).astype(int)
+        n_img = 0
+        for i in range(-n[0], n[0] + 1):
+            for j in range(-n[1], n[1] + 1):
+                for k in range(-n[2], n[2] + 1):
+                    e = np.maximum(0.0, np.abs([i, j, k]) * cell - 0.5 * cell)
+                    if (e * e).sum() <= info.r_cut ** 2 * (1 + 1e-12):
+                        n_img += 1
+        assert info.n_img == n_img
+        # the terms left out are below tol
+        assert math.erfc(info.eta * info.r_cut) <= 1e-17
+        assert 4 * np.pi / np.prod(cell) * math.exp(-info.g_cut ** 2 / (4 * info.eta ** 2)) \
+            / info.g_cut ** 2 <= 1e-17
