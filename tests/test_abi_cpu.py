@@ -254,3 +254,24 @@ def test_coulomb_periodic_host_plan():
         assert math.erfc(info.eta * info.r_cut) <= 1e-17
         assert 4 * np.pi / np.prod(cell) * math.exp(-info.g_cut ** 2 / (4 * info.eta ** 2)) \
             / info.g_cut ** 2 <= 1e-17
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/gw.h is a C header: a C99 translation unit that includes it and
+    names every struct it declares compiles without warnings."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    hdr = open(HEADER).read()
+    types = sorted(set(re.findall(r"}\s*(gw_\w+)\s*;", hdr)))
+    assert "gw_system" in types and "gw_coulomb_info" in types
+    src = tmp_path / "hdr.c"
+    src.write_text('#include "gw.h"\nint main(void) {\n'
+                   + "".join(f"  {t} v{i}; (void)v{i};\n" for i, t in enumerate(types))
+                   + "  return 0;\n}\n")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                        "-I" + os.path.dirname(HEADER), "-I/opt/rocm/include", "-c", str(src),
+                        "-o", str(tmp_path / "hdr.o")], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
