@@ -326,16 +326,24 @@ gw_status gw_contract_sigma_prec(const gw_system *s, int32_t n_gw, const int32_t
                                  hipStream_t stream);
 
 typedef struct {
-  double pade_window;      /* use only nodes with w_k <= window; <= 0: all    */
+  double pade_window;      /* use only nodes with w_k <= window (Ha); <= 0:
+                              all; GW_PADE_WINDOW_HA is the paper's 10 eV     */
   double newton_tol;       /* stop when |dE| < tol (Ha); <= 0: 1e-10           */
   int32_t max_iter;        /* <= 0: 100                                        */
 } gw_qp_opts;
+
+/* The analytic continuation window of the paper's computational details,
+ * i[0, +10 eV] for virtual and i[0, -10 eV] for occupied states, in hartree
+ * (CODATA 2018: 1 Ha = 27.211386245988 eV). */
+#define GW_PADE_WINDOW_HA (10.0 / 27.211386245988)
 
 /* Quasiparticle energies (Eq. 12), host only:
  *   Sigma^c_n(i w_k) = sum_j cos_w[k][j] (vir - occ)[n][j]
  *                      + i sum_j sin_w[k][j] (vir + occ)[n][j]
  * Thiele continued-fraction Pade on nodes +i w_k (virtual states) or -i w_k
- * with conjugated values (occupied), then Newton from E = eps_n on
+ * with conjugated values (occupied), w_k <= opts->pade_window (opts NULL:
+ * GW_PADE_WINDOW_HA, newton_tol 1e-10, 100 iterations), then Newton from
+ * E = eps_n on
  *   E - eps_n + vxc_n - sig_x_n - Re Sigma^c_n(E - mu_F) = 0.
  * state_status[n] = GW_OK or GW_ERR_NO_CONVERGE (e_qp[n] = NaN then); the
  * call returns GW_ERR_NO_CONVERGE if any state failed. */

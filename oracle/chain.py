@@ -37,7 +37,7 @@ class Chain:
 
 
 def g0w0(C, eps, n_occ, t3c, V, ao_off, ri_off, grids, states, filter_eps=0.0,
-         spin=2.0, vxc=None, window=None):
+         spin=2.0, vxc=None, window=qp.PADE_WINDOW_HA):
     """Full chain; ``t3c`` is the dense tensor with its bricks already filtered."""
     mu_f = 0.5 * (eps[n_occ - 1] + eps[n_occ])
     states = np.asarray(states)

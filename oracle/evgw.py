@@ -90,7 +90,7 @@ class EvGW:
 
 
 def evgw(C, eps, n_occ, t3c, V, ao_off, ri_off, grids, states, filter_eps=0.0, spin=2.0,
-         vxc=None, window=None, tol=1e-6, max_iter=20):
+         vxc=None, window=qp.PADE_WINDOW_HA, tol=1e-6, max_iter=20):
     eps0 = np.asarray(eps, dtype=np.float64)
     states = np.asarray(states)
     vxc = np.zeros(len(states)) if vxc is None else np.asarray(vxc, dtype=np.float64)

@@ -51,7 +51,7 @@ def screen_w_metric(chi_tau, V, S, cos_w, icos_w, spin):
 
 
 def g0w0_metric(C, eps, n_occ, t3c, V, S, ao_off, ri_off, grids, states, filter_eps=0.0,
-                spin=2.0, vxc=None, window=None):
+                spin=2.0, vxc=None, window=qp.PADE_WINDOW_HA):
     """The chain with the RI overlap S (C may be non-orthogonal in the AOs);
     Chain.wc_tau holds W~^c."""
     mu_f = 0.5 * (eps[n_occ - 1] + eps[n_occ])

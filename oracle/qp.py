@@ -11,7 +11,9 @@ and the CPU baseline of bench.py, never by the product path.
   with a_i = g_i(z_i), g_1(z_i) = f_i,
        g_p(z) = (g_{p-1}(z_{p-1}) - g_{p-1}(z)) / ((z - z_{p-1}) g_{p-1}(z)).
   Virtual states use the nodes +i w_k with Sigma^c(i w_k), occupied states the
-  nodes -i w_k with conj(Sigma^c(i w_k)); optionally only |w_k| <= window.
+  nodes -i w_k with conj(Sigma^c(i w_k)), with |w_k| <= window: by default the
+  paper's window of 10 eV on the imaginary axis (computational details);
+  window=None takes every node.
 * ``solve_qp``: Newton-Raphson on
       f(E) = E - eps_n + vxc_n - Sigma^x_n - Re Sigma^c_n(E - mu_F) = 0
   from E = eps_n, derivative from the continued fraction, |dE| < tol.
@@ -23,6 +25,10 @@ Sigma^c (tests/test_oracle_screen_sigma_qp.py).
 from __future__ import annotations
 
 import numpy as np
+
+# the analytic continuation window of the computational details: i[0, +10 eV]
+# for virtual and i[0, -10 eV] for occupied states (CODATA 2018 hartree)
+PADE_WINDOW_HA = 10.0 / 27.211386245988
 
 
 def sigma_iw(sig_occ, sig_vir, cos_w, sin_w):
@@ -95,7 +101,7 @@ def solve_qp(eps_n, vxc_n, sigx_n, mu_f, z_nodes, a, tol=1e-10, max_iter=100):
 
 
 def qp_energies(sig_occ, sig_vir, sig_x, eps_n, vxc_n, is_occ, mu_f, omega,
-                cos_w, sin_w, window=None, tol=1e-10, max_iter=100):
+                cos_w, sin_w, window=PADE_WINDOW_HA, tol=1e-10, max_iter=100):
     """eps^QP for every state (NaN where Newton fails) and a status array
     (0 ok, 1 no convergence)."""
     siw = sigma_iw(sig_occ, sig_vir, cos_w, sin_w)

@@ -55,7 +55,7 @@ def mu_common(eps_up, n_up, eps_dn, n_dn):
 
 
 def g0w0_spin(chan_up, chan_dn, t3c, V, ao_off, ri_off, grids, states_up, states_dn,
-              filter_eps=0.0, window=None, S=None):
+              filter_eps=0.0, window=qp.PADE_WINDOW_HA, S=None):
     """chan_* = (C, eps, n_occ); states_*: computed MOs of each channel; S:
     RI overlap (None: S = 1)."""
     chans = (chan_up, chan_dn)

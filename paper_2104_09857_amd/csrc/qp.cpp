@@ -7,7 +7,8 @@
 //   g_p(z_i) = (g_{p-1}(z_{p-1}) - g_{p-1}(z_i)) / ((z_i - z_{p-1}) g_{p-1}(z_i)),
 // evaluated with the three-term recurrence for numerator and denominator
 // (and their z derivatives).  Virtual states use nodes +i w_k, occupied
-// states -i w_k with conjugated values.  Newton-Raphson from E = eps_n on
+// states -i w_k with conjugated values, w_k within the window (the paper's
+// 10 eV without options).  Newton-Raphson from E = eps_n on
 //   f(E) = E - eps_n + vxc_n - sig_x_n - Re Sigma^c_n(E - mu_F).
 #include <algorithm>
 #include <cmath>
@@ -66,7 +67,9 @@ extern "C" gw_status gw_continue_qp(int32_t n_gw, const double* sig_occ, const d
     gw::set_error("gw_continue_qp: invalid argument");
     return GW_ERR_ARG;
   }
-  const double window = opts ? opts->pade_window : 0.0;
+  // without options: the analytic continuation window of the paper's
+  // computational details, i[0, +-10 eV] (10 eV in hartree, CODATA 2018)
+  const double window = opts ? opts->pade_window : 10.0 / 27.211386245988;
   const double tol = (opts && opts->newton_tol > 0) ? opts->newton_tol : 1e-10;
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 100;
   for (int k = 0; k < n_w; ++k)

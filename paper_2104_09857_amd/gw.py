@@ -14,11 +14,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgw.so")
 
-GW_OK, GW_ERR_ARG, GW_ERR_HIP, GW_ERR_NOMEM, GW_ERR_NOT_SPD, GW_ERR_NO_CONVERGE, GW_ERR_BLAS = range(7)
+(GW_OK, GW_ERR_ARG, GW_ERR_HIP, GW_ERR_NOMEM, GW_ERR_NOT_SPD, GW_ERR_NO_CONVERGE, GW_ERR_BLAS,
+ GW_ERR_AUDIT) = range(8)
 GW_FP64 = 0
 GW_FP32 = 1
 GW_BF16X3 = 2
 PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "bf16x3": GW_BF16X3}
+# GW_PADE_WINDOW_HA of include/gw.h: the paper's analytic continuation window, 10 eV
+PADE_WINDOW_HA = 10.0 / 27.211386245988
 
 
 class GWError(RuntimeError):
@@ -482,7 +485,9 @@ def evgw_update(eps0, n_occ, states, e_qp):
 
 
 def continue_qp(sig_occ, sig_vir, sig_x, eps_n, vxc_n, is_occ, mu_f, omega, cos_w, sin_w,
-                window=0.0, tol=1e-10, max_iter=100, raise_on_fail=False):
+                window=PADE_WINDOW_HA, tol=1e-10, max_iter=100, raise_on_fail=False):
+    """gw_continue_qp: (e_qp, status).  window: Pade nodes w_k <= window (Ha);
+    the paper's 10 eV by default, <= 0 for every node."""
     so, so_p = _host(sig_occ)
     sv, sv_p = _host(sig_vir)
     sx, sx_p = _host(sig_x)

@@ -11,7 +11,8 @@ from . import gw
 
 
 def g0w0(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_eps,
-         spin=2.0, vxc=None, window=0.0, stream=None, events=False, chi_timing=False,
+         spin=2.0, vxc=None, window=gw.PADE_WINDOW_HA, stream=None, events=False,
+         chi_timing=False,
          prec="fp64", screener=None, screen_margin=1.0, eps_g=None, mu_g=None,
          sigma_prec="fp64", S_ri=None):
     """The chain of library calls.  prec: arithmetic of the chi contraction;
@@ -101,7 +102,8 @@ def evgw(sys, C, eps, mu_f, V, tau, omega, cos_w, sin_w, icos_w, states, filter_
 
 
 def g0w0_spin(sys_up, sys_dn, C_up, C_dn, eps_up, eps_dn, V, tau, omega, cos_w, sin_w, icos_w,
-              states_up, states_dn, filter_eps, vxc_up=None, vxc_dn=None, window=0.0, stream=None,
+              states_up, states_dn, filter_eps, vxc_up=None, vxc_dn=None,
+              window=gw.PADE_WINDOW_HA, stream=None,
               prec="fp64", sigma_prec="fp64", S_ri=None):
     """Open-shell G0W0: one Green's function and chi per spin channel (sys_up
     and sys_dn share the bricks and differ in n_occ), W from chi_up + chi_dn

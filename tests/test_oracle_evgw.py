@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from conftest import get_inputs
-from oracle import evgw as oev, chain as ochain
+from oracle import qp as oqp, evgw as oev, chain as ochain
 
 SCALE = 0.02
 
@@ -72,7 +72,7 @@ def test_first_step_is_g0w0_and_fixed_point(chain_scaled):
     eps_g = oev.update_energies(inp.eps, s.n_occ, inp.states, r.e_qp)
     again, status = oev.one_step(inp.C, inp.eps, eps_g, s.n_occ, t3, inp.V, s.ao_off, s.ri_off,
                                  inp.grids, inp.states, s.filter_eps, 2.0,
-                                 np.zeros(len(inp.states)), None)
+                                 np.zeros(len(inp.states)), oqp.PADE_WINDOW_HA)
     assert np.all(status == 0)
     assert np.abs(again - r.e_qp).max() < 1e-8
     # and evGW moved the energies away from G0W0 (the Green's function changed)
