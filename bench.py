@@ -1,10 +1,18 @@
-"""Benchmark: one step = the whole G0W0 hot path on one synthetic system.
+"""Benchmark of the low-scaling GW hot path on one GPU.
 
-A step runs the five libgw calls (density matrices, block-sparse chi for all
-tau, screening, diagonal self-energy, QP solution) from device-resident
-inputs.  Reported `value` is the chi + Sigma contraction throughput
-(algorithmic FLOPs of the executed block products / their kernel time);
-`time_to_qp_s` is the wall time of the whole step.
+Default mode: one step = one tau point of the hot path from device-resident
+inputs: the density matrices D^occ(tau_j), D^vir(tau_j) (Eq. 2), the
+block-sparse polarizability chi(tau_j) (Eq. 3, norms and filter included)
+through a one-tau chi plan, and the correlation self-energy pieces of the
+computed states at tau_j (Eqs. 10-11), j cycling over the tau grid.
+`value` is the chi + Sigma contraction throughput over the timed steps
+(algorithmic FLOPs of the executed block products / wall time of the
+steps).  Before the steps the whole chain (Eqs. 2-12) runs once:
+`time_to_qp_s`.  The dominant kernel (stage C of chi) is timed per launch
+with HIP events on the library's stream (`roofline`); the FP64 oracle is
+timed on the host cores on a bounded sample (`cpu_baseline`); the precision
+forms run their whole chain next to it while the wall budget allows
+(`precision_form`: speed-up and QP energy differences in meV).
 
 Default workload strip300: 300-atom ribbon 7 atoms wide, 13 AO / 40 RI per
 atom (3900 AO, 12000 RI), half filled, filter 1e-9, 12 tau / 12 omega points,
@@ -275,17 +283,43 @@ def bench_open_shell(args):
     print(json.dumps(res), flush=True)
 
 
-def cpu_baseline(ctx, out, budget_s=20.0):
-    """The oracle on a bounded sample: chi blocks (c, c') at tau_0, contracted
-    from the same bricks (the input generator's device copy) and D(tau_0)."""
-    from oracle import chi as ochi
+def host_facts():
+    """CPU model, logical CPU count and the threads the oracle's BLAS may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", ncpu))
+    return {"cpu_model": model, "nproc": ncpu, "blas_threads": min(threads, ncpu)}
+
+
+def cpu_baseline(ctx, d_occ0, d_vir0, chi_sigma_flops, sample_s=6.0, reps=3):
+    """The oracle (FP64 NumPy, host BLAS) timed on the host cores.
+
+    value: its throughput on a bounded sample of the same workload, output
+    blocks chi_{cc'}(tau_0) contracted by the oracle's block routine from the
+    same bricks and D(tau_0), median of `reps` runs of about `sample_s` s each;
+    the strip's whole chi + Sigma contraction at that rate is reported as
+    extrapolated.  full_chain_chain12: the oracle's whole chain (Eqs. 2-12)
+    on the 12-atom chain, median of `reps`."""
+    from oracle import chi as ochi, chain as ochain
+    from gwinputs import configs
     s = ctx["s"]
-    d_occ = out["d_occ"][0].cpu().numpy()
-    d_vir = out["d_vir"][0].cpu().numpy()
+    d_occ = d_occ0.cpu().numpy()
+    d_vir = d_vir0.cpu().numpy()
     trip = ctx["trip"]
     rng = np.random.default_rng(0)
     mid = s.n_atoms // 2
-    pairs = [(mid, mid), (mid, mid + 9)] + [tuple(sorted(rng.integers(0, s.n_atoms, 2))) for _ in range(30)]
+    pairs = [(mid, mid), (mid, min(mid + 9, s.n_atoms - 1))] + \
+        [tuple(sorted(rng.integers(0, s.n_atoms, 2))) for _ in range(60)]
     cache = {}
     loaded = set()
 
@@ -295,31 +329,61 @@ def cpu_baseline(ctx, out, budget_s=20.0):
         for r, v in zip(rows, vals):
             cache[tuple(trip[r])] = v.reshape(s.n_ao_atom, s.n_ao_atom, s.n_ri_atom)
 
-    flops = 0.0
-    elapsed = 0.0
-    done = []
     nr = s.n_ri_atom
-    for (c, c2) in pairs:
-        for cc in (c, c2):
-            if cc not in loaded:
-                load(cc)
-                loaded.add(cc)
+
+    def block_flops(c, c2):
         n_lam = len({t[0] for t in trip[trip[:, 2] == c]}) * s.n_ao_atom
         n_mu = len({t[0] for t in trip[trip[:, 2] == c2]}) * s.n_ao_atom
-        t0 = time.perf_counter()
-        ochi.chi_block(c, c2, trip, lambda a, b, cc: cache[(a, b, cc)], d_occ, d_vir, s.ao_off,
-                       s.ri_off, s.filter_eps)
-        elapsed += time.perf_counter() - t0
         # M: mu x lambda x (sigma P); N: mu x nu x (Q sigma); chi: P x Q x (mu sigma)
-        flops += (2.0 * n_mu * n_lam * n_lam * nr + 2.0 * n_mu * n_mu * nr * n_lam
-                  + 2.0 * nr * nr * n_mu * n_lam)
-        done.append((int(c), int(c2)))
-        if elapsed > budget_s:
-            break
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": flops / elapsed / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(done)} chi blocks (c, c') at tau_0 of the same workload, FP64 "
-                      f"NumPy/OpenBLAS dense within the brick supports, {elapsed:.1f} s: {done}"}
+        return (2.0 * n_mu * n_lam * n_lam * nr + 2.0 * n_mu * n_mu * nr * n_lam
+                + 2.0 * nr * nr * n_mu * n_lam)
+
+    rates, samples = [], []
+    for rep in range(reps):
+        flops = elapsed = 0.0
+        done = []
+        for (c, c2) in pairs:
+            for cc in (c, c2):
+                if cc not in loaded:
+                    load(cc)
+                    loaded.add(cc)
+            t0 = time.perf_counter()
+            ochi.chi_block(c, c2, trip, lambda a, b, cc: cache[(a, b, cc)], d_occ, d_vir, s.ao_off,
+                           s.ri_off, s.filter_eps)
+            elapsed += time.perf_counter() - t0
+            flops += block_flops(c, c2)
+            done.append((int(c), int(c2)))
+            if elapsed > sample_s:
+                break
+        rates.append(flops / elapsed)
+        samples.append(len(done))
+    rate = float(np.median(rates))
+    # the oracle's whole chain on the 12-atom chain
+    w = configs.chain12()
+    cs = w.system
+    C, eps = cs.mean_field()
+    g = configs.grids_for(w, eps)
+    tr = cs.triples()
+    dense = ochi.dense_from_bricks(tr, cs.bricks(tr), cs.ao_off, cs.ri_off, cs.n_ao, cs.n_ri,
+                                   cs.filter_eps)
+    Vc = cs.coulomb()
+    walls = []
+    for rep in range(reps):
+        t0 = time.perf_counter()
+        ochain.g0w0(C, eps, cs.n_occ, dense, Vc, cs.ao_off, cs.ri_off, g, w.states(), cs.filter_eps)
+        walls.append(time.perf_counter() - t0)
+    facts = host_facts()
+    return {"value": rate / 1e12, "unit": "TFLOP/s", "cores": facts["blas_threads"],
+            "kind": "oracle",
+            "sample": f"chi blocks (c, c') at tau_0 of {ctx['w'].name} contracted by the oracle's "
+                      f"block routine (FP64 NumPy, host BLAS) from the same bricks and D(tau_0); "
+                      f"median of {reps} runs of {samples} blocks (~{sample_s:.0f} s each)",
+            "rates_tflops": [r / 1e12 for r in rates],
+            "extrapolated_chi_sigma_s": chi_sigma_flops / rate,
+            "extrapolated_note": "whole chi + Sigma contraction of the workload (all tau) at the "
+                                 "sampled rate: extrapolated, not run",
+            "full_chain_chain12_s": float(np.median(walls)),
+            "full_chain_chain12_runs_s": walls, **facts}
 
 
 def setup_molecules(name, seed=0):
@@ -585,11 +649,168 @@ def bench_screened(args):
     print(json.dumps(out), flush=True)
 
 
+def full_chain(ctx, prec):
+    """Time-to-QP: the whole chain once from device-resident inputs (a1 -> a10
+    of the hot path: the library's chain, chi for all tau in one call)."""
+    import torch
+    out = step(ctx, prec)
+    torch.cuda.synchronize()
+    out["wall_s"] = sum(out["ms"].values()) / 1e3
+    return out
+
+
+def bench_chain(args):
+    """Default mode: one step = one tau point of the hot path (Eq. 2 for tau_j,
+    Eq. 3 through a one-tau plan, Eqs. 10-11 for tau_j), cycling over the
+    grid; the whole chain (time-to-QP) runs once before the steps."""
+    import torch
+    from paper_2104_09857_amd import gw
+    t_start = time.perf_counter()
+    ctx = setup(args.workload)
+    if args.metric:
+        use_metric(ctx)
+    s, g, w = ctx["s"], ctx["g"], ctx["w"]
+    sysd, Cd, eps, mu = ctx["sys"], ctx["Cd"], ctx["eps"], ctx["mu"]
+    states = w.states()
+    n_tau = len(g.tau)
+    chain = full_chain(ctx, args.prec)
+    log(f"[chain] time-to-QP {chain['wall_s']:.2f} s " +
+        json.dumps({k: round(v, 1) for k, v in chain["ms"].items()}))
+    for k in ("chi", "d_occ", "d_vir"):
+        chain.pop(k)
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    plan = gw.ChiBatch([sysd], 1, s.filter_eps, prec=args.prec, timing=True)
+    plan_s = time.perf_counter() - t0
+    log(f"[plan] one-tau {args.prec} plan {plan_s:.1f} s")
+    wc = chain["wc"]
+    do1 = torch.empty((1, s.n_ao, s.n_ao), dtype=torch.float64, device="cuda")
+    dv1 = torch.empty_like(do1)
+    chi1 = torch.empty((1, s.n_ri, s.n_ri), dtype=torch.float64, device="cuda")
+
+    def tau_step(j):
+        gw.build_gt(sysd, Cd, eps, mu, g.tau[j:j + 1], d_occ=do1, d_vir=dv1)
+        st = plan.execute([do1], [dv1], [chi1])
+        _, _, _, sst = gw.contract_sigma(sysd, states, Cd, do1, dv1, None, wc[j:j + 1], None,
+                                         s.filter_eps)
+        return st, sst
+
+    for i in range(args.warmup):
+        ts = time.perf_counter()
+        tau_step(i % n_tau)
+        torch.cuda.synchronize()
+        log(f"[warmup {i}] tau_{i % n_tau} {time.perf_counter() - ts:.2f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flops = c_ms = c_fl = 0.0
+    c_n = 0
+    stage_ms = np.zeros(3)
+    stage_fl = np.zeros(3)
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        st, sst = tau_step((args.warmup + i) % n_tau)
+        flops += st["flops_ab"] + st["flops_c"] + sst["flops"]
+        stage_ms += st["ms_stage"]
+        stage_fl += st["flops_stage"]
+        c_ms += st["ms_stage"][2]
+        c_n += st["n_launch"][2]
+        c_fl += st["flops_stage"][2]
+        log(f"[step {i}] tau_{(args.warmup + i) % n_tau} {time.perf_counter() - ts:.2f} s "
+            f"stages(ms) {[round(x, 1) for x in st['ms_stage']]}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = flops / wall / 1e12
+    # dominant kernel: the outer contraction (stage C), timed per launch with
+    # HIP events on the library's stream
+    per_launch_ms = c_ms / max(c_n, 1)
+    achieved = (c_fl / max(c_n, 1)) / (per_launch_ms / 1e3) / 1e12
+    cs = chain["chi_stats"]
+    c_kernel = stage_c_kernel(args.prec, cs["c_variant"], cs["launch_mask"], batched=True)
+    traffic = measured_traffic(args.traffic_json, args.workload + ":tau1", c_kernel)
+    chain_flops = cs["flops_ab"] + cs["flops_c"] + chain["sig_stats"]["flops"]
+    res = {
+        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "paper_context": PAPER_CONTEXT,
+        "dtype": DTYPE[args.prec], "data": "synthetic",
+        "config": {"workload": args.workload, "step": "one tau point: build_gt, chi (one-tau plan), "
+                   "Sigma (correlation part) for tau_j, j cycling over the grid",
+                   "n_atoms": s.n_atoms, "n_ao": s.n_ao, "n_ri": s.n_ri,
+                   "n_occ": s.n_occ, "n_tau": n_tau, "filter_eps": s.filter_eps,
+                   "n_gw": len(states), "n_trip": int(len(ctx["trip"])),
+                   "n_trip_kept": int(cs["n_trip_kept"]),
+                   "bases": "non-orthogonal (Gaussian RI and AO overlaps)" if args.metric
+                   else "orthonormal"},
+        "time_to_qp_s": chain["wall_s"],
+        "chain_stage_ms": {k: round(v, 1) for k, v in chain["ms"].items()},
+        "chain_chi_sigma_tflops": chain_flops / ((chain["ms"]["chi"] + chain["ms"]["sigma"]) / 1e3) / 1e12,
+        "chain_flops": {"chi_ab": cs["flops_ab"], "chi_c": cs["flops_c"],
+                        "sigma": chain["sig_stats"]["flops"]},
+        "step_chi_stage": {"names": ["A (D^occ half)", "B (D^vir half)", "C (outer)"],
+                           "ms_per_step": [round(x / args.steps, 1) for x in stage_ms],
+                           "tflops": [f / (m / 1e3) / 1e12 if m > 0 else None
+                                      for f, m in zip(stage_fl, stage_ms)]},
+        "e_qp": [float(x) for x in chain["e_qp"]],
+        "qp_status": [int(x) for x in chain["status"]],
+        "roofline": {"kernel": c_kernel + " (chi outer contraction)",
+                     "bound": "mfma", "achieved": achieved, "peak": PEAK[args.prec],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.prec],
+                     "traffic": traffic, "launches": int(c_n), "avg_launch_ms": per_launch_ms,
+                     "flops_per_launch": c_fl / max(c_n, 1)},
+        "before_steps_s": t0 - t_start,
+    }
+    log(f"[bench] {value:.2f} TFLOP/s, stage C {achieved:.2f} TFLOP/s, "
+        f"{time.perf_counter() - t_start:.0f} s so far")
+    if not args.no_cpu_baseline:
+        t1 = time.perf_counter()
+        do0, dv0 = gw.build_gt(sysd, Cd, eps, mu, g.tau[:1])
+        res["cpu_baseline"] = cpu_baseline(ctx, do0[0], dv0[0], chain_flops)
+        del do0, dv0
+        log(f"[cpu] oracle {res['cpu_baseline']['value']:.4f} TFLOP/s ({time.perf_counter() - t1:.0f} s)")
+    # precision forms next to the FP64 chain, within the wall budget
+    others = [] if args.no_compare or args.compare == "none" else \
+        [x for x in args.compare.split(",") if x and x != args.prec]
+    forms = {}
+    plan.close()
+    del chi1, do1, dv1
+    del tau_step, wc
+    chain.pop("wc")
+    for other in others:
+        used = time.perf_counter() - t_start
+        if used > args.wall_budget:
+            forms[other] = {"skipped": f"wall budget ({used:.0f} s used of {args.wall_budget:.0f} s)"}
+            continue
+        torch.cuda.empty_cache()
+        o2 = full_chain(ctx, other)
+        log(f"[{other}] chain {o2['wall_s']:.2f} s " +
+            json.dumps({k: round(v, 1) for k, v in o2["ms"].items()}))
+        c2 = o2["chi_stats"]
+        pf = {"chi_ms": o2["ms"]["chi"], "time_to_qp_s": o2["wall_s"],
+              "chi_tflops": (c2["flops_ab"] + c2["flops_c"]) / (o2["ms"]["chi"] / 1e3) / 1e12,
+              "stage_ms": [round(x, 1) for x in c2["ms_stage"]],
+              "chi_speedup_vs_" + args.prec: chain["ms"]["chi"] / o2["ms"]["chi"]}
+        ok = (chain["status"] == 0) & (o2["status"] == 0)
+        de = np.abs(o2["e_qp"] - chain["e_qp"]) * 27211.386245988
+        pf.update({"dE_meV_vs_" + args.prec: [round(float(x), 4) if k else None
+                                              for x, k in zip(de, ok)],
+                   "max_abs_dE_meV": float(de[ok].max()) if ok.any() else None,
+                   "states_within_1meV": int((de[ok] <= 1.0).sum()),
+                   "states_compared": int(ok.sum()),
+                   "status": [int(x) for x in o2["status"]]})
+        forms[other] = pf
+        del o2
+        torch.cuda.empty_cache()
+    if forms:
+        res["precision_form"] = forms
+    res["wall_s"] = time.perf_counter() - t_start
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="strip300")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
@@ -605,6 +826,8 @@ def main():
                     help="time open-shell G0W0 instead, channels split by DELTA Ha per AO")
     ap.add_argument("--metric", action="store_true",
                     help="non-orthogonal RI and AO bases (Gaussian overlaps)")
+    ap.add_argument("--wall-budget", type=float, default=330.0,
+                    help="seconds after which the precision-form legs are skipped")
     ap.add_argument("--t3c-scale", type=float, default=1.0,
                     help="scale of the three-center tensor in the --open-shell mode")
     args = ap.parse_args()
@@ -626,94 +849,7 @@ def main():
     if args.open_shell is not None:
         bench_open_shell(args)
         return
-    ctx = setup(args.workload)
-    if args.metric:
-        use_metric(ctx)
-    for i in range(args.warmup):
-        t0 = time.perf_counter()
-        step(ctx, args.prec)
-        torch.cuda.synchronize()
-        log(f"[warmup {i}] {time.perf_counter() - t0:.2f} s")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = []
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        outs.append(step(ctx, args.prec))
-        log(f"[step {i}] {time.perf_counter() - ts:.2f} s stages(ms) "
-            + json.dumps({k: round(v, 1) for k, v in outs[-1]['ms'].items()}))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    out = outs[-1]
-    cs, ss = out["chi_stats"], out["sig_stats"]
-    chi_ms = float(np.mean([o["ms"]["chi"] for o in outs]))
-    sig_ms = float(np.mean([o["ms"]["sigma"] for o in outs]))
-    flops = cs["flops_ab"] + cs["flops_c"] + ss["flops"]
-    value = flops / ((chi_ms + sig_ms) / 1e3) / 1e12
-    # dominant kernel: the outer contraction (stage C), timed per launch on the library's stream
-    c_ms = float(np.mean([o["chi_stats"]["ms_stage"][2] for o in outs]))
-    c_n = out["chi_stats"]["n_launch"][2]
-    c_flops = out["chi_stats"]["flops_stage"][2]
-    per_launch_ms = c_ms / max(c_n, 1)
-    achieved = (c_flops / max(c_n, 1)) / (per_launch_ms / 1e3) / 1e12
-    c_kernel = stage_c_kernel(args.prec, cs["c_variant"], cs["launch_mask"])
-    traffic = measured_traffic(args.traffic_json, args.workload, c_kernel)
-    s = ctx["s"]
-    res = {
-        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "paper_context": PAPER_CONTEXT,
-        "dtype": DTYPE[args.prec],
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n_atoms": s.n_atoms, "n_ao": s.n_ao, "n_ri": s.n_ri,
-                   "n_occ": s.n_occ, "n_tau": ctx["w"].n_tau, "filter_eps": s.filter_eps,
-                   "n_gw": len(ctx["w"].states()), "n_trip": int(len(ctx["trip"])),
-                   "n_trip_kept": int(cs["n_trip_kept"]),
-                   "bases": "non-orthogonal (Gaussian RI and AO overlaps)" if args.metric
-                   else "orthonormal"},
-        "time_to_qp_s": wall / args.steps,
-        "periodic_coulomb": ctx["coulomb"],
-        "stage_ms": {k: round(v, 2) for k, v in out["ms"].items()},
-        "flops": {"chi_ab": cs["flops_ab"], "chi_c": cs["flops_c"], "sigma": ss["flops"]},
-        "chi_stage": {"names": ["A (D^occ half)", "B (D^vir half)", "C (outer)"],
-                      "ms": [round(x, 1) for x in cs["ms_stage"]],
-                      "tflops": [f / (m / 1e3) / 1e12 if m > 0 else None
-                                 for f, m in zip(cs["flops_stage"], cs["ms_stage"])],
-                      "launches": list(cs["n_launch"])},
-        "e_qp": [float(x) for x in out["e_qp"]], "qp_status": [int(x) for x in out["status"]],
-        "roofline": {"kernel": c_kernel + " (chi outer contraction)",
-                     "bound": "mfma", "achieved": achieved, "peak": PEAK[args.prec],
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.prec],
-                     "traffic": traffic, "launches": int(c_n), "avg_launch_ms": per_launch_ms},
-    }
-    others = [] if args.no_compare or args.compare == "none" else \
-        [x for x in args.compare.split(",") if x and x != args.prec]
-    forms = {}
-    for other in others:
-        t1 = time.perf_counter()
-        o2 = step(ctx, other)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter() - t1
-        pf = {"chi_ms": o2["ms"]["chi"], "time_to_qp_s": t2,
-              "chi_tflops": (o2["chi_stats"]["flops_ab"] + o2["chi_stats"]["flops_c"])
-              / (o2["ms"]["chi"] / 1e3) / 1e12,
-              "stage_ms": [round(x, 1) for x in o2["chi_stats"]["ms_stage"]]}
-        if args.prec == "fp64":
-            ok = (out["status"] == 0) & (o2["status"] == 0)
-            de = np.abs(o2["e_qp"] - out["e_qp"])[ok] * 27211.386245988
-            shift = np.abs(out["e_qp"] - ctx["eps"][ctx["w"].states()])[ok] * 27211.386245988
-            pf.update({"chi_speedup_vs_fp64": out["ms"]["chi"] / o2["ms"]["chi"],
-                       "max_abs_dE_meV_vs_fp64": float(de.max()) if de.size else None,
-                       "dE_meV": [round(float(x), 4) for x in de],
-                       "max_dE_over_shift": float((de / np.maximum(shift, 1e-30)).max())
-                       if de.size else None,
-                       "status": [int(x) for x in o2["status"]]})
-        forms[other] = pf
-    if forms:
-        res["precision_form"] = forms
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(ctx, out)
-    print(json.dumps(res), flush=True)
+    bench_chain(args)
 
 
 if __name__ == "__main__":

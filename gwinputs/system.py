@@ -198,6 +198,60 @@ class System:
         w, v = np.linalg.eigh(linv @ self.hamiltonian() @ linv.T)
         return np.ascontiguousarray((linv.T @ v).T), w
 
+    # ---- atoms of two elements
+    def light_atoms(self, light: np.ndarray, n_ao_light: int, n_ri_light: int) -> dict:
+        """Per-atom sizes: the atoms listed in `light` keep only their first
+        n_ao_light AO and n_ri_light RI functions (the hydrogens at the edge of
+        a nanoribbon beside its carbons), the others all of theirs.  Returns
+        dict(ao_off, ri_off [n_atoms + 1], ao_idx, ri_idx: the kept functions
+        as indices into this system's uniform numbering, ao_mask [n_atoms]
+        [n_ao_atom], ri_mask [n_atoms][n_ri_atom]: 1 for kept functions)."""
+        is_light = np.zeros(self.n_atoms, dtype=bool)
+        is_light[np.asarray(light, dtype=np.int64)] = True
+        na = np.where(is_light, n_ao_light, self.n_ao_atom)
+        nr = np.where(is_light, n_ri_light, self.n_ri_atom)
+        ao_mask = (np.arange(self.n_ao_atom)[None, :] < na[:, None]).astype(np.float64)
+        ri_mask = (np.arange(self.n_ri_atom)[None, :] < nr[:, None]).astype(np.float64)
+        return dict(ao_off=np.concatenate([[0], np.cumsum(na)]).astype(np.int32),
+                    ri_off=np.concatenate([[0], np.cumsum(nr)]).astype(np.int32),
+                    ao_idx=np.nonzero(ao_mask.ravel())[0], ri_idx=np.nonzero(ri_mask.ravel())[0],
+                    ao_mask=ao_mask, ri_mask=ri_mask)
+
+    # ---- s-type Gaussian functions for the three-center integrals of Eq. 4
+    def gaussian_functions(self, ao_alpha=(0.25, 1.2), ao_radius=0.5, ri_alpha=(0.2, 2.0),
+                           ri_radius=0.9):
+        """Normalized s-type Gaussian AO and RI functions, the same set on every
+        atom: function i of an atom sits at the atom plus an offset on a
+        Fibonacci sphere of the given radius (standing in for the angular
+        structure of a real basis; concentric s functions of close exponents
+        are nearly dependent) with an exponent geometric over the given range.
+        Returns dict(ao_exp [n_ao_atom], ao_off [n_ao_atom][3],
+        ri_exp [n_ri_atom], ri_off [n_ri_atom][3])."""
+        def geo(lo_hi, n):
+            lo, hi = lo_hi
+            return lo * (hi / lo) ** (np.arange(n) / max(n - 1, 1))
+        return dict(ao_exp=geo(ao_alpha, self.n_ao_atom),
+                    ao_off=fibonacci_sphere(self.n_ao_atom, ao_radius),
+                    ri_exp=geo(ri_alpha, self.n_ri_atom),
+                    ri_off=fibonacci_sphere(self.n_ri_atom, ri_radius))
+
+    def gaussian_overlap(self, exps: np.ndarray, offs: np.ndarray) -> np.ndarray:
+        """Overlap matrix of normalized s Gaussians (exponents exps, offsets
+        offs, the same on every atom; atom-major order):
+        S_ij = (2 sqrt(a_i a_j) / (a_i + a_j))^(3/2) exp(-a_i a_j d_ij^2 / (a_i + a_j))."""
+        cen = (self.xyz[:, None, :] + np.asarray(offs)[None, :, :]).reshape(-1, 3)
+        a = np.tile(np.asarray(exps, dtype=np.float64), self.n_atoms)
+        d2 = ((cen[:, None, :] - cen[None, :, :]) ** 2).sum(-1)
+        sa = a[:, None] + a[None, :]
+        pa = a[:, None] * a[None, :]
+        return (2.0 * np.sqrt(pa) / sa) ** 1.5 * np.exp(-pa * d2 / sa)
+
+    def all_triples(self) -> np.ndarray:
+        """Every ordered atom triple (a, b, c), sorted by (c, b, a), int32 [n^3, 3]."""
+        n = self.n_atoms
+        c, b, a = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+        return np.ascontiguousarray(np.stack([a.ravel(), b.ravel(), c.ravel()], 1).astype(np.int32))
+
     def ri_charges(self, radius: float = 0.8, alpha_lo: float = 0.5, alpha_hi: float = 2.0):
         """RI functions as normalized Gaussian charges for the periodic
         Coulomb matrix: function p of atom a centred at xyz[a] + o_p (o_p on a

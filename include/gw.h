@@ -27,8 +27,8 @@
  *    host memory (then they synchronize the stream before returning).
  *  - Arguments are validated on the host before any launch; on error nothing
  *    is launched and gw_last_error() describes the problem.
- *  - Matrices are row-major FP64.  All atoms of a system carry the same
- *    number of AO functions (ao_per_atom) and RI functions (ri_per_atom).
+ *  - Matrices are row-major FP64.  Atoms carry ao_per_atom AO and
+ *    ri_per_atom RI functions, or per-atom counts given by offsets (gw_system).
  */
 #ifndef GW_H_
 #define GW_H_
@@ -49,7 +49,9 @@ enum {
   GW_ERR_NOMEM = 3,        /* scratch allocation failed                      */
   GW_ERR_NOT_SPD = 4,      /* Cholesky of V or of epsilon(i w) failed        */
   GW_ERR_NO_CONVERGE = 5,  /* Newton did not converge for at least one state */
-  GW_ERR_BLAS = 6          /* rocBLAS / rocSOLVER returned an error          */
+  GW_ERR_BLAS = 6,         /* rocBLAS / rocSOLVER returned an error          */
+  GW_ERR_AUDIT = 7         /* the screener skipped an output block that the
+                              exact contraction keeps (gw_contract_chi audit) */
 };
 
 /* Arithmetic of the chi contraction: GW_FP64 (FP64 MFMA throughout),
@@ -64,11 +66,25 @@ typedef enum { GW_FP64 = 0, GW_FP32 = 1, GW_BF16X3 = 2 } gw_prec;
  * tensor (mu nu|P) (Eq. 4): mu on AO atom a, nu on AO atom b, P on RI atom c.
  * Brick i of `trip` is stored at t3c + i * ao_per_atom^2 * ri_per_atom as
  * [mu][nu][P] row-major.  The list must contain (b, a, c) whenever it contains
- * (a, b, c) (the tensor is symmetric in mu nu); triples left out are zero. */
+ * (a, b, c) (the tensor is symmetric in mu nu); triples left out are zero.
+ *
+ * Atoms of different elements (the paper's nanoribbons: C and H) carry
+ * different numbers of functions: ao_off / ri_off then give atom a the
+ * functions ao_off[a] .. ao_off[a+1]-1 (1 .. ao_per_atom of them) and
+ * ri_off[a] .. ri_off[a+1]-1 (1 .. ri_per_atom); n_ao = ao_off[n_atoms],
+ * n_ri = ri_off[n_atoms], and every matrix argument (C, D, chi, V, W, S) has
+ * these compact sizes.  The bricks keep the per-atom maxima: element
+ * (mu, nu, P) of brick (a, b, c) for the function numbers mu, nu, P within
+ * the atoms, zero where a function does not exist.  The calls with atom-block
+ * structure (gw_contract_chi, gw_contract_sigma) run on the padded form (the
+ * missing functions as zero functions) and convert their inputs and outputs;
+ * the flop counts in their statistics are those of the padded blocks.  The
+ * batched plans, the block screener and gw_t3c_gaussian take systems without
+ * offsets only (GW_ERR_ARG). */
 typedef struct {
   int32_t n_atoms;
-  int32_t ao_per_atom;     /* n_ao = n_atoms * ao_per_atom                   */
-  int32_t ri_per_atom;     /* n_ri = n_atoms * ri_per_atom                   */
+  int32_t ao_per_atom;     /* n_ao = n_atoms * ao_per_atom (without ao_off)  */
+  int32_t ri_per_atom;     /* n_ri = n_atoms * ri_per_atom (without ri_off)  */
   int32_t n_occ;           /* occupied MOs, 1 <= n_occ < n_ao                */
   int64_t n_trip;
   const int32_t *trip;     /* host [n_trip][3] = (a, b, c)                   */
@@ -76,6 +92,8 @@ typedef struct {
   const double *xyz;       /* host [n_atoms][3] bohr, or NULL; only the block
                               screener uses it (distance feature) and then
                               requires it                                     */
+  const int32_t *ao_off;   /* host [n_atoms+1] per-atom AO offsets, or NULL  */
+  const int32_t *ri_off;   /* host [n_atoms+1] per-atom RI offsets, or NULL  */
 } gw_system;
 
 /* Block screener network (beyond the paper): a perceptron x (F) -> 64 -> 64
@@ -119,6 +137,16 @@ typedef struct {
   int32_t keep_small_blocks; /* 1: skip the output filter (chi blocks below
                               filter_eps are kept; for audits of the skipped
                               mass); 0: the filter of the computational details */
+  int32_t screen_audit;    /* with a screener: 1 = judge the skipped blocks by
+                              the exact contraction (the same call run again
+                              without the screener, on call-owned scratch of
+                              one chi stack): a skipped block whose exact norm
+                              is >= filter_eps (one the filter keeps) fails
+                              the audit                                        */
+  int32_t screen_fallback; /* with screen_audit: 1 = on a failed audit return
+                              the exact chi (bit-equal to the call without a
+                              screener) and GW_OK; 0 = return GW_ERR_AUDIT with
+                              the screened chi left in `chi`                    */
 } gw_chi_opts;
 
 typedef struct {
@@ -154,7 +182,17 @@ typedef struct {
  * (variant 0 when ri_per_atom is not a multiple of 4) with stages B and C
  * persistent (stage B as a grid when the
  * basis has at most 64 AO x RI functions per atom pair), BF16x3 variant 0
- * with all stages persistent). */
+ * with all stages persistent).
+ * With a block screener (opts->screener, beyond the paper; the filter idea of
+ * the computational details) the output blocks (c <= c', tau) predicted below
+ * log10(filter_eps) - screen_margin are not computed and left zero; blocks in
+ * the band above that are computed exactly.  opts->screen_audit makes the
+ * exact contraction the judge: the call runs again without the screener and
+ * every skipped block is compared with the filter's decision on the exact
+ * result (stats: violations, largest skipped norm, skipped mass).  A failed
+ * audit returns GW_ERR_AUDIT, or with opts->screen_fallback the exact chi.
+ * Errors: GW_ERR_ARG (sizes, pointers, options), GW_ERR_NOMEM, GW_ERR_HIP,
+ * GW_ERR_AUDIT. */
 gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double *d_vir,
                           int32_t n_tau, const gw_chi_opts *opts, double *chi,
                           gw_chi_stats *stats, hipStream_t stream);
@@ -307,7 +345,10 @@ typedef struct {
  * The same filter as gw_contract_chi is applied to the bricks and to the D
  * atom blocks.  states: host [n_gw] MO indices; C: dev [n_ao][n_ao];
  * d_occ, d_vir, wc: dev stacks of n_tau; d_occ0: dev [n_ao][n_ao] = D^occ(0);
- * V: dev [n_ri][n_ri]; outputs are host arrays (the call synchronizes). */
+ * V: dev [n_ri][n_ri]; outputs are host arrays (the call synchronizes).
+ * d_occ0, V and sig_x may all be NULL together: the exchange term (which does
+ * not depend on tau) is then skipped, e.g. when the tau points are contracted
+ * one call at a time; giving only some of the three is GW_ERR_ARG. */
 gw_status gw_contract_sigma(const gw_system *s, int32_t n_gw, const int32_t *states,
                             const double *C, const double *d_occ, const double *d_vir,
                             const double *d_occ0, const double *wc, const double *V,
@@ -370,6 +411,17 @@ gw_status gw_evgw_update(int32_t n_mo, int32_t n_occ, const double *eps0, int32_
                          const int32_t *states, const double *e_qp, double *eps_out,
                          double *mu_out);
 
+/* Energy zero mu_F of the Green's function (Eq. 2 decays with tau only for
+ * occupied levels below mu_F and virtual levels above it), host only: the
+ * midpoint of the highest occupied and the lowest virtual level over n_chan
+ * channels (1: closed shell; 2: the spin channels of an open shell, which
+ * share one mu_F).  n_mo, n_occ: host [n_chan]; eps: host [n_chan] arrays of
+ * n_mo[c] energies, the first n_occ[c] occupied.  *mu_out receives mu_F.
+ * GW_ERR_ARG for bad arguments, non-finite energies, or an occupied level at
+ * or above a virtual level of any channel. */
+gw_status gw_fermi_level(int32_t n_chan, const int32_t *n_mo, const int32_t *n_occ,
+                         const double *const *eps, double *mu_out);
+
 /* Screener features of every output block: dev [n_tau][n_atoms][n_atoms][6] =
  * (distance/10 bohr, log10 tau, log10 ||T_c||, log10 ||T_c'||,
  *  log10 ||D^occ_{cc'}(tau)||, log10 ||D^vir_{cc'}(tau)||) with norms over the
@@ -397,6 +449,12 @@ gw_status gw_mlp_train_step(gw_mlp *net, int32_t n, const float *x, const float 
                             float lr, float *loss_dev, hipStream_t stream);
 /* params16 <- params (after the caller changed the FP32 parameters). */
 gw_status gw_mlp_sync_half(gw_mlp *net, hipStream_t stream);
+
+/* Releases the state the library keeps between calls outside plans (the
+ * per-device rocBLAS / rocSOLVER handles of the screening calls); plans are
+ * released by gw_chi_batch_destroy.  Later calls recreate the state on
+ * demand.  Must not overlap with other calls into the library. */
+gw_status gw_finalize(void);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *gw_last_error(void);

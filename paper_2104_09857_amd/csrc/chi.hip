@@ -182,7 +182,9 @@ struct gw_chi_batch {
   std::vector<SysPlan> sys;
   std::vector<int> order;            // systems by decreasing size
   int variant = 0, persistent = 0;
-  int RS = 0;
+  int RS = 0;              // rows of one pivot's half contraction (n_tau * NA)
+  int GB = 1;              // pivots per FP64 / FP32 stage-B launch (a group)
+  int RSB = 0;             // rows of a full group (GB * RS): row stride of dvg
   int ab_nb = AB_NBW;      // 16-column blocks per wave of the stage-A/B tiles
   bool b_dma = false;      // FP32 stage B on the direct-to-LDS engine
   bool a_dma = false;      // FP32 stage A on the direct-to-LDS engine
@@ -234,7 +236,7 @@ struct Index {
 // scratch and problem descriptions of the FP64 / FP32 form of one system
 template <class T>
 gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index& ix, hipStream_t st) {
-  const int n_tau = B.n_tau, NA = B.NA, NR = B.NR, N = P.N, RS = n_tau * NA;
+  const int n_tau = B.n_tau, NA = B.NA, NR = B.NR, N = P.N, RS = B.RSB;
   Scratch& M = B.mem;
   FBufs<T>& F = bufs<T>(P);
   gw_status rc;
@@ -264,9 +266,10 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
                  "column panel too large for 32-bit tile offsets");
   if ((rc = M.alloc(&F.dvg, (size_t)N * RS)) != GW_OK) return rc;
   if ((rc = M.alloc(&F.mb, (size_t)n_tau * NA * P.nRmax * N * NR)) != GW_OK) return rc;
-  if ((rc = M.alloc(&F.bp, (size_t)n_tau * P.BPS)) != GW_OK) return rc;
+  // N_b of every pivot of a stage-B group: [pivot][tau] slabs of BPS
+  if ((rc = M.alloc(&F.bp, (size_t)B.GB * n_tau * P.BPS)) != GW_OK) return rc;
   // entries of N_b that no group writes stay zero for the life of the plan
-  GW_HIP(hipMemsetAsync(F.bp, 0, sizeof(T) * (size_t)n_tau * P.BPS, st));
+  GW_HIP(hipMemsetAsync(F.bp, 0, sizeof(T) * (size_t)B.GB * n_tau * P.BPS, st));
 
   StageA<T>& sa = F.sa;
   sa.dof = F.dof; sa.t3c = F.t3c; sa.mb = F.mb; sa.goff = ix.goff; sa.seg_atom = ix.seg_atom;
@@ -281,7 +284,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
   StageB<T>& sb = F.sb;
   sb.dvg = F.dvg; sb.t3c = F.t3c; sb.bp = F.bp; sb.goff = ix.goff; sb.seg_atom = ix.seg_atom;
   sb.seg_brick = ix.seg_brick; sb.gc = ix.gc; sb.gslot = ix.gslot; sb.ulen = ix.ulen;
-  sb.bp_off = ix.bp_off; sb.RS = RS; sb.NA = NA; sb.NR = NR; sb.PG = P.PG; sb.PC = P.PC;
+  sb.bp_off = ix.bp_off; sb.RS = RS; sb.ld = RS; sb.NA = NA; sb.NR = NR; sb.PG = P.PG; sb.PC = P.PC;
   sb.bs = P.bs; sb.bs32 = (int)P.bs; sb.BPS = P.BPS;
   sb.rows_pt = 32 * b_wm(RS);
   sb.cols_pt = 16 * B.ab_nb * AB_WN;
@@ -366,6 +369,15 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
   if ((rc = M.upload(&d_bp_off, P.pan.off)) != GW_OK) return rc;
 
   const Index ix{d_goff, d_seg_atom, d_gc, d_gslot, d_ulen, d_kmap, d_km_off, d_seg_brick, d_bp_off};
+  if (B.GB == 0) {
+    // pivots per stage-B launch, fixed by the first system of the plan: up to
+    // 160 rows (pivot, tau, sigma) per tile, the group's N_b within 16 GiB
+    const int64_t tsz = B.prec == GW_FP64 ? 8 : 4;
+    int gb = B.prec == GW_BF16X3 ? 1 : std::max(1, 160 / B.RS);
+    while (gb > 1 && (int64_t)gb * n_tau * P.BPS * tsz > (16ll << 30)) --gb;
+    B.GB = gb;
+    B.RSB = gb * B.RS;
+  }
   if (B.prec == GW_FP64) {
     if ((rc = prepare_f<double>(B, P, s, ix, st)) != GW_OK) return rc;
   } else if (B.prec == GW_FP32) {
@@ -471,8 +483,15 @@ gw_status ab_tables_f(gw_chi_batch& B, hipStream_t st) {
       StageA<T> a = pb.sa;
       a.g0 = g0;
       F.tA.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
-      F.tB.add(piv, pb.sb, P.n_groups * pb.sb.n_rt * pb.sb.n_ct, 1, 1);
-      F.gath.push_back(GatherEnt<T>{pb.dvf, pb.dvg, P.N, piv});
+      // stage B once per group of GB pivots, at its first pivot: rows
+      // (pivot, tau, sigma) of the group's pivots this system has
+      if (piv % B.GB != 0) continue;
+      const int ng = std::min(B.GB, P.na - piv);
+      StageB<T> b = pb.sb;
+      b.RS = ng * B.RS;
+      b.n_rt = (b.RS + b.rows_pt - 1) / b.rows_pt;
+      F.tB.add(piv, b, P.n_groups * b.n_rt * b.n_ct, 1, 1);
+      F.gath.push_back(GatherEnt<T>{pb.dvf, pb.dvg, P.N, piv, ng});
       F.gathn[piv]++;
     }
   }
@@ -516,6 +535,7 @@ gw_status build_ab_tables(gw_chi_batch& B, hipStream_t st) {
 // stage-C tables for the current variant and output pointers
 template <class C, class Get>
 void c_tables(gw_chi_batch& B, Table<C>& tab, Get get, double* const* chi) {
+  // get(P, piv): the system's stage-C problem for pivot piv
   const int n_piv = B.max_na, n_tau = B.n_tau, rows = c_rows(B.prec, B.variant);
   tab.begin(n_piv);
   for (int piv = 0; piv < n_piv; ++piv) {
@@ -526,7 +546,7 @@ void c_tables(gw_chi_batch& B, Table<C>& tab, Get get, double* const* chi) {
       const int nR = pivot_groups(P, piv, g0);
       if (nR == 0) continue;
       const int n_rt = (nR * B.NR + rows - 1) / rows;
-      C c = get(P);
+      C c = get(P, piv);
       c.chi = chi[m];
       c.g0 = g0;
       c.nR = nR;
@@ -541,14 +561,24 @@ void c_tables(gw_chi_batch& B, Table<C>& tab, Get get, double* const* chi) {
 
 gw_status build_c_tables(gw_chi_batch& B, double* const* chi, hipStream_t st) {
   gw_status rc;
+  // FP64 / FP32: pivot piv reads its slab of the group's N_b
+  const int64_t slab = (int64_t)B.n_tau;
   if (B.prec == GW_FP64) {
-    c_tables(B, B.t64.tC, [](SysPlan& P) { return P.f64.sc; }, chi);
+    c_tables(B, B.t64.tC, [&](SysPlan& P, int piv) {
+      StageC<double> c = P.f64.sc;
+      c.bp += (piv % B.GB) * slab * P.BPS;
+      return c;
+    }, chi);
     rc = B.t64.tC.upload(B.mem, st);
   } else if (B.prec == GW_FP32) {
-    c_tables(B, B.t32.tC, [](SysPlan& P) { return P.f32.sc; }, chi);
+    c_tables(B, B.t32.tC, [&](SysPlan& P, int piv) {
+      StageC<float> c = P.f32.sc;
+      c.bp += (piv % B.GB) * slab * P.BPS;
+      return c;
+    }, chi);
     rc = B.t32.tC.upload(B.mem, st);
   } else {
-    c_tables(B, B.tCb, [](SysPlan& P) { return P.bc; }, chi);
+    c_tables(B, B.tCb, [](SysPlan& P, int) { return P.bc; }, chi);
     rc = B.tCb.upload(B.mem, st);
   }
   if (rc != GW_OK) return rc;
@@ -628,7 +658,7 @@ hipError_t stage_a_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStrea
 }
 template <int NB, class Tab>
 hipError_t stage_b_rows(const gw_chi_batch& B, const Tab& t, int piv, bool pers, int* q, hipStream_t st) {
-  switch (b_wm(B.RS)) {
+  switch (b_wm(B.RSB)) {
     case 2: return run_mfma<2, AB_WN, NB, 16>(t, piv, pers, q, st);
     case 3: return run_mfma<3, AB_WN, NB, 16>(t, piv, pers, q, st);
     case 5: return run_mfma<5, AB_WN, NB, 16>(t, piv, pers, q, st);
@@ -637,7 +667,7 @@ hipError_t stage_b_rows(const gw_chi_batch& B, const Tab& t, int piv, bool pers,
 }
 template <int NB, class Tab>
 hipError_t stage_b_dma_rows(const gw_chi_batch& B, const Tab& t, int piv, bool pers, int* q, hipStream_t st) {
-  switch (b_wm(B.RS)) {
+  switch (b_wm(B.RSB)) {
     case 2: return run_dma<2, AB_WN, NB, 16, 2>(t, piv, pers, q, st);
     case 3: return run_dma<3, AB_WN, NB, 16, 2>(t, piv, pers, q, st);
     case 5: return run_dma<5, AB_WN, NB, 16, 2>(t, piv, pers, q, st);
@@ -724,10 +754,10 @@ gw_status pivot_f(gw_chi_batch& B, int piv, int pers, int* q, std::vector<hipEve
   if (F.gathn[piv] > 0) {
     int64_t most = 0;
     for (int e = 0; e < F.gathn[piv]; ++e)
-      most = std::max<int64_t>(most, (int64_t)F.gath[F.gath0[piv] + e].N * B.RS);
+      most = std::max<int64_t>(most, (int64_t)F.gath[F.gath0[piv] + e].N * B.RSB);
     const unsigned bx = (unsigned)std::min<int64_t>((most + 255) / 256, 4096);
     hipLaunchKernelGGL(gather_dvir_kernel<T>, dim3(bx, (unsigned)F.gathn[piv]), dim3(256), 0, st,
-                       F.d_gath + F.gath0[piv], B.NA, B.n_tau);
+                       F.d_gath + F.gath0[piv], B.NA, B.n_tau, B.RSB);
     GW_HIP(hipGetLastError());
   }
   GW_HIP(mark(0));
@@ -942,10 +972,8 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   B->NA = NA;
   B->NR = NR;
   B->RS = n_tau * NA;
+  B->GB = 0;               // set by the first system (prepare_sys)
   B->ab_nb = ab_nb(NA * NR);
-  // 16-byte copies need the rows of the gathered D^vir (n_tau * NA floats) and
-  // the brick rows (NA * NR floats) in whole groups of four
-  B->b_dma = prec == GW_FP32 && NR % 4 == 0 && (n_tau * NA) % 4 == 0;
   B->prec = prec;
   B->eps_f = eps_f;
   B->timing = opts && opts->timing;
@@ -965,6 +993,9 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
     if ((rc = prepare_sys(*B, B->sys[m], &systems[m], st)) != GW_OK) return rc;
     B->max_na = std::max(B->max_na, systems[m].n_atoms);
   }
+  // 16-byte copies need the rows of the gathered D^vir (GB * n_tau * NA floats)
+  // and the brick rows (NA * NR floats) in whole groups of four
+  B->b_dma = prec == GW_FP32 && NR % 4 == 0 && B->RSB % 4 == 0;
   // largest systems first: their tiles lead every batched launch
   B->order.resize(n_sys);
   std::iota(B->order.begin(), B->order.end(), 0);
@@ -1001,6 +1032,10 @@ extern "C" gw_status gw_chi_batch_create(int32_t n_sys, const gw_system* systems
                                          const gw_chi_opts* opts, gw_chi_batch** plan,
                                          hipStream_t st) {
   clear_error();
+  if (systems && n_sys >= 1 && n_sys <= 65536)
+    for (int32_t m = 0; m < n_sys; ++m)
+      GW_CHECK_ARG(!systems[m].ao_off && !systems[m].ri_off,
+                   "batched plans take systems without per-atom offsets (use gw_contract_chi)");
   GW_CHECK_ARG(!(opts && opts->screener), "the batched form takes no screener");
   return create(n_sys, systems, n_tau, opts, plan, st);
 }
@@ -1136,6 +1171,27 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
   gw_status rc = check_system(s);
   if (rc != GW_OK) return rc;
   GW_CHECK_ARG(d_occ && d_vir && chi, "d_occ, d_vir and chi must be non-null");
+  if (s->ao_off || s->ri_off) {
+    // per-atom sizes: the padded system (missing functions as zero functions)
+    GW_CHECK_ARG(!(opts && opts->screener), "the block screener takes systems without per-atom offsets");
+    GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
+    Scratch sc(st);
+    PadMaps pm;
+    if ((rc = pad_maps(s, sc, pm)) != GW_OK) return rc;
+    double *po, *pv, *pc;
+    if ((rc = sc.alloc(&po, (size_t)n_tau * pm.N * pm.N)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&pv, (size_t)n_tau * pm.N * pm.N)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&pc, (size_t)n_tau * pm.NRI * pm.NRI)) != GW_OK) return rc;
+    GW_HIP(scatter_square(d_occ, pm.n_ao, po, pm.N, pm.ao, n_tau, st));
+    GW_HIP(scatter_square(d_vir, pm.n_ao, pv, pm.N, pm.ao, n_tau, st));
+    const gw_system ps = padded_view(s);
+    if ((rc = gw_contract_chi(&ps, po, pv, n_tau, opts, pc, stats, st)) != GW_OK) return rc;
+    GW_HIP(gather_square(pc, pm.NRI, chi, pm.n_ri, pm.ri, n_tau, st));
+    GW_HIP(hipStreamSynchronize(st));
+    if (stats)
+      stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return GW_OK;
+  }
   const bool screening = opts && opts->screener && opts->filter_eps > 0.0;
   if (screening) {
     GW_CHECK_ARG(opts->screen_tau != nullptr, "screen_tau is required with a screener");
@@ -1176,8 +1232,82 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
     GW_HIP(hipStreamSynchronize(st));
   }
   if ((rc = execute(*B, &d_occ, &d_vir, &chi, false, stats, st)) != GW_OK) return rc;
+  // audit: the exact contraction (same plan, no screener, no output filter)
+  // judges every skipped block by the output filter's own FP64 decision
+  gw_chi_stats audit{};
+  bool audit_failed = false;
+  if (screening && opts->screen_audit && !keep_h.empty()) {
+    const auto t_a = std::chrono::steady_clock::now();
+    const int64_t nb = (int64_t)n_tau * na * na;
+    const int64_t nsq = (int64_t)P.NRI * P.NRI;
+    Scratch sc(st);
+    double* ex;
+    float* nrm;
+    uint8_t* small;
+    if ((rc = sc.alloc(&ex, (size_t)n_tau * nsq)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&nrm, (size_t)nb)) != GW_OK) return rc;
+    if ((rc = sc.alloc(&small, (size_t)nb)) != GW_OK) return rc;
+    uint8_t* keep_dev = P.keep;
+    const bool out_filter = B->out_filter;
+    P.keep = nullptr;
+    B->out_filter = false;
+    B->c_built_variant = -1;            // rebuild the stage-C tables without the mask
+    rc = execute(*B, &d_occ, &d_vir, &ex, false, nullptr, st);
+    P.keep = keep_dev;
+    B->out_filter = out_filter;
+    if (rc != GW_OK) return rc;
+    GW_HIP(block_norms_f32(ex, n_tau, na, B->NR, 0, nrm, st));
+    // small[e] = 1 for blocks the output filter zeroes (norm < filter_eps, FP64)
+    GW_HIP(filter_square_blocks(ex, ex, n_tau, na, B->NR, opts->filter_eps, small, st));
+    std::vector<float> nh(nb);
+    std::vector<uint8_t> sh(nb);
+    GW_HIP(hipMemcpyAsync(nh.data(), nrm, sizeof(float) * nb, hipMemcpyDeviceToHost, st));
+    GW_HIP(hipMemcpyAsync(sh.data(), small, nb, hipMemcpyDeviceToHost, st));
+    GW_HIP(hipStreamSynchronize(st));
+    double mass = 0.0, total = 0.0, mx = 0.0;
+    int64_t viol = 0;
+    for (int j = 0; j < n_tau; ++j)
+      for (int c = 0; c < na; ++c)
+        for (int c2 = 0; c2 < na; ++c2) {
+          const int64_t e = ((int64_t)j * na + c) * na + c2;
+          const double v = nh[e];
+          total += v * v;
+          const int64_t u = ((int64_t)j * na + std::min(c, c2)) * na + std::max(c, c2);
+          if (keep_h[u]) continue;
+          mass += v * v;
+          mx = std::max(mx, v);
+          if (!sh[e] && c <= c2) ++viol;
+        }
+    audit.audit_done = 1;
+    audit.n_audit_violations = viol;
+    audit.audit_max_skipped = mx;
+    audit.audit_skipped_mass = total > 0.0 ? std::sqrt(mass / total) : 0.0;
+    audit_failed = viol > 0;
+    if (audit_failed && opts->screen_fallback) {
+      // ex now holds the exact chi after the output filter: the plain result
+      // (unless the caller asked to keep the small blocks)
+      if (out_filter) {
+        GW_HIP(hipMemcpyAsync(chi, ex, sizeof(double) * n_tau * nsq, hipMemcpyDeviceToDevice, st));
+      } else {
+        B->c_built_variant = -1;
+        P.keep = nullptr;
+        rc = execute(*B, &d_occ, &d_vir, &chi, false, nullptr, st);
+        P.keep = keep_dev;
+        if (rc != GW_OK) return rc;
+      }
+      GW_HIP(hipStreamSynchronize(st));
+      audit.audit_fallback = 1;
+    }
+    audit.audit_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
+  }
   if (stats) {
-    if (!keep_h.empty()) {
+    stats->audit_done = audit.audit_done;
+    stats->audit_fallback = audit.audit_fallback;
+    stats->n_audit_violations = audit.n_audit_violations;
+    stats->audit_max_skipped = audit.audit_max_skipped;
+    stats->audit_skipped_mass = audit.audit_skipped_mass;
+    stats->audit_ms = audit.audit_ms;
+    if (!keep_h.empty() && !audit.audit_fallback) {
       int skipped = 0;
       GW_HIP(hipMemcpyAsync(&skipped, B->tiles_skipped, sizeof(int), hipMemcpyDeviceToHost, st));
       GW_HIP(hipStreamSynchronize(st));
@@ -1206,6 +1336,12 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
       stats->flops_stage[2] = fl;
     }
     stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  if (audit_failed && !audit.audit_fallback) {
+    set_error("screener audit failed: " + std::to_string(audit.n_audit_violations) +
+              " skipped output blocks are kept by the exact contraction's filter (largest skipped "
+              "norm " + std::to_string(audit.audit_max_skipped) + ")");
+    return GW_ERR_AUDIT;
   }
   return GW_OK;
 }

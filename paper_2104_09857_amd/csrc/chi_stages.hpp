@@ -117,7 +117,7 @@ struct StageB {
   };
   static constexpr bool kAScale = false, kDot = false;
   static constexpr int kTabA = kSegTab, kTabB = kSegTab;
-  const T* dvg;             // [N][RS]
+  const T* dvg;             // [N][ld]: rows (pivot of the group, tau, sigma)
   const T* t3c;
   T* bp;
   const int32_t* goff;
@@ -128,7 +128,8 @@ struct StageB {
   const int32_t* ulen;
   const int64_t* bp_off;
   int n_rt, n_ct, rows_pt, cols_pt;
-  int RS, NA, NR, PG, PC;
+  int RS, NA, NR, PG, PC;   // RS: rows of this group (its pivots x n_tau x NA)
+  int ld;                   // row stride of dvg (the plan's group rows)
   int64_t bs, BPS;
   int bs32;
   FastDiv fdNA, fdNR;
@@ -158,12 +159,12 @@ struct StageB {
     }
   }
   __device__ const T* abase(const Tile& t) const { return dvg + t.row0; }
-  // A(r = (tau, sigma), k = (segment sg, nu = ta[sg] * NA + u)) = dvg[nu][r]
+  // A(r = (pivot, tau, sigma), k = (segment sg, nu = ta[sg] * NA + u)) = dvg[nu][r]
   static constexpr bool kAStep = true;
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
   __device__ int adiv(const Tile&) const { return NA; }
   __device__ uint32_t akoff2(const Tile&, int sg, int u, const int* ta) const {
-    return (uint32_t)(ta[sg] * NA + u) * (uint32_t)RS;
+    return (uint32_t)(ta[sg] * NA + u) * (uint32_t)ld;
   }
   __device__ const T* bbase(const Tile& t) const { return t3c + t.col0; }
   __device__ int64_t bkoff(const Tile&, int k, const int* tb) const {
@@ -171,7 +172,8 @@ struct StageB {
     return (int64_t)tb[sg] * bs32 + i * NA * NR;
   }
   __device__ T ascale(const Tile&, int) const { return T(1); }
-  // N_b panel: [tau][panel][sigma][u = slot*NA + mu][(cl, Q)]: row (tau, sigma), column (mu, Q)
+  // N_b panel: [pivot][tau][panel][sigma][u = slot*NA + mu][(cl, Q)]: row (pivot, tau,
+  // sigma), column (mu, Q); (pivot, tau) is one merged index of BPS-sized slabs
   __device__ T* obase(const Tile& t) const { return bp + bp_off[t.p]; }
   __device__ int64_t rowoff(const Tile& t, int r) const {
     const int row = t.row0 + r, tau = (int)fdNA.div((uint32_t)row), sg = row - tau * NA;
@@ -281,25 +283,28 @@ struct StageC {
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
-// D^vir columns of pivot atom b, gathered as dvg[nu][(tau, sigma)] for the
-// systems of one batch (blockIdx.y = entry)
+// D^vir columns of the pivot atoms b .. b + ng - 1 of one stage-B group,
+// gathered as dvg[nu][(g, tau, sigma)] (row stride ld; rows of pivots beyond
+// ng are zero) for the systems of one batch (blockIdx.y = entry)
 template <class T>
 struct GatherEnt {
   const T* dv;
   T* dvg;
-  int N, b;
+  int N, b, ng;
 };
 
 template <class T>
-__global__ void gather_dvir_kernel(const GatherEnt<T>* __restrict__ ents, int NA, int n_tau) {
+__global__ void gather_dvir_kernel(const GatherEnt<T>* __restrict__ ents, int NA, int n_tau, int ld) {
   const GatherEnt<T> en = ents[blockIdx.y];
-  const int RS = n_tau * NA, N = en.N;
-  const int64_t total = (int64_t)N * RS;
+  const int RS1 = n_tau * NA, N = en.N;
+  const int64_t total = (int64_t)N * ld;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int nu = (int)(e / RS), rc = (int)(e % RS);
-    const int tau = rc / NA, sg = rc % NA;
-    en.dvg[e] = en.dv[(int64_t)tau * N * N + (int64_t)nu * N + (int64_t)en.b * NA + sg];
+    const int nu = (int)(e / ld), rc = (int)(e % ld);
+    const int g = rc / RS1, r2 = rc - g * RS1;
+    const int tau = r2 / NA, sg = r2 - tau * NA;
+    en.dvg[e] = g < en.ng ? en.dv[(int64_t)tau * N * N + (int64_t)nu * N + (int64_t)(en.b + g) * NA + sg]
+                          : T(0);
   }
 }
 

@@ -13,14 +13,49 @@ static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 
-gw_status check_system(const gw_system* s) {
+// per-atom function offsets: monotone from 0, 1 .. per functions per atom
+static gw_status check_offsets(const int32_t* off, int n_atoms, int per, const char* what) {
+  if (!off) return GW_OK;
+  if (off[0] != 0) {
+    set_error(std::string(what) + "[0] must be 0");
+    return GW_ERR_ARG;
+  }
+  for (int a = 0; a < n_atoms; ++a) {
+    const int64_t k = (int64_t)off[a + 1] - off[a];
+    if (k < 1 || k > per) {
+      set_error(std::string(what) + ": atom " + std::to_string(a) + " carries " + std::to_string(k) +
+                " functions, outside [1, " + std::to_string(per) + "]");
+      return GW_ERR_ARG;
+    }
+  }
+  return GW_OK;
+}
+
+int64_t sys_n_ao(const gw_system* s) {
+  return s->ao_off ? (int64_t)s->ao_off[s->n_atoms] : (int64_t)s->n_atoms * s->ao_per_atom;
+}
+int64_t sys_n_ri(const gw_system* s) {
+  return s->ri_off ? (int64_t)s->ri_off[s->n_atoms] : (int64_t)s->n_atoms * s->ri_per_atom;
+}
+
+gw_status check_system_sizes(const gw_system* s) {
   GW_CHECK_ARG(s != nullptr, "system is null");
   GW_CHECK_ARG(s->n_atoms > 0, "n_atoms must be positive");
   GW_CHECK_ARG(s->ao_per_atom > 0 && s->ri_per_atom > 0, "atom sizes must be positive");
-  const int64_t n_ao = (int64_t)s->n_atoms * s->ao_per_atom;
-  GW_CHECK_ARG(n_ao < (1 << 30) && (int64_t)s->n_atoms * s->ri_per_atom < (1 << 30),
+  GW_CHECK_ARG((int64_t)s->n_atoms * s->ao_per_atom < (1 << 30) &&
+                   (int64_t)s->n_atoms * s->ri_per_atom < (1 << 30),
                "system too large");
+  gw_status rc;
+  if ((rc = check_offsets(s->ao_off, s->n_atoms, s->ao_per_atom, "ao_off")) != GW_OK) return rc;
+  if ((rc = check_offsets(s->ri_off, s->n_atoms, s->ri_per_atom, "ri_off")) != GW_OK) return rc;
+  const int64_t n_ao = sys_n_ao(s);
   GW_CHECK_ARG(s->n_occ >= 1 && s->n_occ < n_ao, "n_occ must be in [1, n_ao)");
+  return GW_OK;
+}
+
+gw_status check_system(const gw_system* s) {
+  gw_status rc = check_system_sizes(s);
+  if (rc != GW_OK) return rc;
   GW_CHECK_ARG(s->n_trip >= 0, "n_trip must be >= 0");
   GW_CHECK_ARG(s->n_trip == 0 || (s->trip != nullptr && s->t3c != nullptr),
                "trip and t3c must be given when n_trip > 0");
@@ -33,6 +68,90 @@ gw_status check_system(const gw_system* s) {
   return GW_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Systems with per-atom sizes run on their padded form: atom a's functions
+// occupy the first n_a of its ao_per_atom (ri_per_atom) slots, the other
+// slots are zero functions.  map[i] = padded index of compact function i.
+gw_status pad_maps(const gw_system* s, Scratch& sc, PadMaps& m) {
+  m.n_ao = (int)sys_n_ao(s);
+  m.n_ri = (int)sys_n_ri(s);
+  m.N = s->n_atoms * s->ao_per_atom;
+  m.NRI = s->n_atoms * s->ri_per_atom;
+  auto build = [&](const int32_t* off, int per, int n) {
+    std::vector<int32_t> v(n);
+    for (int a = 0, i = 0; a < s->n_atoms; ++a) {
+      const int k = off ? off[a + 1] - off[a] : per;
+      for (int j = 0; j < k; ++j) v[i++] = a * per + j;
+    }
+    return v;
+  };
+  gw_status rc = sc.upload(&m.ao, build(s->ao_off, s->ao_per_atom, m.n_ao));
+  if (rc != GW_OK) return rc;
+  return sc.upload(&m.ri, build(s->ri_off, s->ri_per_atom, m.n_ri));
+}
+
+gw_system padded_view(const gw_system* s) {
+  gw_system p = *s;
+  p.ao_off = nullptr;
+  p.ri_off = nullptr;
+  return p;
+}
+
+// out[m][map[i]][map[j]] = in[m][i][j] (rows of cols_in doubles, cols map)
+__global__ void scatter_square_kernel(const double* __restrict__ in, int n_rows, int n, int ld_in,
+                                      double* __restrict__ out, int np, const int32_t* __restrict__ rmap,
+                                      const int32_t* __restrict__ cmap, int64_t n_mat) {
+  const int64_t per = (int64_t)n_rows * n, total = n_mat * per;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = e / per;
+    const int r = (int)((e - m * per) / n), c = (int)(e - m * per - (int64_t)r * n);
+    const int rp = rmap ? rmap[r] : r;
+    out[m * (int64_t)(rmap ? np : n_rows) * np + (int64_t)rp * np + cmap[c]] =
+        in[m * (int64_t)n_rows * ld_in + (int64_t)r * ld_in + c];
+  }
+}
+
+// out[m][i][j] = in[m][map[i]][map[j]]
+__global__ void gather_square_kernel(const double* __restrict__ in, int np, double* __restrict__ out,
+                                     int n, const int32_t* __restrict__ map, int64_t n_mat) {
+  const int64_t per = (int64_t)n * n, total = n_mat * per;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = e / per;
+    const int i = (int)((e - m * per) / n), j = (int)(e - m * per - (int64_t)i * n);
+    out[e] = in[m * (int64_t)np * np + (int64_t)map[i] * np + map[j]];
+  }
+}
+
+static unsigned blocks_for(int64_t total) {
+  return (unsigned)std::min<int64_t>(std::max<int64_t>((total + 255) / 256, 1), 1 << 20);
+}
+
+hipError_t scatter_square(const double* in, int n, double* out, int np, const int32_t* map,
+                          int64_t n_mat, hipStream_t st) {
+  hipError_t e = fill_zero(out, 2 * n_mat * (int64_t)np * np, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scatter_square_kernel, dim3(blocks_for(n_mat * n * n)), dim3(256), 0, st, in, n,
+                     n, n, out, np, map, map, n_mat);
+  return hipGetLastError();
+}
+
+hipError_t scatter_cols(const double* in, int rows, int n, double* out, int np, const int32_t* map,
+                        hipStream_t st) {
+  hipError_t e = fill_zero(out, 2 * (int64_t)rows * np, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scatter_square_kernel, dim3(blocks_for((int64_t)rows * n)), dim3(256), 0, st, in,
+                     rows, n, n, out, np, (const int32_t*)nullptr, map, (int64_t)1);
+  return hipGetLastError();
+}
+
+hipError_t gather_square(const double* in, int np, double* out, int n, const int32_t* map,
+                         int64_t n_mat, hipStream_t st) {
+  hipLaunchKernelGGL(gather_square_kernel, dim3(blocks_for(n_mat * n * n)), dim3(256), 0, st, in, np,
+                     out, n, map, n_mat);
+  return hipGetLastError();
+}
 
 gw_status build_groups(const gw_system* s, double eps, hipStream_t st, Scratch& sc,
                        BrickGroups& out) {

@@ -87,6 +87,31 @@ hipError_t fill_zero(void* x, int64_t n_words32, hipStream_t st);
 
 // Validates the system description (host side, before any launch).
 gw_status check_system(const gw_system* s);
+// The same without the triple list (sizes, offsets, occupation).
+gw_status check_system_sizes(const gw_system* s);
+// AO / RI function counts (the offsets' totals, or atoms x per-atom size).
+int64_t sys_n_ao(const gw_system* s);
+int64_t sys_n_ri(const gw_system* s);
+
+// Systems with per-atom sizes (ao_off / ri_off) run on their padded form:
+// atom a's functions take the first of its ao_per_atom (ri_per_atom) slots.
+// ao / ri: device maps compact function index -> padded index.
+struct PadMaps {
+  int n_ao = 0, n_ri = 0, N = 0, NRI = 0;
+  int32_t *ao = nullptr, *ri = nullptr;
+};
+gw_status pad_maps(const gw_system* s, Scratch& sc, PadMaps& m);
+// the same system without offsets (its padded form; bricks are already padded)
+gw_system padded_view(const gw_system* s);
+// out[m] (np x np, zeroed first) with out[m][map[i]][map[j]] = in[m][i][j]
+hipError_t scatter_square(const double* in, int n, double* out, int np, const int32_t* map,
+                          int64_t n_mat, hipStream_t st);
+// out (rows x np, zeroed first) with out[r][map[j]] = in[r][j]
+hipError_t scatter_cols(const double* in, int rows, int n, double* out, int np, const int32_t* map,
+                        hipStream_t st);
+// out[m][i][j] = in[m][map[i]][map[j]] (in: np x np per matrix)
+hipError_t gather_square(const double* in, int np, double* out, int n, const int32_t* map,
+                         int64_t n_mat, hipStream_t st);
 
 // Kept bricks grouped by (second atom s, RI atom c); each group lists the
 // bricks (f, s, c) in ascending first atom f.  Groups are ordered by (s, c).

@@ -167,3 +167,39 @@ extern "C" gw_status gw_evgw_update(int32_t n_mo, int32_t n_occ, const double* e
   }
   return GW_OK;
 }
+
+// Energy zero of the Green's function (Eq. 2 decays in tau only when every
+// occupied level lies below it and every virtual level above): the midpoint
+// of the highest occupied and the lowest virtual level over all channels.
+extern "C" gw_status gw_fermi_level(int32_t n_chan, const int32_t* n_mo, const int32_t* n_occ,
+                                    const double* const* eps, double* mu_out) {
+  gw::clear_error();
+  if (n_chan < 1 || n_chan > 16 || !n_mo || !n_occ || !eps || !mu_out) {
+    gw::set_error("gw_fermi_level: n_chan in [1, 16] and non-null arrays required");
+    return GW_ERR_ARG;
+  }
+  double homo = -INFINITY, lumo = INFINITY;
+  for (int c = 0; c < n_chan; ++c) {
+    if (!eps[c] || n_mo[c] < 2 || n_occ[c] < 0 || n_occ[c] > n_mo[c]) {
+      gw::set_error("gw_fermi_level: channel " + std::to_string(c) +
+                    " needs eps and 0 <= n_occ <= n_mo, n_mo >= 2");
+      return GW_ERR_ARG;
+    }
+    for (int i = 0; i < n_mo[c]; ++i) {
+      const double e = eps[c][i];
+      if (!std::isfinite(e)) {
+        gw::set_error("gw_fermi_level: non-finite energy");
+        return GW_ERR_ARG;
+      }
+      if (i < n_occ[c]) homo = std::max(homo, e);
+      else lumo = std::min(lumo, e);
+    }
+  }
+  if (!(homo < lumo)) {
+    gw::set_error("gw_fermi_level: an occupied level lies at or above a virtual level "
+                  "(no energy zero between them; the Green's function would not decay)");
+    return GW_ERR_ARG;
+  }
+  *mu_out = 0.5 * (homo + lumo);
+  return GW_OK;
+}

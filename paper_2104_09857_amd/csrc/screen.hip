@@ -106,6 +106,32 @@ gw_status get_handle(hipStream_t st, rocblas_handle* h) {
   return GW_OK;
 }
 
+}  // namespace
+}  // namespace gw
+
+// Releases the per-device rocBLAS / rocSOLVER handles the screening calls
+// keep between calls; later calls create them again.
+extern "C" gw_status gw_finalize(void) {
+  gw::clear_error();
+  std::lock_guard<std::mutex> lk(gw::g_handle_mu);
+  int cur = 0;
+  GW_HIP(hipGetDevice(&cur));
+  gw_status rc = GW_OK;
+  for (int dev = 0; dev < 64; ++dev) {
+    if (!gw::g_handle[dev]) continue;
+    if (hipSetDevice(dev) != hipSuccess || rocblas_destroy_handle(gw::g_handle[dev]) != rocblas_status_success) {
+      gw::set_error("releasing the rocBLAS handle of device " + std::to_string(dev) + " failed");
+      rc = GW_ERR_BLAS;
+    }
+    gw::g_handle[dev] = nullptr;
+  }
+  GW_HIP(hipSetDevice(cur));
+  return rc;
+}
+
+namespace gw {
+namespace {
+
 #define GW_BLAS(call)                                                          \
   do {                                                                         \
     rocblas_status s_ = (call);                                                \
@@ -129,8 +155,9 @@ gw_status screen_impl(const gw_system* s, const double* chi, const double* chi2,
                       const double* Smet, int32_t n_tau, int32_t n_w, const double* cos_w,
                       const double* icos_w, double spin, double* wc, double* v_tilde,
                       hipStream_t st) {
-  GW_CHECK_ARG(s != nullptr && s->n_atoms > 0 && s->ri_per_atom > 0, "bad system");
-  const int64_t n64 = (int64_t)s->n_atoms * s->ri_per_atom;
+  gw_status rc0 = check_system_sizes(s);
+  if (rc0 != GW_OK) return rc0;
+  const int64_t n64 = sys_n_ri(s);   // the screening is dense over the RI functions
   GW_CHECK_ARG(n64 < 46341, "n_ri too large for 32-bit BLAS indexing");
   const int n = (int)n64;
   GW_CHECK_ARG(chi && V && wc && cos_w && icos_w, "null pointer argument");

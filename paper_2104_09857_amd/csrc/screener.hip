@@ -188,6 +188,7 @@ extern "C" gw_status gw_chi_block_features(const gw_system* s, const double* d_o
   clear_error();
   gw_status rc = check_system(s);
   if (rc != GW_OK) return rc;
+  GW_CHECK_ARG(!s->ao_off && !s->ri_off, "the block screener takes systems without per-atom offsets");
   GW_CHECK_ARG(d_occ && d_vir && tau && feat, "null argument");
   GW_CHECK_ARG(s->xyz, "block features need the atom coordinates (gw_system.xyz)");
   GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
@@ -239,6 +240,7 @@ extern "C" gw_status gw_chi_block_lognorms(const gw_system* s, const double* chi
                                            float* out, hipStream_t st) {
   clear_error();
   GW_CHECK_ARG(s && s->n_atoms > 0 && s->ri_per_atom > 0, "bad system");
+  GW_CHECK_ARG(!s->ao_off && !s->ri_off, "block norms take systems without per-atom offsets");
   GW_CHECK_ARG(chi && out && n_tau >= 1, "bad arguments");
   GW_HIP(block_norms_f32(chi, n_tau, s->n_atoms, s->ri_per_atom, 1, out, st));
   return GW_OK;

@@ -264,12 +264,42 @@ extern "C" gw_status gw_contract_sigma_prec(const gw_system* s, int32_t n_gw, co
   const int N = na * NA, NRI = na * NR;
   GW_CHECK_ARG(n_gw >= 1 && n_gw <= 128, "n_gw must be in [1, 128]");
   GW_CHECK_ARG(states != nullptr, "states is null");
-  for (int i = 0; i < n_gw; ++i) GW_CHECK_ARG(states[i] >= 0 && states[i] < N, "state index out of range");
-  GW_CHECK_ARG(C && d_occ && d_vir && d_occ0 && wc && V, "null device pointer");
-  GW_CHECK_ARG(sig_occ && sig_vir && sig_x, "null output pointer");
+  const int64_t n_mo = sys_n_ao(s);
+  for (int i = 0; i < n_gw; ++i) GW_CHECK_ARG(states[i] >= 0 && states[i] < n_mo, "state index out of range");
+  // d_occ0, V and sig_x all NULL: the exchange term is skipped (it does not
+  // depend on tau; callers that contract one tau point at a time take it once)
+  const bool with_x = d_occ0 || V || sig_x;
+  GW_CHECK_ARG(!with_x || (d_occ0 && V && sig_x),
+               "d_occ0, V and sig_x must be given together (or all be null)");
+  GW_CHECK_ARG(C && d_occ && d_vir && wc, "null device pointer");
+  GW_CHECK_ARG(sig_occ && sig_vir, "null output pointer");
   GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
   GW_CHECK_ARG(std::isfinite(filter_eps) && filter_eps >= 0.0, "filter_eps must be finite and >= 0");
   GW_CHECK_ARG(NA <= Z_COLS, "ao_per_atom must be <= 160");
+  if (s->ao_off || s->ri_off) {
+    // per-atom sizes: the padded system (missing functions as zero functions)
+    Scratch sp(st);
+    PadMaps pm;
+    if ((rc = pad_maps(s, sp, pm)) != GW_OK) return rc;
+    double *pC, *po, *pv, *pw, *pd0 = nullptr, *pV = nullptr;
+    if ((rc = sp.alloc(&pC, (size_t)pm.n_ao * pm.N)) != GW_OK) return rc;
+    if ((rc = sp.alloc(&po, (size_t)n_tau * pm.N * pm.N)) != GW_OK) return rc;
+    if ((rc = sp.alloc(&pv, (size_t)n_tau * pm.N * pm.N)) != GW_OK) return rc;
+    if ((rc = sp.alloc(&pw, (size_t)n_tau * pm.NRI * pm.NRI)) != GW_OK) return rc;
+    GW_HIP(scatter_cols(C, pm.n_ao, pm.n_ao, pC, pm.N, pm.ao, st));
+    GW_HIP(scatter_square(d_occ, pm.n_ao, po, pm.N, pm.ao, n_tau, st));
+    GW_HIP(scatter_square(d_vir, pm.n_ao, pv, pm.N, pm.ao, n_tau, st));
+    GW_HIP(scatter_square(wc, pm.n_ri, pw, pm.NRI, pm.ri, n_tau, st));
+    if (with_x) {
+      if ((rc = sp.alloc(&pd0, (size_t)pm.N * pm.N)) != GW_OK) return rc;
+      if ((rc = sp.alloc(&pV, (size_t)pm.NRI * pm.NRI)) != GW_OK) return rc;
+      GW_HIP(scatter_square(d_occ0, pm.n_ao, pd0, pm.N, pm.ao, 1, st));
+      GW_HIP(scatter_square(V, pm.n_ri, pV, pm.NRI, pm.ri, 1, st));
+    }
+    const gw_system ps = padded_view(s);
+    return gw_contract_sigma_prec(&ps, n_gw, states, pC, po, pv, pd0, pw, pV, n_tau, filter_eps,
+                                  prec, sig_occ, sig_vir, sig_x, stats, st);
+  }
   if (stats) *stats = gw_sigma_stats{};
 
   Scratch sc(st);
@@ -307,7 +337,7 @@ extern "C" gw_status gw_contract_sigma_prec(const gw_system* s, int32_t n_gw, co
   const int z_rt = (NRI + 32 * Z_WM - 1) / (32 * Z_WM);
   const int y_rt = (N + 32 * Z_WM - 1) / (32 * Z_WM);
   const int n_tiles = y_rt * n_pan;
-  const int n_slots = n_tau + 1;
+  const int n_slots = n_tau + (with_x ? 1 : 0);
   if ((rc = sc.alloc(&partial, (size_t)n_slots * n_gw * n_tiles * 2)) != GW_OK) return rc;
   if ((rc = sc.upload(&d_states, std::vector<int32_t>(states, states + n_gw))) != GW_OK) return rc;
   int32_t *d_goff, *d_seg_atom, *d_gs, *d_gslot, *d_ulen, *d_kmap, *d_km_off;
@@ -324,7 +354,7 @@ extern "C" gw_status gw_contract_sigma_prec(const gw_system* s, int32_t n_gw, co
 
   GW_HIP(filter_square_blocks(d_occ, dof, n_tau, na, NA, filter_eps, nullptr, st));
   GW_HIP(filter_square_blocks(d_vir, dvf, n_tau, na, NA, filter_eps, nullptr, st));
-  GW_HIP(filter_square_blocks(d_occ0, d0f, 1, na, NA, filter_eps, nullptr, st));
+  if (with_x) GW_HIP(filter_square_blocks(d_occ0, d0f, 1, na, NA, filter_eps, nullptr, st));
   GW_HIP(hipMemsetAsync(fp, 0, sizeof(double) * (size_t)n_gw * std::max<int64_t>(FPS, 1), st));
   // panels without coupled RI atoms never write their Z columns; those stay 0
   if (f32) GW_HIP(hipMemsetAsync(z32, 0, sizeof(float) * (size_t)n_gw * NRI * N, st));

@@ -34,7 +34,7 @@ class _System(ctypes.Structure):
     _fields_ = [("n_atoms", ctypes.c_int32), ("ao_per_atom", ctypes.c_int32),
                 ("ri_per_atom", ctypes.c_int32), ("n_occ", ctypes.c_int32),
                 ("n_trip", ctypes.c_int64), ("trip", ctypes.c_void_p), ("t3c", ctypes.c_void_p),
-                ("xyz", ctypes.c_void_p)]
+                ("xyz", ctypes.c_void_p), ("ao_off", ctypes.c_void_p), ("ri_off", ctypes.c_void_p)]
 
 
 class _Mlp(ctypes.Structure):
@@ -46,7 +46,8 @@ class _Mlp(ctypes.Structure):
 class _ChiOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("filter_eps", ctypes.c_double), ("timing", ctypes.c_int32),
                 ("screener", ctypes.c_void_p), ("screen_margin", ctypes.c_double),
-                ("screen_tau", ctypes.c_void_p), ("keep_small_blocks", ctypes.c_int32)]
+                ("screen_tau", ctypes.c_void_p), ("keep_small_blocks", ctypes.c_int32),
+                ("screen_audit", ctypes.c_int32), ("screen_fallback", ctypes.c_int32)]
 
 
 class _ChiStats(ctypes.Structure):
@@ -56,7 +57,10 @@ class _ChiStats(ctypes.Structure):
                 ("ms_stage", ctypes.c_double * 3), ("n_launch", ctypes.c_int64 * 3),
                 ("flops_stage", ctypes.c_double * 3), ("n_blocks_screened", ctypes.c_int64),
                 ("n_tiles_screened", ctypes.c_int64), ("c_variant", ctypes.c_int32),
-                ("launch_mask", ctypes.c_int32)]
+                ("launch_mask", ctypes.c_int32), ("audit_done", ctypes.c_int32),
+                ("audit_fallback", ctypes.c_int32), ("n_audit_violations", ctypes.c_int64),
+                ("audit_max_skipped", ctypes.c_double), ("audit_skipped_mass", ctypes.c_double),
+                ("audit_ms", ctypes.c_double)]
 
 
 class _SigmaStats(ctypes.Structure):
@@ -122,6 +126,8 @@ def lib():
         for f in ("gw_chi_batch_create", "gw_chi_batch_execute", "gw_chi_batch_set_config",
                   "gw_chi_batch_get_config", "gw_chi_batch_tune", "gw_chi_batch_destroy"):
             getattr(L, f).restype = ctypes.c_int32
+        L.gw_finalize.argtypes = []
+        L.gw_finalize.restype = ctypes.c_int32
         L.gw_last_error.restype = ctypes.c_char_p
         L.gw_last_error.argtypes = []
         L.gw_version.restype = ctypes.c_char_p
@@ -149,11 +155,18 @@ def _host(a, dtype=np.float64):
     return a, a.ctypes.data_as(ctypes.c_void_p)
 
 
-def _dev(t):
-    import torch
+def _dev(t, shape=None, dtype="float64", name="device argument"):
+    """Pointer of a device tensor after checking its dtype and shape (checked
+    first, so that a wrong argument raises before anything reaches the
+    library), then that it is a contiguous GPU tensor."""
     if t is None:
         return None
-    assert t.is_cuda and t.is_contiguous(), "device arguments must be contiguous CUDA tensors"
+    if dtype is not None and str(t.dtype) != "torch." + dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected torch.{dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError(f"{name}: must be a contiguous GPU tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -192,30 +205,42 @@ def build_gt(sys, C, eps, mu_f, tau, d_occ=None, d_vir=None, stream=None):
         d_occ = torch.empty((len(tau_h), n, n), dtype=torch.float64, device=C.device)
     if d_vir is None:
         d_vir = torch.empty((len(tau_h), n, n), dtype=torch.float64, device=C.device)
+    _dev(C, (n, n), name="C")
     d_occ = None if d_occ is False else d_occ
     d_vir = None if d_vir is False else d_vir
-    _check(lib().gw_build_gt(sys.ref, _dev(C), eps_p, float(mu_f), len(tau_h), tau_p,
-                             _dev(d_occ), _dev(d_vir), _stream(stream)))
+    if len(eps_h) != n:
+        raise ValueError(f"eps: {len(eps_h)} energies for {n} AO functions")
+    dshape = (len(tau_h), n, n)
+    pc = _dev(C, (n, n), name="C")
+    po, pv = _dev(d_occ, dshape, name="d_occ"), _dev(d_vir, dshape, name="d_vir")
+    _check(lib().gw_build_gt(sys.ref, pc, eps_p, float(mu_f), len(tau_h), tau_p, po, pv,
+                             _stream(stream)))
     return d_occ, d_vir
 
 
 def contract_chi(sys, d_occ, d_vir, filter_eps=0.0, chi=None, stream=None, timing=False,
-                 prec="fp64", screener=None, screen_margin=1.0, tau=None, keep_small_blocks=False):
+                 prec="fp64", screener=None, screen_margin=1.0, tau=None, keep_small_blocks=False,
+                 audit=False, fallback=False):
+    """gw_contract_chi: (chi, stats).  With a screener, audit=True judges the
+    skipped blocks by the exact contraction (GWError with GW_ERR_AUDIT when one
+    of them is kept by the exact filter, unless fallback=True, which returns the
+    exact chi instead)."""
     import torch
     n_tau = d_occ.shape[0]
     if chi is None:
         chi = torch.empty((n_tau, sys.n_ri, sys.n_ri), dtype=torch.float64, device=d_occ.device)
-    assert tuple(d_occ.shape) == tuple(d_vir.shape) == (n_tau, sys.n_ao, sys.n_ao), "D stack shape"
-    assert tuple(chi.shape) == (n_tau, sys.n_ri, sys.n_ri), "chi shape"
+    dshape, cshape = (n_tau, sys.n_ao, sys.n_ao), (n_tau, sys.n_ri, sys.n_ri)
+    po, pv = _dev(d_occ, dshape, name="d_occ"), _dev(d_vir, dshape, name="d_vir")
+    pchi = _dev(chi, cshape, name="chi")
     tau_h = None if tau is None else np.ascontiguousarray(tau, dtype=np.float64)
     opts = _ChiOpts(PRECISIONS[prec], float(filter_eps), int(bool(timing)),
                     None if screener is None else ctypes.addressof(screener.c),
                     float(screen_margin),
                     None if tau_h is None else tau_h.ctypes.data_as(ctypes.c_void_p).value,
-                    int(bool(keep_small_blocks)))
+                    int(bool(keep_small_blocks)), int(bool(audit)), int(bool(fallback)))
     st = _ChiStats()
-    _check(lib().gw_contract_chi(sys.ref, _dev(d_occ), _dev(d_vir), n_tau, ctypes.byref(opts),
-                                 _dev(chi), ctypes.byref(st), _stream(stream)))
+    _check(lib().gw_contract_chi(sys.ref, po, pv, n_tau, ctypes.byref(opts), pchi, ctypes.byref(st),
+                                 _stream(stream)))
     return chi, _stats_dict(st)
 
 
@@ -250,12 +275,14 @@ class ChiBatch:
                 for s in self.systems]
 
     def _check_shapes(self, d_occ, d_vir, chi):
+        if not len(d_occ) == len(d_vir) == len(chi) == len(self.systems):
+            raise ValueError("one d_occ, d_vir and chi per system expected")
         for s, o, v, c in zip(self.systems, d_occ, d_vir, chi):
             want_d = (self.n_tau, s.n_ao, s.n_ao)
             want_c = (self.n_tau, s.n_ri, s.n_ri)
-            assert tuple(o.shape) == want_d and tuple(v.shape) == want_d, "D stack shape"
-            assert tuple(c.shape) == want_c, "chi shape"
-            assert o.dtype == v.dtype == c.dtype == __import__("torch").float64
+            _dev(o, want_d, name="d_occ")
+            _dev(v, want_d, name="d_vir")
+            _dev(c, want_c, name="chi")
 
     def execute(self, d_occ, d_vir, chi, graph=False, stats=True, stream=None):
         self._check_shapes(d_occ, d_vir, chi)
@@ -305,8 +332,14 @@ def chi_block_features(sys, d_occ, d_vir, tau, filter_eps, feat=None, stream=Non
     if feat is None:
         feat = torch.empty((n_tau, na, na, 6), dtype=torch.float32, device=d_occ.device)
     tau_h, tau_p = _host(tau)
-    _check(lib().gw_chi_block_features(sys.ref, _dev(d_occ), _dev(d_vir), n_tau, tau_p,
-                                       float(filter_eps), _dev(feat), _stream(stream)))
+    if len(tau_h) != n_tau:
+        raise ValueError("tau: one value per D matrix expected")
+    dshape = (n_tau, sys.n_ao, sys.n_ao)
+    _check(lib().gw_chi_block_features(sys.ref, _dev(d_occ, dshape, name="d_occ"),
+                                       _dev(d_vir, dshape, name="d_vir"), n_tau, tau_p,
+                                       float(filter_eps),
+                                       _dev(feat, (n_tau, na, na, 6), "float32", "feat"),
+                                       _stream(stream)))
     return feat
 
 
@@ -316,7 +349,9 @@ def chi_block_lognorms(sys, chi, out=None, stream=None):
     na = sys.c.n_atoms
     if out is None:
         out = torch.empty((n_tau, na, na), dtype=torch.float32, device=chi.device)
-    _check(lib().gw_chi_block_lognorms(sys.ref, _dev(chi), n_tau, _dev(out), _stream(stream)))
+    _check(lib().gw_chi_block_lognorms(sys.ref, _dev(chi, (n_tau, sys.n_ri, sys.n_ri), name="chi"),
+                                       n_tau, _dev(out, (n_tau, na, na), "float32", "out"),
+                                       _stream(stream)))
     return out
 
 
@@ -343,19 +378,26 @@ class Mlp:
         import torch
         n = x.shape[0]
         y = torch.empty(n, dtype=torch.float32, device=x.device)
-        _check(lib().gw_mlp_forward(ctypes.byref(self.c), n, _dev(x), _dev(y), int(fp16),
+        px = _dev(x, (n, self.c.n_features), "float32", "x")
+        _check(lib().gw_mlp_forward(ctypes.byref(self.c), n, px, _dev(y, dtype="float32"), int(fp16),
                                     _stream(stream)))
         return y
 
     def gradient(self, x, t, alpha, stream=None):
-        _check(lib().gw_mlp_gradient(ctypes.byref(self.c), x.shape[0], _dev(x), _dev(t),
-                                     float(alpha), _dev(self.grad), _dev(self.loss),
-                                     _stream(stream)))
+        n = x.shape[0]
+        _check(lib().gw_mlp_gradient(ctypes.byref(self.c), n, _dev(x, (n, self.c.n_features),
+                                                                   "float32", "x"),
+                                     _dev(t, (n,), "float32", "t"), float(alpha),
+                                     _dev(self.grad, dtype="float32"),
+                                     _dev(self.loss, dtype="float32"), _stream(stream)))
         return self.grad, self.loss
 
     def train_step(self, x, t, alpha, lr, stream=None):
-        _check(lib().gw_mlp_train_step(ctypes.byref(self.c), x.shape[0], _dev(x), _dev(t),
-                                       float(alpha), float(lr), _dev(self.loss), _stream(stream)))
+        n = x.shape[0]
+        _check(lib().gw_mlp_train_step(ctypes.byref(self.c), n, _dev(x, (n, self.c.n_features),
+                                                                      "float32", "x"),
+                                       _dev(t, (n,), "float32", "t"), float(alpha), float(lr),
+                                       _dev(self.loss, dtype="float32"), _stream(stream)))
         return self.loss
 
 
@@ -364,10 +406,14 @@ def screen_w(sys, chi, V, cos_w, icos_w, spin=2.0, wc=None, stream=None):
     cw, cw_p = _host(cos_w)
     iw, iw_p = _host(icos_w)
     n_w, n_tau = cw.shape
+    n = sys.n_ri
+    if iw.shape != (n_tau, n_w):
+        raise ValueError("icos_w must be [n_tau][n_w] for cos_w [n_w][n_tau]")
     if wc is None:
         wc = torch.empty_like(chi)
-    _check(lib().gw_screen_w(sys.ref, _dev(chi), _dev(V), n_tau, n_w, cw_p, iw_p, float(spin),
-                             _dev(wc), _stream(stream)))
+    _check(lib().gw_screen_w(sys.ref, _dev(chi, (n_tau, n, n), name="chi"),
+                             _dev(V, (n, n), name="V"), n_tau, n_w, cw_p, iw_p, float(spin),
+                             _dev(wc, (n_tau, n, n), name="wc"), _stream(stream)))
     return wc
 
 
@@ -379,10 +425,14 @@ def screen_w_spins(sys, chi_up, chi_dn, V, cos_w, icos_w, wc=None, stream=None):
     n_w, n_tau = cw.shape
     if chi_up.shape != chi_dn.shape:
         raise ValueError("chi_up and chi_dn must have the same shape")
+    n = sys.n_ri
     if wc is None:
         wc = torch.empty_like(chi_up)
-    _check(lib().gw_screen_w_spins(sys.ref, _dev(chi_up), _dev(chi_dn), _dev(V), n_tau, n_w, cw_p,
-                                   iw_p, _dev(wc), _stream(stream)))
+    cs = (n_tau, n, n)
+    _check(lib().gw_screen_w_spins(sys.ref, _dev(chi_up, cs, name="chi_up"),
+                                   _dev(chi_dn, cs, name="chi_dn"), _dev(V, (n, n), name="V"),
+                                   n_tau, n_w, cw_p, iw_p, _dev(wc, cs, name="wc"),
+                                   _stream(stream)))
     return wc
 
 
@@ -400,8 +450,10 @@ def screen_w_metric(sys, chi, V, S_ri, cos_w, icos_w, spin=2.0, wc=None, v_tilde
     if wc is None:
         wc = torch.empty_like(chi)
     vt = torch.empty_like(V) if v_tilde is True else (None if v_tilde is False else v_tilde)
-    _check(lib().gw_screen_w_metric(sys.ref, _dev(chi), _dev(V), _dev(S_ri), n_tau, n_w, cw_p, iw_p,
-                                    float(spin), _dev(wc), _dev(vt), _stream(stream)))
+    _check(lib().gw_screen_w_metric(sys.ref, _dev(chi, name="chi"), _dev(V, name="V"),
+                                    _dev(S_ri, name="S_ri"), n_tau, n_w, cw_p, iw_p, float(spin),
+                                    _dev(wc, (n_tau, n, n), name="wc"),
+                                    _dev(vt, (n, n), name="v_tilde"), _stream(stream)))
     return wc, vt
 
 
@@ -420,9 +472,11 @@ def screen_w_spins_metric(sys, chi_up, chi_dn, V, S_ri, cos_w, icos_w, wc=None, 
     if wc is None:
         wc = torch.empty_like(chi_up)
     vt = torch.empty_like(V) if v_tilde is True else (None if v_tilde is False else v_tilde)
-    _check(lib().gw_screen_w_spins_metric(sys.ref, _dev(chi_up), _dev(chi_dn), _dev(V), _dev(S_ri),
-                                          n_tau, n_w, cw_p, iw_p, _dev(wc), _dev(vt),
-                                          _stream(stream)))
+    _check(lib().gw_screen_w_spins_metric(sys.ref, _dev(chi_up, name="chi_up"),
+                                          _dev(chi_dn, name="chi_dn"), _dev(V, name="V"),
+                                          _dev(S_ri, name="S_ri"), n_tau, n_w, cw_p, iw_p,
+                                          _dev(wc, (n_tau, n, n), name="wc"),
+                                          _dev(vt, (n, n), name="v_tilde"), _stream(stream)))
     return wc, vt
 
 
@@ -446,7 +500,8 @@ def coulomb_periodic(centres, alpha, cell, eta=0.0, tol=1e-17, V=None, device="c
         V = torch.empty((n, n), dtype=torch.float64, device=device)
     info = _CoulombInfo()
     _check(lib().gw_coulomb_periodic(n, c.ctypes.data_as(_P), a.ctypes.data_as(_P),
-                                     cl.ctypes.data_as(_P), float(eta), float(tol), _dev(V),
+                                     cl.ctypes.data_as(_P), float(eta), float(tol),
+                                     _dev(V, (n, n), name="V"),
                                      ctypes.byref(info), _stream(stream)))
     return V, {k: getattr(info, k) for k, _ in _CoulombInfo._fields_}
 
@@ -458,17 +513,40 @@ def contract_sigma(sys, states, C, d_occ, d_vir, d_occ0, wc, V, filter_eps=0.0, 
     n_gw, n_tau = len(st_h), d_occ.shape[0]
     so = np.zeros((n_gw, n_tau))
     sv = np.zeros((n_gw, n_tau))
-    sx = np.zeros(n_gw)
+    # d_occ0 = V = None: the exchange term is skipped (sig_x returned as None)
+    sx = None if d_occ0 is None and V is None else np.zeros(n_gw)
     stats = _SigmaStats()
-    args = (sys.ref, n_gw, st_p, _dev(C), _dev(d_occ), _dev(d_vir), _dev(d_occ0), _dev(wc), _dev(V),
+    N, NRI = sys.n_ao, sys.n_ri
+    args = (sys.ref, n_gw, st_p, _dev(C, (N, N), name="C"),
+            _dev(d_occ, (n_tau, N, N), name="d_occ"), _dev(d_vir, (n_tau, N, N), name="d_vir"),
+            _dev(d_occ0, (N, N) if d_occ0 is None or d_occ0.dim() == 2 else (1, N, N),
+                 name="d_occ0"),
+            _dev(wc, (n_tau, NRI, NRI), name="wc"), _dev(V, (NRI, NRI), name="V"),
             n_tau, float(filter_eps))
-    outs = (so.ctypes.data_as(_P), sv.ctypes.data_as(_P), sx.ctypes.data_as(_P), ctypes.byref(stats),
-            _stream(stream))
+    outs = (so.ctypes.data_as(_P), sv.ctypes.data_as(_P),
+            None if sx is None else sx.ctypes.data_as(_P), ctypes.byref(stats), _stream(stream))
     if prec == "fp64":
         _check(lib().gw_contract_sigma(*args, *outs))
     else:
         _check(lib().gw_contract_sigma_prec(*args, PRECISIONS[prec], *outs))
     return so, sv, sx, {"flops": stats.flops, "ms_total": stats.ms_total}
+
+
+def finalize():
+    """gw_finalize: release the library's cached per-device handles."""
+    _check(lib().gw_finalize())
+
+
+def fermi_level(channels):
+    """gw_fermi_level: mu_F of one or more channels, each (eps, n_occ)."""
+    eps = [np.ascontiguousarray(e, dtype=np.float64) for e, _ in channels]
+    n_mo = np.array([len(e) for e in eps], dtype=np.int32)
+    n_occ = np.array([int(n) for _, n in channels], dtype=np.int32)
+    ptrs = (ctypes.c_void_p * len(eps))(*[e.ctypes.data for e in eps])
+    mu = ctypes.c_double(0.0)
+    _check(lib().gw_fermi_level(len(eps), n_mo.ctypes.data_as(_P), n_occ.ctypes.data_as(_P),
+                                ctypes.cast(ptrs, _P), ctypes.byref(mu)))
+    return mu.value
 
 
 def evgw_update(eps0, n_occ, states, e_qp):

@@ -116,11 +116,7 @@ def g0w0_spin(sys_up, sys_dn, C_up, C_dn, eps_up, eps_dn, V, tau, omega, cos_w, 
     st = torch.cuda.current_stream() if stream is None else stream
     chans = ((sys_up, C_up, np.asarray(eps_up, dtype=np.float64), states_up, vxc_up),
              (sys_dn, C_dn, np.asarray(eps_dn, dtype=np.float64), states_dn, vxc_dn))
-    homo = max(e[:s.c.n_occ].max() for s, _, e, _, _ in chans)
-    lumo = min(e[s.c.n_occ:].min() for s, _, e, _, _ in chans)
-    if not homo < lumo:
-        raise ValueError("an occupied level of one channel lies above a virtual level")
-    mu_f = 0.5 * (homo + lumo)
+    mu_f = gw.fermi_level([(e, s.c.n_occ) for s, _, e, _, _ in chans])
     ds, chis = [], []
     for sysc, C, eps, _, _ in chans:
         d_occ, d_vir = gw.build_gt(sysc, C, eps, mu_f, tau, stream=st)

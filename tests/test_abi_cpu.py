@@ -275,3 +275,72 @@ def test_header_is_plain_c(tmp_path):
                         "-I" + os.path.dirname(HEADER), "-I/opt/rocm/include", "-c", str(src),
                         "-o", str(tmp_path / "hdr.o")], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr[-2000:]
+
+
+def test_sigma_exchange_arguments_together():
+    """gw_contract_sigma: d_occ0, V and sig_x are given together or all null."""
+    L = gw.lib()
+    trip = np.zeros((1, 3), dtype=np.int32)
+    s = gw._System(2, 3, 4, 3, 1, trip.ctypes.data_as(ctypes.c_void_p).value, 1)
+    states = np.array([0], dtype=np.int32)
+    so, sv, sx = np.zeros(1), np.zeros(1), np.zeros(1)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    for d0, V, x in ((1, None, None), (None, 1, None), (None, None, P(sx)), (1, 1, None)):
+        rc = L.gw_contract_sigma(ctypes.byref(s), 1, P(states), 1, 1, 1, d0, 1, V, 1, 0.0, P(so),
+                                 P(sv), x, None, None)
+        assert rc == gw.GW_ERR_ARG and b"together" in L.gw_last_error()
+
+
+def test_fermi_level():
+    """gw_fermi_level: midpoint of the highest occupied and lowest virtual level
+    over the channels; occupations without such a gap are rejected."""
+    up = np.array([-0.5, -0.2, 0.1, 0.4])
+    dn = np.array([-0.45, -0.3, 0.05, 0.2])
+    assert gw.fermi_level([(up, 2)]) == 0.5 * (-0.2 + 0.1)
+    assert gw.fermi_level([(up, 2), (dn, 2)]) == 0.5 * (-0.2 + 0.05)
+    # one electron moved to the up channel: HOMO 0.1 (up), LUMO -0.3 (dn) -> no gap
+    with pytest.raises(gw.GWError) as e:
+        gw.fermi_level([(up, 3), (dn, 1)])
+    assert e.value.code == gw.GW_ERR_ARG
+    with pytest.raises(gw.GWError):
+        gw.fermi_level([(np.array([0.0, np.nan]), 1)])
+    # levels need not be sorted (an evGW update may reorder them)
+    assert gw.fermi_level([(np.array([-0.1, -0.3, 0.5, 0.2]), 2)]) == 0.5 * (-0.1 + 0.2)
+
+
+def test_binding_checks_device_arguments_before_the_library():
+    """The binding rejects a wrong dtype, shape or device before any call into
+    libgw.so (a wrong-size buffer would otherwise be read or written past its
+    end by the kernels)."""
+    import torch
+    trip = np.zeros((1, 3), dtype=np.int32)
+    with pytest.raises(ValueError):
+        gw.System(2, 3, 4, 3, trip, torch.zeros(36, dtype=torch.float32))
+    with pytest.raises(ValueError):
+        gw.System(2, 3, 4, 3, trip, torch.zeros(35, dtype=torch.float64))
+    s = gw.System(2, 3, 4, 3, trip, torch.zeros(36, dtype=torch.float64))
+    eps = np.linspace(-1, 1, 6)
+    C32 = torch.zeros((6, 6), dtype=torch.float32)
+    C64 = torch.zeros((6, 6), dtype=torch.float64)
+    with pytest.raises(ValueError, match="dtype"):
+        gw.build_gt(s, C32, eps, 0.0, [0.1], d_occ=torch.zeros((1, 6, 6), dtype=torch.float64),
+                    d_vir=torch.zeros((1, 6, 6), dtype=torch.float64))
+    with pytest.raises(ValueError, match="shape"):
+        gw.build_gt(s, torch.zeros((6, 5), dtype=torch.float64), eps, 0.0, [0.1],
+                    d_occ=torch.zeros((1, 6, 6), dtype=torch.float64), d_vir=False)
+    with pytest.raises(ValueError, match="GPU"):
+        gw.build_gt(s, C64, eps, 0.0, [0.1], d_occ=torch.zeros((1, 6, 6), dtype=torch.float64),
+                    d_vir=False)
+    d = torch.zeros((2, 6, 6), dtype=torch.float64)
+    with pytest.raises(ValueError, match="d_occ"):
+        gw.contract_chi(s, torch.zeros((2, 6, 5), dtype=torch.float64), d,
+                        chi=torch.zeros((2, 8, 8), dtype=torch.float64))
+    with pytest.raises(ValueError, match="d_occ"):
+        gw.contract_chi(s, d.float(), d, chi=torch.zeros((2, 8, 8), dtype=torch.float64))
+    cw = np.zeros((2, 2))
+    with pytest.raises(ValueError, match="chi"):
+        gw.screen_w(s, torch.zeros((2, 8, 7), dtype=torch.float64),
+                    torch.zeros((8, 8), dtype=torch.float64), cw, cw,
+                    wc=torch.zeros((2, 8, 8), dtype=torch.float64))
+    with pytest.raises(ValueError, match="C"):
+        gw.contract_sigma(s, [0], C32, d, d, None, torch.zeros((2, 8, 8), dtype=torch.float64), None)

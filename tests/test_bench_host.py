@@ -53,3 +53,4 @@ def test_committed_traffic_records_match_the_sources(prec):
         pytest.skip("kernel sources changed since the counters were taken: bench.py reports "
                     "traffic null until FETCH_SIZE / WRITE_SIZE are taken again")
     assert got == rec["bytes_per_launch"]
+

@@ -90,13 +90,36 @@ def test_screening_mechanics(wires):
     chi_k, st = gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=hi,
                                 screen_margin=1.0, tau=r["g"].tau)
     assert torch.equal(chi_k, r["chi"]) and st["n_blocks_screened"] == 0
-    # a network that predicts -100 everywhere skips everything: chi == 0
+    # a network that predicts -100 everywhere skips everything; without the
+    # audit nothing is computed (chi == 0)
     lo = gw.Mlp(6, 64, screener.pack(p[0], p[1], p[2], p[3], 0 * p[4], np.array([-100.0])))
     chi_s, st = gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=lo,
                                 screen_margin=1.0, tau=r["g"].tau)
     na, nt = s.n_atoms, r["do"].shape[0]
     assert float(chi_s.abs().max()) == 0.0
     assert st["n_blocks_screened"] == nt * na * (na + 1) // 2 and st["n_tiles_screened"] > 0
+    assert st["audit_done"] == 0
+    # with the audit, the exact contraction judges the skipped blocks: the call fails
+    with pytest.raises(gw.GWError) as e:
+        gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=lo, screen_margin=1.0,
+                        tau=r["g"].tau, audit=True)
+    assert e.value.code == gw.GW_ERR_AUDIT
+    # ... and with the fallback it returns the exact chi, bit for bit
+    chi_f, st = gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=lo,
+                                screen_margin=1.0, tau=r["g"].tau, audit=True, fallback=True)
+    assert torch.equal(chi_f, r["chi"])
+    assert st["audit_done"] == 1 and st["audit_fallback"] == 1 and st["n_audit_violations"] > 0
+    assert st["audit_max_skipped"] >= s.filter_eps and st["audit_skipped_mass"] > 0.99
+    # the same with the output filter off: the exact unfiltered chi
+    chi_fu, _ = gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=lo,
+                                screen_margin=1.0, tau=r["g"].tau, audit=True, fallback=True,
+                                keep_small_blocks=True)
+    assert torch.equal(chi_fu, r["chi_u"])
+    # a keep-everything network passes the audit with nothing skipped
+    chi_k, st = gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=hi,
+                                screen_margin=1.0, tau=r["g"].tau, audit=True)
+    assert torch.equal(chi_k, r["chi"]) and st["audit_done"] == 1
+    assert st["n_audit_violations"] == 0 and st["audit_skipped_mass"] == 0.0
 
 
 def test_trained_screener_audit_and_gain(wires):
@@ -137,3 +160,11 @@ def test_trained_screener_audit_and_gain(wires):
     assert not skipped.any() or lg[skipped].max() < np.log10(s.filter_eps)
     assert float((chi_s - exact).abs().max()) == 0.0
     assert st["flops_c"] < r["st"]["flops_c"]
+    # the library's own audit agrees: no violation, the screened chi is returned
+    chi_a, sa = gw.contract_chi(r["sys"], r["do"], r["dv"], s.filter_eps, screener=sc.net,
+                                screen_margin=margin, tau=r["g"].tau, audit=True, fallback=True)
+    print("audit", {k: sa[k] for k in ("n_audit_violations", "audit_max_skipped",
+                                       "audit_skipped_mass", "audit_ms")}, flush=True)
+    assert sa["audit_done"] == 1 and sa["audit_fallback"] == 0 and sa["n_audit_violations"] == 0
+    assert sa["audit_max_skipped"] < s.filter_eps and sa["audit_skipped_mass"] < 1e-6
+    assert torch.equal(chi_a, exact) and sa["n_blocks_screened"] == total
