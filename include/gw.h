@@ -123,6 +123,19 @@ gw_status gw_build_gt(const gw_system *s, const double *C, const double *eps, do
                       int32_t n_tau, const double *tau, double *d_occ, double *d_vir,
                       hipStream_t stream);
 
+/* gw_build_gt without any allocation, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the per-tau weights are staged in an array the
+ * library holds on every device it runs on (8 MiB, kept until the process
+ * ends) instead of call-owned scratch.  Arguments, layouts, outputs and
+ * errors as gw_build_gt, plus GW_ERR_ARG when 2 * n_tau * n_ao exceeds
+ * 2^20 (the array's size in doubles).  Every call on one device shares that
+ * device's array: calls that overlap on one device (different streams, or
+ * host threads) race and must be ordered by the caller. */
+gw_status gw_build_gt_noalloc(const gw_system *s, const double *C, const double *eps,
+                              double mu_f, int32_t n_tau, const double *tau, double *d_occ,
+                              double *d_vir, hipStream_t stream);
+
 typedef struct {
   int32_t prec;            /* gw_prec                                         */
   double filter_eps;       /* atom-block filter (Frobenius norm), >= 0        */

@@ -4,6 +4,7 @@
 // One launch for all tau and both branches; the weight multiplies the A
 // operand as it is staged.
 #include <cmath>
+#include <mutex>
 
 #include "gw_internal.hpp"
 #include "tile_gemm.hpp"
@@ -60,21 +61,37 @@ struct GtProblem {
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
-}  // namespace
-}  // namespace gw
+// Staging array of gw_build_gt_noalloc: weights of up to kGtStage / 2
+// (tau, MO) pairs per branch, 8 MiB on every device the library runs on.
+constexpr int64_t kGtStage = 1 << 20;
+__device__ __align__(256) double scratch[kGtStage];
 
-using namespace gw;
+std::mutex g_stage_mu;
+double* g_stage_ptr[64] = {};
 
-extern "C" gw_status gw_build_gt(const gw_system* s, const double* C, const double* eps,
-                                 double mu_f, int32_t n_tau, const double* tau, double* d_occ,
-                                 double* d_vir, hipStream_t st) {
-  clear_error();
-  GW_CHECK_ARG(s != nullptr, "system is null");
-  GW_CHECK_ARG(s->n_atoms > 0 && s->ao_per_atom > 0, "bad system sizes");
-  const int64_t N64 = (int64_t)s->n_atoms * s->ao_per_atom;
-  GW_CHECK_ARG(N64 < (1 << 30), "system too large");
-  const int N = (int)N64;
-  GW_CHECK_ARG(s->n_occ >= 1 && s->n_occ < N, "n_occ must be in [1, n_ao)");
+// device address of `scratch` on the current device (looked up once per device)
+gw_status gt_stage_ptr(double** out) {
+  int dev = 0;
+  GW_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) {
+    set_error("device index out of range");
+    return GW_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  if (!g_stage_ptr[dev]) {
+    void* ptr = nullptr;
+    GW_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_stage_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_stage_ptr[dev];
+  return GW_OK;
+}
+
+gw_status check_gt_args(const gw_system* s, const double* C, const double* eps, double mu_f,
+                        int32_t n_tau, const double* tau, const double* d_occ, const double* d_vir) {
+  gw_status rc = check_system_sizes(s);
+  if (rc != GW_OK) return rc;
+  const int N = (int)sys_n_ao(s);     // D is dense over the AO functions
   GW_CHECK_ARG(C && eps && tau, "C, eps and tau must be non-null");
   GW_CHECK_ARG(d_occ || d_vir, "at least one output is required");
   GW_CHECK_ARG(n_tau >= 1 && n_tau <= 4096, "n_tau must be in [1, 4096]");
@@ -85,17 +102,68 @@ extern "C" gw_status gw_build_gt(const gw_system* s, const double* C, const doub
                  "occupied levels must lie below mu_f and virtual levels above it");
   }
   for (int j = 0; j < n_tau; ++j) GW_CHECK_ARG(std::isfinite(tau[j]) && tau[j] >= 0.0, "tau must be finite and >= 0");
+  return GW_OK;
+}
 
+gw_status build_gt_launch(const gw_system* s, const double* C, const double* eps, double mu_f,
+                          int32_t n_tau, const double* tau, double* d_occ, double* d_vir,
+                          double* d_w, hipStream_t st);
+
+}  // namespace
+}  // namespace gw
+
+using namespace gw;
+
+extern "C" gw_status gw_build_gt(const gw_system* s, const double* C, const double* eps,
+                                 double mu_f, int32_t n_tau, const double* tau, double* d_occ,
+                                 double* d_vir, hipStream_t st) {
+  clear_error();
+  gw_status rc0 = check_gt_args(s, C, eps, mu_f, n_tau, tau, d_occ, d_vir);
+  if (rc0 != GW_OK) return rc0;
+  Scratch sc(st);
+  double* d_w = nullptr;
+  gw_status rc = sc.alloc(&d_w, (size_t)2 * n_tau * sys_n_ao(s));
+  if (rc != GW_OK) return rc;
+  return build_gt_launch(s, C, eps, mu_f, n_tau, tau, d_occ, d_vir, d_w, st);
+}
+
+// The same without any allocation: the weights are staged in the library's
+// per-device array (see gw_build_gt_noalloc in include/gw.h).
+extern "C" gw_status gw_build_gt_noalloc(const gw_system* s, const double* C, const double* eps,
+                                         double mu_f, int32_t n_tau, const double* tau,
+                                         double* d_occ, double* d_vir, hipStream_t st) {
+  clear_error();
+  gw_status rc = check_gt_args(s, C, eps, mu_f, n_tau, tau, d_occ, d_vir);
+  if (rc != GW_OK) return rc;
+  const int64_t need = 2 * (int64_t)n_tau * sys_n_ao(s);
+  if (need > kGtStage) {
+    set_error("gw_build_gt_noalloc: 2 * n_tau * n_ao = " + std::to_string(need) +
+              " weights exceed the staging array of " + std::to_string(kGtStage) +
+              " (use gw_build_gt)");
+    return GW_ERR_ARG;
+  }
+  double* d_w = nullptr;
+  if ((rc = gt_stage_ptr(&d_w)) != GW_OK) return rc;
+  return build_gt_launch(s, C, eps, mu_f, n_tau, tau, d_occ, d_vir, d_w, st);
+}
+
+namespace gw {
+namespace {
+
+// weights w[branch][tau][k] into the device buffer d_w (2 n_tau N doubles,
+// zeros beyond the branch's K), then one launch for all tau and both branches
+gw_status build_gt_launch(const gw_system* s, const double* C, const double* eps, double mu_f,
+                          int32_t n_tau, const double* tau, double* d_occ, double* d_vir,
+                          double* d_w, hipStream_t st) {
+  const int N = (int)sys_n_ao(s);
   std::vector<double> w((size_t)2 * n_tau * N, 0.0);
   for (int j = 0; j < n_tau; ++j) {
     for (int i = 0; i < s->n_occ; ++i) w[(size_t)j * N + i] = std::exp((eps[i] - mu_f) * tau[j]);
     for (int a = s->n_occ; a < N; ++a)
       w[((size_t)n_tau + j) * N + (a - s->n_occ)] = std::exp(-(eps[a] - mu_f) * tau[j]);
   }
-  Scratch sc(st);
-  double* d_w = nullptr;
-  gw_status rc = sc.upload(&d_w, w);
-  if (rc != GW_OK) return rc;
+  // a copy from pageable host memory has consumed w when it returns
+  GW_HIP(hipMemcpyAsync(d_w, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, st));
 
   GtProblem p{};
   p.C = C;
@@ -110,3 +178,6 @@ extern "C" gw_status gw_build_gt(const gw_system* s, const double* C, const doub
   GW_HIP((launch_tile_gemm<G_WM, G_WN, G_NBW, 16>(p, dim3((unsigned)(p.n_rt * n_ct), n_tau, 2), st)));
   return GW_OK;
 }
+
+}  // namespace
+}  // namespace gw
