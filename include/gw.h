@@ -177,7 +177,33 @@ typedef struct {
   int64_t n_tiles_screened;  /* outer-contraction tiles skipped by the screener */
   int32_t c_variant;       /* stage-C tile variant used (see gw_chi_batch_*)    */
   int32_t launch_mask;     /* stages launched in the persistent form (bit k)    */
+  int32_t audit_done;      /* 1 when the screener audit ran                    */
+  int32_t audit_fallback;  /* 1 when the audit failed and the exact chi was
+                              returned (screen_fallback)                       */
+  int64_t n_audit_violations; /* skipped blocks the exact filter keeps        */
+  double audit_max_skipped;/* largest exact Frobenius norm of a skipped block */
+  double audit_skipped_mass; /* sqrt(sum of squared exact norms of the skipped
+                              blocks) / Frobenius norm of the exact chi        */
+  double audit_ms;         /* wall time of the audit (host clock)             */
 } gw_chi_stats;
+
+/* Three-center overlap integrals (Eq. 4), (mu nu P) = int phi_mu phi_nu phi_P dr,
+ * of s-type Gaussian basis functions, written as the system's bricks.  Every
+ * atom carries the same functions: AO function i at xyz[atom] + ao_offset[i]
+ * with exponent ao_exp[i] (i < ao_per_atom), RI function p at xyz[atom] +
+ * ri_offset[p] with exponent ri_exp[p], each normalized,
+ * g(r) = (2a/pi)^(3/4) exp(-a |r - R|^2); by the Gaussian product theorem
+ *   (mu nu P) = N_a N_b N_c (pi/s)^(3/2) exp(-(ab|A-B|^2 + ac|A-C|^2 + bc|B-C|^2)/s),
+ * s = a + b + c.  s: n_atoms, sizes, the triple list (host) and xyz (host,
+ * bohr) are read; s->t3c is ignored.  ao_exp host [ao_per_atom], ri_exp host
+ * [ri_per_atom] (> 0); ao_offset host [ao_per_atom][3], ri_offset host
+ * [ri_per_atom][3] (bohr), either may be NULL for functions at the atoms.
+ * t3c: dev [n_trip][ao][ao][ri], overwritten (the brick layout of gw_system).
+ * Asynchronous on stream.  Errors: GW_ERR_ARG (sizes, null or non-finite
+ * inputs, exponents <= 0), GW_ERR_NOMEM, GW_ERR_HIP. */
+gw_status gw_t3c_gaussian(const gw_system *s, const double *ao_exp, const double *ao_offset,
+                          const double *ri_exp, const double *ri_offset, double *t3c,
+                          hipStream_t stream);
 
 /* Polarizability chi_PQ(tau_j) for all tau at once (Eq. 3), with the atom-block
  * filter of the paper's computational details: bricks of norm < filter_eps and

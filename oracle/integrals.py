@@ -43,16 +43,22 @@ def three_center(ra, a, rb, b, rc, c):
 def bricks(xyz, trip, ao_exp, ao_off, ri_exp, ri_off):
     """Brick of every triple (a, b, c): [n_trip][n_ao][n_ao][n_ri], element
     (mu, nu, P) = (mu nu P) of AO function mu of atom a, nu of atom b and RI
-    function P of atom c."""
-    na, nr = len(ao_exp), len(ri_exp)
-    out = np.empty((len(trip), na, na, nr))
-    for t, (a, b, c) in enumerate(trip):
-        for m in range(na):
-            for n in range(na):
-                for p in range(nr):
-                    out[t, m, n, p] = three_center(xyz[a] + ao_off[m], ao_exp[m],
-                                                   xyz[b] + ao_off[n], ao_exp[n],
-                                                   xyz[c] + ri_off[p], ri_exp[p])
+    function P of atom c (the formula above, broadcast over mu, nu, P)."""
+    ao_e = np.asarray(ao_exp, dtype=np.float64)
+    ri_e = np.asarray(ri_exp, dtype=np.float64)
+    a = ao_e[:, None, None]
+    b = ao_e[None, :, None]
+    c = ri_e[None, None, :]
+    s = a + b + c
+    pref = _norm(a) * _norm(b) * _norm(c) * (np.pi / s) ** 1.5
+    out = np.empty((len(trip), len(ao_e), len(ao_e), len(ri_e)))
+    for t, (ia, ib, ic) in enumerate(trip):
+        ra = (xyz[ia] + np.asarray(ao_off))[:, None, None, :]
+        rb = (xyz[ib] + np.asarray(ao_off))[None, :, None, :]
+        rc = (xyz[ic] + np.asarray(ri_off))[None, None, :, :]
+        e = (a * b * np.sum((ra - rb) ** 2, -1) + a * c * np.sum((ra - rc) ** 2, -1)
+             + b * c * np.sum((rb - rc) ** 2, -1)) / s
+        out[t] = pref * np.exp(-e)
     return out
 
 

@@ -20,7 +20,8 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include")]
-SOURCES = ["common.hip", "gt.hip", "chi.hip", "screen.hip", "sigma.hip", "screener.hip", "qp.cpp"]
+SOURCES = ["common.hip", "gt.hip", "chi.hip", "screen.hip", "sigma.hip", "screener.hip", "qp.cpp",
+           "integrals.hip"]
 LIBS = ["-lrocsolver", "-lrocblas"]
 
 

@@ -95,12 +95,16 @@ def lib():
         L.gw_continue_qp.argtypes = [_I32, _P, _P, _P, _P, _P, _P, _D, _I32, _I32, _P, _P, _P, _P,
                                      _P, _P]
         L.gw_evgw_update.argtypes = [_I32, _I32, _P, _I32, _P, _P, _P, _P]
+        L.gw_fermi_level.argtypes = [_I32, _P, _P, _P, _P]
+        L.gw_fermi_level.restype = ctypes.c_int32
         L.gw_screen_w_spins.argtypes = [_P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P]
         L.gw_screen_w_spins.restype = ctypes.c_int32
         L.gw_screen_w_metric.argtypes = [_P, _P, _P, _P, _I32, _I32, _P, _P, _D, _P, _P, _P]
         L.gw_screen_w_metric.restype = ctypes.c_int32
         L.gw_screen_w_spins_metric.argtypes = [_P, _P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P]
         L.gw_screen_w_spins_metric.restype = ctypes.c_int32
+        L.gw_t3c_gaussian.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+        L.gw_t3c_gaussian.restype = ctypes.c_int32
         L.gw_coulomb_periodic.argtypes = [_I32, _P, _P, _P, _D, _D, _P, _P, _P]
         L.gw_coulomb_periodic.restype = ctypes.c_int32
         for f in ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma",
@@ -142,7 +146,8 @@ EXPORTED = ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma"
             "gw_mlp_train_step", "gw_mlp_sync_half", "gw_chi_batch_create", "gw_chi_batch_execute",
             "gw_chi_batch_set_config", "gw_chi_batch_get_config", "gw_chi_batch_tune",
             "gw_chi_batch_destroy", "gw_evgw_update", "gw_contract_sigma_prec", "gw_screen_w_spins",
-            "gw_screen_w_metric", "gw_coulomb_periodic", "gw_screen_w_spins_metric")
+            "gw_screen_w_metric", "gw_coulomb_periodic", "gw_screen_w_spins_metric",
+            "gw_fermi_level", "gw_finalize", "gw_t3c_gaussian")
 
 
 def _check(code):
@@ -177,22 +182,61 @@ def _stream(stream=None):
 
 
 class System:
-    """A system description (gw_system) with its host triple list and device bricks."""
+    """A system description (gw_system) with its host triple list and device
+    bricks.  ao_off / ri_off (host [n_atoms + 1], optional): per-atom function
+    offsets of atoms with different numbers of functions (the bricks keep the
+    per-atom maxima ao_per_atom / ri_per_atom, zeros where a function does
+    not exist)."""
 
-    def __init__(self, n_atoms, ao_per_atom, ri_per_atom, n_occ, trip, t3c, xyz=None):
+    def __init__(self, n_atoms, ao_per_atom, ri_per_atom, n_occ, trip, t3c, xyz=None, ao_off=None,
+                 ri_off=None):
         self.trip = np.ascontiguousarray(trip, dtype=np.int32).reshape(-1, 3)
+        if t3c is not None and len(self.trip):
+            if str(t3c.dtype) != "torch.float64" or not t3c.is_contiguous():
+                raise ValueError("t3c: contiguous float64 bricks expected")
+            if t3c.numel() != len(self.trip) * ao_per_atom * ao_per_atom * ri_per_atom:
+                raise ValueError(f"t3c: {t3c.numel()} elements for {len(self.trip)} bricks of "
+                                 f"{ao_per_atom}x{ao_per_atom}x{ri_per_atom}")
         self.t3c = t3c
         self.xyz = None if xyz is None else np.ascontiguousarray(xyz, dtype=np.float64)
+        off = lambda o: None if o is None else np.ascontiguousarray(o, dtype=np.int32)
+        self.ao_off, self.ri_off = off(ao_off), off(ri_off)
+        for o in (self.ao_off, self.ri_off):
+            if o is not None and o.shape != (n_atoms + 1,):
+                raise ValueError("per-atom offsets: n_atoms + 1 entries expected")
+        ptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p).value
         self.c = _System(int(n_atoms), int(ao_per_atom), int(ri_per_atom), int(n_occ),
                          len(self.trip), self.trip.ctypes.data_as(ctypes.c_void_p).value,
                          t3c.data_ptr() if t3c is not None and len(self.trip) else None,
-                         None if self.xyz is None else self.xyz.ctypes.data_as(ctypes.c_void_p).value)
-        self.n_ao = n_atoms * ao_per_atom
-        self.n_ri = n_atoms * ri_per_atom
+                         ptr(self.xyz), ptr(self.ao_off), ptr(self.ri_off))
+        self.n_ao = n_atoms * ao_per_atom if self.ao_off is None else int(self.ao_off[-1])
+        self.n_ri = n_atoms * ri_per_atom if self.ri_off is None else int(self.ri_off[-1])
 
     @property
     def ref(self):
         return ctypes.byref(self.c)
+
+
+def t3c_gaussian(sys, ao_exp, ao_off, ri_exp, ri_off, t3c=None, stream=None):
+    """gw_t3c_gaussian: the bricks of the system's triples (sys.trip, sys.xyz)
+    as three-center overlap integrals (Eq. 4) of s-type Gaussians; returns
+    the device bricks [n_trip][ao][ao][ri]."""
+    import torch
+    na, nr = sys.c.ao_per_atom, sys.c.ri_per_atom
+    ae, ae_p = _host(ao_exp)
+    re_, re_p = _host(ri_exp)
+    ao_o, ao_p = _host(np.reshape(ao_off, (-1, 3)))
+    ri_o, ri_p = _host(np.reshape(ri_off, (-1, 3)))
+    if len(ae) != na or len(re_) != nr or ao_o.shape != (na, 3) or ri_o.shape != (nr, 3):
+        raise ValueError("one exponent and offset per AO / RI function of an atom expected")
+    if sys.xyz is None:
+        raise ValueError("the system needs its atom coordinates")
+    shape = (len(sys.trip), na, na, nr)
+    if t3c is None:
+        t3c = torch.empty(shape, dtype=torch.float64, device="cuda")
+    _check(lib().gw_t3c_gaussian(sys.ref, ae_p, ao_p, re_p, ri_p,
+                                 _dev(t3c, shape, name="t3c"), _stream(stream)))
+    return t3c
 
 
 def build_gt(sys, C, eps, mu_f, tau, d_occ=None, d_vir=None, stream=None):

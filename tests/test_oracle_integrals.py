@@ -57,6 +57,14 @@ def test_bricks_layout_symmetry_and_diffuse_limit():
     assert b.shape == (3, 2, 2, 3)
     # (a, b, c) and (b, a, c) are transposes in (mu, nu)
     np.testing.assert_allclose(b[0], b[1].transpose(1, 0, 2), rtol=1e-14, atol=0)
+    # every element equals the single-function formula
+    for t, (ia, ib, ic) in enumerate(trip):
+        for m in range(2):
+            for n in range(2):
+                for p in range(3):
+                    one = oint.three_center(xyz[ia] + ao_o[m], ao_e[m], xyz[ib] + ao_o[n], ao_e[n],
+                                            xyz[ic] + ri_o[p], ri_e[p])
+                    assert abs(b[t, m, n, p] - one) <= 1e-15 * one
     # element (mu, nu, P) of brick (a, b, c) by quadrature
     want = _quad3([(xyz[0] + ao_o[1], ao_e[1], 0), (xyz[1] + ao_o[0], ao_e[0], 0),
                    (xyz[2] + ri_o[2], ri_e[2], 0)])
