@@ -746,6 +746,7 @@ def bench_chain(args):
         "chain_chi_sigma_tflops": chain_flops / ((chain["ms"]["chi"] + chain["ms"]["sigma"]) / 1e3) / 1e12,
         "chain_flops": {"chi_ab": cs["flops_ab"], "chi_c": cs["flops_c"],
                         "sigma": chain["sig_stats"]["flops"]},
+        "chain_chi_stage_ms": [round(x, 1) for x in cs["ms_stage"]],
         "step_chi_stage": {"names": ["A (D^occ half)", "B (D^vir half)", "C (outer)"],
                            "ms_per_step": [round(x / args.steps, 1) for x in stage_ms],
                            "tflops": [f / (m / 1e3) / 1e12 if m > 0 else None

@@ -121,6 +121,10 @@ struct FBufs {
   T* dvg = nullptr;            // gathered D^vir columns of the pivot
   T* mb = nullptr;             // M_b
   T* bp = nullptr;             // N_b panels
+  // the same for the second pivot of a pair (SysPlan::pair_h)
+  T* dvg1 = nullptr;
+  T* mb1 = nullptr;
+  T* bp1 = nullptr;
   StageA<T> sa{};
   StageB<T> sb{};
   StageC<T> sc{};
@@ -130,6 +134,9 @@ struct FBufs {
 struct SysPlan {
   gw_system s{};
   int na = 0, N = 0, NRI = 0, n_groups = 0, nRmax = 1, PG = 1, PC = 0, n_pan = 0;
+  // pivot pairs: loop index i runs pivot i and pivot i + pair_h together (their
+  // chi rows are disjoint); 0: one pivot per loop index
+  int pair_h = 0;
   int64_t bs = 0, BPS = 0, BPS16 = 0;
   BrickGroups G;
   Panels pan;
@@ -175,6 +182,7 @@ using namespace gw;
 
 struct gw_chi_batch {
   int n_sys = 0, n_tau = 0, NA = 0, NR = 0, prec = GW_FP64, max_na = 0;
+  int n_loop = 0;                    // pivot loop length (pairs count once)
   double eps_f = 0.0;
   bool timing = false;
   bool out_filter = true;            // zero chi blocks below eps_f at the end
@@ -264,12 +272,21 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
   for (int p = 0; p < P.n_pan; ++p)
     GW_CHECK_ARG((int64_t)NA * NA * P.pan.ulen[p] * P.PC < (1ll << 31),
                  "column panel too large for 32-bit tile offsets");
+  const size_t n_mb = (size_t)n_tau * NA * P.nRmax * N * NR, n_bp = (size_t)B.GB * n_tau * P.BPS;
   if ((rc = M.alloc(&F.dvg, (size_t)N * RS)) != GW_OK) return rc;
-  if ((rc = M.alloc(&F.mb, (size_t)n_tau * NA * P.nRmax * N * NR)) != GW_OK) return rc;
+  if ((rc = M.alloc(&F.mb, n_mb)) != GW_OK) return rc;
   // N_b of every pivot of a stage-B group: [pivot][tau] slabs of BPS
-  if ((rc = M.alloc(&F.bp, (size_t)B.GB * n_tau * P.BPS)) != GW_OK) return rc;
+  if ((rc = M.alloc(&F.bp, n_bp)) != GW_OK) return rc;
   // entries of N_b that no group writes stay zero for the life of the plan
-  GW_HIP(hipMemsetAsync(F.bp, 0, sizeof(T) * (size_t)B.GB * n_tau * P.BPS, st));
+  GW_HIP(hipMemsetAsync(F.bp, 0, sizeof(T) * n_bp, st));
+  // buffers of the second pivot of a pair, within 32 GiB (else no pairs)
+  if (P.pair_h > 0 && sizeof(T) * (n_mb + n_bp + (size_t)N * RS) > (32ull << 30)) P.pair_h = 0;
+  if (P.pair_h > 0) {
+    if ((rc = M.alloc(&F.dvg1, (size_t)N * RS)) != GW_OK) return rc;
+    if ((rc = M.alloc(&F.mb1, n_mb)) != GW_OK) return rc;
+    if ((rc = M.alloc(&F.bp1, n_bp)) != GW_OK) return rc;
+    GW_HIP(hipMemsetAsync(F.bp1, 0, sizeof(T) * n_bp, st));
+  }
 
   StageA<T>& sa = F.sa;
   sa.dof = F.dof; sa.t3c = F.t3c; sa.mb = F.mb; sa.goff = ix.goff; sa.seg_atom = ix.seg_atom;
@@ -369,6 +386,22 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
   if ((rc = M.upload(&d_bp_off, P.pan.off)) != GW_OK) return rc;
 
   const Index ix{d_goff, d_seg_atom, d_gc, d_gslot, d_ulen, d_kmap, d_km_off, d_seg_brick, d_bp_off};
+  // pivot pairs (FP64 / FP32): pivots i and i + h, h = ceil(na / 2), share the
+  // stage-C launch when no RI atom couples to both (their chi rows are then
+  // disjoint); the launches of the strip's last pivots, whose upper-triangle
+  // blocks are few, then carry the first pivots' tiles as well
+  P.pair_h = 0;
+  if (B.prec != GW_BF16X3 && na >= 4) {
+    const int h = (na + 1) / 2;
+    std::vector<int> mark(na, -1);
+    bool disjoint = true;
+    for (int i = 0; i + h < na && disjoint; ++i) {
+      for (int g = G.gb_start[i]; g < G.gb_start[i + 1]; ++g) mark[G.gc[g]] = i;
+      for (int g = G.gb_start[i + h]; g < G.gb_start[i + h + 1]; ++g)
+        if (mark[G.gc[g]] == i) disjoint = false;
+    }
+    if (disjoint) P.pair_h = h;
+  }
   if (B.GB == 0) {
     // pivots per stage-B launch, fixed by the first system of the plan: up to
     // 160 rows (pivot, tau, sigma) per tile, the group's N_b within 16 GiB
@@ -460,39 +493,66 @@ inline int pivot_groups(const SysPlan& P, int piv, int& g0) {
   return P.G.gb_start[piv + 1] - g0;
 }
 
-// tables of stages A and B (and the D^vir gathers) for every pivot index
+// the pivots of system P at loop index i: pivot, buffer slot and the range
+// [lo, hi) of pivots of that slot (stage-B groups do not cross it)
+struct PivSlot {
+  int piv, slot, lo, hi;
+};
+inline int loop_pivots(const SysPlan& P, int i, PivSlot out[2]) {
+  if (P.pair_h == 0) {
+    if (i >= P.na) return 0;
+    out[0] = PivSlot{i, 0, 0, P.na};
+    return 1;
+  }
+  int n = 0;
+  if (i < P.pair_h) out[n++] = PivSlot{i, 0, 0, P.pair_h};
+  if (i + P.pair_h < P.na) out[n++] = PivSlot{i + P.pair_h, 1, P.pair_h, P.na};
+  return n;
+}
+
+// tables of stages A and B (and the D^vir gathers) for every loop index
 template <class T>
 gw_status ab_tables_f(gw_chi_batch& B, hipStream_t st) {
   FTables<T>& F = tabs<T>(B);
-  const int n_piv = B.max_na, n_tau = B.n_tau;
-  F.tA.begin(n_piv);
-  F.tB.begin(n_piv);
+  const int n_idx = B.n_loop, n_tau = B.n_tau;
+  F.tA.begin(n_idx);
+  F.tB.begin(n_idx);
   F.gath.clear();
-  F.gath0.assign(n_piv, 0);
-  F.gathn.assign(n_piv, 0);
-  for (int piv = 0; piv < n_piv; ++piv) {
-    F.tA.open(piv);
-    F.tB.open(piv);
-    F.gath0[piv] = (int)F.gath.size();
+  F.gath0.assign(n_idx, 0);
+  F.gathn.assign(n_idx, 0);
+  for (int i = 0; i < n_idx; ++i) {
+    F.tA.open(i);
+    F.tB.open(i);
+    F.gath0[i] = (int)F.gath.size();
     for (int m : B.order) {
       SysPlan& P = B.sys[m];
       FBufs<T>& pb = bufs<T>(P);
-      int g0 = 0;
-      const int nR = pivot_groups(P, piv, g0);
-      if (nR == 0) continue;
-      StageA<T> a = pb.sa;
-      a.g0 = g0;
-      F.tA.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
-      // stage B once per group of GB pivots, at its first pivot: rows
-      // (pivot, tau, sigma) of the group's pivots this system has
-      if (piv % B.GB != 0) continue;
-      const int ng = std::min(B.GB, P.na - piv);
-      StageB<T> b = pb.sb;
-      b.RS = ng * B.RS;
-      b.n_rt = (b.RS + b.rows_pt - 1) / b.rows_pt;
-      F.tB.add(piv, b, P.n_groups * b.n_rt * b.n_ct, 1, 1);
-      F.gath.push_back(GatherEnt<T>{pb.dvf, pb.dvg, P.N, piv, ng});
-      F.gathn[piv]++;
+      PivSlot ps[2];
+      const int np = loop_pivots(P, i, ps);
+      for (int k = 0; k < np; ++k) {
+        const int piv = ps[k].piv;
+        const bool s1 = ps[k].slot == 1;
+        int g0 = 0;
+        const int nR = pivot_groups(P, piv, g0);
+        if (nR > 0) {
+          StageA<T> a = pb.sa;
+          a.g0 = g0;
+          a.mb = s1 ? pb.mb1 : pb.mb;
+          F.tA.add(i, a, nR * a.n_rt * a.n_ct, n_tau, 1);
+        }
+        // stage B once per group of GB pivots of the slot, at its first
+        // pivot: rows (pivot, tau, sigma) of the group's pivots
+        if ((piv - ps[k].lo) % B.GB != 0) continue;
+        const int ng = std::min(B.GB, ps[k].hi - piv);
+        StageB<T> b = pb.sb;
+        b.RS = ng * B.RS;
+        b.n_rt = (b.RS + b.rows_pt - 1) / b.rows_pt;
+        b.dvg = s1 ? pb.dvg1 : pb.dvg;
+        b.bp = s1 ? pb.bp1 : pb.bp;
+        F.tB.add(i, b, P.n_groups * b.n_rt * b.n_ct, 1, 1);
+        F.gath.push_back(GatherEnt<T>{pb.dvf, s1 ? pb.dvg1 : pb.dvg, P.N, piv, ng});
+        F.gathn[i]++;
+      }
     }
   }
   gw_status rc;
@@ -502,7 +562,7 @@ gw_status ab_tables_f(gw_chi_batch& B, hipStream_t st) {
 }
 
 gw_status ab_tables_bf(gw_chi_batch& B, hipStream_t st) {
-  const int n_piv = B.max_na, n_tau = B.n_tau;
+  const int n_piv = B.n_loop, n_tau = B.n_tau;   // no pairs in this form
   B.tAb.begin(n_piv);
   B.tBb.begin(n_piv);
   for (int piv = 0; piv < n_piv; ++piv) {
@@ -535,50 +595,54 @@ gw_status build_ab_tables(gw_chi_batch& B, hipStream_t st) {
 // stage-C tables for the current variant and output pointers
 template <class C, class Get>
 void c_tables(gw_chi_batch& B, Table<C>& tab, Get get, double* const* chi) {
-  // get(P, piv): the system's stage-C problem for pivot piv
-  const int n_piv = B.max_na, n_tau = B.n_tau, rows = c_rows(B.prec, B.variant);
-  tab.begin(n_piv);
-  for (int piv = 0; piv < n_piv; ++piv) {
-    tab.open(piv);
+  // get(P, ps): the system's stage-C problem for pivot ps.piv of buffer slot ps.slot
+  const int n_idx = B.n_loop, n_tau = B.n_tau, rows = c_rows(B.prec, B.variant);
+  tab.begin(n_idx);
+  for (int i = 0; i < n_idx; ++i) {
+    tab.open(i);
     for (int m : B.order) {
       SysPlan& P = B.sys[m];
-      int g0 = 0;
-      const int nR = pivot_groups(P, piv, g0);
-      if (nR == 0) continue;
-      const int n_rt = (nR * B.NR + rows - 1) / rows;
-      C c = get(P, piv);
-      c.chi = chi[m];
-      c.g0 = g0;
-      c.nR = nR;
-      c.rows_pt = rows;
-      c.n_rt = n_rt;
-      c.keep = P.keep;
-      c.tiles_skipped = B.tiles_skipped;
-      tab.add(piv, c, n_rt * P.n_pan, 1, n_tau);
+      PivSlot ps[2];
+      const int np = loop_pivots(P, i, ps);
+      for (int k = 0; k < np; ++k) {
+        int g0 = 0;
+        const int nR = pivot_groups(P, ps[k].piv, g0);
+        if (nR == 0) continue;
+        const int n_rt = (nR * B.NR + rows - 1) / rows;
+        C c = get(P, ps[k]);
+        c.chi = chi[m];
+        c.g0 = g0;
+        c.nR = nR;
+        c.rows_pt = rows;
+        c.n_rt = n_rt;
+        c.keep = P.keep;
+        c.tiles_skipped = B.tiles_skipped;
+        tab.add(i, c, n_rt * P.n_pan, 1, n_tau);
+      }
     }
   }
 }
 
 gw_status build_c_tables(gw_chi_batch& B, double* const* chi, hipStream_t st) {
   gw_status rc;
-  // FP64 / FP32: pivot piv reads its slab of the group's N_b
+  // FP64 / FP32: pivot piv reads M_b of its slot and its slab of the slot's
+  // stage-B group N_b
   const int64_t slab = (int64_t)B.n_tau;
+  auto slot_c = [&](auto& F, const SysPlan& P, const PivSlot& ps) {
+    auto c = F.sc;
+    const bool s1 = ps.slot == 1;
+    c.mb = s1 ? F.mb1 : F.mb;
+    c.bp = (s1 ? F.bp1 : F.bp) + ((ps.piv - ps.lo) % B.GB) * slab * P.BPS;
+    return c;
+  };
   if (B.prec == GW_FP64) {
-    c_tables(B, B.t64.tC, [&](SysPlan& P, int piv) {
-      StageC<double> c = P.f64.sc;
-      c.bp += (piv % B.GB) * slab * P.BPS;
-      return c;
-    }, chi);
+    c_tables(B, B.t64.tC, [&](SysPlan& P, const PivSlot& ps) { return slot_c(P.f64, P, ps); }, chi);
     rc = B.t64.tC.upload(B.mem, st);
   } else if (B.prec == GW_FP32) {
-    c_tables(B, B.t32.tC, [&](SysPlan& P, int piv) {
-      StageC<float> c = P.f32.sc;
-      c.bp += (piv % B.GB) * slab * P.BPS;
-      return c;
-    }, chi);
+    c_tables(B, B.t32.tC, [&](SysPlan& P, const PivSlot& ps) { return slot_c(P.f32, P, ps); }, chi);
     rc = B.t32.tC.upload(B.mem, st);
   } else {
-    c_tables(B, B.tCb, [](SysPlan& P, int) { return P.bc; }, chi);
+    c_tables(B, B.tCb, [](SysPlan& P, const PivSlot&) { return P.bc; }, chi);
     rc = B.tCb.upload(B.mem, st);
   }
   if (rc != GW_OK) return rc;
@@ -802,7 +866,7 @@ gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const
   auto mark = [&](int piv, int k) -> hipError_t {
     return ev ? hipEventRecord((*ev)[4 * piv + k], st) : hipSuccess;
   };
-  for (int piv = 0; piv < B.max_na; ++piv) {
+  for (int piv = 0; piv < B.n_loop; ++piv) {
     int* q = B.queues + 3 * kXcds * piv;
     gw_status rc = GW_OK;
     if (B.prec == GW_FP64) {
@@ -880,8 +944,8 @@ gw_status execute(gw_chi_batch& B, const double* const* occ, const double* const
     }
     GW_HIP(hipGraphLaunch(B.gexec, st));
   } else {
-    if (timing && B.ev.size() < 4 * (size_t)B.max_na) {
-      while (B.ev.size() < 4 * (size_t)B.max_na) {
+    if (timing && B.ev.size() < 4 * (size_t)B.n_loop) {
+      while (B.ev.size() < 4 * (size_t)B.n_loop) {
         hipEvent_t e;
         GW_HIP(hipEventCreate(&e));
         B.ev.push_back(e);
@@ -920,13 +984,13 @@ gw_status execute(gw_chi_batch& B, const double* const* occ, const double* const
     stats->flops_c = fc * B.n_tau;
     for (int k = 0; k < 3; ++k) {
       int64_t nl = 0;
-      for (int piv = 0; piv < B.max_na; ++piv)
+      for (int piv = 0; piv < B.n_loop; ++piv)
         nl += (B.prec == GW_FP64   ? (k == 0 ? B.t64.tA.n[piv] : k == 1 ? B.t64.tB.n[piv] : B.t64.tC.n[piv])
                : B.prec == GW_FP32 ? (k == 0 ? B.t32.tA.n[piv] : k == 1 ? B.t32.tB.n[piv] : B.t32.tC.n[piv])
                                    : (k == 0 ? B.tAb.n[piv] : k == 1 ? B.tBb.n[piv] : B.tCb.n[piv])) > 0;
       stats->n_launch[k] = nl;
     }
-    for (int piv = 0; timing && piv < B.max_na; ++piv)
+    for (int piv = 0; timing && piv < B.n_loop; ++piv)
       for (int k = 0; k < 3; ++k) {
         float ms;
         GW_HIP(hipEventElapsedTime(&ms, B.ev[4 * piv + k], B.ev[4 * piv + k + 1]));
@@ -1002,7 +1066,8 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   std::stable_sort(B->order.begin(), B->order.end(), [&](int x, int y) {
     return B->sys[x].fl_c + B->sys[x].fl_a > B->sys[y].fl_c + B->sys[y].fl_a;
   });
-  B->n_queues = 3 * kXcds * std::max(B->max_na, 1);
+  for (const SysPlan& P : B->sys) B->n_loop = std::max(B->n_loop, P.pair_h > 0 ? P.pair_h : P.na);
+  B->n_queues = 3 * kXcds * std::max(B->n_loop, 1);
   if ((rc = B->mem.alloc(&B->queues, B->n_queues)) != GW_OK) return rc;
   if ((rc = B->mem.alloc(&B->tiles_skipped, 1)) != GW_OK) return rc;
   GW_HIP(hipMemsetAsync(B->tiles_skipped, 0, sizeof(int), st));

@@ -1,0 +1,98 @@
+"""Pivot pairs in the chi plans: when no RI atom couples to both pivot atoms
+i and i + ceil(n/2), their outer contractions write disjoint chi rows and
+share one stage-C launch (the last pivots of a long system, whose
+upper-triangle blocks are few, then ride along with the first ones).
+
+A 48-atom wire (13 AO / 40 RI per atom, filter 1e-8, 12 tau) pairs its
+pivots: the all-tau call launches stage C 24 times instead of 48, chi matches
+the oracle's block routine on sampled output blocks (1e-12 relative), is
+symmetric and negative semidefinite (up to the block filter) on random
+principal submatrices,
+and a one-tau plan (which pairs too) reproduces every tau slice bit for bit,
+in FP64 and FP32."""
+import numpy as np
+import pytest
+
+from gwinputs import configs
+from oracle import gt as ogt, chi as ochi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wire():
+    import torch
+    from gwinputs import device as gdev
+    from paper_2104_09857_amd import gw
+    w = configs.wire(48)
+    s = w.system
+    C, eps = s.mean_field()
+    g = configs.grids_for(w, eps)
+    mu = configs.mu_fermi(eps, s.n_occ)
+    trip = s.triples()
+    t3c = gdev.bricks_on_device(s, trip)
+    sysd = gw.System(s.n_atoms, s.n_ao_atom, s.n_ri_atom, s.n_occ, trip, t3c)
+    do, dv = gw.build_gt(sysd, torch.as_tensor(C, device="cuda"), eps, mu, g.tau)
+    return dict(w=w, s=s, C=C, eps=eps, g=g, mu=mu, trip=trip, sys=sysd, do=do, dv=dv)
+
+
+def test_pairs_match_oracle_blocks(wire):
+    import torch
+    from paper_2104_09857_amd import gw
+    s, trip = wire["s"], wire["trip"]
+    chi, st = gw.contract_chi(wire["sys"], wire["do"], wire["dv"], s.filter_eps)
+    torch.cuda.synchronize()
+    print("case wire48 stage launches", st["n_launch"], flush=True)
+    assert st["n_launch"][2] == (s.n_atoms + 1) // 2 and st["n_launch"][0] == (s.n_atoms + 1) // 2
+    cache = {}
+
+    def brick(a, b, c):
+        if (a, b, c) not in cache:
+            sel = trip[trip[:, 2] == c]
+            for t, v in zip(sel, s.bricks(sel)):
+                cache[tuple(t)] = v.reshape(s.n_ao_atom, s.n_ao_atom, s.n_ri_atom)
+        return cache[(a, b, c)]
+
+    j_list = [0, 6, 11]
+    do, dv = ogt.density_matrices(wire["C"], wire["eps"], s.n_occ, wire["mu"], wire["g"].tau[j_list])
+    # blocks on rows of first-half pivots, of second-half pivots, and of the middle
+    for (c, c2) in [(3, 5), (30, 31), (23, 24), (24, 30), (20, 27), (45, 47)]:
+        for jj, j in enumerate(j_list):
+            ref = ochi.chi_block(c, c2, trip, brick, do[jj], dv[jj], s.ao_off, s.ri_off, s.filter_eps)
+            if np.sqrt((ref * ref).sum()) < s.filter_eps:
+                ref = np.zeros_like(ref)
+            got = chi[j, s.ri_off[c]:s.ri_off[c + 1], s.ri_off[c2]:s.ri_off[c2 + 1]].cpu().numpy()
+            scale = np.abs(chi[j].diagonal().cpu().numpy()).max()
+            print("case block", c, c2, "tau", j, flush=True)
+            assert np.abs(got - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300) + 1e-14 * scale
+    rng = np.random.default_rng(2)
+    for j in (0, 11):
+        x = chi[j]
+        # off-diagonal atom blocks are mirrored; the diagonal ones are full
+        # products, symmetric up to rounding
+        assert float((x - x.T).abs().max()) <= 1e-14 * float(x.abs().max())
+        idx = torch.as_tensor(np.sort(rng.choice(x.shape[0], 400, replace=False)), device="cuda")
+        sub = x[idx][:, idx].cpu().numpy()
+        ev = np.linalg.eigvalsh(0.5 * (sub + sub.T))
+        # negative semidefinite up to the block filter: every dropped block
+        # has a Frobenius norm below eps_f, which bounds its shift of the
+        # spectrum (Weyl); n_atoms * eps_f covers the blocks of one row
+        assert ev.max() <= 1e-12 * np.abs(ev).max() + s.n_atoms * s.filter_eps
+        assert ev.min() < -1e3 * s.n_atoms * s.filter_eps
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pairs_one_tau_equals_all_tau(wire, prec):
+    import torch
+    from paper_2104_09857_amd import gw
+    s = wire["s"]
+    ref, st = gw.contract_chi(wire["sys"], wire["do"], wire["dv"], s.filter_eps, prec=prec)
+    assert st["n_launch"][2] == (s.n_atoms + 1) // 2
+    plan = gw.ChiBatch([wire["sys"]], 1, s.filter_eps, prec=prec)
+    out = torch.empty_like(ref[:1])
+    for j in range(ref.shape[0]):
+        print("case pairs one-tau", prec, "tau", j, flush=True)
+        plan.execute([wire["do"][j:j + 1]], [wire["dv"][j:j + 1]], [out])
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], ref[j]), (prec, j)
+    plan.close()
