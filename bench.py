@@ -77,14 +77,17 @@ DTYPE = {"fp64": "f64", "fp32": "f32 (FP32 MFMA and accumulation in a tile, FP64
          "bf16x3": "bf16x3 (bf16 hi/lo MFMA, FP32 accumulation in a tile, FP64 across pivots)"}
 _C_TILES = {"fp64": ["4,2,5,32", "2,2,5,32", "4,2,5,16", "4,2,5,32,2"],
             "fp32": ["4,2,5,32", "2,2,5,32", "4,2,5,16", "4,2,5,16,3"],
-            "bf16x3": ["4,2,4,5,32", "4,2,2,5,32", "2,2,4,5,32", "4,2,3,5,32"]}
+            "bf16x3": ["4,2,4,5,32", "4,2,2,5,32", "2,2,4,5,32", "4,2,4,5,3"]}
 _C_PROB = {"fp64": "StageC<double>", "fp32": "StageC<float>", "bf16x3": "StageCBf"}
 
 
 def stage_c_kernel(prec, variant, mask, batched=False):
     """Name of the stage-C kernel a chi run launched (as rocprofv3 lists it);
-    variant 3 of FP64 / FP32 is the direct-to-LDS engine (tile_dma)."""
-    eng = "tile_bf16x3" if prec == "bf16x3" else "tile_dma" if variant == 3 else "tile_gemm"
+    variant 3 is the direct-to-LDS engine (tile_dma; tile_bf3_dma in BF16x3)."""
+    if prec == "bf16x3":
+        eng = "tile_bf3_dma" if variant == 3 else "tile_bf16x3"
+    else:
+        eng = "tile_dma" if variant == 3 else "tile_gemm"
     prob = _C_PROB[prec]
     if mask & 4:
         return f"{eng}_persistent<{_C_TILES[prec][variant]},Batched<{prob}>>"

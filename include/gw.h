@@ -220,8 +220,8 @@ gw_status gw_t3c_gaussian(const gw_system *s, const double *ao_exp, const double
  * when ri_per_atom is odd) with all stages persistent, FP32 variant 3
  * (variant 0 when ri_per_atom is not a multiple of 4) with stages B and C
  * persistent (stage B as a grid when the
- * basis has at most 64 AO x RI functions per atom pair), BF16x3 variant 0
- * with all stages persistent).
+ * basis has at most 64 AO x RI functions per atom pair), BF16x3 variant 3
+ * (its direct-to-LDS outer contraction) with all stages persistent).
  * With a block screener (opts->screener, beyond the paper; the filter idea of
  * the computational details) the output blocks (c <= c', tau) predicted below
  * log10(filter_eps) - screen_margin are not computed and left zero; blocks in

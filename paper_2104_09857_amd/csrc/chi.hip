@@ -31,16 +31,17 @@ namespace {
 
 // stage-C tile variants: rows of a tile (columns are one 160-wide panel)
 //   FP64 and FP32  0: <WM 4, KC 32> 128 rows  1: <WM 2, KC 32> 64 rows  2: <WM 4, KC 16> 128 rows
-//                  3: direct-to-LDS copies three chunks deep, two workgroups per CU:
-//                     FP64 <WM 2, WN 5, NB 2, KC 8> 64 rows (10 waves of 32 x 32),
-//                     FP32 <WM 4, WN 2, NB 5, KC 16> 128 rows; needs NR a multiple of
-//                     2 (FP64) / 4 (FP32)
+//                  3: direct-to-LDS copies (tile_dma.hpp), 128 rows:
+//                     FP64 <WM 4, WN 2, NB 5, KC 32> two chunks deep, one workgroup per CU,
+//                     FP32 <WM 4, WN 2, NB 5, KC 16> three chunks deep, two per CU;
+//                     needs NR a multiple of 2 (FP64) / 4 (FP32)
 //   BF16x3  0: <WM 4, RB 4> 256 rows    1: <WM 4, RB 2> 128 rows   2: <WM 2, RB 4> 128 rows
-//           3: <WM 4, RB 3> 192 rows
+//           3: direct-to-LDS copies three chunks deep (tile_bf16x3_dma.hpp),
+//              <WM 4, RB 4> 256 rows
 constexpr int kNVar = 4;
 int c_rows(int prec, int v) {
   static const int f64[kNVar] = {128, 64, 128, 128}, f32[kNVar] = {128, 64, 128, 128},
-                   bf[kNVar] = {256, 128, 128, 192};
+                   bf[kNVar] = {256, 128, 128, 256};
   return prec == GW_BF16X3 ? bf[v] : prec == GW_FP32 ? f32[v] : f64[v];
 }
 // stage-C variant usable for this precision and RI block size
@@ -425,6 +426,9 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     if ((rc = M.upload(&d_poffb, poffb)) != GW_OK) return rc;
     const size_t tsz = (size_t)s->n_trip * NR * NA * 16, dsz16 = (size_t)n_tau * N * na * 16;
     const size_t msz = (size_t)n_tau * P.nRmax * N * NR * 16, nsz = (size_t)n_tau * P.BPS16;
+    // the direct-to-LDS outer contraction takes its M_b offsets within one tau in 32 bits
+    GW_CHECK_ARG((int64_t)(P.nRmax + 1) * N * NR * 16 < (1ll << 31),
+                 "system too large for 32-bit tile offsets");
     if ((rc = M.alloc(&P.th, tsz)) != GW_OK) return rc;
     if ((rc = M.alloc(&P.tl, tsz)) != GW_OK) return rc;
     if ((rc = M.alloc(&P.doh, dsz16)) != GW_OK) return rc;
@@ -709,6 +713,23 @@ hipError_t run_bf(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t
               : launch_tile_bf16x3<WM, WN, RB, NB, KC>(b, dim3((unsigned)work), st);
 }
 
+template <int WM, int WN, int RB, int NB, int S, class P>
+hipError_t run_bf_dma(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t st) {
+  if (!queue) {
+    (void)persistent_cap_bf3_dma<WM, WN, RB, NB, S, Batched<P>>();
+    return hipSuccess;
+  }
+  const int work = T.work[piv];
+  if (T.n[piv] == 0 || work == 0) return hipSuccess;
+  if (!pers && T.n[piv] == 1) {
+    const BatchEntry<P>& e = T.ent[T.ent0[piv]];
+    return launch_tile_bf3_dma<WM, WN, RB, NB, S>(e.p, dim3(e.gx, e.gy, work / (e.gx * e.gy)), st);
+  }
+  const Batched<P> b = T.at(piv);
+  return pers ? launch_tile_bf3_dma_persistent<WM, WN, RB, NB, S>(b, work, queue, st)
+              : launch_tile_bf3_dma<WM, WN, RB, NB, S>(b, dim3((unsigned)work), st);
+}
+
 template <class T>
 hipError_t stage_a_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
   if constexpr (std::is_same<T, float>::value) {
@@ -782,7 +803,7 @@ hipError_t stage_c_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStre
   switch (B.variant) {
     case 1: return run_bf<4, BF_WN, 2, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
     case 2: return run_bf<2, BF_WN, 4, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
-    case 3: return run_bf<4, BF_WN, 3, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
+    case 3: return run_bf_dma<4, BF_WN, 4, BF_NB_C, 3>(B.tCb, piv, pers, q, st);
     default: return run_bf<4, BF_WN, 4, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
   }
 }
@@ -1044,8 +1065,8 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   B->out_filter = !(opts && opts->keep_small_blocks);
   // default tile configuration per precision (fastest measured for 13 AO / 40 RI per atom)
   // direct-to-LDS outer contraction (variant 3) when the RI block size allows
-  // its 16-byte copies; else the register-staged tiles
-  B->variant = variant_ok(prec, NR, 3) && prec != GW_BF16X3 ? 3 : prec == GW_FP64 ? 2 : 0;
+  // its 16-byte copies (always in BF16x3); else the register-staged tiles
+  B->variant = variant_ok(prec, NR, 3) ? 3 : prec == GW_FP64 ? 2 : 0;
   // FP32: stage A as a grid; stage B persistent on the wide tiles, a grid on
   // the narrow ones (measured on 13/40 and 5/12 bases)
   B->persistent = prec == GW_FP32 ? (B->ab_nb == AB_NBN ? 4 : 6) : 7;

@@ -17,6 +17,7 @@
 #pragma once
 #include "gw_internal.hpp"
 #include "tile_bf16x3.hpp"
+#include "tile_bf16x3_dma.hpp"
 #include "tile_dma.hpp"
 
 namespace gw {

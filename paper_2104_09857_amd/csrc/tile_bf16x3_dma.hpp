@@ -1,0 +1,267 @@
+// Direct-to-LDS form of the split-precision (BF16 x 3) engine, for the outer
+// contraction of chi.
+//
+// The register-staged engine (tile_bf16x3.hpp) keeps one K chunk in flight:
+// it loads the next chunk into registers while the current one feeds the
+// matrix cores, so each 32-deep chunk (about 1900 matrix-core cycles per SIMD
+// on a 256 x 160 tile) must hide a whole global-memory round trip, and it
+// waits at two barriers per chunk.  Here the load units copy the operands
+// straight into LDS (global_load_lds, 16 bytes per lane), S chunks deep,
+// with one barrier per chunk; the per-tile LDS table of panel offsets is
+// replaced by wave-uniform (scalar) reads of the index array, which leaves
+// room for three stages of a 256 x 160 tile.
+//
+// Operands (bf16 hi and lo arrays, same offsets) are addressed by k pairs:
+// pair u holds 16 consecutive k values (two 16-byte groups) of a row:
+//   A(r, 16 u + j) at abase + arow(r) + a_tab[u] * a_mul + j
+//   B(16 u + j, c) at bbase + 16 c + u * b_mul + j              (bf16 units)
+// with u < t.K / 16; the table a_tab is read with scalar loads (its address
+// and u are wave-uniform), which do not count against the vector-memory
+// counter that tracks the copies in flight.  One LDS stage holds, per array, [KC / 16][ROWS][2]
+// (A) and [KC / 16][COLS][2] (B) cells of 16 bytes; the two cells of a row
+// and pair are swapped when bit 2 of the row is set, so the 16 rows read by
+// one quarter of a wave fall on distinct banks.  A copy instruction fills 64
+// consecutive cells (32 rows of one pair); each lane fetches the cell the
+// swap places at its position, so a copy reads 32 whole 32-byte row pieces.
+//
+// The matrix-core steps, the k values of each lane and the order of every
+// sum are those of the register-staged engine: results are bit-identical.
+// Rows and columns outside the tile are copied from clamped valid addresses
+// (their outputs are not stored); pairs past the end are copied from the
+// last pair and their A values are zeroed when read.
+#pragma once
+
+#include "tile_bf16x3.hpp"
+#include "tile_dma.hpp"
+
+namespace gw {
+
+template <int WM, int WN, int RB, int NB, int S, class P>
+__device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, int bz) {
+  constexpr int ROWS = 16 * RB * WM, COLS = 16 * NB * WN, NT = 64 * WM * WN, NW = NT / 64;
+  constexpr int KC = 32, NP = KC / 16;                       // k pairs per chunk
+  constexpr int AC = NP * ROWS * 2, BC = NP * COLS * 2;      // cells per array per stage
+  constexpr int SC = 2 * AC + 2 * BC;                        // cells per stage
+  constexpr int NCA = AC / 64, NCB = BC / 64;                // copies per array
+  constexpr int NC = 2 * NCA + 2 * NCB, CPW = (NC + NW - 1) / NW, CMIN = NC / NW;
+  static_assert(ROWS % 32 == 0 && COLS % 32 == 0 && S >= 2 && CMIN >= 1, "copy layout");
+  static_assert(S == 3 && CPW < 16, "three stages; vmcnt immediate");
+  __shared__ __attribute__((aligned(16))) u32x4_t L0[SC];
+  __shared__ __attribute__((aligned(16))) u32x4_t L1[SC];
+  __shared__ __attribute__((aligned(16))) u32x4_t L2[SC];
+
+  typename P::Tile t;
+  if (!p.tile(bx, by, bz, t)) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave % WM, wn = wave / WM;
+  const auto lp = resolve(p, t);
+  const int npairs = t.K / 16, pmax = npairs - 1;
+  // the pair table through the scalar (constant) path
+  const uint64_t tp = (uint64_t)(uintptr_t)lp.a_tab(t);
+  const uint32_t tlo = __builtin_amdgcn_readfirstlane((uint32_t)tp);
+  const uint32_t thi = __builtin_amdgcn_readfirstlane((uint32_t)(tp >> 32));
+  const __attribute__((address_space(4))) int32_t* atab =
+      (const __attribute__((address_space(4))) int32_t*)(((uint64_t)thi << 32) | tlo);
+  const uint32_t amul = __builtin_amdgcn_readfirstlane(lp.a_mul());
+  const uint32_t bmul = __builtin_amdgcn_readfirstlane(lp.b_mul());
+
+  // copies of this wave: copy c = wave + NW * j over [A hi | A lo | B hi | B lo];
+  // for each, its array, its pair inside the chunk, the cell offset inside
+  // the stage and the lane's fixed part of the global offset
+  const gmem<const uint16_t>* cbase[CPW];
+  bool cisb[CPW];
+  int cpair[CPW], ccell[CPW];
+  uint32_t clane[CPW];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int c = wave + NW * j < NC ? wave + NW * j : NC - 1;
+    const int arr = c < NCA ? 0 : c < 2 * NCA ? 1 : c < 2 * NCA + NCB ? 2 : 3;
+    const int cc = arr == 0 ? c : arr == 1 ? c - NCA : arr == 2 ? c - 2 * NCA : c - 2 * NCA - NCB;
+    const bool isb = arr >= 2;
+    const int width = isb ? COLS : ROWS;
+    const int e = cc * 64 + lane;                            // cell inside the array
+    const int pair = e / (2 * width), rem = e % (2 * width);
+    const int x = rem >> 1, half = (rem & 1) ^ ((x >> 2) & 1);
+    cbase[j] = to_global(arr == 0 ? lp.abase_hi(t) : arr == 1 ? lp.abase_lo(t)
+                         : arr == 2 ? lp.bbase_hi(t) : lp.bbase_lo(t));
+    cisb[j] = isb;
+    cpair[j] = pair;
+    ccell[j] = (arr == 0 ? 0 : arr == 1 ? AC : arr == 2 ? 2 * AC : 2 * AC + BC) + cc * 64;
+    if (isb) clane[j] = (uint32_t)(16 * (x < t.cols ? x : t.cols - 1) + 8 * half);
+    else clane[j] = (uint32_t)lp.arow(t, x < t.rows ? x : t.rows - 1) + (uint32_t)(8 * half);
+  }
+
+  // every wave issues CPW copies per chunk (a wave with fewer repeats the
+  // last copy: the same cells, the same data), chunks past the end copy the
+  // last pair, so that the code has no branches and the compiler can count
+  // the copies in flight
+  auto issue = [&](int ch, u32x4_t* dst) {
+    // the table entries first (one wait for all of them), then the copies
+    int uj[CPW], tv[CPW];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int u = ch * NP + cpair[j];
+      uj[j] = __builtin_amdgcn_readfirstlane(u < pmax ? u : pmax);
+      tv[j] = atab[uj[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const uint32_t po = cisb[j] ? (uint32_t)uj[j] * bmul : (uint32_t)tv[j] * amul;
+      const gmem<const uint16_t>* g = cbase[j] + (po + clane[j]);
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                       (void __attribute__((address_space(3)))*)(dst + ccell[j]),
+                                       16, 0, 0);
+    }
+  };
+
+  f32x4_t acc[RB][NB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  // this lane's cells: group g = 4 kk + lk of the chunk is half (lk & 1) of
+  // pair 2 kk + (lk >> 1); row / column x sits in cell 2 x + (half ^ bit 2 of x)
+  const int lr = lane & 15, lk = lane >> 4, lh = lk & 1, lpr = lk >> 1;
+  int ao[RB], bo[NB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int r = (wm * RB + rb) * 16 + lr;
+    ao[rb] = (lpr * ROWS + r) * 2 + (lh ^ ((r >> 2) & 1));
+  }
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    const int c = (wn * NB + cb) * 16 + lr;
+    bo[cb] = 2 * AC + (lpr * COLS + c) * 2 + (lh ^ ((c >> 2) & 1));
+  }
+
+  const int ngroups = 2 * npairs;
+  const int nch = (npairs + NP - 1) / NP;
+  // One chunk: wait for its copies, barrier, the copies of chunk ch + S - 1
+  // into stage dst, then the matrix-core steps on stage ls.
+  auto chunk = [&](int ch, u32x4_t* dst, const u32x4_t* ls) {
+    wait_vm<CPW>();                  // this wave's copies of chunk ch have landed
+    stage_barrier();                 // everyone's have; stage dst is free
+    issue(ch + S - 1, dst);
+    // groups past the end (last chunk only) read as zero in A
+    const bool ok = ch * 4 + lk < ngroups;
+    bf16x8_t ah[RB], al[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const u32x4_t z = {0u, 0u, 0u, 0u};
+      const u32x4_t h = ls[ao[rb]], l = ls[ao[rb] + AC];
+      ah[rb] = __builtin_bit_cast(bf16x8_t, ok ? h : z);
+      al[rb] = __builtin_bit_cast(bf16x8_t, ok ? l : z);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      const bf16x8_t bh = __builtin_bit_cast(bf16x8_t, ls[bo[cb]]);
+      const bf16x8_t bl = __builtin_bit_cast(bf16x8_t, ls[bo[cb] + BC]);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bh, acc[rb][cb], 0, 0, 0);
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bl, acc[rb][cb], 0, 0, 0);
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rb], bh, acc[rb][cb], 0, 0, 0);
+      }
+    }
+  };
+  // The stages are distinct LDS arrays and every access below names one of
+  // them (the chunk loop is unrolled by S): the compiler then knows that
+  // the copies in flight write other stages than the one read, and does not
+  // wait for them before each LDS read (the waits the pipeline needs are the
+  // explicit wait_vm + barrier of each chunk).
+  issue(0, L0);
+  issue(1, L1);
+  int c0 = 0;
+  for (; c0 + 3 <= nch; c0 += 3) {
+    chunk(c0, L2, L0);
+    chunk(c0 + 1, L0, L1);
+    chunk(c0 + 2, L1, L2);
+  }
+  if (c0 < nch) chunk(c0, L2, L0);
+  if (c0 + 1 < nch) chunk(c0 + 1, L0, L1);
+  wait_vm<0>();                      // no copy of a past-the-end chunk outlives the tile
+
+  // f32 16x16 MFMA output: lane l, element i -> row 4*(l/16) + i, col l%16;
+  // added with factor kSign to the FP64 output
+  static_assert(P::kOut == 0, "direct-to-LDS BF16 x 3 form accumulates into an FP64 output");
+  gmem<double>* __restrict__ ob = to_global(lp.obase(t));
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    const int c = (wn * NB + cb) * 16 + lr;
+    const bool cv = c < t.cols;
+    const int64_t co = cv ? lp.coloff(t, c) : 0;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      double old[4];
+      int64_t off[4];
+      bool okr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = (wm * RB + rb) * 16 + 4 * lk + i;
+        okr[i] = cv && r < t.rows;
+        off[i] = okr[i] ? lp.rowoff(t, r) + co : 0;
+        old[i] = ob[off[i]];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (okr[i]) ob[off[i]] = old[i] + P::kSign * (double)acc[rb][cb][i];
+    }
+  }
+}
+
+template <int WM, int WN, int RB, int NB, int S, class P>
+__global__ __launch_bounds__(64 * WM * WN) void tile_bf3_dma_kernel(P p) {
+  int bx, by, bz;
+  grid_tile(bx, by, bz);
+  tile_bf3_dma_body<WM, WN, RB, NB, S>(p, bx, by, bz);
+}
+
+// persistent form (same per-XCD queue protocol as tile_gemm_persistent)
+template <int WM, int WN, int RB, int NB, int S, class P>
+__global__ __launch_bounds__(64 * WM * WN) void tile_bf3_dma_persistent(P p, int n_work, int* queue) {
+  __shared__ int next;
+  const uint32_t q = (uint32_t)n_work / kXcds, r = (uint32_t)n_work % kXcds;
+  const uint32_t home = blockIdx.x % kXcds;
+  for (uint32_t j = 0; j < kXcds; ++j) {
+    const uint32_t x = (home + j) % kXcds;
+    const int start = (int)(x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q);
+    const int len = (int)(x < r ? q + 1 : q);
+    for (;;) {
+      __syncthreads();
+      if (threadIdx.x == 0) next = atomicAdd(queue + x, 1);
+      __syncthreads();
+      const int l = next;
+      if (l >= len) break;
+      tile_bf3_dma_body<WM, WN, RB, NB, S>(p, start + l, 0, 0);
+    }
+  }
+}
+
+template <int WM, int WN, int RB, int NB, int S, class P>
+inline hipError_t launch_tile_bf3_dma(const P& p, dim3 grid, hipStream_t st) {
+  if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
+  hipLaunchKernelGGL((tile_bf3_dma_kernel<WM, WN, RB, NB, S, P>), grid, dim3(64 * WM * WN), 0, st, p);
+  return hipGetLastError();
+}
+
+template <int WM, int WN, int RB, int NB, int S, class P>
+inline int persistent_cap_bf3_dma() {
+  static int cap = 0;
+  if (cap == 0) cap = resident_groups(tile_bf3_dma_persistent<WM, WN, RB, NB, S, P>, 64 * WM * WN);
+  return cap;
+}
+
+template <int WM, int WN, int RB, int NB, int S, class P>
+inline hipError_t launch_tile_bf3_dma_persistent(const P& p, int n_work, int* queue, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  const int cap = persistent_cap_bf3_dma<WM, WN, RB, NB, S, P>();
+  const int grid = cap > 0 ? (n_work < cap ? n_work : cap) : n_work;
+  hipLaunchKernelGGL((tile_bf3_dma_persistent<WM, WN, RB, NB, S, P>), dim3(grid), dim3(64 * WM * WN), 0,
+                     st, p, n_work, queue);
+  return hipGetLastError();
+}
+
+}  // namespace gw

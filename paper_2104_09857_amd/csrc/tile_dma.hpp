@@ -58,14 +58,21 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
   constexpr int ROWS = 32 * WM, COLS = 16 * NB * WN, NT = 64 * WM * WN, NW = NT / 64;
   constexpr int EPL = 16 / (int)sizeof(TI), PER = 64 * EPL;
   constexpr int ACH = KC * ROWS, BCH = KC * COLS;
-  constexpr int NCA = ACH / PER, NCB = BCH / PER, NC = NCA + NCB;   // copies per chunk
-  constexpr int CPW = (NC + NW - 1) / NW, CMIN = NC / NW;            // copies per wave (max, min)
+  constexpr int NCA = ACH / PER, NCB = BCH / PER;                   // copies per chunk
+  // copies per wave: JA of A then JB of B, the same count on every wave (a
+  // wave with fewer repeats its operand's last copy: same cells, same data)
+  constexpr int JA = (NCA + NW - 1) / NW, JB = (NCB + NW - 1) / NW, CPW = JA + JB;
   constexpr int BW = sizeof(TI) == 8 ? 32 : 64, G = BW / 16;
   auto rot = [](int k, int w) { return ((16 * (k % G) - (k * w) % BW) % BW + BW) % BW; };
   static_assert(ACH % PER == 0 && BCH % PER == 0 && ROWS % 16 == 0 && COLS % 16 == 0, "copy layout");
-  static_assert(KC % 4 == 0 && S >= 2 && CMIN >= 1, "pipeline shape");
-  __shared__ __attribute__((aligned(16))) TI As[S][ACH];
-  __shared__ __attribute__((aligned(16))) TI Bs[S][BCH];
+  static_assert(KC % 4 == 0 && (S == 2 || S == 3) && CPW * (S - 2) < 16, "pipeline shape");
+  // one LDS array per stage and operand (see the main loop)
+  __shared__ __attribute__((aligned(16))) TI As0[ACH];
+  __shared__ __attribute__((aligned(16))) TI As1[ACH];
+  __shared__ __attribute__((aligned(16))) TI As2[S > 2 ? ACH : EPL];
+  __shared__ __attribute__((aligned(16))) TI Bs0[BCH];
+  __shared__ __attribute__((aligned(16))) TI Bs1[BCH];
+  __shared__ __attribute__((aligned(16))) TI Bs2[S > 2 ? BCH : EPL];
   __shared__ int tabA[P::kTabA > 0 ? P::kTabA : 1];
   __shared__ int tabB[P::kTabB > 0 ? P::kTabB : 1];
 
@@ -88,55 +95,52 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
   afd.set((uint32_t)adiv);
   const int sgmax = kmax / adiv;
 
-  // copies of this wave: copy c = wave + NW * j (A copies first, then B); for
-  // each, the k row inside the chunk, the LDS offset inside the stage and the
-  // lane's fixed part of the global offset (A: row offset; B: k row * stride
-  // + column for a linear panel, the column for a gathered one)
+  // copies of this wave: A copy c = wave + NW * j (j < JA), B copy
+  // c = wave + NW * (j - JA) (j >= JA), each clamped to its operand's last;
+  // for each, the k row inside the chunk, the LDS offset inside the stage and
+  // the lane's fixed part of the global offset (A: row offset; B: k row *
+  // stride + column for a linear panel, the column for a gathered one)
   int ck[CPW], cl[CPW];
   uint32_t cg[CPW];
-  bool cb_[CPW];
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
-    const int c = wave + NW * j < NC ? wave + NW * j : NC - 1;
-    const bool isb = c >= NCA;
-    const int e = (isb ? c - NCA : c) * PER + lane * EPL;   // element of the chunk
+    const bool isb = j >= JA;
+    const int n = isb ? NCB : NCA, cj = wave + NW * (isb ? j - JA : j);
+    const int c = cj < n ? cj : n - 1;
+    const int e = c * PER + lane * EPL;                       // element of the chunk
     const int width = isb ? COLS : ROWS;
     const int k = e / width, pos = e % width;
     int x = pos - rot(k, width);
     x += x < 0 ? width : 0;                                   // row / column in the tile
     ck[j] = k;
-    cl[j] = (isb ? c - NCA : c) * PER;
-    cb_[j] = isb;
+    cl[j] = c * PER;
     if (isb) {
       cg[j] = (uint32_t)((BLIN ? k * bstr : 0) + (x < t.cols ? x : 0));
     } else {
       cg[j] = x < t.rows ? (uint32_t)lp.aroff(t, x) : (uint32_t)lp.aroff(t, 0);
     }
   }
-  const int nmine = wave + NW * (CPW - 1) < NC ? CPW : CPW - 1;
-
-  auto issue = [&](int ch, int stg) {
+  // the copies of chunk ch (k clamped: chunks past the end copy the last k row)
+  auto issue = [&](int ch, TI* adst, TI* bdst) {
     const int k0 = ch * KC;
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
-      if (j < nmine) {
-        int k = k0 + ck[j];
-        k = k < kmax ? k : kmax;
-        if (cb_[j]) {
-          const gmem<const TI>* g;
-          if constexpr (BLIN) g = bbase + (cg[j] + (uint32_t)((k - ck[j]) * bstr));
-          else g = bbase + (lp.bkoff(t, k, tabB) + cg[j]);
-          __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
-                                           (void __attribute__((address_space(3)))*)(&Bs[stg][cl[j]]),
-                                           16, 0, 0);
-        } else {
-          const int sg = (int)afd.div((uint32_t)k), u = k - sg * adiv;
-          const uint32_t ko = lp.akoff2(t, sg < sgmax ? sg : sgmax, u, tabA);
-          const gmem<const TI>* g = abase + (cg[j] + ko);
-          __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
-                                           (void __attribute__((address_space(3)))*)(&As[stg][cl[j]]),
-                                           16, 0, 0);
-        }
+      int k = k0 + ck[j];
+      k = k < kmax ? k : kmax;
+      if (j >= JA) {
+        const gmem<const TI>* g;
+        if constexpr (BLIN) g = bbase + (cg[j] + (uint32_t)((k - ck[j]) * bstr));
+        else g = bbase + (lp.bkoff(t, k, tabB) + cg[j]);
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                         (void __attribute__((address_space(3)))*)(bdst + cl[j]),
+                                         16, 0, 0);
+      } else {
+        const int sg = (int)afd.div((uint32_t)k), u = k - sg * adiv;
+        const uint32_t ko = lp.akoff2(t, sg < sgmax ? sg : sgmax, u, tabA);
+        const gmem<const TI>* g = abase + (cg[j] + ko);
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                         (void __attribute__((address_space(3)))*)(adst + cl[j]),
+                                         16, 0, 0);
       }
     }
   };
@@ -157,19 +161,14 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
   for (int cb = 0; cb < NB; ++cb) bo[cb] = lk * COLS + (((wn * NB + cb) * 16 + lr + rbo) % COLS);
 
   const int nch = (t.K + KC - 1) / KC;
-#pragma unroll
-  for (int s = 0; s + 1 < S; ++s)
-    if (s < nch) issue(s, s);
-  for (int ch = 0; ch < nch; ++ch) {
-    // this wave's copies of chunk ch have landed (later chunks may still be
-    // in flight); then every wave's have, and stage (ch + S - 1) % S is free
-    if (S > 2 && ch + S - 2 < nch) wait_vm<CMIN * (S > 2 ? S - 2 : 0)>();
-    else wait_vm<0>();
+  // One chunk: this wave's copies of chunk ch have landed (those of the
+  // chunks after it may still be in flight), then every wave's have and the
+  // stage of chunk ch - 1 is free: the copies of chunk ch + S - 1 go there,
+  // and the matrix cores take chunk ch.
+  auto chunk = [&](int ch, TI* adst, TI* bdst, const TI* as, const TI* bs) {
+    wait_vm<CPW * (S - 2)>();
     stage_barrier();
-    if (ch + S - 1 < nch) issue(ch + S - 1, (ch + S - 1) % S);
-    const int stg = ch % S;
-    const TI* as = As[stg];
-    const TI* bs = Bs[stg];
+    issue(ch + S - 1, adst, bdst);
     const int kv = t.K - ch * KC;            // valid k rows of this chunk
     if (kv >= KC) {
 #pragma unroll
@@ -197,7 +196,32 @@ __device__ __forceinline__ void tile_dma_body(const P& p, int bx, int by, int bz
         }
       }
     }
+  };
+  // Every access names its stage array (the loop is unrolled by S), and the
+  // copies are issued without branches, the same number on every wave: the
+  // compiler then sees that the copies in flight write other stages than
+  // the one read, and does not wait for all of them before each LDS read
+  // (which would serialize the copies with the matrix cores).  The waits
+  // the pipeline needs are the explicit ones at the top of each chunk.
+  issue(0, As0, Bs0);
+  int c0 = 0;
+  if constexpr (S == 2) {
+    for (; c0 + 2 <= nch; c0 += 2) {
+      chunk(c0, As1, Bs1, As0, Bs0);
+      chunk(c0 + 1, As0, Bs0, As1, Bs1);
+    }
+    if (c0 < nch) chunk(c0, As1, Bs1, As0, Bs0);
+  } else {
+    issue(1, As1, Bs1);
+    for (; c0 + 3 <= nch; c0 += 3) {
+      chunk(c0, As2, Bs2, As0, Bs0);
+      chunk(c0 + 1, As0, Bs0, As1, Bs1);
+      chunk(c0 + 2, As1, Bs1, As2, Bs2);
+    }
+    if (c0 < nch) chunk(c0, As2, Bs2, As0, Bs0);
+    if (c0 + 1 < nch) chunk(c0 + 1, As0, Bs0, As1, Bs1);
   }
+  wait_vm<0>();                              // no copy of a past-the-end chunk outlives the tile
 
   // epilogue one 16-row block at a time (keeps the live registers of the
   // accumulators, row offsets and old values within the occupancy budget)
