@@ -195,8 +195,9 @@ struct gw_chi_batch {
   int GB = 1;              // pivots per FP64 / FP32 stage-B launch (a group)
   int RSB = 0;             // rows of a full group (GB * RS): row stride of dvg
   int ab_nb = AB_NBW;      // 16-column blocks per wave of the stage-A/B tiles
-  bool b_dma = false;      // FP32 stage B on the direct-to-LDS engine
-  bool a_dma = false;      // FP32 stage A on the direct-to-LDS engine
+  bool b_dma = false;      // stage B on the direct-to-LDS engine (FP64, FP32)
+  bool a_dma = false;      // stage A on the direct-to-LDS engine (FP64, FP32)
+  bool bf_dma_ab = false;  // BF16x3 stages A and B on the direct-to-LDS engine
   FTables<double> t64;
   FTables<float> t32;
   Table<StageABf> tAb;
@@ -732,11 +733,9 @@ hipError_t run_bf_dma(const Table<P>& T, int piv, bool pers, int* queue, hipStre
 
 template <class T>
 hipError_t stage_a_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
-  if constexpr (std::is_same<T, float>::value) {
-    if (B.a_dma) {
-      if (B.ab_nb == AB_NBN) return run_dma<A_WM, AB_WN, AB_NBN, 16, 2>(tabs<T>(B).tA, piv, pers, q, st);
-      return run_dma<A_WM, AB_WN, AB_NBW, 16, 2>(tabs<T>(B).tA, piv, pers, q, st);
-    }
+  if (B.a_dma) {
+    if (B.ab_nb == AB_NBN) return run_dma<A_WM, AB_WN, AB_NBN, 16, 2>(tabs<T>(B).tA, piv, pers, q, st);
+    return run_dma<A_WM, AB_WN, AB_NBW, 16, 2>(tabs<T>(B).tA, piv, pers, q, st);
   }
   if (B.ab_nb == AB_NBN) return run_mfma<A_WM, AB_WN, AB_NBN, 16>(tabs<T>(B).tA, piv, pers, q, st);
   return run_mfma<A_WM, AB_WN, AB_NBW, 16>(tabs<T>(B).tA, piv, pers, q, st);
@@ -761,11 +760,9 @@ hipError_t stage_b_dma_rows(const gw_chi_batch& B, const Tab& t, int piv, bool p
 }
 template <class T>
 hipError_t stage_b_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
-  if constexpr (std::is_same<T, float>::value) {
-    if (B.b_dma) {
-      if (B.ab_nb == AB_NBN) return stage_b_dma_rows<AB_NBN>(B, tabs<T>(B).tB, piv, pers, q, st);
-      return stage_b_dma_rows<AB_NBW>(B, tabs<T>(B).tB, piv, pers, q, st);
-    }
+  if (B.b_dma) {
+    if (B.ab_nb == AB_NBN) return stage_b_dma_rows<AB_NBN>(B, tabs<T>(B).tB, piv, pers, q, st);
+    return stage_b_dma_rows<AB_NBW>(B, tabs<T>(B).tB, piv, pers, q, st);
   }
   if (B.ab_nb == AB_NBN) return stage_b_rows<AB_NBN>(B, tabs<T>(B).tB, piv, pers, q, st);
   return stage_b_rows<AB_NBW>(B, tabs<T>(B).tB, piv, pers, q, st);
@@ -783,11 +780,23 @@ hipError_t stage_c_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStrea
   }
 }
 hipError_t stage_a_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  if (B.bf_dma_ab) {
+    if (bf_ab_nb(B) == BF_NB_ABN) return run_bf_dma<4, BF_WN, 4, BF_NB_ABN, 3>(B.tAb, piv, pers, q, st);
+    return run_bf_dma<4, BF_WN, 4, BF_NB_AB, 2>(B.tAb, piv, pers, q, st);
+  }
   if (bf_ab_nb(B) == BF_NB_ABN) return run_bf<4, BF_WN, 4, BF_NB_ABN, BF_KC>(B.tAb, piv, pers, q, st);
   return run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, piv, pers, q, st);
 }
 template <int NB>
 hipError_t stage_b_bf_rows(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  if (B.bf_dma_ab) {
+    switch (b_rb(B.RS)) {
+      case 2: return run_bf_dma<2, BF_WN, 2, NB, 3>(B.tBb, piv, pers, q, st);
+      case 3: return run_bf_dma<2, BF_WN, 3, NB, 3>(B.tBb, piv, pers, q, st);
+      case 4: return run_bf_dma<2, BF_WN, 4, NB, 3>(B.tBb, piv, pers, q, st);
+      default: return run_bf_dma<2, BF_WN, 5, NB, 3>(B.tBb, piv, pers, q, st);
+    }
+  }
   switch (b_rb(B.RS)) {
     case 2: return run_bf<2, BF_WN, 2, NB, BF_KC>(B.tBb, piv, pers, q, st);
     case 3: return run_bf<2, BF_WN, 3, NB, BF_KC>(B.tBb, piv, pers, q, st);
@@ -1078,9 +1087,23 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
     if ((rc = prepare_sys(*B, B->sys[m], &systems[m], st)) != GW_OK) return rc;
     B->max_na = std::max(B->max_na, systems[m].n_atoms);
   }
-  // 16-byte copies need the rows of the gathered D^vir (GB * n_tau * NA floats)
-  // and the brick rows (NA * NR floats) in whole groups of four
-  B->b_dma = prec == GW_FP32 && NR % 4 == 0 && B->RSB % 4 == 0;
+  // 16-byte copies need the rows of the gathered D^vir (GB * n_tau * NA
+  // elements) and the brick rows (NA * NR elements) in whole groups of 16
+  // bytes, and in FP64 stage A the D^occ rows (N doubles; the FP32 copy is
+  // padded)
+  B->b_dma = prec == GW_FP32 ? NR % 4 == 0 && B->RSB % 4 == 0
+                             : prec == GW_FP64 && NR % 2 == 0 && B->RSB % 2 == 0;
+  if (prec == GW_FP64) {
+    B->a_dma = NR % 2 == 0;
+    for (const SysPlan& P : B->sys) B->a_dma = B->a_dma && P.N % 2 == 0;
+  }
+  // BF16x3 stages A and B on the direct-to-LDS engine, whose per-lane parts
+  // of the D offsets (rows tau * N + mu of na 16-entry groups) are 32-bit
+  if (prec == GW_BF16X3) {
+    B->bf_dma_ab = true;
+    for (const SysPlan& P : B->sys)
+      B->bf_dma_ab = B->bf_dma_ab && (int64_t)(n_tau + 1) * P.N * P.na * 16 < (1ll << 32);
+  }
   // largest systems first: their tiles lead every batched launch
   B->order.resize(n_sys);
   std::iota(B->order.begin(), B->order.end(), 0);
