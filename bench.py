@@ -684,6 +684,8 @@ def bench_chain(args):
     torch.cuda.empty_cache()
     t0 = time.perf_counter()
     plan = gw.ChiBatch([sysd], 1, s.filter_eps, prec=args.prec, timing=True)
+    if args.c_variant is not None:
+        plan.set_config(args.c_variant, plan.config()[1])
     plan_s = time.perf_counter() - t0
     log(f"[plan] one-tau {args.prec} plan {plan_s:.1f} s")
     wc = chain["wc"]
@@ -728,7 +730,8 @@ def bench_chain(args):
     per_launch_ms = c_ms / max(c_n, 1)
     achieved = (c_fl / max(c_n, 1)) / (per_launch_ms / 1e3) / 1e12
     cs = chain["chi_stats"]
-    c_kernel = stage_c_kernel(args.prec, cs["c_variant"], cs["launch_mask"], batched=True)
+    # the kernel of the timed launches: the one-tau plan's (its variant may be set)
+    c_kernel = stage_c_kernel(args.prec, st["c_variant"], st["launch_mask"], batched=True)
     traffic = measured_traffic(args.traffic_json, args.workload + ":tau1", c_kernel)
     chain_flops = cs["flops_ab"] + cs["flops_c"] + chain["sig_stats"]["flops"]
     res = {
@@ -824,6 +827,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="same as --compare none")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--tune-cache", default=None, help="autotune cache file of the batched form")
+    ap.add_argument("--c-variant", type=int, default=None,
+                    help="stage-C tile variant of the one-tau plan of the steps (default: the plan's)")
     ap.add_argument("--evgw", type=float, default=None, metavar="SCALE",
                     help="time evGW instead, the three-center tensor scaled by SCALE")
     ap.add_argument("--open-shell", type=float, default=None, metavar="DELTA",

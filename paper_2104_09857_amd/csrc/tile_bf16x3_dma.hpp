@@ -1,5 +1,5 @@
-// Direct-to-LDS form of the split-precision (BF16 x 3) engine, for the outer
-// contraction of chi.
+// Direct-to-LDS form of the split-precision (BF16 x 3) engine, for the three
+// stages of chi.
 //
 // The register-staged engine (tile_bf16x3.hpp) keeps one K chunk in flight:
 // it loads the next chunk into registers while the current one feeds the
@@ -14,10 +14,13 @@
 // Operands (bf16 hi and lo arrays, same offsets) are addressed by k pairs:
 // pair u holds 16 consecutive k values (two 16-byte groups) of a row:
 //   A(r, 16 u + j) at abase + arow(r) + a_tab[u] * a_mul + j
-//   B(16 u + j, c) at bbase + 16 c + u * b_mul + j              (bf16 units)
-// with u < t.K / 16; the table a_tab is read with scalar loads (its address
-// and u are wave-uniform), which do not count against the vector-memory
-// counter that tracks the copies in flight.  One LDS stage holds, per array, [KC / 16][ROWS][2]
+//   B(16 u + j, c) at bbase + 16 c + b_tab[u] * b_mul + j       (bf16 units)
+// with u < t.K / 16, and b_tab[u] = u unless the problem has a B table
+// (P::kBTab, 64-bit entries); the tables are read with scalar loads (their
+// addresses and u are wave-uniform), which do not count against the
+// vector-memory counter that tracks the copies in flight.  The output is
+// added to an FP64 array (P::kOut == 0) or stored split into bf16 hi / lo
+// arrays (P::kOut == 1), at rowoff(r) + coloff(c).  One LDS stage holds, per array, [KC / 16][ROWS][2]
 // (A) and [KC / 16][COLS][2] (B) cells of 16 bytes; the two cells of a row
 // and pair are swapped when bit 2 of the row is set, so the 16 rows read by
 // one quarter of a wave fall on distinct banks.  A copy instruction fills 64
@@ -36,6 +39,20 @@
 
 namespace gw {
 
+template <class P, class = void>
+struct has_btab : std::false_type {};
+template <class P>
+struct has_btab<P, std::void_t<decltype(P::kBTab)>> : std::bool_constant<P::kBTab> {};
+
+// wave-uniform pointer in the constant address space (scalar loads)
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* scalar_view(const T* p) {
+  const uint64_t v = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const __attribute__((address_space(4))) T*)(((uint64_t)hi << 32) | lo);
+}
+
 template <int WM, int WN, int RB, int NB, int S, class P>
 __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, int bz) {
   constexpr int ROWS = 16 * RB * WM, COLS = 16 * NB * WN, NT = 64 * WM * WN, NW = NT / 64;
@@ -43,12 +60,13 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
   constexpr int AC = NP * ROWS * 2, BC = NP * COLS * 2;      // cells per array per stage
   constexpr int SC = 2 * AC + 2 * BC;                        // cells per stage
   constexpr int NCA = AC / 64, NCB = BC / 64;                // copies per array
-  constexpr int NC = 2 * NCA + 2 * NCB, CPW = (NC + NW - 1) / NW, CMIN = NC / NW;
-  static_assert(ROWS % 32 == 0 && COLS % 32 == 0 && S >= 2 && CMIN >= 1, "copy layout");
-  static_assert(S == 3 && CPW < 16, "three stages; vmcnt immediate");
+  constexpr int NC = 2 * NCA + 2 * NCB, CPW = (NC + NW - 1) / NW;
+  constexpr bool BTAB = has_btab<P>::value;
+  static_assert(ROWS % 32 == 0 && COLS % 32 == 0 && NC >= NW, "copy layout");
+  static_assert((S == 2 || S == 3) && CPW * (S - 2) < 16, "two or three stages; vmcnt immediate");
   __shared__ __attribute__((aligned(16))) u32x4_t L0[SC];
   __shared__ __attribute__((aligned(16))) u32x4_t L1[SC];
-  __shared__ __attribute__((aligned(16))) u32x4_t L2[SC];
+  __shared__ __attribute__((aligned(16))) u32x4_t L2[S > 2 ? SC : 1];
 
   typename P::Tile t;
   if (!p.tile(bx, by, bz, t)) return;
@@ -58,14 +76,12 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
   const int wm = wave % WM, wn = wave / WM;
   const auto lp = resolve(p, t);
   const int npairs = t.K / 16, pmax = npairs - 1;
-  // the pair table through the scalar (constant) path
-  const uint64_t tp = (uint64_t)(uintptr_t)lp.a_tab(t);
-  const uint32_t tlo = __builtin_amdgcn_readfirstlane((uint32_t)tp);
-  const uint32_t thi = __builtin_amdgcn_readfirstlane((uint32_t)(tp >> 32));
-  const __attribute__((address_space(4))) int32_t* atab =
-      (const __attribute__((address_space(4))) int32_t*)(((uint64_t)thi << 32) | tlo);
+  // the pair tables through the scalar (constant) path
+  const auto atab = scalar_view(lp.a_tab(t));
+  const __attribute__((address_space(4))) int64_t* btab = nullptr;
+  if constexpr (BTAB) btab = scalar_view(lp.b_tab(t));
   const uint32_t amul = __builtin_amdgcn_readfirstlane(lp.a_mul());
-  const uint32_t bmul = __builtin_amdgcn_readfirstlane(lp.b_mul());
+  const int64_t bmul = (int64_t)__builtin_amdgcn_readfirstlane(lp.b_mul());
 
   // copies of this wave: copy c = wave + NW * j over [A hi | A lo | B hi | B lo];
   // for each, its array, its pair inside the chunk, the cell offset inside
@@ -100,16 +116,25 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
   auto issue = [&](int ch, u32x4_t* dst) {
     // the table entries first (one wait for all of them), then the copies
     int uj[CPW], tv[CPW];
+    int64_t tb[CPW];
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
       const int u = ch * NP + cpair[j];
       uj[j] = __builtin_amdgcn_readfirstlane(u < pmax ? u : pmax);
       tv[j] = atab[uj[j]];
+      if constexpr (BTAB) tb[j] = btab[uj[j]];
+      else tb[j] = uj[j];
     }
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
-      const uint32_t po = cisb[j] ? (uint32_t)uj[j] * bmul : (uint32_t)tv[j] * amul;
-      const gmem<const uint16_t>* g = cbase[j] + (po + clane[j]);
+      const gmem<const uint16_t>* g;
+      if constexpr (BTAB) {      // brick offsets need 64 bits
+        const int64_t po = cisb[j] ? tb[j] * bmul : (int64_t)((uint32_t)tv[j] * amul);
+        g = cbase[j] + (po + (int64_t)clane[j]);
+      } else {                   // offsets within one tau slab below 2^32 (host check)
+        const uint32_t po = cisb[j] ? (uint32_t)uj[j] * (uint32_t)bmul : (uint32_t)tv[j] * amul;
+        g = cbase[j] + (po + clane[j]);
+      }
       __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
                                        (void __attribute__((address_space(3)))*)(dst + ccell[j]),
                                        16, 0, 0);
@@ -142,7 +167,7 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
   // One chunk: wait for its copies, barrier, the copies of chunk ch + S - 1
   // into stage dst, then the matrix-core steps on stage ls.
   auto chunk = [&](int ch, u32x4_t* dst, const u32x4_t* ls) {
-    wait_vm<CPW>();                  // this wave's copies of chunk ch have landed
+    wait_vm<CPW * (S - 2)>();        // this wave's copies of chunk ch have landed
     stage_barrier();                 // everyone's have; stage dst is free
     issue(ch + S - 1, dst);
     // groups past the end (last chunk only) read as zero in A
@@ -172,22 +197,27 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
   // the copies in flight write other stages than the one read, and does not
   // wait for them before each LDS read (the waits the pipeline needs are the
   // explicit wait_vm + barrier of each chunk).
-  issue(0, L0);
-  issue(1, L1);
   int c0 = 0;
-  for (; c0 + 3 <= nch; c0 += 3) {
-    chunk(c0, L2, L0);
-    chunk(c0 + 1, L0, L1);
-    chunk(c0 + 2, L1, L2);
+  issue(0, L0);
+  if constexpr (S == 2) {
+    for (; c0 + 2 <= nch; c0 += 2) {
+      chunk(c0, L1, L0);
+      chunk(c0 + 1, L0, L1);
+    }
+    if (c0 < nch) chunk(c0, L1, L0);
+  } else {
+    issue(1, L1);
+    for (; c0 + 3 <= nch; c0 += 3) {
+      chunk(c0, L2, L0);
+      chunk(c0 + 1, L0, L1);
+      chunk(c0 + 2, L1, L2);
+    }
+    if (c0 < nch) chunk(c0, L2, L0);
+    if (c0 + 1 < nch) chunk(c0 + 1, L0, L1);
   }
-  if (c0 < nch) chunk(c0, L2, L0);
-  if (c0 + 1 < nch) chunk(c0 + 1, L0, L1);
   wait_vm<0>();                      // no copy of a past-the-end chunk outlives the tile
 
-  // f32 16x16 MFMA output: lane l, element i -> row 4*(l/16) + i, col l%16;
-  // added with factor kSign to the FP64 output
-  static_assert(P::kOut == 0, "direct-to-LDS BF16 x 3 form accumulates into an FP64 output");
-  gmem<double>* __restrict__ ob = to_global(lp.obase(t));
+  // f32 16x16 MFMA output: lane l, element i -> row 4*(l/16) + i, col l%16
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     const int c = (wn * NB + cb) * 16 + lr;
@@ -195,19 +225,38 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
     const int64_t co = cv ? lp.coloff(t, c) : 0;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-      double old[4];
-      int64_t off[4];
-      bool okr[4];
+      if constexpr (P::kOut == 0) {
+        // added with factor kSign to the FP64 output
+        gmem<double>* __restrict__ ob = to_global(lp.obase(t));
+        double old[4];
+        int64_t off[4];
+        bool okr[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = (wm * RB + rb) * 16 + 4 * lk + i;
-        okr[i] = cv && r < t.rows;
-        off[i] = okr[i] ? lp.rowoff(t, r) + co : 0;
-        old[i] = ob[off[i]];
+        for (int i = 0; i < 4; ++i) {
+          const int r = (wm * RB + rb) * 16 + 4 * lk + i;
+          okr[i] = cv && r < t.rows;
+          off[i] = okr[i] ? lp.rowoff(t, r) + co : 0;
+          old[i] = ob[off[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (okr[i]) ob[off[i]] = old[i] + P::kSign * (double)acc[rb][cb][i];
+      } else {
+        // stored split into bf16 hi and lo
+        gmem<uint16_t>* __restrict__ oh = to_global(lp.obase_hi(t));
+        gmem<uint16_t>* __restrict__ ol = to_global(lp.obase_lo(t));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = (wm * RB + rb) * 16 + 4 * lk + i;
+          if (cv && r < t.rows) {
+            const int64_t o = lp.rowoff(t, r) + co;
+            const float v = acc[rb][cb][i];
+            const uint16_t h = f32_to_bf16_bits(v);
+            oh[o] = h;
+            ol[o] = f32_to_bf16_bits(v - bf16_bits_to_f32(h));
+          }
+        }
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (okr[i]) ob[off[i]] = old[i] + P::kSign * (double)acc[rb][cb][i];
     }
   }
 }
