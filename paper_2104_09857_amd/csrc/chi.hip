@@ -406,9 +406,11 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
   }
   if (B.GB == 0) {
     // pivots per stage-B launch, fixed by the first system of the plan: up to
-    // 160 rows (pivot, tau, sigma) per tile, the group's N_b within 16 GiB
+    // 128 (FP64) / 160 (FP32) rows (pivot, tau, sigma) per tile, the group's N_b
+    // within 16 GiB (FP64: a 160-row tile needs ten waves, whose register
+    // budget of 168 spills; 128 rows run on eight waves without spills)
     const int64_t tsz = B.prec == GW_FP64 ? 8 : 4;
-    int gb = B.prec == GW_BF16X3 ? 1 : std::max(1, 160 / B.RS);
+    int gb = B.prec == GW_BF16X3 ? 1 : std::max(1, (B.prec == GW_FP64 ? 128 : 160) / B.RS);
     while (gb > 1 && (int64_t)gb * n_tau * P.BPS * tsz > (16ll << 30)) --gb;
     B.GB = gb;
     B.RSB = gb * B.RS;
