@@ -251,8 +251,9 @@ gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double 
  * An execution walks the pivot atom index i = 0 .. max n_atoms - 1 and
  * issues, per stage, one launch over the tiles of every system with a pivot
  * atom i, for all n_tau points at once.  Stage B (the D^vir half
- * contraction) runs once per group of consecutive pivots (up to 160 rows of
- * pivot x tau x function per tile).  In the FP64 and FP32 forms a system whose
+ * contraction) runs once per group of consecutive pivots (up to 128 rows of
+ * pivot x tau x function per tile in FP64, 160 otherwise).  In the FP64 and
+ * FP32 forms a system whose
  * pivot atoms i and i + ceil(n_atoms/2) never couple to a common RI atom
  * runs them in the same launches (their chi rows are disjoint; the second
  * pivot's half-contracted tensors take a second set of buffers, if within

@@ -138,7 +138,7 @@ struct SysPlan {
   // pivot pairs: loop index i runs pivot i and pivot i + pair_h together (their
   // chi rows are disjoint); 0: one pivot per loop index
   int pair_h = 0;
-  int64_t bs = 0, BPS = 0, BPS16 = 0;
+  int64_t bs = 0, BPS = 0, BPS16 = 0;   // BPS16: BF16x3 N_b entries per tau
   BrickGroups G;
   Panels pan;
   std::vector<int32_t> acount;
@@ -192,7 +192,7 @@ struct gw_chi_batch {
   std::vector<int> order;            // systems by decreasing size
   int variant = 0, persistent = 0;
   int RS = 0;              // rows of one pivot's half contraction (n_tau * NA)
-  int GB = 1;              // pivots per FP64 / FP32 stage-B launch (a group)
+  int GB = 1;              // pivots per stage-B launch (a group)
   int RSB = 0;             // rows of a full group (GB * RS): row stride of dvg
   int ab_nb = AB_NBW;      // 16-column blocks per wave of the stage-A/B tiles
   bool b_dma = false;      // stage B on the direct-to-LDS engine (FP64, FP32)
@@ -409,9 +409,15 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     // 128 (FP64) / 160 (FP32) rows (pivot, tau, sigma) per tile, the group's N_b
     // within 16 GiB (FP64: a 160-row tile needs ten waves, whose register
     // budget of 168 spills; 128 rows run on eight waves without spills)
-    const int64_t tsz = B.prec == GW_FP64 ? 8 : 4;
-    int gb = B.prec == GW_BF16X3 ? 1 : std::max(1, (B.prec == GW_FP64 ? 128 : 160) / B.RS);
-    while (gb > 1 && (int64_t)gb * n_tau * P.BPS * tsz > (16ll << 30)) --gb;
+    // (BF16x3: N_b hi + lo, its index packed per atom to E entries)
+    int64_t slab = P.BPS * (B.prec == GW_FP64 ? 8 : 4);
+    if (B.prec == GW_BF16X3) {
+      const int64_t E = (NA * NA + 15) / 16 * 16;
+      slab = 0;
+      for (int p = 0; p < P.n_pan; ++p) slab += (int64_t)P.pan.ulen[p] * P.PC * E * 4;
+    }
+    int gb = std::max(1, (B.prec == GW_FP64 ? 128 : 160) / B.RS);
+    while (gb > 1 && (int64_t)gb * n_tau * slab > (16ll << 30)) --gb;
     B.GB = gb;
     B.RSB = gb * B.RS;
   }
@@ -420,18 +426,36 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
   } else if (B.prec == GW_FP32) {
     if ((rc = prepare_f<float>(B, P, s, ix, st)) != GW_OK) return rc;
   } else {
-    // split-precision form: operands as bf16 hi/lo pairs; T is split once per plan
+    // split-precision form: operands as bf16 hi/lo pairs; T is split once per plan.
+    // M_b and N_b hold the outer contraction's index (AO function i of an atom,
+    // sigma) packed per atom: E = NA^2 rounded up to 16 entries, G = E / 16 k
+    // pairs of 16 per atom, each pair stored [pair][row or column][16]
+    const int E = (NA * NA + 15) / 16 * 16, Gp = E / 16;
     std::vector<int64_t> poffb(P.n_pan + 1, 0);
-    for (int p = 0; p < P.n_pan; ++p)
-      poffb[p + 1] = poffb[p] + (int64_t)NA * P.pan.ulen[p] * P.PC * 16;
+    std::vector<int32_t> ptab, pt_off(P.n_pan + 1, 0);
+    for (int p = 0; p < P.n_pan; ++p) {
+      poffb[p + 1] = poffb[p] + (int64_t)P.pan.ulen[p] * P.PC * E;
+      GW_CHECK_ARG((int64_t)Gp * P.pan.ulen[p] <= kPanTab,
+                   "too many AO atoms coupled to one RI column panel");
+      for (int j = 0; j < P.pan.ulen[p]; ++j) {
+        const int a = P.pan.kmap[P.pan.km_off[p] + j * NA] / NA;   // union atom j
+        for (int e = 0; e < Gp; ++e) ptab.push_back(a * Gp + e);
+      }
+      pt_off[p + 1] = (int32_t)ptab.size();
+    }
     P.BPS16 = poffb[P.n_pan];
     int64_t* d_poffb;
+    int32_t *d_ptab, *d_pt_off;
     if ((rc = M.upload(&d_poffb, poffb)) != GW_OK) return rc;
+    if ((rc = M.upload(&d_ptab, ptab)) != GW_OK) return rc;
+    if ((rc = M.upload(&d_pt_off, pt_off)) != GW_OK) return rc;
     const size_t tsz = (size_t)s->n_trip * NR * NA * 16, dsz16 = (size_t)n_tau * N * na * 16;
-    const size_t msz = (size_t)n_tau * P.nRmax * N * NR * 16, nsz = (size_t)n_tau * P.BPS16;
+    // N_b of every pivot of a stage-B group: [pivot][tau] slabs of BPS16
+    const size_t msz = (size_t)n_tau * P.nRmax * NR * na * E, nsz = (size_t)B.GB * n_tau * P.BPS16;
     // the direct-to-LDS outer contraction takes its M_b offsets within one tau in 32 bits
-    GW_CHECK_ARG((int64_t)(P.nRmax + 1) * N * NR * 16 < (1ll << 31),
+    GW_CHECK_ARG((int64_t)(P.nRmax + 1) * NR * na * E < (1ll << 31),
                  "system too large for 32-bit tile offsets");
+    (void)d_kmap; (void)d_km_off; (void)d_ulen;
     if ((rc = M.alloc(&P.th, tsz)) != GW_OK) return rc;
     if ((rc = M.alloc(&P.tl, tsz)) != GW_OK) return rc;
     if ((rc = M.alloc(&P.doh, dsz16)) != GW_OK) return rc;
@@ -442,7 +466,7 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     if ((rc = M.alloc(&P.ml, msz)) != GW_OK) return rc;
     if ((rc = M.alloc(&P.nh, nsz)) != GW_OK) return rc;
     if ((rc = M.alloc(&P.nl, nsz)) != GW_OK) return rc;
-    // padding lanes (sigma >= NA) and uncoupled panel entries stay zero
+    // padding entries (past NA^2 of an atom block) and uncoupled panel entries stay zero
     GW_HIP(hipMemsetAsync(P.mh, 0, 2 * msz, st));
     GW_HIP(hipMemsetAsync(P.ml, 0, 2 * msz, st));
     GW_HIP(hipMemsetAsync(P.nh, 0, 2 * nsz, st));
@@ -460,25 +484,27 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     ba.rows_pt = 16 * 4 * 4; ba.cols_pt = 16 * bf_ab_nb(B) * BF_WN;
     ba.n_rt = (N + ba.rows_pt - 1) / ba.rows_pt;
     ba.n_ct = (NA * NR + ba.cols_pt - 1) / ba.cols_pt;
-    ba.N = N; ba.NA = NA; ba.NR = NR; ba.na = na; ba.nRmax = P.nRmax;
+    ba.N = N; ba.NA = NA; ba.NR = NR; ba.na = na; ba.nRmax = P.nRmax; ba.G = Gp;
     ba.fdNA.set((uint32_t)NA);
 
     StageBBf& bb = P.bb;
     bb.dh = P.dvh; bb.dl = P.dvl; bb.th = P.th; bb.tl = P.tl; bb.nh = P.nh; bb.nl = P.nl;
     bb.goff = d_goff; bb.seg_atom = d_seg_atom; bb.seg_brick = d_seg_brick; bb.gc = d_gc;
     bb.gslot = d_gslot; bb.poffb = d_poffb; bb.N = N; bb.NA = NA; bb.NR = NR; bb.na = na;
-    bb.RS = RS; bb.PG = P.PG; bb.PC = P.PC; bb.BPS16 = P.BPS16;
-    bb.rows_pt = 16 * b_rb(RS) * 2;
+    bb.RS = RS; bb.PG = P.PG; bb.PC = P.PC; bb.G = Gp; bb.BPSE = P.BPS16;
+    bb.n_tau = n_tau; bb.ng = 1;
+    bb.fdGN.set((uint32_t)NA);
+    bb.rows_pt = 16 * b_rb(B.RSB) * 2;
     bb.cols_pt = 16 * bf_ab_nb(B) * BF_WN;
     bb.n_rt = (RS + bb.rows_pt - 1) / bb.rows_pt;
     bb.n_ct = (NA * NR + bb.cols_pt - 1) / bb.cols_pt;
     bb.fdNA.set((uint32_t)NA);
 
     StageCBf& bc = P.bc;
-    bc.mh = P.mh; bc.ml = P.ml; bc.nh = P.nh; bc.nl = P.nl; bc.gc = d_gc; bc.kmap = d_kmap;
-    bc.km_off = d_km_off; bc.ulen = d_ulen; bc.poffb = d_poffb; bc.N = N; bc.NA = NA;
-    bc.NR = NR; bc.NRI = P.NRI; bc.PG = P.PG; bc.PC = P.PC; bc.nRmax = P.nRmax;
-    bc.n_atoms = na; bc.BPS16 = P.BPS16;
+    bc.mh = P.mh; bc.ml = P.ml; bc.nh = P.nh; bc.nl = P.nl; bc.gc = d_gc; bc.ptab = d_ptab;
+    bc.pt_off = d_pt_off; bc.poffb = d_poffb; bc.NA = NA; bc.NR = NR; bc.NRI = P.NRI;
+    bc.PG = P.PG; bc.PC = P.PC; bc.nRmax = P.nRmax; bc.n_atoms = na; bc.na = na;
+    bc.G = Gp; bc.BPSE = P.BPS16;
     bc.fdNR.set((uint32_t)NR);
   }
   return GW_OK;
@@ -577,14 +603,23 @@ gw_status ab_tables_bf(gw_chi_batch& B, hipStream_t st) {
     B.tBb.open(piv);
     for (int m : B.order) {
       SysPlan& P = B.sys[m];
+      if (piv >= P.na) continue;
       int g0 = 0;
       const int nR = pivot_groups(P, piv, g0);
-      if (nR == 0) continue;
-      StageABf a = P.ba;
-      a.g0 = g0;
-      B.tAb.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
+      if (nR > 0) {
+        StageABf a = P.ba;
+        a.g0 = g0;
+        B.tAb.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
+      }
+      // stage B once per group of GB pivots, at its first pivot: rows
+      // (tau, pivot, sigma) of the group's pivots
+      if (piv % B.GB != 0) continue;
       StageBBf b = P.bb;
       b.b = piv;
+      b.ng = std::min(B.GB, P.na - piv);
+      b.RS = n_tau * b.ng * B.NA;
+      b.fdGN.set((uint32_t)(b.ng * B.NA));
+      b.n_rt = (b.RS + b.rows_pt - 1) / b.rows_pt;
       B.tBb.add(piv, b, P.n_groups * b.n_rt * b.n_ct, 1, 1);
     }
   }
@@ -649,7 +684,14 @@ gw_status build_c_tables(gw_chi_batch& B, double* const* chi, hipStream_t st) {
     c_tables(B, B.t32.tC, [&](SysPlan& P, const PivSlot& ps) { return slot_c(P.f32, P, ps); }, chi);
     rc = B.t32.tC.upload(B.mem, st);
   } else {
-    c_tables(B, B.tCb, [](SysPlan& P, const PivSlot&) { return P.bc; }, chi);
+    // BF16x3: pivot piv reads its slab of the stage-B group's N_b
+    c_tables(B, B.tCb, [&](SysPlan& P, const PivSlot& ps) {
+      StageCBf c = P.bc;
+      const int64_t off = (int64_t)(ps.piv % B.GB) * B.n_tau * P.BPS16;
+      c.nh += off;
+      c.nl += off;
+      return c;
+    }, chi);
     rc = B.tCb.upload(B.mem, st);
   }
   if (rc != GW_OK) return rc;
@@ -792,14 +834,14 @@ hipError_t stage_a_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStre
 template <int NB>
 hipError_t stage_b_bf_rows(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
   if (B.bf_dma_ab) {
-    switch (b_rb(B.RS)) {
+    switch (b_rb(B.RSB)) {
       case 2: return run_bf_dma<2, BF_WN, 2, NB, 3>(B.tBb, piv, pers, q, st);
       case 3: return run_bf_dma<2, BF_WN, 3, NB, 3>(B.tBb, piv, pers, q, st);
       case 4: return run_bf_dma<2, BF_WN, 4, NB, 3>(B.tBb, piv, pers, q, st);
       default: return run_bf_dma<2, BF_WN, 5, NB, 3>(B.tBb, piv, pers, q, st);
     }
   }
-  switch (b_rb(B.RS)) {
+  switch (b_rb(B.RSB)) {
     case 2: return run_bf<2, BF_WN, 2, NB, BF_KC>(B.tBb, piv, pers, q, st);
     case 3: return run_bf<2, BF_WN, 3, NB, BF_KC>(B.tBb, piv, pers, q, st);
     case 4: return run_bf<2, BF_WN, 4, NB, BF_KC>(B.tBb, piv, pers, q, st);

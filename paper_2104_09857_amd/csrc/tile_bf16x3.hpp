@@ -11,13 +11,13 @@
 // (wm, wn) owns RB x NB MFMA blocks (f32 accumulators, four per lane).  The
 // contraction index is stored k-contiguous in groups of 8 bf16 (16 bytes):
 //   A group (r, g) at abase + aroff(r) + akoff(g)      (offsets in bf16 units)
-//   B group (g, c) at bbase + bkoff(g) + 16 c
+//   B group (g, c) at bbase + bkoff(g) + bcs() c
 // for both the hi and the lo arrays (same offsets).  LDS holds A[r][k] and
 // B[c][k] so that each lane reads its 8 k values with one 16-byte access.
 // Groups outside rows / cols / K groups read as zero.  Output: kOut == 0 adds
 // kSign * C (converted to FP64) to an FP64 array; kOut == 1 stores C split
-// into bf16 hi/lo arrays.  Offsets of the output are separable:
-// rowoff(t, r) + coloff(t, c).
+// into bf16 hi/lo arrays.  Offsets of the output are rowoff(t, r) +
+// coloff(t, c), or outoff(t, r, c) when the problem sets kOutOff.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -46,6 +46,19 @@ __host__ __device__ inline float bf16_bits_to_f32(uint16_t h) {
 __host__ __device__ inline void split_bf16(double x, uint16_t& hi, uint16_t& lo) {
   hi = f32_to_bf16_bits((float)x);
   lo = f32_to_bf16_bits((float)(x - (double)bf16_bits_to_f32(hi)));
+}
+
+// Offset of output element (r, c) of a split (kOut == 1) store: rowoff(t, r) +
+// coloff(t, c) (co), or outoff(t, r, c) for problems whose layout mixes the
+// two (P::kOutOff).
+template <class P, class = void>
+struct has_outoff : std::false_type {};
+template <class P>
+struct has_outoff<P, std::void_t<decltype(P::kOutOff)>> : std::bool_constant<P::kOutOff> {};
+template <class P, class T>
+__device__ __forceinline__ int64_t out_offset(const P& lp, const T& t, int r, int c, int64_t co) {
+  if constexpr (has_outoff<P>::value) return lp.outoff(t, r, c);
+  else return lp.rowoff(t, r) + co;
 }
 
 template <int WM, int WN, int RB, int NB, int KC, class P>
@@ -95,7 +108,7 @@ __device__ __forceinline__ void tile_bf16x3_body(const P& p, int bx, int by, int
       const int e = tid + i * NT, c = e % COLS, g = g0 + e / COLS;
       const bool ok = e < COLS * KG && c < t.cols && g < ngroups;
       bmask = ok ? (bmask | (1u << i)) : (bmask & ~(1u << i));
-      const int64_t o = lp.bkoff(t, g < gmax ? g : gmax, tabB) + 16 * (int64_t)c;
+      const int64_t o = lp.bkoff(t, g < gmax ? g : gmax, tabB) + (int64_t)lp.bcs() * c;
       boff[i] = ok ? o : 0;
     }
 #pragma unroll
@@ -204,7 +217,7 @@ __device__ __forceinline__ void tile_bf16x3_body(const P& p, int bx, int by, int
         for (int i = 0; i < 4; ++i) {
           const int r = (wm * RB + rb) * 16 + 4 * lk + i;
           if (cv && r < t.rows) {
-            const int64_t o = lp.rowoff(t, r) + co;
+            const int64_t o = out_offset(lp, t, r, c, co);
             const float v = acc[rb][cb][i];
             const uint16_t h = f32_to_bf16_bits(v);
             oh[o] = h;

@@ -14,14 +14,15 @@
 // Operands (bf16 hi and lo arrays, same offsets) are addressed by k pairs:
 // pair u holds 16 consecutive k values (two 16-byte groups) of a row:
 //   A(r, 16 u + j) at abase + arow(r) + a_tab[u] * a_mul + j
-//   B(16 u + j, c) at bbase + 16 c + b_tab[u] * b_mul + j       (bf16 units)
-// with u < t.K / 16, and b_tab[u] = u unless the problem has a B table
-// (P::kBTab, 64-bit entries); the tables are read with scalar loads (their
-// addresses and u are wave-uniform), which do not count against the
-// vector-memory counter that tracks the copies in flight.  The output is
-// added to an FP64 array (P::kOut == 0) or stored split into bf16 hi / lo
-// arrays (P::kOut == 1), at rowoff(r) + coloff(c).  One LDS stage holds, per array, [KC / 16][ROWS][2]
-// (A) and [KC / 16][COLS][2] (B) cells of 16 bytes; the two cells of a row
+//   B(16 u + j, c) at bbase + bcs c + b_tab[u] * b_mul + j      (bf16 units)
+// with u < t.K / 16, and b_tab[u] * b_mul replaced by b_pairoff(u) unless the
+// problem has a B table (P::kBTab, 64-bit entries); the tables are read with
+// scalar loads (their addresses and u are wave-uniform), which do not count
+// against the vector-memory counter that tracks the copies in flight.  The
+// output is added to an FP64 array (P::kOut == 0) or stored split into bf16
+// hi / lo arrays (P::kOut == 1), at rowoff(r) + coloff(c) (or outoff(r, c)).
+// One LDS stage holds, per array, [KC / 16][ROWS][2] (A) and
+// [KC / 16][COLS][2] (B) cells of 16 bytes; the two cells of a row
 // and pair are swapped when bit 2 of the row is set, so the 16 rows read by
 // one quarter of a wave fall on distinct banks.  A copy instruction fills 64
 // consecutive cells (32 rows of one pair); each lane fetches the cell the
@@ -81,7 +82,9 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
   const __attribute__((address_space(4))) int64_t* btab = nullptr;
   if constexpr (BTAB) btab = scalar_view(lp.b_tab(t));
   const uint32_t amul = __builtin_amdgcn_readfirstlane(lp.a_mul());
-  const int64_t bmul = (int64_t)__builtin_amdgcn_readfirstlane(lp.b_mul());
+  int64_t bmul = 0;
+  if constexpr (BTAB) bmul = (int64_t)__builtin_amdgcn_readfirstlane(lp.b_mul());
+  const int bcs = lp.bcs();
 
   // copies of this wave: copy c = wave + NW * j over [A hi | A lo | B hi | B lo];
   // for each, its array, its pair inside the chunk, the cell offset inside
@@ -105,7 +108,7 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
     cisb[j] = isb;
     cpair[j] = pair;
     ccell[j] = (arr == 0 ? 0 : arr == 1 ? AC : arr == 2 ? 2 * AC : 2 * AC + BC) + cc * 64;
-    if (isb) clane[j] = (uint32_t)(16 * (x < t.cols ? x : t.cols - 1) + 8 * half);
+    if (isb) clane[j] = (uint32_t)(bcs * (x < t.cols ? x : t.cols - 1) + 8 * half);
     else clane[j] = (uint32_t)lp.arow(t, x < t.rows ? x : t.rows - 1) + (uint32_t)(8 * half);
   }
 
@@ -132,7 +135,7 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
         const int64_t po = cisb[j] ? tb[j] * bmul : (int64_t)((uint32_t)tv[j] * amul);
         g = cbase[j] + (po + (int64_t)clane[j]);
       } else {                   // offsets within one tau slab below 2^32 (host check)
-        const uint32_t po = cisb[j] ? (uint32_t)uj[j] * (uint32_t)bmul : (uint32_t)tv[j] * amul;
+        const uint32_t po = cisb[j] ? lp.b_pairoff(uj[j]) : (uint32_t)tv[j] * amul;
         g = cbase[j] + (po + clane[j]);
       }
       __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
@@ -249,7 +252,7 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
         for (int i = 0; i < 4; ++i) {
           const int r = (wm * RB + rb) * 16 + 4 * lk + i;
           if (cv && r < t.rows) {
-            const int64_t o = lp.rowoff(t, r) + co;
+            const int64_t o = out_offset(lp, t, r, c, co);
             const float v = acc[rb][cb][i];
             const uint16_t h = f32_to_bf16_bits(v);
             oh[o] = h;
