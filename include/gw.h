@@ -252,8 +252,7 @@ gw_status gw_contract_chi(const gw_system *s, const double *d_occ, const double 
  * issues, per stage, one launch over the tiles of every system with a pivot
  * atom i, for all n_tau points at once.  Stage B (the D^vir half
  * contraction) runs once per group of consecutive pivots (up to 128 rows of
- * pivot x tau x function per tile in FP64, 160 otherwise).  In the FP64 and
- * FP32 forms a system whose
+ * pivot x tau x function per tile in FP64, 160 otherwise).  A system whose
  * pivot atoms i and i + ceil(n_atoms/2) never couple to a common RI atom
  * runs them in the same launches (their chi rows are disjoint; the second
  * pivot's half-contracted tensors take a second set of buffers, if within
@@ -296,6 +295,13 @@ gw_status gw_chi_batch_execute(gw_chi_batch *plan, const double *const *d_occ,
                                const double *const *d_vir, double *const *chi,
                                int32_t use_graph, gw_chi_stats *stats, hipStream_t stream);
 gw_status gw_chi_batch_set_config(gw_chi_batch *plan, int32_t variant, int32_t persistent);
+/* gw_chi_batch_set_engine: engine of the half contractions (stages A and B):
+ *   0 (default): the direct-to-LDS engine wherever the plan's rows allow its
+ *   16-byte copies, else the register-staged one; 1: the register-staged
+ *   engine.  Both take the same k values in the same order into every sum:
+ *   the results are bit-identical.  A captured graph is dropped.  ARG error
+ *   for other values. */
+gw_status gw_chi_batch_set_engine(gw_chi_batch *plan, int32_t engine);
 gw_status gw_chi_batch_get_config(const gw_chi_batch *plan, int32_t *variant,
                                   int32_t *persistent, int32_t *n_variants);
 gw_status gw_chi_batch_tune(gw_chi_batch *plan, const double *const *d_occ,

@@ -150,6 +150,7 @@ struct SysPlan {
   uint8_t* dropped = nullptr;
   uint16_t *th = nullptr, *tl = nullptr, *doh = nullptr, *dol = nullptr, *dvh = nullptr, *dvl = nullptr;
   uint16_t *mh = nullptr, *ml = nullptr, *nh = nullptr, *nl = nullptr;
+  uint16_t *mh1 = nullptr, *ml1 = nullptr, *nh1 = nullptr, *nl1 = nullptr;   // second pivot of a pair
   uint8_t* keep = nullptr;          // screener mask (one-system calls only)
   FBufs<double> f64;
   FBufs<float> f32;
@@ -198,6 +199,10 @@ struct gw_chi_batch {
   bool b_dma = false;      // stage B on the direct-to-LDS engine (FP64, FP32)
   bool a_dma = false;      // stage A on the direct-to-LDS engine (FP64, FP32)
   bool bf_dma_ab = false;  // BF16x3 stages A and B on the direct-to-LDS engine
+  // where the plan's rows allow the direct-to-LDS half contractions (the
+  // flags above follow these unless gw_chi_batch_set_engine chose engine 1)
+  bool a_dma_ok = false, b_dma_ok = false, bf_dma_ok = false;
+  int ab_engine = 0;
   FTables<double> t64;
   FTables<float> t32;
   Table<StageABf> tAb;
@@ -393,7 +398,7 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
   // disjoint); the launches of the strip's last pivots, whose upper-triangle
   // blocks are few, then carry the first pivots' tiles as well
   P.pair_h = 0;
-  if (B.prec != GW_BF16X3 && na >= 4) {
+  if (na >= 4) {
     const int h = (na + 1) / 2;
     std::vector<int> mark(na, -1);
     bool disjoint = true;
@@ -471,6 +476,18 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     GW_HIP(hipMemsetAsync(P.ml, 0, 2 * msz, st));
     GW_HIP(hipMemsetAsync(P.nh, 0, 2 * nsz, st));
     GW_HIP(hipMemsetAsync(P.nl, 0, 2 * nsz, st));
+    // buffers of the second pivot of a pair, within 32 GiB (else no pairs)
+    if (P.pair_h > 0 && 2 * 2 * (msz + nsz) > (32ull << 30)) P.pair_h = 0;
+    if (P.pair_h > 0) {
+      if ((rc = M.alloc(&P.mh1, msz)) != GW_OK) return rc;
+      if ((rc = M.alloc(&P.ml1, msz)) != GW_OK) return rc;
+      if ((rc = M.alloc(&P.nh1, nsz)) != GW_OK) return rc;
+      if ((rc = M.alloc(&P.nl1, nsz)) != GW_OK) return rc;
+      GW_HIP(hipMemsetAsync(P.mh1, 0, 2 * msz, st));
+      GW_HIP(hipMemsetAsync(P.ml1, 0, 2 * msz, st));
+      GW_HIP(hipMemsetAsync(P.nh1, 0, 2 * nsz, st));
+      GW_HIP(hipMemsetAsync(P.nl1, 0, 2 * nsz, st));
+    }
     if (s->n_trip > 0) {
       const unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)tsz + 255) / 256, 1 << 20);
       hipLaunchKernelGGL(split_t_kernel, dim3(blocks), dim3(256), 0, st, s->t3c, P.th, P.tl,
@@ -595,32 +612,41 @@ gw_status ab_tables_f(gw_chi_batch& B, hipStream_t st) {
 }
 
 gw_status ab_tables_bf(gw_chi_batch& B, hipStream_t st) {
-  const int n_piv = B.n_loop, n_tau = B.n_tau;   // no pairs in this form
-  B.tAb.begin(n_piv);
-  B.tBb.begin(n_piv);
-  for (int piv = 0; piv < n_piv; ++piv) {
-    B.tAb.open(piv);
-    B.tBb.open(piv);
+  const int n_idx = B.n_loop, n_tau = B.n_tau;
+  B.tAb.begin(n_idx);
+  B.tBb.begin(n_idx);
+  for (int i = 0; i < n_idx; ++i) {
+    B.tAb.open(i);
+    B.tBb.open(i);
     for (int m : B.order) {
       SysPlan& P = B.sys[m];
-      if (piv >= P.na) continue;
-      int g0 = 0;
-      const int nR = pivot_groups(P, piv, g0);
-      if (nR > 0) {
-        StageABf a = P.ba;
-        a.g0 = g0;
-        B.tAb.add(piv, a, nR * a.n_rt * a.n_ct, n_tau, 1);
+      PivSlot ps[2];
+      const int np = loop_pivots(P, i, ps);
+      for (int k = 0; k < np; ++k) {
+        const int piv = ps[k].piv;
+        const bool s1 = ps[k].slot == 1;
+        int g0 = 0;
+        const int nR = pivot_groups(P, piv, g0);
+        if (nR > 0) {
+          StageABf a = P.ba;
+          a.g0 = g0;
+          a.mh = s1 ? P.mh1 : P.mh;
+          a.ml = s1 ? P.ml1 : P.ml;
+          B.tAb.add(i, a, nR * a.n_rt * a.n_ct, n_tau, 1);
+        }
+        // stage B once per group of GB pivots of the slot, at its first
+        // pivot: rows (tau, pivot, sigma) of the group's pivots
+        if ((piv - ps[k].lo) % B.GB != 0) continue;
+        StageBBf b = P.bb;
+        b.b = piv;
+        b.ng = std::min(B.GB, ps[k].hi - piv);
+        b.RS = n_tau * b.ng * B.NA;
+        b.fdGN.set((uint32_t)(b.ng * B.NA));
+        b.n_rt = (b.RS + b.rows_pt - 1) / b.rows_pt;
+        b.nh = s1 ? P.nh1 : P.nh;
+        b.nl = s1 ? P.nl1 : P.nl;
+        B.tBb.add(i, b, P.n_groups * b.n_rt * b.n_ct, 1, 1);
       }
-      // stage B once per group of GB pivots, at its first pivot: rows
-      // (tau, pivot, sigma) of the group's pivots
-      if (piv % B.GB != 0) continue;
-      StageBBf b = P.bb;
-      b.b = piv;
-      b.ng = std::min(B.GB, P.na - piv);
-      b.RS = n_tau * b.ng * B.NA;
-      b.fdGN.set((uint32_t)(b.ng * B.NA));
-      b.n_rt = (b.RS + b.rows_pt - 1) / b.rows_pt;
-      B.tBb.add(piv, b, P.n_groups * b.n_rt * b.n_ct, 1, 1);
     }
   }
   gw_status rc;
@@ -684,12 +710,16 @@ gw_status build_c_tables(gw_chi_batch& B, double* const* chi, hipStream_t st) {
     c_tables(B, B.t32.tC, [&](SysPlan& P, const PivSlot& ps) { return slot_c(P.f32, P, ps); }, chi);
     rc = B.t32.tC.upload(B.mem, st);
   } else {
-    // BF16x3: pivot piv reads its slab of the stage-B group's N_b
+    // BF16x3: pivot piv reads M_b of its slot and its slab of the slot's
+    // stage-B group N_b
     c_tables(B, B.tCb, [&](SysPlan& P, const PivSlot& ps) {
       StageCBf c = P.bc;
-      const int64_t off = (int64_t)(ps.piv % B.GB) * B.n_tau * P.BPS16;
-      c.nh += off;
-      c.nl += off;
+      const bool s1 = ps.slot == 1;
+      const int64_t off = (int64_t)((ps.piv - ps.lo) % B.GB) * B.n_tau * P.BPS16;
+      c.mh = s1 ? P.mh1 : P.mh;
+      c.ml = s1 ? P.ml1 : P.ml;
+      c.nh = (s1 ? P.nh1 : P.nh) + off;
+      c.nl = (s1 ? P.nl1 : P.nl) + off;
       return c;
     }, chi);
     rc = B.tCb.upload(B.mem, st);
@@ -1160,6 +1190,9 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   if ((rc = B->mem.alloc(&B->tiles_skipped, 1)) != GW_OK) return rc;
   GW_HIP(hipMemsetAsync(B->tiles_skipped, 0, sizeof(int), st));
   if ((rc = build_ab_tables(*B, st)) != GW_OK) return rc;
+  B->a_dma_ok = B->a_dma;
+  B->b_dma_ok = B->b_dma;
+  B->bf_dma_ok = B->bf_dma_ab;
   prime(*B);
   GW_HIP(hipStreamSynchronize(st));
   *out = B.release();
@@ -1213,6 +1246,20 @@ extern "C" gw_status gw_chi_batch_set_config(gw_chi_batch* plan, int32_t variant
   GW_CHECK_ARG(persistent >= 0 && persistent <= 7, "persistent must be a mask of bits 0..2");
   plan->variant = variant;
   plan->persistent = persistent;
+  return GW_OK;
+}
+
+extern "C" gw_status gw_chi_batch_set_engine(gw_chi_batch* plan, int32_t engine) {
+  clear_error();
+  GW_CHECK_ARG(plan != nullptr, "plan must be non-null");
+  GW_CHECK_ARG(engine == 0 || engine == 1, "engine must be 0 or 1");
+  if (engine == plan->ab_engine) return GW_OK;
+  plan->ab_engine = engine;
+  plan->a_dma = engine == 0 && plan->a_dma_ok;
+  plan->b_dma = engine == 0 && plan->b_dma_ok;
+  plan->bf_dma_ab = engine == 0 && plan->bf_dma_ok;
+  plan->drop_graph();
+  prime(*plan);          // persistent grid sizes of the kernels now in use
   return GW_OK;
 }
 

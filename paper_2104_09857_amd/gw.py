@@ -124,11 +124,13 @@ def lib():
         L.gw_chi_batch_create.argtypes = [_I32, _P, _I32, _P, _P, _P]
         L.gw_chi_batch_execute.argtypes = [_P, _P, _P, _P, _I32, _P, _P]
         L.gw_chi_batch_set_config.argtypes = [_P, _I32, _I32]
+        L.gw_chi_batch_set_engine.argtypes = [_P, _I32]
         L.gw_chi_batch_get_config.argtypes = [_P, _P, _P, _P]
         L.gw_chi_batch_tune.argtypes = [_P, _P, _P, _P, _I32, ctypes.c_char_p, _P, _P]
         L.gw_chi_batch_destroy.argtypes = [_P]
         for f in ("gw_chi_batch_create", "gw_chi_batch_execute", "gw_chi_batch_set_config",
-                  "gw_chi_batch_get_config", "gw_chi_batch_tune", "gw_chi_batch_destroy"):
+                  "gw_chi_batch_set_engine", "gw_chi_batch_get_config", "gw_chi_batch_tune",
+                  "gw_chi_batch_destroy"):
             getattr(L, f).restype = ctypes.c_int32
         L.gw_finalize.argtypes = []
         L.gw_finalize.restype = ctypes.c_int32
@@ -144,8 +146,8 @@ EXPORTED = ("gw_build_gt", "gw_contract_chi", "gw_screen_w", "gw_contract_sigma"
             "gw_continue_qp", "gw_last_error", "gw_version", "gw_chi_block_features",
             "gw_chi_block_lognorms", "gw_mlp_param_count", "gw_mlp_forward", "gw_mlp_gradient",
             "gw_mlp_train_step", "gw_mlp_sync_half", "gw_chi_batch_create", "gw_chi_batch_execute",
-            "gw_chi_batch_set_config", "gw_chi_batch_get_config", "gw_chi_batch_tune",
-            "gw_chi_batch_destroy", "gw_evgw_update", "gw_contract_sigma_prec", "gw_screen_w_spins",
+            "gw_chi_batch_set_config", "gw_chi_batch_set_engine", "gw_chi_batch_get_config",
+            "gw_chi_batch_tune", "gw_chi_batch_destroy", "gw_evgw_update", "gw_contract_sigma_prec", "gw_screen_w_spins",
             "gw_screen_w_metric", "gw_coulomb_periodic", "gw_screen_w_spins_metric",
             "gw_fermi_level", "gw_finalize", "gw_t3c_gaussian")
 
@@ -341,6 +343,11 @@ class ChiBatch:
         form; True means all three."""
         mask = 7 if persistent is True else int(persistent)
         _check(lib().gw_chi_batch_set_config(self.h, int(variant), mask))
+
+    def set_engine(self, engine):
+        """Engine of the half contractions: 0 direct-to-LDS where the rows allow
+        it (the default), 1 register-staged; the results are bit-identical."""
+        _check(lib().gw_chi_batch_set_engine(self.h, int(engine)))
 
     def config(self):
         v, p, n = _I32(), _I32(), _I32()

@@ -127,6 +127,7 @@ def test_batch_plan_validation():
     assert h.value is None
     assert L.gw_chi_batch_execute(None, None, None, None, 0, None, None) == gw.GW_ERR_ARG
     assert L.gw_chi_batch_set_config(None, 0, 0) == gw.GW_ERR_ARG
+    assert L.gw_chi_batch_set_engine(None, 0) == gw.GW_ERR_ARG
     assert L.gw_chi_batch_tune(None, None, None, None, 1, None, None, None) == gw.GW_ERR_ARG
     assert L.gw_last_error()
     assert L.gw_chi_batch_destroy(None) == gw.GW_OK

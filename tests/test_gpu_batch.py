@@ -75,6 +75,33 @@ def test_batch_equals_single_calls(mols, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_half_contraction_engines_agree(mols, prec):
+    """The register-staged engine of stages A and B (gw_chi_batch_set_engine 1)
+    and the direct-to-LDS one (the default where the rows allow it) take the
+    same k values in the same order into every sum: chi bit for bit, switching
+    back and forth on one plan."""
+    import torch
+    from paper_2104_09857_amd import gw
+    name, ms = mols
+    eps_f = ms[0]["s"].filter_eps
+    plan = gw.ChiBatch([m["sys"] for m in ms], ms[0]["do"].shape[0], eps_f, prec=prec)
+    do, dv = [m["do"] for m in ms], [m["dv"] for m in ms]
+    ref = plan.outputs()
+    plan.execute(do, dv, ref)
+    for engine in (1, 0, 1):
+        print("case", name, prec, "half-contraction engine", engine, flush=True)
+        plan.set_engine(engine)
+        out = plan.outputs()
+        plan.execute(do, dv, out)
+        torch.cuda.synchronize()
+        for m, a, b in zip(ms, out, ref):
+            assert torch.equal(a, b), (m["w"].name, engine)
+    with pytest.raises(gw.GWError):
+        plan.set_engine(2)
+    plan.close()
+
+
 def test_batch_vs_oracle(mols):
     import torch
     from paper_2104_09857_amd import gw

@@ -9,7 +9,7 @@ the oracle's block routine on sampled output blocks (1e-12 relative), is
 symmetric and negative semidefinite (up to the block filter) on random
 principal submatrices,
 and a one-tau plan (which pairs too) reproduces every tau slice bit for bit,
-in FP64 and FP32."""
+in FP64, FP32 and BF16x3."""
 import numpy as np
 import pytest
 
@@ -81,7 +81,7 @@ def test_pairs_match_oracle_blocks(wire):
         assert ev.min() < -1e3 * s.n_atoms * s.filter_eps
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_pairs_one_tau_equals_all_tau(wire, prec):
     import torch
     from paper_2104_09857_amd import gw
