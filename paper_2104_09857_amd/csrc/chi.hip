@@ -56,6 +56,8 @@ int b_wm(int RS) { return RS <= 64 ? 2 : RS <= 96 ? 3 : RS <= 128 ? 4 : RS <= 16
 // atom block: 64-wide tiles for small bases, 192-wide otherwise
 int ab_nb(int cols) { return cols <= 16 * AB_NBN * AB_WN ? AB_NBN : AB_NBW; }
 int b_rb(int RS) { return RS <= 64 ? 2 : RS <= 96 ? 3 : RS <= 128 ? 4 : 5; }
+// BF16x3 entries per atom of D and the bricks (the half contractions' index)
+int bf_width(int NA) { return NA <= 8 ? 8 : 16; }
 
 // Work of one stage at every pivot index, for a batched launch.
 template <class P>
@@ -454,7 +456,9 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     if ((rc = M.upload(&d_poffb, poffb)) != GW_OK) return rc;
     if ((rc = M.upload(&d_ptab, ptab)) != GW_OK) return rc;
     if ((rc = M.upload(&d_pt_off, pt_off)) != GW_OK) return rc;
-    const size_t tsz = (size_t)s->n_trip * NR * NA * 16, dsz16 = (size_t)n_tau * N * na * 16;
+    // D and the bricks carry W entries per atom (8 for bases of at most 8 functions)
+    const int W = bf_width(NA);
+    const size_t tsz = (size_t)s->n_trip * NR * NA * W, dsz16 = (size_t)n_tau * N * na * W;
     // N_b of every pivot of a stage-B group: [pivot][tau] slabs of BPS16
     const size_t msz = (size_t)n_tau * P.nRmax * NR * na * E, nsz = (size_t)B.GB * n_tau * P.BPS16;
     // the direct-to-LDS outer contraction takes its M_b offsets within one tau in 32 bits
@@ -491,7 +495,7 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     if (s->n_trip > 0) {
       const unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)tsz + 255) / 256, 1 << 20);
       hipLaunchKernelGGL(split_t_kernel, dim3(blocks), dim3(256), 0, st, s->t3c, P.th, P.tl,
-                         s->n_trip, NA, NR);
+                         s->n_trip, NA, NR, W);
       GW_HIP(hipGetLastError());
     }
 
@@ -501,14 +505,14 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     ba.rows_pt = 16 * 4 * 4; ba.cols_pt = 16 * bf_ab_nb(B) * BF_WN;
     ba.n_rt = (N + ba.rows_pt - 1) / ba.rows_pt;
     ba.n_ct = (NA * NR + ba.cols_pt - 1) / ba.cols_pt;
-    ba.N = N; ba.NA = NA; ba.NR = NR; ba.na = na; ba.nRmax = P.nRmax; ba.G = Gp;
+    ba.N = N; ba.NA = NA; ba.NR = NR; ba.na = na; ba.nRmax = P.nRmax; ba.G = Gp; ba.W = W;
     ba.fdNA.set((uint32_t)NA);
 
     StageBBf& bb = P.bb;
     bb.dh = P.dvh; bb.dl = P.dvl; bb.th = P.th; bb.tl = P.tl; bb.nh = P.nh; bb.nl = P.nl;
     bb.goff = d_goff; bb.seg_atom = d_seg_atom; bb.seg_brick = d_seg_brick; bb.gc = d_gc;
     bb.gslot = d_gslot; bb.poffb = d_poffb; bb.N = N; bb.NA = NA; bb.NR = NR; bb.na = na;
-    bb.RS = RS; bb.PG = P.PG; bb.PC = P.PC; bb.G = Gp; bb.BPSE = P.BPS16;
+    bb.RS = RS; bb.PG = P.PG; bb.PC = P.PC; bb.G = Gp; bb.W = W; bb.BPSE = P.BPS16;
     bb.n_tau = n_tau; bb.ng = 1;
     bb.fdGN.set((uint32_t)NA);
     bb.rows_pt = 16 * b_rb(B.RSB) * 2;
@@ -788,21 +792,21 @@ hipError_t run_bf(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t
               : launch_tile_bf16x3<WM, WN, RB, NB, KC>(b, dim3((unsigned)work), st);
 }
 
-template <int WM, int WN, int RB, int NB, int S, class P>
+template <int WM, int WN, int RB, int NB, int S, int HS, class P>
 hipError_t run_bf_dma(const Table<P>& T, int piv, bool pers, int* queue, hipStream_t st) {
   if (!queue) {
-    (void)persistent_cap_bf3_dma<WM, WN, RB, NB, S, Batched<P>>();
+    (void)persistent_cap_bf3_dma<WM, WN, RB, NB, S, HS, Batched<P>>();
     return hipSuccess;
   }
   const int work = T.work[piv];
   if (T.n[piv] == 0 || work == 0) return hipSuccess;
   if (!pers && T.n[piv] == 1) {
     const BatchEntry<P>& e = T.ent[T.ent0[piv]];
-    return launch_tile_bf3_dma<WM, WN, RB, NB, S>(e.p, dim3(e.gx, e.gy, work / (e.gx * e.gy)), st);
+    return launch_tile_bf3_dma<WM, WN, RB, NB, S, HS>(e.p, dim3(e.gx, e.gy, work / (e.gx * e.gy)), st);
   }
   const Batched<P> b = T.at(piv);
-  return pers ? launch_tile_bf3_dma_persistent<WM, WN, RB, NB, S>(b, work, queue, st)
-              : launch_tile_bf3_dma<WM, WN, RB, NB, S>(b, dim3((unsigned)work), st);
+  return pers ? launch_tile_bf3_dma_persistent<WM, WN, RB, NB, S, HS>(b, work, queue, st)
+              : launch_tile_bf3_dma<WM, WN, RB, NB, S, HS>(b, dim3((unsigned)work), st);
 }
 
 template <class T>
@@ -853,10 +857,25 @@ hipError_t stage_c_f(const gw_chi_batch& B, int piv, bool pers, int* q, hipStrea
     default: return run_mfma<4, C_WN, C_NBW, C_KC>(t, piv, pers, q, st);
   }
 }
+// the direct-to-LDS stage A / B instance for the plan's table width: with
+// 8 entries per atom a k pair spans two segments (half select)
+template <int HS>
+hipError_t stage_a_bf_dma(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  if (bf_ab_nb(B) == BF_NB_ABN) return run_bf_dma<4, BF_WN, 4, BF_NB_ABN, 3, HS>(B.tAb, piv, pers, q, st);
+  return run_bf_dma<4, BF_WN, 4, BF_NB_AB, 2, HS>(B.tAb, piv, pers, q, st);
+}
+template <int NB, int HS>
+hipError_t stage_b_bf_dma(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
+  switch (b_rb(B.RSB)) {
+    case 2: return run_bf_dma<2, BF_WN, 2, NB, 3, HS>(B.tBb, piv, pers, q, st);
+    case 3: return run_bf_dma<2, BF_WN, 3, NB, 3, HS>(B.tBb, piv, pers, q, st);
+    case 4: return run_bf_dma<2, BF_WN, 4, NB, 3, HS>(B.tBb, piv, pers, q, st);
+    default: return run_bf_dma<2, BF_WN, 5, NB, 3, HS>(B.tBb, piv, pers, q, st);
+  }
+}
 hipError_t stage_a_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
   if (B.bf_dma_ab) {
-    if (bf_ab_nb(B) == BF_NB_ABN) return run_bf_dma<4, BF_WN, 4, BF_NB_ABN, 3>(B.tAb, piv, pers, q, st);
-    return run_bf_dma<4, BF_WN, 4, BF_NB_AB, 2>(B.tAb, piv, pers, q, st);
+    return bf_width(B.NA) == 8 ? stage_a_bf_dma<1>(B, piv, pers, q, st) : stage_a_bf_dma<0>(B, piv, pers, q, st);
   }
   if (bf_ab_nb(B) == BF_NB_ABN) return run_bf<4, BF_WN, 4, BF_NB_ABN, BF_KC>(B.tAb, piv, pers, q, st);
   return run_bf<4, BF_WN, 4, BF_NB_AB, BF_KC>(B.tAb, piv, pers, q, st);
@@ -864,12 +883,7 @@ hipError_t stage_a_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStre
 template <int NB>
 hipError_t stage_b_bf_rows(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
   if (B.bf_dma_ab) {
-    switch (b_rb(B.RSB)) {
-      case 2: return run_bf_dma<2, BF_WN, 2, NB, 3>(B.tBb, piv, pers, q, st);
-      case 3: return run_bf_dma<2, BF_WN, 3, NB, 3>(B.tBb, piv, pers, q, st);
-      case 4: return run_bf_dma<2, BF_WN, 4, NB, 3>(B.tBb, piv, pers, q, st);
-      default: return run_bf_dma<2, BF_WN, 5, NB, 3>(B.tBb, piv, pers, q, st);
-    }
+    return bf_width(B.NA) == 8 ? stage_b_bf_dma<NB, 1>(B, piv, pers, q, st) : stage_b_bf_dma<NB, 0>(B, piv, pers, q, st);
   }
   switch (b_rb(B.RSB)) {
     case 2: return run_bf<2, BF_WN, 2, NB, BF_KC>(B.tBb, piv, pers, q, st);
@@ -886,7 +900,7 @@ hipError_t stage_c_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStre
   switch (B.variant) {
     case 1: return run_bf<4, BF_WN, 2, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
     case 2: return run_bf<2, BF_WN, 4, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
-    case 3: return run_bf_dma<4, BF_WN, 4, BF_NB_C, 3>(B.tCb, piv, pers, q, st);
+    case 3: return run_bf_dma<4, BF_WN, 4, BF_NB_C, 3, 0>(B.tCb, piv, pers, q, st);
     default: return run_bf<4, BF_WN, 4, BF_NB_C, BF_KC>(B.tCb, piv, pers, q, st);
   }
 }
@@ -957,13 +971,14 @@ gw_status enqueue(gw_chi_batch& B, const double* const* occ, const double* const
       GW_HIP(to_f32_rows(P.dof, P.dof32, (int64_t)n_tau * P.N, P.N, P.ld32, st));
       GW_HIP(to_f32(P.dvf, P.dvf32, (int64_t)n_tau * P.N * P.N, st));
     } else if (B.prec == GW_BF16X3) {
-      const int64_t dsz16 = (int64_t)n_tau * P.N * P.na * 16;
-      const unsigned blocks = (unsigned)std::min<int64_t>((dsz16 + 255) / 256, 1 << 20);
+      const int W = bf_width(NA);
+      const int64_t dsz = (int64_t)n_tau * P.N * P.na * W;
+      const unsigned blocks = (unsigned)std::min<int64_t>((dsz + 255) / 256, 1 << 20);
       hipLaunchKernelGGL(split_d_kernel, dim3(blocks), dim3(256), 0, st, P.dof, P.doh, P.dol, n_tau,
-                         P.N, P.na, NA);
+                         P.N, P.na, NA, W);
       GW_HIP(hipGetLastError());
       hipLaunchKernelGGL(split_d_kernel, dim3(blocks), dim3(256), 0, st, P.dvf, P.dvh, P.dvl, n_tau,
-                         P.N, P.na, NA);
+                         P.N, P.na, NA, W);
       GW_HIP(hipGetLastError());
     }
   }
@@ -1176,7 +1191,7 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   if (prec == GW_BF16X3) {
     B->bf_dma_ab = true;
     for (const SysPlan& P : B->sys)
-      B->bf_dma_ab = B->bf_dma_ab && (int64_t)(n_tau + 1) * P.N * P.na * 16 < (1ll << 32);
+      B->bf_dma_ab = B->bf_dma_ab && (int64_t)(n_tau + 1) * P.N * P.na * bf_width(NA) < (1ll << 32);
   }
   // largest systems first: their tiles lead every batched launch
   B->order.resize(n_sys);

@@ -54,7 +54,7 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T* scalar_vie
   return (const __attribute__((address_space(4))) T*)(((uint64_t)hi << 32) | lo);
 }
 
-template <int WM, int WN, int RB, int NB, int S, class P>
+template <int WM, int WN, int RB, int NB, int S, int HS, class P>
 __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, int bz) {
   constexpr int ROWS = 16 * RB * WM, COLS = 16 * NB * WN, NT = 64 * WM * WN, NW = NT / 64;
   constexpr int KC = 32, NP = KC / 16;                       // k pairs per chunk
@@ -76,7 +76,10 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave % WM, wn = wave / WM;
   const auto lp = resolve(p, t);
-  const int npairs = t.K / 16, pmax = npairs - 1;
+  // K is a multiple of 8; a pair's two halves are table entry u, 8 apart
+  // (HS == 0), or entries 2u and 2u + 1, each 8 wide (HS == 1)
+  const int npairs = (t.K + 15) / 16, pmax = npairs - 1;
+  const int emax = (HS ? t.K / 8 : t.K / 16) - 1;        // last table entry
   // the pair tables through the scalar (constant) path
   const auto atab = scalar_view(lp.a_tab(t));
   const __attribute__((address_space(4))) int64_t* btab = nullptr;
@@ -92,6 +95,7 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
   const gmem<const uint16_t>* cbase[CPW];
   bool cisb[CPW];
   int cpair[CPW], ccell[CPW];
+  bool chalf[CPW];    // the lane's half (HS == 1 only)
   uint32_t clane[CPW];
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
@@ -106,10 +110,12 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
     cbase[j] = to_global(arr == 0 ? lp.abase_hi(t) : arr == 1 ? lp.abase_lo(t)
                          : arr == 2 ? lp.bbase_hi(t) : lp.bbase_lo(t));
     cisb[j] = isb;
-    cpair[j] = pair;
+    cpair[j] = __builtin_amdgcn_readfirstlane(pair);         // one pair per copy (2 * width % 64 == 0)
+    chalf[j] = half != 0;
+    const int hoff = HS ? 0 : 8 * half;
     ccell[j] = (arr == 0 ? 0 : arr == 1 ? AC : arr == 2 ? 2 * AC : 2 * AC + BC) + cc * 64;
-    if (isb) clane[j] = (uint32_t)(bcs * (x < t.cols ? x : t.cols - 1) + 8 * half);
-    else clane[j] = (uint32_t)lp.arow(t, x < t.rows ? x : t.rows - 1) + (uint32_t)(8 * half);
+    if (isb) clane[j] = (uint32_t)(bcs * (x < t.cols ? x : t.cols - 1) + hoff);
+    else clane[j] = (uint32_t)lp.arow(t, x < t.rows ? x : t.rows - 1) + (uint32_t)hoff;
   }
 
   // every wave issues CPW copies per chunk (a wave with fewer repeats the
@@ -117,25 +123,43 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
   // last pair, so that the code has no branches and the compiler can count
   // the copies in flight
   auto issue = [&](int ch, u32x4_t* dst) {
-    // the table entries first (one wait for all of them), then the copies
-    int uj[CPW], tv[CPW];
-    int64_t tb[CPW];
+    // the table entries of the chunk's NP pairs first (one wait for all of
+    // them), then the copies, each taking its pair's (and its lane's) entry
+    constexpr int NE = HS ? 2 : 1;                           // entries per pair
+    int up[NP], tv[NP][NE];
+    int64_t tb[NP][NE];
 #pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      const int u = ch * NP + cpair[j];
-      uj[j] = __builtin_amdgcn_readfirstlane(u < pmax ? u : pmax);
-      tv[j] = atab[uj[j]];
-      if constexpr (BTAB) tb[j] = btab[uj[j]];
-      else tb[j] = uj[j];
+    for (int q = 0; q < NP; ++q) {
+      const int u = __builtin_amdgcn_readfirstlane(ch * NP + q < pmax ? ch * NP + q : pmax);
+      up[q] = u;
+#pragma unroll
+      for (int h = 0; h < NE; ++h) {
+        const int e = __builtin_amdgcn_readfirstlane(NE * u + h < emax ? NE * u + h : emax);
+        tv[q][h] = atab[e];
+        if constexpr (BTAB) tb[q][h] = btab[e];
+      }
     }
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
       const gmem<const uint16_t>* g;
+      int u = up[0], v0 = tv[0][0], v1 = tv[0][NE - 1];
+      int64_t b0 = 0, b1 = 0;
+      if constexpr (BTAB) b0 = tb[0][0], b1 = tb[0][NE - 1];
+#pragma unroll
+      for (int q = 1; q < NP; ++q) {                         // wave-uniform selects
+        const bool m = cpair[j] == q;
+        u = m ? up[q] : u;
+        v0 = m ? tv[q][0] : v0;
+        v1 = m ? tv[q][NE - 1] : v1;
+        if constexpr (BTAB) b0 = m ? tb[q][0] : b0, b1 = m ? tb[q][NE - 1] : b1;
+      }
+      const bool h = HS && chalf[j];                         // this lane's entry
+      const int v = h ? v1 : v0;
       if constexpr (BTAB) {      // brick offsets need 64 bits
-        const int64_t po = cisb[j] ? tb[j] * bmul : (int64_t)((uint32_t)tv[j] * amul);
+        const int64_t po = cisb[j] ? (h ? b1 : b0) * bmul : (int64_t)((uint32_t)v * amul);
         g = cbase[j] + (po + (int64_t)clane[j]);
       } else {                   // offsets within one tau slab below 2^32 (host check)
-        const uint32_t po = cisb[j] ? lp.b_pairoff(uj[j]) : (uint32_t)tv[j] * amul;
+        const uint32_t po = cisb[j] ? lp.b_pairoff(u) : (uint32_t)v * amul;
         g = cbase[j] + (po + clane[j]);
       }
       __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
@@ -165,7 +189,7 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
     bo[cb] = 2 * AC + (lpr * COLS + c) * 2 + (lh ^ ((c >> 2) & 1));
   }
 
-  const int ngroups = 2 * npairs;
+  const int ngroups = t.K / 8;
   const int nch = (npairs + NP - 1) / NP;
   // One chunk: wait for its copies, barrier, the copies of chunk ch + S - 1
   // into stage dst, then the matrix-core steps on stage ls.
@@ -264,15 +288,15 @@ __device__ __forceinline__ void tile_bf3_dma_body(const P& p, int bx, int by, in
   }
 }
 
-template <int WM, int WN, int RB, int NB, int S, class P>
+template <int WM, int WN, int RB, int NB, int S, int HS, class P>
 __global__ __launch_bounds__(64 * WM * WN) void tile_bf3_dma_kernel(P p) {
   int bx, by, bz;
   grid_tile(bx, by, bz);
-  tile_bf3_dma_body<WM, WN, RB, NB, S>(p, bx, by, bz);
+  tile_bf3_dma_body<WM, WN, RB, NB, S, HS>(p, bx, by, bz);
 }
 
 // persistent form (same per-XCD queue protocol as tile_gemm_persistent)
-template <int WM, int WN, int RB, int NB, int S, class P>
+template <int WM, int WN, int RB, int NB, int S, int HS, class P>
 __global__ __launch_bounds__(64 * WM * WN) void tile_bf3_dma_persistent(P p, int n_work, int* queue) {
   __shared__ int next;
   const uint32_t q = (uint32_t)n_work / kXcds, r = (uint32_t)n_work % kXcds;
@@ -287,31 +311,31 @@ __global__ __launch_bounds__(64 * WM * WN) void tile_bf3_dma_persistent(P p, int
       __syncthreads();
       const int l = next;
       if (l >= len) break;
-      tile_bf3_dma_body<WM, WN, RB, NB, S>(p, start + l, 0, 0);
+      tile_bf3_dma_body<WM, WN, RB, NB, S, HS>(p, start + l, 0, 0);
     }
   }
 }
 
-template <int WM, int WN, int RB, int NB, int S, class P>
+template <int WM, int WN, int RB, int NB, int S, int HS, class P>
 inline hipError_t launch_tile_bf3_dma(const P& p, dim3 grid, hipStream_t st) {
   if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
-  hipLaunchKernelGGL((tile_bf3_dma_kernel<WM, WN, RB, NB, S, P>), grid, dim3(64 * WM * WN), 0, st, p);
+  hipLaunchKernelGGL((tile_bf3_dma_kernel<WM, WN, RB, NB, S, HS, P>), grid, dim3(64 * WM * WN), 0, st, p);
   return hipGetLastError();
 }
 
-template <int WM, int WN, int RB, int NB, int S, class P>
+template <int WM, int WN, int RB, int NB, int S, int HS, class P>
 inline int persistent_cap_bf3_dma() {
   static int cap = 0;
-  if (cap == 0) cap = resident_groups(tile_bf3_dma_persistent<WM, WN, RB, NB, S, P>, 64 * WM * WN);
+  if (cap == 0) cap = resident_groups(tile_bf3_dma_persistent<WM, WN, RB, NB, S, HS, P>, 64 * WM * WN);
   return cap;
 }
 
-template <int WM, int WN, int RB, int NB, int S, class P>
+template <int WM, int WN, int RB, int NB, int S, int HS, class P>
 inline hipError_t launch_tile_bf3_dma_persistent(const P& p, int n_work, int* queue, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
-  const int cap = persistent_cap_bf3_dma<WM, WN, RB, NB, S, P>();
+  const int cap = persistent_cap_bf3_dma<WM, WN, RB, NB, S, HS, P>();
   const int grid = cap > 0 ? (n_work < cap ? n_work : cap) : n_work;
-  hipLaunchKernelGGL((tile_bf3_dma_persistent<WM, WN, RB, NB, S, P>), dim3(grid), dim3(64 * WM * WN), 0,
+  hipLaunchKernelGGL((tile_bf3_dma_persistent<WM, WN, RB, NB, S, HS, P>), dim3(grid), dim3(64 * WM * WN), 0,
                      st, p, n_work, queue);
   return hipGetLastError();
 }
