@@ -77,7 +77,7 @@ DTYPE = {"fp64": "f64", "fp32": "f32 (FP32 MFMA and accumulation in a tile, FP64
          "bf16x3": "bf16x3 (bf16 hi/lo MFMA, FP32 accumulation in a tile, FP64 across pivots)"}
 _C_TILES = {"fp64": ["4,2,5,32", "2,2,5,32", "4,2,5,16", "4,2,5,32,2"],
             "fp32": ["4,2,5,32", "2,2,5,32", "4,2,5,16", "4,2,5,16,3"],
-            "bf16x3": ["4,2,4,5,32", "4,2,2,5,32", "2,2,4,5,32", "4,2,4,5,3"]}
+            "bf16x3": ["4,2,4,5,32", "4,2,2,5,32", "2,2,4,5,32", "4,2,4,5,3,0"]}
 _C_PROB = {"fp64": "StageC<double>", "fp32": "StageC<float>", "bf16x3": "StageCBf"}
 
 

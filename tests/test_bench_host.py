@@ -41,7 +41,7 @@ def test_stage_c_kernel_names():
         "tile_gemm_persistent<4,2,5,16,Batched<StageC<double>>>"
     assert bench.stage_c_kernel("fp32", 3, 7).startswith("tile_dma_persistent<")
     assert bench.stage_c_kernel("bf16x3", 0, 0).startswith("tile_bf16x3_kernel<")
-    assert bench.stage_c_kernel("bf16x3", 3, 7) == "tile_bf3_dma_persistent<4,2,4,5,3,Batched<StageCBf>>"
+    assert bench.stage_c_kernel("bf16x3", 3, 7) == "tile_bf3_dma_persistent<4,2,4,5,3,0,Batched<StageCBf>>"
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
