@@ -196,7 +196,8 @@ struct gw_chi_batch {
   int variant = 0, persistent = 0;
   int RS = 0;              // rows of one pivot's half contraction (n_tau * NA)
   int GB = 1;              // pivots per stage-B launch (a group)
-  int RSB = 0;             // rows of a full group (GB * RS): row stride of dvg
+  int RSB = 0;             // rows of a full group (GB * RS)
+  int LDB = 0;             // row stride of dvg: RSB rounded up to whole 16-byte groups
   int ab_nb = AB_NBW;      // 16-column blocks per wave of the stage-A/B tiles
   bool b_dma = false;      // stage B on the direct-to-LDS engine (FP64, FP32)
   bool a_dma = false;      // stage A on the direct-to-LDS engine (FP64, FP32)
@@ -253,7 +254,7 @@ struct Index {
 // scratch and problem descriptions of the FP64 / FP32 form of one system
 template <class T>
 gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index& ix, hipStream_t st) {
-  const int n_tau = B.n_tau, NA = B.NA, NR = B.NR, N = P.N, RS = B.RSB;
+  const int n_tau = B.n_tau, NA = B.NA, NR = B.NR, N = P.N, RS = B.RSB, LD = B.LDB;
   Scratch& M = B.mem;
   FBufs<T>& F = bufs<T>(P);
   gw_status rc;
@@ -275,23 +276,23 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
     F.t3c = t32;
   }
   // per-tile offsets of the stage maps are 32-bit
-  GW_CHECK_ARG((int64_t)N * P.ld32 < (1ll << 31) && (int64_t)N * RS < (1ll << 31) &&
+  GW_CHECK_ARG((int64_t)N * P.ld32 < (1ll << 31) && (int64_t)N * LD < (1ll << 31) &&
                    (int64_t)NA * P.nRmax * N * NR < (1ll << 31) && P.bs < (1ll << 31),
                "system too large for 32-bit tile offsets");
   for (int p = 0; p < P.n_pan; ++p)
     GW_CHECK_ARG((int64_t)NA * NA * P.pan.ulen[p] * P.PC < (1ll << 31),
                  "column panel too large for 32-bit tile offsets");
   const size_t n_mb = (size_t)n_tau * NA * P.nRmax * N * NR, n_bp = (size_t)B.GB * n_tau * P.BPS;
-  if ((rc = M.alloc(&F.dvg, (size_t)N * RS)) != GW_OK) return rc;
+  if ((rc = M.alloc(&F.dvg, (size_t)N * LD)) != GW_OK) return rc;
   if ((rc = M.alloc(&F.mb, n_mb)) != GW_OK) return rc;
   // N_b of every pivot of a stage-B group: [pivot][tau] slabs of BPS
   if ((rc = M.alloc(&F.bp, n_bp)) != GW_OK) return rc;
   // entries of N_b that no group writes stay zero for the life of the plan
   GW_HIP(hipMemsetAsync(F.bp, 0, sizeof(T) * n_bp, st));
   // buffers of the second pivot of a pair, within 32 GiB (else no pairs)
-  if (P.pair_h > 0 && sizeof(T) * (n_mb + n_bp + (size_t)N * RS) > (32ull << 30)) P.pair_h = 0;
+  if (P.pair_h > 0 && sizeof(T) * (n_mb + n_bp + (size_t)N * LD) > (32ull << 30)) P.pair_h = 0;
   if (P.pair_h > 0) {
-    if ((rc = M.alloc(&F.dvg1, (size_t)N * RS)) != GW_OK) return rc;
+    if ((rc = M.alloc(&F.dvg1, (size_t)N * LD)) != GW_OK) return rc;
     if ((rc = M.alloc(&F.mb1, n_mb)) != GW_OK) return rc;
     if ((rc = M.alloc(&F.bp1, n_bp)) != GW_OK) return rc;
     GW_HIP(hipMemsetAsync(F.bp1, 0, sizeof(T) * n_bp, st));
@@ -310,7 +311,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
   StageB<T>& sb = F.sb;
   sb.dvg = F.dvg; sb.t3c = F.t3c; sb.bp = F.bp; sb.goff = ix.goff; sb.seg_atom = ix.seg_atom;
   sb.seg_brick = ix.seg_brick; sb.gc = ix.gc; sb.gslot = ix.gslot; sb.ulen = ix.ulen;
-  sb.bp_off = ix.bp_off; sb.RS = RS; sb.ld = RS; sb.NA = NA; sb.NR = NR; sb.PG = P.PG; sb.PC = P.PC;
+  sb.bp_off = ix.bp_off; sb.RS = RS; sb.ld = LD; sb.NA = NA; sb.NR = NR; sb.PG = P.PG; sb.PC = P.PC;
   sb.bs = P.bs; sb.bs32 = (int)P.bs; sb.BPS = P.BPS;
   sb.rows_pt = 32 * b_wm(RS);
   sb.cols_pt = 16 * B.ab_nb * AB_WN;
@@ -427,6 +428,10 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     while (gb > 1 && (int64_t)gb * n_tau * slab > (16ll << 30)) --gb;
     B.GB = gb;
     B.RSB = gb * B.RS;
+    // the direct-to-LDS copies take D^vir rows in 16-byte groups (2 FP64 /
+    // 4 FP32 elements); the padding rows of dvg are zeros (gather kernel)
+    const int q = B.prec == GW_FP32 ? 4 : 2;
+    B.LDB = (B.RSB + q - 1) / q * q;
   }
   if (B.prec == GW_FP64) {
     if ((rc = prepare_f<double>(B, P, s, ix, st)) != GW_OK) return rc;
@@ -936,10 +941,10 @@ gw_status pivot_f(gw_chi_batch& B, int piv, int pers, int* q, std::vector<hipEve
   if (F.gathn[piv] > 0) {
     int64_t most = 0;
     for (int e = 0; e < F.gathn[piv]; ++e)
-      most = std::max<int64_t>(most, (int64_t)F.gath[F.gath0[piv] + e].N * B.RSB);
+      most = std::max<int64_t>(most, (int64_t)F.gath[F.gath0[piv] + e].N * B.LDB);
     const unsigned bx = (unsigned)std::min<int64_t>((most + 255) / 256, 4096);
     hipLaunchKernelGGL(gather_dvir_kernel<T>, dim3(bx, (unsigned)F.gathn[piv]), dim3(256), 0, st,
-                       F.d_gath + F.gath0[piv], B.NA, B.n_tau, B.RSB);
+                       F.d_gath + F.gath0[piv], B.NA, B.n_tau, B.LDB);
     GW_HIP(hipGetLastError());
   }
   GW_HIP(mark(0));
@@ -1176,12 +1181,10 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
     if ((rc = prepare_sys(*B, B->sys[m], &systems[m], st)) != GW_OK) return rc;
     B->max_na = std::max(B->max_na, systems[m].n_atoms);
   }
-  // 16-byte copies need the rows of the gathered D^vir (GB * n_tau * NA
-  // elements) and the brick rows (NA * NR elements) in whole groups of 16
-  // bytes, and in FP64 stage A the D^occ rows (N doubles; the FP32 copy is
-  // padded)
-  B->b_dma = prec == GW_FP32 ? NR % 4 == 0 && B->RSB % 4 == 0
-                             : prec == GW_FP64 && NR % 2 == 0 && B->RSB % 2 == 0;
+  // 16-byte copies need the brick rows (NA * NR elements) in whole groups of
+  // 16 bytes (the gathered D^vir rows are padded to them, LDB), and in FP64
+  // stage A the D^occ rows (N doubles; the FP32 copy is padded)
+  B->b_dma = prec == GW_FP32 ? NR % 4 == 0 : prec == GW_FP64 && NR % 2 == 0;
   if (prec == GW_FP64) {
     B->a_dma = NR % 2 == 0;
     for (const SysPlan& P : B->sys) B->a_dma = B->a_dma && P.N % 2 == 0;
