@@ -59,7 +59,7 @@ enum {
  * products with FP32 accumulation inside a tile, FP64 accumulation of chi
  * across pivots) or GW_BF16X3 (operands split into bf16 hi + lo, three bf16
  * MFMA products with FP32 accumulation inside a tile, FP64 accumulation
- * across pivots). */
+ * across pivots; ao_per_atom <= 16, else GW_ERR_ARG). */
 typedef enum { GW_FP64 = 0, GW_FP32 = 1, GW_BF16X3 = 2 } gw_prec;
 
 /* One molecule / strip.  Atom-triple bricks (a, b, c) of the three-center

@@ -1149,6 +1149,8 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   const int NA = systems[0].ao_per_atom, NR = systems[0].ri_per_atom;
   GW_CHECK_ARG(NR <= C_COLS, "ri_per_atom must be <= 160");
   GW_CHECK_ARG((int64_t)n_tau * NA <= (1 << 20), "n_tau * ao_per_atom too large");
+  // the BF16x3 half contractions hold an atom's AO functions in one k pair
+  GW_CHECK_ARG(prec != GW_BF16X3 || NA <= 16, "GW_BF16X3 needs ao_per_atom <= 16");
 
   std::unique_ptr<gw_chi_batch> B(new (std::nothrow) gw_chi_batch(st));
   if (!B) {

@@ -121,6 +121,8 @@ def test_batch_plan_validation():
     assert create([a, bad]) == gw.GW_ERR_ARG          # invalid member
     assert create([a], n_tau=0) == gw.GW_ERR_ARG
     assert create([a], o=gw._ChiOpts(5, 0.0)) == gw.GW_ERR_ARG       # unknown precision
+    big = gw._System(2, 17, 4, 3, 1, tp, 1)
+    assert create([big], o=gw._ChiOpts(2, 0.0)) == gw.GW_ERR_ARG     # BF16x3 beyond 16 AO per atom
     assert create([a], o=gw._ChiOpts(0, 1e-6, 0, 1, 1.0, None)) == gw.GW_ERR_ARG   # screener
     assert L.gw_chi_batch_create(0, None, 4, ctypes.byref(opts), ctypes.byref(h), None) == gw.GW_ERR_ARG
     assert L.gw_chi_batch_create(1, None, 4, ctypes.byref(opts), None, None) == gw.GW_ERR_ARG
