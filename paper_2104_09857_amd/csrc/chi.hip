@@ -326,6 +326,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
   sc.PG = P.PG; sc.PC = P.PC; sc.nRmax = P.nRmax; sc.n_atoms = P.na; sc.BPS = P.BPS;
   sc.sgs = P.nRmax * N * NR;
   sc.fdNR.set((uint32_t)NR);
+  sc.fdNA.set((uint32_t)NA);
   return GW_OK;
 }
 
@@ -358,7 +359,7 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
   for (int g = 0; g < P.n_groups; ++g)
     GW_CHECK_ARG(G.goff[g + 1] - G.goff[g] <= kSegTab, "too many bricks in one (atom, RI atom) group");
   for (int p = 0; p < P.n_pan; ++p)
-    GW_CHECK_ARG(NA * P.pan.ulen[p] <= kPanTab, "too many AO atoms coupled to one RI column panel");
+    GW_CHECK_ARG(P.pan.ulen[p] <= kPanTab, "too many AO atoms coupled to one RI column panel");
 
   // FLOPs of the three stages per tau (every output block computed)
   P.acount.assign(na, 0);
@@ -447,8 +448,7 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     std::vector<int32_t> ptab, pt_off(P.n_pan + 1, 0);
     for (int p = 0; p < P.n_pan; ++p) {
       poffb[p + 1] = poffb[p] + (int64_t)P.pan.ulen[p] * P.PC * E;
-      GW_CHECK_ARG((int64_t)Gp * P.pan.ulen[p] <= kPanTab,
-                   "too many AO atoms coupled to one RI column panel");
+      GW_CHECK_ARG(P.pan.ulen[p] <= kPanTab, "too many AO atoms coupled to one RI column panel");
       for (int j = 0; j < P.pan.ulen[p]; ++j) {
         const int a = P.pan.kmap[P.pan.km_off[p] + j * NA] / NA;   // union atom j
         for (int e = 0; e < Gp; ++e) ptab.push_back(a * Gp + e);
@@ -532,6 +532,7 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
     bc.PG = P.PG; bc.PC = P.PC; bc.nRmax = P.nRmax; bc.n_atoms = na; bc.na = na;
     bc.G = Gp; bc.BPSE = P.BPS16;
     bc.fdNR.set((uint32_t)NR);
+    bc.fdG.set((uint32_t)Gp);
   }
   return GW_OK;
 }

@@ -30,9 +30,9 @@ constexpr int C_COLS = 16 * C_NBW * C_WN;
 constexpr int C_KC = 32;                          // K chunk staged per barrier pair
 
 constexpr int kSegTab = 2048;     // max bricks per group (first atoms)
-// max K functions per column panel (NA * |U_p|); sized so that the FP64
-// direct-to-LDS outer contraction with 32-deep K chunks (144 KB of operand
-// stages) and this table fit in the 160 KB of LDS
+// max union atoms per RI column panel (|U_p|: one table entry per atom); the
+// FP64 direct-to-LDS outer contraction with 32-deep K chunks (144 KB of
+// operand stages) and this table fit in the 160 KB of LDS
 constexpr int kPanTab = 3968;
 
 // T: operand type (double: FP64 form, float: FP32 form)
@@ -224,7 +224,7 @@ struct StageC {
   int N, NA, NR, NRI, PG, PC, nRmax, n_atoms;
   int sgs;                  // nRmax * N * NR: stride of sigma in M_b
   int64_t BPS;
-  FastDiv fdNR;
+  FastDiv fdNR, fdNA;
   const uint8_t* keep;      // screener mask [tau][c][c'] (c <= c'), or null
   int* tiles_skipped;
 
@@ -248,8 +248,11 @@ struct StageC {
     t.K = NA * t.KU;
     return t.K > 0;
   }
+  // one table entry per union atom j: the M_b offset of its first AO
+  // function (the panel's functions are whole atoms, NA each)
   __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
-    for (int i = tid; i < t.KU; i += nt) ta[i] = kmap[t.km0 + i] * NR;
+    const int nu = t.KU / NA;
+    for (int j = tid; j < nu; j += nt) ta[j] = kmap[t.km0 + j * NA] * NR;
   }
   __device__ const T* abase(const Tile& t) const {
     return mb + (int64_t)t.tau * NA * nRmax * N * NR;
@@ -263,7 +266,8 @@ struct StageC {
   static constexpr bool kAStep = true, kBLin = true;
   __device__ int adiv(const Tile& t) const { return t.KU; }
   __device__ uint32_t akoff2(const Tile&, int sg, int u, const int* ta) const {
-    return (uint32_t)sg * (uint32_t)sgs + (uint32_t)ta[u];
+    const int j = (int)fdNA.div((uint32_t)u), i = u - j * NA;    // union atom j, function i
+    return (uint32_t)sg * (uint32_t)sgs + (uint32_t)ta[j] + (uint32_t)(i * NR);
   }
   __device__ int bstride(const Tile&) const { return PC; }
   __device__ const T* bbase(const Tile& t) const {

@@ -24,7 +24,7 @@ constexpr int Z_WM = 4, Z_WN = 2, Z_NBW = 5;   // W product / dot: 128 x 160 til
 constexpr int Z_COLS = 16 * Z_NBW * Z_WN;
 
 constexpr int kSegTab = 2048;     // max bricks per group
-constexpr int kPanTab = 8192;     // max K functions per AO column panel (NR * |U_q|)
+constexpr int kPanTab = 8192;     // max RI atoms per AO column panel (|U_q|: one table entry each)
 
 struct HalfProblem {
   struct Tile : TileBase {
@@ -115,6 +115,7 @@ struct ZProblem {
   const int64_t* poff;
   int n_rt, rows_pt, NRI, N, NR, PCa;
   int64_t FPS;
+  FastDiv fdNR;
 
   __device__ bool tile(int bx, int, int bz, Tile& t) const {
     t.row0 = (bx % n_rt) * rows_pt;
@@ -126,12 +127,17 @@ struct ZProblem {
     t.km0 = km_off[t.q];
     return t.rows > 0 && t.cols > 0 && t.K > 0;
   }
+  // one table entry per union RI atom j: its first function (NR each)
   __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
-    for (int i = tid; i < t.K; i += nt) ta[i] = kmap[t.km0 + i];
+    const int nu = t.K / NR;
+    for (int j = tid; j < nu; j += nt) ta[j] = kmap[t.km0 + j * NR];
   }
   __device__ const T* abase(const Tile& t) const { return w + t.row0; }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile&, int k, const int* ta) const { return (int64_t)ta[k] * NRI; }
+  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
+    const int j = (int)fdNR.div((uint32_t)k);
+    return (int64_t)(ta[j] + k - j * NR) * NRI;
+  }
   __device__ const T* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
   __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PCa; }
   __device__ T ascale(const Tile&, int) const { return T(1); }
@@ -168,6 +174,7 @@ struct DotProblem {
   const int64_t* poff;
   int n_rt, n_tiles, rows_pt, NRI, N, NR, PCa;
   int64_t FPS;
+  FastDiv fdNR;
 
   __device__ bool tile(int bx, int, int bz, Tile& t) const {
     t.row0 = (bx % n_rt) * rows_pt;
@@ -191,11 +198,16 @@ struct DotProblem {
   __device__ const T* abase(const Tile& t) const {
     return z + (int64_t)t.n * NRI * N + t.row0;
   }
+  // one table entry per union RI atom j: its first function (NR each)
   __device__ void fill(const Tile& t, int* ta, int*, int tid, int nt) const {
-    for (int i = tid; i < t.K; i += nt) ta[i] = kmap[t.km0 + i];
+    const int nu = t.K / NR;
+    for (int j = tid; j < nu; j += nt) ta[j] = kmap[t.km0 + j * NR];
   }
   __device__ int64_t aroff(const Tile&, int r) const { return r; }
-  __device__ int64_t akoff(const Tile&, int k, const int* ta) const { return (int64_t)ta[k] * N; }
+  __device__ int64_t akoff(const Tile&, int k, const int* ta) const {
+    const int j = (int)fdNR.div((uint32_t)k);
+    return (int64_t)(ta[j] + k - j * NR) * N;
+  }
   __device__ const T* bbase(const Tile& t) const { return fp + (int64_t)t.n * FPS + poff[t.q]; }
   __device__ int64_t bkoff(const Tile&, int k, const int*) const { return (int64_t)k * PCa; }
   __device__ T ascale(const Tile&, int) const { return T(1); }
@@ -316,7 +328,7 @@ extern "C" gw_status gw_contract_sigma_prec(const gw_system* s, int32_t n_gw, co
   for (int g = 0; g < n_groups; ++g)
     GW_CHECK_ARG(G.goff[g + 1] - G.goff[g] <= kSegTab, "too many bricks in one (atom, RI atom) group");
   for (int q = 0; q < n_pan; ++q)
-    GW_CHECK_ARG(NR * pan.ulen[q] <= kPanTab, "too many RI atoms coupled to one AO column panel");
+    GW_CHECK_ARG(pan.ulen[q] <= kPanTab, "too many RI atoms coupled to one AO column panel");
 
   double *dof, *dvf, *d0f, *cg, *fp, *z = nullptr, *partial;
   float *fp32 = nullptr, *z32 = nullptr, *w32 = nullptr;   // FP32 form
@@ -387,10 +399,12 @@ extern "C" gw_status gw_contract_sigma_prec(const gw_system* s, int32_t n_gw, co
     zp.fp = fpx; zp.z = zx; zp.kmap = d_kmap; zp.km_off = d_km_off; zp.ulen = d_ulen; zp.poff = d_poff;
     zp.n_rt = z_rt; zp.rows_pt = 32 * Z_WM; zp.NRI = NRI; zp.N = N; zp.NR = NR; zp.PCa = PCa;
     zp.FPS = FPS;
+    zp.fdNR.set((uint32_t)NR);
     DotProblem<T> dp{};
     dp.z = zx; dp.fp = fpx; dp.kmap = d_kmap; dp.km_off = d_km_off; dp.ulen = d_ulen; dp.poff = d_poff;
     dp.n_rt = y_rt; dp.n_tiles = n_tiles; dp.rows_pt = 32 * Z_WM; dp.NRI = NRI; dp.N = N; dp.NR = NR;
     dp.PCa = PCa; dp.FPS = FPS;
+    dp.fdNR.set((uint32_t)NR);
     for (int j = 0; j < n_slots; ++j) {
       const bool xslot = (j == n_tau);
       const double* w = xslot ? V : wc + (int64_t)j * NRI * NRI;
