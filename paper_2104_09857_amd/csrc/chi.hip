@@ -872,11 +872,20 @@ hipError_t stage_a_bf_dma(const gw_chi_batch& B, int piv, bool pers, int* q, hip
 }
 template <int NB, int HS>
 hipError_t stage_b_bf_dma(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
-  switch (b_rb(B.RSB)) {
-    case 2: return run_bf_dma<2, BF_WN, 2, NB, 3, HS>(B.tBb, piv, pers, q, st);
-    case 3: return run_bf_dma<2, BF_WN, 3, NB, 3, HS>(B.tBb, piv, pers, q, st);
-    case 4: return run_bf_dma<2, BF_WN, 4, NB, 3, HS>(B.tBb, piv, pers, q, st);
-    default: return run_bf_dma<2, BF_WN, 5, NB, 3, HS>(B.tBb, piv, pers, q, st);
+  if constexpr (NB == BF_NB_AB) {
+    switch (b_rb(B.RSB)) {
+      case 2: return run_bf_dma<2, BF_WN_B, 2, BF_NB_B, 3, HS>(B.tBb, piv, pers, q, st);
+      case 3: return run_bf_dma<2, BF_WN_B, 3, BF_NB_B, 3, HS>(B.tBb, piv, pers, q, st);
+      case 4: return run_bf_dma<2, BF_WN_B, 4, BF_NB_B, 3, HS>(B.tBb, piv, pers, q, st);
+      default: return run_bf_dma<2, BF_WN_B, 5, BF_NB_B, 3, HS>(B.tBb, piv, pers, q, st);
+    }
+  } else {
+    switch (b_rb(B.RSB)) {
+      case 2: return run_bf_dma<2, BF_WN, 2, NB, 3, HS>(B.tBb, piv, pers, q, st);
+      case 3: return run_bf_dma<2, BF_WN, 3, NB, 3, HS>(B.tBb, piv, pers, q, st);
+      case 4: return run_bf_dma<2, BF_WN, 4, NB, 3, HS>(B.tBb, piv, pers, q, st);
+      default: return run_bf_dma<2, BF_WN, 5, NB, 3, HS>(B.tBb, piv, pers, q, st);
+    }
   }
 }
 hipError_t stage_a_bf(const gw_chi_batch& B, int piv, bool pers, int* q, hipStream_t st) {
