@@ -15,8 +15,11 @@
 // pair u holds 16 consecutive k values (two 16-byte groups) of a row:
 //   A(r, 16 u + j) at abase + arow(r) + a_tab[u] * a_mul + j
 //   B(16 u + j, c) at bbase + bcs c + b_tab[u] * b_mul + j      (bf16 units)
-// with u < t.K / 16, and b_tab[u] * b_mul replaced by b_pairoff(u) unless the
-// problem has a B table (P::kBTab, 64-bit entries); the tables are read with
+// with 16 u < t.K, and b_tab[u] * b_mul replaced by b_pairoff(u) unless the
+// problem has a B table (P::kBTab, 64-bit entries).  In the half-select
+// instance (HS = 1, tables of 8-wide segments) half h of pair u comes from
+// entry 2 u + h instead: A(r, 16 u + 8 h + j) at abase + arow(r) +
+// a_tab[2 u + h] * a_mul + j (j < 8), and B alike.  The tables are read with
 // scalar loads (their addresses and u are wave-uniform), which do not count
 // against the vector-memory counter that tracks the copies in flight.  The
 // output is added to an FP64 array (P::kOut == 0) or stored split into bf16
