@@ -154,6 +154,8 @@ struct SysPlan {
   uint16_t *mh = nullptr, *ml = nullptr, *nh = nullptr, *nl = nullptr;
   uint16_t *mh1 = nullptr, *ml1 = nullptr, *nh1 = nullptr, *nl1 = nullptr;   // second pivot of a pair
   uint8_t* keep = nullptr;          // screener mask (one-system calls only)
+  uint8_t* needb = nullptr;         // stage-B column blocks needed per pivot [na][na] (same)
+  uint8_t* needa = nullptr;         // stage-A rows (AO atoms) needed per slot atom [na][na] (same)
   FBufs<double> f64;
   FBufs<float> f32;
   StageABf ba{};
@@ -300,6 +302,7 @@ gw_status prepare_f(gw_chi_batch& B, SysPlan& P, const gw_system* s, const Index
 
   StageA<T>& sa = F.sa;
   sa.dof = F.dof; sa.t3c = F.t3c; sa.mb = F.mb; sa.goff = ix.goff; sa.seg_atom = ix.seg_atom;
+  sa.gc = ix.gc; sa.nat = P.na;
   sa.seg_brick = ix.seg_brick; sa.rows_pt = 32 * A_WM; sa.cols_pt = 16 * B.ab_nb * AB_WN;
   sa.n_rt = (N + sa.rows_pt - 1) / sa.rows_pt;
   sa.n_ct = (NA * NR + sa.cols_pt - 1) / sa.cols_pt;
@@ -506,7 +509,7 @@ gw_status prepare_sys(gw_chi_batch& B, SysPlan& P, const gw_system* s, hipStream
 
     StageABf& ba = P.ba;
     ba.dh = P.doh; ba.dl = P.dol; ba.th = P.th; ba.tl = P.tl; ba.mh = P.mh; ba.ml = P.ml;
-    ba.goff = d_goff; ba.seg_atom = d_seg_atom; ba.seg_brick = d_seg_brick;
+    ba.goff = d_goff; ba.seg_atom = d_seg_atom; ba.seg_brick = d_seg_brick; ba.gc = d_gc;
     ba.rows_pt = 16 * 4 * 4; ba.cols_pt = 16 * bf_ab_nb(B) * BF_WN;
     ba.n_rt = (N + ba.rows_pt - 1) / ba.rows_pt;
     ba.n_ct = (NA * NR + ba.cols_pt - 1) / ba.cols_pt;
@@ -596,6 +599,7 @@ gw_status ab_tables_f(gw_chi_batch& B, hipStream_t st) {
         const int nR = pivot_groups(P, piv, g0);
         if (nR > 0) {
           StageA<T> a = pb.sa;
+          a.needa = P.needa;
           a.g0 = g0;
           a.mb = s1 ? pb.mb1 : pb.mb;
           F.tA.add(i, a, nR * a.n_rt * a.n_ct, n_tau, 1);
@@ -606,6 +610,10 @@ gw_status ab_tables_f(gw_chi_batch& B, hipStream_t st) {
         const int ng = std::min(B.GB, ps[k].hi - piv);
         StageB<T> b = pb.sb;
         b.RS = ng * B.RS;
+        b.needb = P.needb;
+        b.b0 = piv;
+        b.ng = ng;
+        b.nat = P.na;
         b.n_rt = (b.RS + b.rows_pt - 1) / b.rows_pt;
         b.dvg = s1 ? pb.dvg1 : pb.dvg;
         b.bp = s1 ? pb.bp1 : pb.bp;
@@ -639,6 +647,7 @@ gw_status ab_tables_bf(gw_chi_batch& B, hipStream_t st) {
         const int nR = pivot_groups(P, piv, g0);
         if (nR > 0) {
           StageABf a = P.ba;
+          a.needa = P.needa;
           a.g0 = g0;
           a.mh = s1 ? P.mh1 : P.mh;
           a.ml = s1 ? P.ml1 : P.ml;
@@ -648,6 +657,7 @@ gw_status ab_tables_bf(gw_chi_batch& B, hipStream_t st) {
         // pivot: rows (tau, pivot, sigma) of the group's pivots
         if ((piv - ps[k].lo) % B.GB != 0) continue;
         StageBBf b = P.bb;
+        b.needb = P.needb;
         b.b = piv;
         b.ng = std::min(B.GB, ps[k].hi - piv);
         b.RS = n_tau * b.ng * B.NA;
@@ -1219,6 +1229,15 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   if ((rc = B->mem.alloc(&B->queues, B->n_queues)) != GW_OK) return rc;
   if ((rc = B->mem.alloc(&B->tiles_skipped, 1)) != GW_OK) return rc;
   GW_HIP(hipMemsetAsync(B->tiles_skipped, 0, sizeof(int), st));
+  // screened one-system calls: stage B may skip column blocks (the mask is
+  // set per call from the screener's keep mask; all needed until then)
+  if (n_sys == 1 && opts && opts->screener && opts->filter_eps > 0.0) {
+    SysPlan& P = B->sys[0];
+    if ((rc = B->mem.alloc(&P.needb, (size_t)P.na * P.na)) != GW_OK) return rc;
+    if ((rc = B->mem.alloc(&P.needa, (size_t)P.na * P.na)) != GW_OK) return rc;
+    GW_HIP(hipMemsetAsync(P.needb, 1, (size_t)P.na * P.na, st));
+    GW_HIP(hipMemsetAsync(P.needa, 1, (size_t)P.na * P.na, st));
+  }
   if ((rc = build_ab_tables(*B, st)) != GW_OK) return rc;
   B->a_dma_ok = B->a_dma;
   B->b_dma_ok = B->b_dma;
@@ -1459,6 +1478,46 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
           keep_h[e] = (ph[e] >= thr) || !std::isfinite(ph[e]) ? 1 : 0;
         }
     GW_HIP(hipMemcpyAsync(P.keep, keep_h.data(), nb, hipMemcpyHostToDevice, st));
+    // stage B: N_b column block c of pivot b feeds the chi blocks (c_r, c),
+    // c_r an RI atom of the pivot's groups, c_r <= c (the lower ones are
+    // mirrored); it is needed when one of them is kept at some tau
+    if (P.needb) {
+      const int nw = (na + 63) / 64;
+      std::vector<uint64_t> any((size_t)na * nw, 0);       // kept at some tau, bit c2 of row c
+      for (int j = 0; j < n_tau; ++j)
+        for (int c = 0; c < na; ++c) {
+          const uint8_t* k = &keep_h[((int64_t)j * na + c) * na];
+          for (int c2 = c; c2 < na; ++c2)
+            if (k[c2]) any[(size_t)c * nw + c2 / 64] |= 1ull << (c2 % 64);
+        }
+      std::vector<uint8_t> need_h((size_t)na * na, 0);
+      std::vector<uint64_t> acc(nw);
+      for (int b = 0; b < na; ++b) {
+        int g0 = 0;
+        const int nR = pivot_groups(P, b, g0);
+        std::fill(acc.begin(), acc.end(), 0ull);
+        for (int sl = 0; sl < nR; ++sl) {
+          const int cr = P.G.gc[g0 + sl];
+          for (int w = 0; w < nw; ++w) acc[w] |= any[(size_t)cr * nw + w];
+        }
+        for (int c2 = 0; c2 < na; ++c2) need_h[(size_t)b * na + c2] = (acc[c2 / 64] >> (c2 % 64)) & 1;
+      }
+      GW_HIP(hipMemcpyAsync(P.needb, need_h.data(), need_h.size(), hipMemcpyHostToDevice, st));
+      // stage A: the M_b rows of slot atom c enter stage C as the K rows of the
+      // panels that hold a kept block (c, c'), c' >= c: the AO atoms of their unions
+      std::vector<uint8_t> needa_h((size_t)na * na, 0);      // [c][a]
+      for (int c = 0; c < na; ++c)
+        for (int p = 0; p < P.n_pan; ++p) {
+          bool kept = false;
+          for (int c2 = p * P.PG; c2 < std::min(na, p * P.PG + P.PG) && !kept; ++c2)
+            kept = (any[(size_t)c * nw + c2 / 64] >> (c2 % 64)) & 1;
+          if (!kept) continue;
+          for (int j = 0; j < P.pan.ulen[p]; ++j)
+            needa_h[(size_t)c * na + P.pan.kmap[P.pan.km_off[p] + j * B->NA] / B->NA] = 1;
+        }
+      GW_HIP(hipMemcpyAsync(P.needa, needa_h.data(), needa_h.size(), hipMemcpyHostToDevice, st));
+      GW_HIP(hipStreamSynchronize(st));          // the host vectors outlive the copies
+    }
     GW_HIP(hipStreamSynchronize(st));
   }
   if ((rc = execute(*B, &d_occ, &d_vir, &chi, false, stats, st)) != GW_OK) return rc;
@@ -1481,6 +1540,9 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
     const bool out_filter = B->out_filter;
     P.keep = nullptr;
     B->out_filter = false;
+    // every stage-B block of the exact run (and of a fallback after it)
+    if (P.needb) GW_HIP(hipMemsetAsync(P.needb, 1, (size_t)na * na, st));
+    if (P.needa) GW_HIP(hipMemsetAsync(P.needa, 1, (size_t)na * na, st));
     B->c_built_variant = -1;            // rebuild the stage-C tables without the mask
     rc = execute(*B, &d_occ, &d_vir, &ex, false, nullptr, st);
     P.keep = keep_dev;

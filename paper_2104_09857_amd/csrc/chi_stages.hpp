@@ -36,6 +36,13 @@ constexpr int kSegTab = 2048;     // max bricks per group (first atoms)
 constexpr int kPanTab = 3968;
 
 // T: operand type (double: FP64 form, float: FP32 form)
+// screening masks of the half contractions: any AO atom a0 .. a1 needed
+__device__ inline bool any_row_needed(const uint8_t* need, int a0, int a1) {
+  for (int a = a0; a <= a1; ++a)
+    if (need[a]) return true;
+  return false;
+}
+
 template <class T>
 struct StageA {
   using In = T;
@@ -57,6 +64,11 @@ struct StageA {
   int64_t bs;
   int bs32;                 // brick size (elements) as int for the offset products
   FastDiv fdNA, fdNR;
+  // screened calls: needa[c * nat + a] = 0 when the M_b rows of AO atom a for
+  // slot atom c feed no kept chi block (the rows are then not computed)
+  const uint8_t* needa;
+  const int32_t* gc;        // RI atom of each brick group
+  int nat;
 
   __device__ bool tile(int bx, int by, int bz, Tile& t) const {
     const int per = n_rt * n_ct;
@@ -66,10 +78,13 @@ struct StageA {
     t.col0 = (rem / n_rt) * cols_pt;
     t.g = g0 + t.slot;
     t.tau = by;
+    t.rows = min(rows_pt, N - t.row0);
+    if (needa && t.rows > 0 &&
+        !any_row_needed(needa + (int64_t)gc[t.g] * nat, t.row0 / NA, (t.row0 + t.rows - 1) / NA))
+      return false;
     t.seg0 = goff[t.g];
     t.nseg = goff[t.g + 1] - t.seg0;
     t.K = NA * t.nseg;
-    t.rows = min(rows_pt, N - t.row0);
     t.cols = min(cols_pt, NA * NR - t.col0);
     return t.rows > 0 && t.cols > 0;
   }
@@ -109,6 +124,13 @@ struct StageA {
   __device__ void dot_out(const Tile&, double, double) const {}
 };
 
+// any pivot b0 .. b0 + ng - 1 whose stage-B column block c is needed
+__device__ inline bool any_needed(const uint8_t* needb, int b0, int ng, int nat, int c) {
+  for (int i = 0; i < ng; ++i)
+    if (needb[(int64_t)(b0 + i) * nat + c]) return true;
+  return false;
+}
+
 template <class T>
 struct StageB {
   using In = T;
@@ -134,17 +156,22 @@ struct StageB {
   int64_t bs, BPS;
   int bs32;
   FastDiv fdNA, fdNR;
+  // screened calls: needb[b * nat + c] = 0 when no chi block that N_b column
+  // block c of pivot b feeds is kept (the block is then not computed)
+  const uint8_t* needb;
+  int b0, ng, nat;          // pivots b0 .. b0 + ng - 1 of this launch
 
   __device__ bool tile(int bx, int, int, Tile& t) const {
     const int per = n_rt * n_ct;
     t.g = bx / per;
+    const int c = gc[t.g];
+    if (needb && !any_needed(needb, b0, ng, nat, c)) return false;
     const int rem = bx % per;
     t.row0 = (rem % n_rt) * rows_pt;
     t.col0 = (rem / n_rt) * cols_pt;
     t.seg0 = goff[t.g];
     t.nseg = goff[t.g + 1] - t.seg0;
     t.K = NA * t.nseg;
-    const int c = gc[t.g];
     t.p = c / PG;
     t.cl = c % PG;
     t.slot = gslot[t.g];
