@@ -224,8 +224,10 @@ gw_status gw_t3c_gaussian(const gw_system *s, const double *ao_exp, const double
  * (its direct-to-LDS outer contraction) with all stages persistent).
  * With a block screener (opts->screener, beyond the paper; the filter idea of
  * the computational details) the output blocks (c <= c', tau) predicted below
- * log10(filter_eps) - screen_margin are not computed and left zero; blocks in
- * the band above that are computed exactly.  opts->screen_audit makes the
+ * log10(filter_eps) - screen_margin are not computed and left zero (the
+ * outer-contraction tiles, the half-contracted N_b column blocks and M_b row
+ * tiles that only such blocks use are skipped); blocks in the band above that
+ * are computed exactly.  opts->screen_audit makes the
  * exact contraction the judge: the call runs again without the screener and
  * every skipped block is compared with the filter's decision on the exact
  * result (stats: violations, largest skipped norm, skipped mass).  A failed
