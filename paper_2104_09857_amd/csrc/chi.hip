@@ -1229,8 +1229,9 @@ gw_status create(int n_sys, const gw_system* systems, int n_tau, const gw_chi_op
   if ((rc = B->mem.alloc(&B->queues, B->n_queues)) != GW_OK) return rc;
   if ((rc = B->mem.alloc(&B->tiles_skipped, 1)) != GW_OK) return rc;
   GW_HIP(hipMemsetAsync(B->tiles_skipped, 0, sizeof(int), st));
-  // screened one-system calls: stage B may skip column blocks (the mask is
-  // set per call from the screener's keep mask; all needed until then)
+  // screened one-system calls: stages A and B may skip tiles that feed only
+  // unkept chi blocks (the masks are set per call from the screener's keep
+  // mask; everything is needed until then)
   if (n_sys == 1 && opts && opts->screener && opts->filter_eps > 0.0) {
     SysPlan& P = B->sys[0];
     if ((rc = B->mem.alloc(&P.needb, (size_t)P.na * P.na)) != GW_OK) return rc;
@@ -1540,7 +1541,7 @@ extern "C" gw_status gw_contract_chi(const gw_system* s, const double* d_occ, co
     const bool out_filter = B->out_filter;
     P.keep = nullptr;
     B->out_filter = false;
-    // every stage-B block of the exact run (and of a fallback after it)
+    // every stage-A and stage-B tile in the exact run (and a fallback after it)
     if (P.needb) GW_HIP(hipMemsetAsync(P.needb, 1, (size_t)na * na, st));
     if (P.needa) GW_HIP(hipMemsetAsync(P.needa, 1, (size_t)na * na, st));
     B->c_built_variant = -1;            // rebuild the stage-C tables without the mask

@@ -35,7 +35,6 @@ constexpr int kSegTab = 2048;     // max bricks per group (first atoms)
 // operand stages) and this table fit in the 160 KB of LDS
 constexpr int kPanTab = 3968;
 
-// T: operand type (double: FP64 form, float: FP32 form)
 // screening masks of the half contractions: any AO atom a0 .. a1 needed
 __device__ inline bool any_row_needed(const uint8_t* need, int a0, int a1) {
   for (int a = a0; a <= a1; ++a)
@@ -43,6 +42,7 @@ __device__ inline bool any_row_needed(const uint8_t* need, int a0, int a1) {
   return false;
 }
 
+// T: operand type (double: FP64 form, float: FP32 form)
 template <class T>
 struct StageA {
   using In = T;
